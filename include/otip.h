@@ -1,0 +1,228 @@
+/*
+ * otip -- interior-point-inspired column generation for the Kantorovich
+ * optimal-transport LP on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Zanetti & Gondzio, "An Interior-Point-Inspired algorithm for Linear
+ * Programs arising in Discrete Optimal Transport" (arXiv 2206.11009).
+ *
+ * Problem (Section 2, eqs. feasible_region, OT_problem, kantorovichlp): given
+ * masses a in R^m_+, b in R^n_+ with sum(a) = sum(b) and a cost C, find the
+ * plan P in R^{m x n}_+ with row sums a and column sums b minimising
+ * sum_ij C_ij P_ij.  Here C_ij is the integer squared Euclidean distance between
+ * integer points xs[i] and xt[j] (the paper's pixel-offset costs of Section 5.1,
+ * in the squared 2-norm), generated on the fly and never stored.
+ *
+ * Variable order is the paper's vec order: variable idx = i + j*m (0-based),
+ * i the source (row of P), j the target (column of P).
+ *
+ * Conventions of every call below
+ *   - "device" pointers live on the context's device (any allocator, e.g.
+ *     torch); "host" pointers are ordinary CPU memory.
+ *   - The caller owns every buffer it passes; nothing is retained after the
+ *     call returns.  The library owns contexts and result objects.
+ *   - All device work is enqueued on the context's stream; a call that returns
+ *     host values synchronises that stream before returning.
+ *   - Calls return OTIP_OK or an error code; otip_last_error() gives the
+ *     message.  No exception crosses this boundary.
+ *   - A context is not thread-safe; use one context per host thread.
+ */
+#ifndef OTIP_H
+#define OTIP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OTIP_ABI_VERSION 1
+
+enum otip_status {
+    OTIP_OK = 0,
+    OTIP_EINVAL = 1,      /* bad argument: sizes, null pointers, masses */
+    OTIP_ENOMEM = 2,      /* device allocation failed */
+    OTIP_EHIP = 3,        /* HIP runtime error */
+    OTIP_EMAXITER = 4,    /* iteration limit: result valid, gap may exceed tol */
+    OTIP_ENUMERIC = 5,    /* NaN or breakdown */
+    OTIP_EUNSUPPORTED = 6 /* request outside what this build supports */
+};
+
+enum otip_linear_solver { OTIP_LS_AUTO = 0, OTIP_LS_PCG = 1, OTIP_LS_DIRECT = 2 };
+enum otip_precision { OTIP_FP64 = 0, OTIP_MIXED = 1 };
+
+/*
+ * Solver parameters.  Defaults (otip_params_default) are the paper's values
+ * where it states them (Section 5.2: tol 1e-6, CG tolerance 1e-6 for
+ * predictors and 1e-3 for correctors, 200 iterations, 1000 CG iterations per
+ * call, 3 correctors; Section 3.3: step 0.995 of the step to the boundary;
+ * Section 4.3: window of 5 iterations for the switch) and otherwise readings of
+ * points it leaves open.
+ */
+typedef struct otip_params {
+    double tol;              /* stop test tolerance (Section 3.2) */
+    double cg_tol_pred;      /* CG relative tolerance, predictor/Mehrotra solves */
+    double cg_tol_corr;      /* CG relative tolerance, centrality correctors */
+    int32_t max_iter;        /* outer iterations */
+    int32_t cg_max_iter;     /* CG iterations per solve */
+    int32_t max_corr;        /* centrality correctors per iteration */
+    double step_scale;       /* fraction of the step to the boundary */
+    double kappa;            /* initial support ~ kappa*(m+n-1) cheapest variables */
+    int32_t switch_window;   /* psi history window for the CG -> direct switch */
+    double switch_drop;      /* relative psi drop over the window that switches */
+    double mcc_beta_min;     /* centrality target box [beta_min, beta_max]*sigma*mu */
+    double mcc_beta_max;
+    double mcc_delta;        /* trial step increase for a corrector */
+    double mcc_accept;       /* minimum step gain to accept a corrector */
+    double remove_gate;      /* remove only when max(rel r1, rel r2) <= gate */
+    double remove_rel;       /* remove p_ij < remove_rel*min(a_i, b_j) */
+    double pivot_tol;        /* LDL^T pivot d_k <= pivot_tol*S_kk becomes +inf */
+    double cert_rel;         /* a-posteriori pricing: significant if sum(a)|r| > cert_rel*max(1,|obj|) */
+    double polish_tol;       /* final primal projection target ||Ap-f||_1/||f||_1 */
+    int32_t polish_steps;
+    double drop_rel;         /* purified flows below drop_rel*min(a_i,b_j) are zero */
+    double cg_eta;           /* CG residual must also be <= cg_eta*max(||r1||, cg_floor*(1+||f||)) */
+    double cg_floor;
+    int32_t linear_solver;   /* otip_linear_solver */
+    int32_t precision;       /* otip_precision */
+    int32_t dense_max_n;     /* largest Schur order factorised by the dense LDL^T */
+    int32_t force_switch_at; /* >= 0: switch to the direct solver at this iteration */
+    int32_t enter_cap;       /* max entering columns per iteration; <= 0 means m */
+    int32_t scale;           /* power-of-two scaling of masses and costs (1 = on) */
+    int32_t verbose;         /* 1: one line per iteration on stderr */
+} otip_params;
+
+/* Problem description.  All four arrays are DEVICE pointers.
+ *   a  : m doubles, > 0          b : n doubles, > 0, |sum a - sum b| <= 1e-12 sum a
+ *   xs : m x 2 int32, row-major   xt: n x 2 int32, row-major, coordinates in
+ *        [-2^14, 2^14] so that every cost fits in 31 bits. */
+typedef struct otip_problem {
+    int32_t m;
+    int32_t n;
+    const double *a;
+    const double *b;
+    const int32_t *xs;
+    const int32_t *xt;
+} otip_problem;
+
+/* Summary of a solve (Section 5.3 reports iterations, time, CG iterations,
+ * fill and iterative/direct iteration counts; Table 3). */
+typedef struct otip_info {
+    int32_t status;            /* OTIP_OK or OTIP_EMAXITER */
+    int32_t iterations;        /* outer iterations */
+    int32_t cg_iterations;     /* total CG iterations */
+    int32_t direct_iterations; /* iterations solved by the direct factorisation */
+    int64_t nnz;               /* nonzeros of the returned plan (<= m+n-1) */
+    int64_t psi_max;           /* largest support size seen */
+    double objective;          /* sum_ij C_ij P_ij of the returned plan */
+    double dual_bound;         /* a.y + b.z + sum(a)*min(0, r_min): a certified lower bound */
+    double rel_gap;            /* (objective - dual_bound) / max(1, |objective|) */
+    double marginal_residual;  /* ||P e - a||_1 + ||P^T e - b||_1 over ||a||_1 + ||b||_1 */
+    double r_min;              /* min over all (i,j) of C_ij - y_i - z_j */
+    double max_fill_pct;       /* largest factor density, 100*nnz(L)/n^2 */
+    double seconds_total;
+    double seconds_pricing;    /* full m*n scans (pricing, certification) */
+    double seconds_newton;     /* Schur assembly, solves, step computation */
+    double seconds_direct;     /* dense factorisations (part of seconds_newton) */
+    double seconds_update;     /* support update and rebuild */
+    double seconds_setup;      /* initial support, starting point */
+    double seconds_final;      /* polish, purification, certificate */
+} otip_info;
+
+typedef struct otip_ctx otip_ctx;
+typedef struct otip_result otip_result;
+
+/* ABI version of the loaded library (OTIP_ABI_VERSION). */
+int otip_version(void);
+
+/* Fill *p with the defaults described above. */
+void otip_params_default(otip_params *p);
+
+/* Create a context on HIP device `device`; `hip_stream` is a hipStream_t to
+ * run on (NULL: the default stream).  On success *ctx owns device scratch
+ * memory that otip_destroy frees.  Errors: OTIP_EINVAL, OTIP_EHIP. */
+int otip_create(otip_ctx **ctx, int device, void *hip_stream);
+void otip_destroy(otip_ctx *ctx);
+
+/* Message of the last error on this context (never NULL). */
+const char *otip_last_error(const otip_ctx *ctx);
+
+/*
+ * Solve one problem (the whole method of Sections 3-4: initial support,
+ * Newton steps on the restricted problem, pricing and support updates, the
+ * CG -> LDL^T switch; then a final primal projection, purification to a basic
+ * plan and the dual certificate).  params may be NULL (defaults).  On OTIP_OK or
+ * OTIP_EMAXITER *out holds a result to query and free.
+ */
+int otip_solve(otip_ctx *ctx, const otip_problem *pr, const otip_params *params,
+               otip_result **out);
+
+/*
+ * Solve `count` independent problems; outs[k] receives each result.  The
+ * per-instance full scans of all problems of one outer iteration run as one
+ * launch over a table of instances.
+ */
+int otip_solve_batch(otip_ctx *ctx, const otip_problem *prs, int32_t count,
+                     const otip_params *params, otip_result **outs);
+
+int otip_result_info(const otip_result *r, otip_info *info);
+/* Copy the plan (COO, sorted by variable index i + j*m, nnz entries) and the
+ * duals, gauge-normalised so that z[n-1] = 0, into HOST buffers.  Any pointer
+ * may be NULL to skip that output. */
+int otip_result_copy(const otip_result *r, int32_t *rows, int32_t *cols, double *vals,
+                     double *y, double *z);
+void otip_result_free(otip_result *r);
+
+/*
+ * Pricing scan (Sections 3.2 and 3.4): over all variables NOT in the support,
+ * the reduced costs r_ij = ((double)C_ij - y_i) - z_j (two IEEE double
+ * subtractions in this order); the at most kmax strictly negative ones, ordered
+ * by (r, i + j*m) ascending, are returned.
+ *   xs, xt, y (m), z (n): DEVICE.  support_bitmap: DEVICE, ceil(m*n/32) words,
+ *   bit (idx & 31) of word idx >> 5 set for variables in the support; NULL for
+ *   an empty support.  out_i, out_j (int32), out_r (double): DEVICE, kmax
+ *   entries.  out_count (selected) and out_nneg (all negative reduced costs
+ *   outside the support): HOST.
+ *   precision: OTIP_FP64, or OTIP_MIXED (FP32 scan with an FP64 re-check of
+ *   every candidate within a proven margin; same result).
+ */
+int otip_price(otip_ctx *ctx, int32_t m, int32_t n, const int32_t *xs, const int32_t *xt,
+               const double *y, const double *z, const uint32_t *support_bitmap,
+               int64_t kmax, int32_t precision, int32_t *out_i, int32_t *out_j, double *out_r,
+               int64_t *out_count, int64_t *out_nneg);
+
+/* min over ALL (i, j) of ((double)C_ij - y_i) - z_j and the first variable index
+ * attaining it (Section 3.3: s_hat = c - A^T y_hat).  Outputs are HOST. */
+int otip_rmin(otip_ctx *ctx, int32_t m, int32_t n, const int32_t *xs, const int32_t *xt,
+              const double *y, const double *z, double *out_rmin, int64_t *out_arg);
+
+/*
+ * Matrix-free Kronecker products of Section 2.1 on a dense m x n array X
+ * stored column-major (x = vec(X)), all DEVICE:
+ *   otip_kron_apply : rowsum = A_1 x = X e_n (m), colsum = A_2 x = X^T e_m (n)
+ *   otip_kron_apply_t: X = vec^{-1}(A_1^T y + A_2^T z), X_ij = y_i + z_j
+ */
+int otip_kron_apply(otip_ctx *ctx, int32_t m, int32_t n, const double *X, double *rowsum,
+                    double *colsum);
+int otip_kron_apply_t(otip_ctx *ctx, int32_t m, int32_t n, const double *y, const double *z,
+                      double *X);
+
+/*
+ * Normal-equation blocks on a support (Sections 3.5 and 4).  idx: DEVICE, psi
+ * variable indices sorted ascending, no duplicates, every row and column of
+ * the plan covered; theta: DEVICE, psi positive values (theta = p/s).
+ * Computes M = row sums, N = column sums of V (vec(V) = theta on the support)
+ * and the Schur complement S_M = N - V^T M^-1 V in CSR form (n x n, column
+ * indices sorted).  Two calls: with rowptr == NULL only *out_nnz (HOST) is
+ * set; then pass rowptr (n+1 int32), colidx (nnz int32), vals (nnz double),
+ * M (m), N (n), all DEVICE.  The diagonal is formed as minus the sum of the
+ * off-diagonal entries of its row, which eq. diagdom shows equal to
+ * N_jj - (V^T M^-1 V)_jj without the cancellation of the latter.
+ */
+int otip_schur(otip_ctx *ctx, int32_t m, int32_t n, int64_t psi, const int64_t *idx,
+               const double *theta, int64_t *out_nnz, int32_t *rowptr, int32_t *colidx,
+               double *vals, double *M, double *N);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OTIP_H */

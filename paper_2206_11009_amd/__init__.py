@@ -1,0 +1,247 @@
+"""otip: interior-point-inspired column generation for the Kantorovich OT LP
+on AMD MI355X (Zanetti & Gondzio, arXiv 2206.11009).
+
+Thin Python binding of the C-ABI library ``libotip.so`` (``include/otip.h``).
+The functions carry the C names; they only marshal arguments -- torch tensors
+hold device memory, torch's current stream is the stream -- and every step of
+the method runs in the library's HIP kernels.  There is no CPU fallback: the
+calls raise if the library is not built or no GPU is present.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _abi
+from ._abi import (OTIP_OK, OTIP_EMAXITER, OTIP_FP64, OTIP_MIXED, OTIP_LS_AUTO, OTIP_LS_PCG,  # noqa: F401
+                   OTIP_LS_DIRECT, otip_params, otip_problem, otip_info)
+
+__all__ = ["otip_version", "otip_params_default", "Context", "OtipError", "SolveResult",
+           "otip_solve", "otip_solve_batch", "otip_price", "otip_rmin", "otip_kron_apply",
+           "otip_kron_apply_t", "otip_schur", "params"]
+
+
+class OtipError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"otip error {code}: {msg}")
+        self.code = code
+
+
+def otip_version() -> int:
+    return _abi.load().otip_version()
+
+
+def otip_params_default() -> otip_params:
+    p = otip_params()
+    _abi.load().otip_params_default(ctypes.byref(p))
+    return p
+
+
+def params(**kw) -> otip_params:
+    """Defaults with some fields overridden, e.g. params(tol=1e-8, verbose=1)."""
+    p = otip_params_default()
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise OtipError(_abi.OTIP_EINVAL, "no GPU: the otip library runs on an AMD GPU only")
+    return torch
+
+
+class Context:
+    """An otip context bound to a device and torch's current stream on it."""
+
+    def __init__(self, device: int = 0):
+        torch = _torch()
+        self.device = device
+        with torch.cuda.device(device):
+            stream = torch.cuda.current_stream(device).cuda_stream
+        self._lib = _abi.load()
+        h = ctypes.c_void_p()
+        rc = self._lib.otip_create(ctypes.byref(h), device, ctypes.c_void_p(stream))
+        if rc != OTIP_OK:
+            raise OtipError(rc, "otip_create failed")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.otip_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, rc, allow=(OTIP_OK,)):
+        if rc not in allow:
+            raise OtipError(rc, self._lib.otip_last_error(self.handle).decode())
+        return rc
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(x, dtype, device):
+    torch = _torch()
+    if isinstance(x, torch.Tensor):
+        return x.to(device=f"cuda:{device}", dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device=f"cuda:{device}")
+
+
+@dataclass
+class SolveResult:
+    status: int
+    info: dict
+    rows: np.ndarray
+    cols: np.ndarray
+    flows: np.ndarray
+    y: np.ndarray
+    z: np.ndarray
+
+    def __getattr__(self, k):
+        info = self.__dict__.get("info", {})
+        if k in info:
+            return info[k]
+        raise AttributeError(k)
+
+
+def _problem(ctx, a, b, xs, xt):
+    torch = _torch()
+    A = _dev(a, torch.float64, ctx.device)
+    B = _dev(b, torch.float64, ctx.device)
+    XS = _dev(xs, torch.int32, ctx.device)
+    XT = _dev(xt, torch.int32, ctx.device)
+    pr = otip_problem(int(A.shape[0]), int(B.shape[0]), A.data_ptr(), B.data_ptr(),
+                      XS.data_ptr(), XT.data_ptr())
+    return pr, (A, B, XS, XT)
+
+
+def _collect(ctx, res_handle, rc):
+    lib = ctx._lib
+    info = otip_info()
+    ctx.check(lib.otip_result_info(res_handle, ctypes.byref(info)))
+    d = info.as_dict()
+    nnz = int(info.nnz)
+    rows = np.empty(nnz, np.int32)
+    cols = np.empty(nnz, np.int32)
+    vals = np.empty(nnz, np.float64)
+    return d, rows, cols, vals
+
+
+def otip_solve(ctx: Context, a, b, xs, xt, prm: otip_params | None = None) -> SolveResult:
+    """Solve one problem; a, b, xs, xt may be numpy arrays or torch tensors."""
+    pr, keep = _problem(ctx, a, b, xs, xt)
+    h = ctypes.c_void_p()
+    rc = ctx._lib.otip_solve(ctx.handle, ctypes.byref(pr),
+                             ctypes.byref(prm) if prm is not None else None, ctypes.byref(h))
+    ctx.check(rc, (OTIP_OK, OTIP_EMAXITER))
+    try:
+        d, rows, cols, vals = _collect(ctx, h, rc)
+        y = np.empty(pr.m, np.float64)
+        z = np.empty(pr.n, np.float64)
+        ctx.check(ctx._lib.otip_result_copy(h, rows.ctypes.data, cols.ctypes.data,
+                                            vals.ctypes.data, y.ctypes.data, z.ctypes.data))
+    finally:
+        ctx._lib.otip_result_free(h)
+    del keep
+    return SolveResult(rc, d, rows, cols, vals, y, z)
+
+
+def otip_solve_batch(ctx: Context, problems, prm: otip_params | None = None):
+    """Solve a list of (a, b, xs, xt) problems; returns a list of SolveResult."""
+    prs = (otip_problem * len(problems))()
+    keep = []
+    for k, (a, b, xs, xt) in enumerate(problems):
+        pr, kk = _problem(ctx, a, b, xs, xt)
+        prs[k] = pr
+        keep.append(kk)
+    outs = (ctypes.c_void_p * len(problems))()
+    rc = ctx._lib.otip_solve_batch(ctx.handle, prs, len(problems),
+                                   ctypes.byref(prm) if prm is not None else None, outs)
+    ctx.check(rc, (OTIP_OK, OTIP_EMAXITER))
+    results = []
+    for k in range(len(problems)):
+        h = ctypes.c_void_p(outs[k])
+        d, rows, cols, vals = _collect(ctx, h, rc)
+        y = np.empty(prs[k].m, np.float64)
+        z = np.empty(prs[k].n, np.float64)
+        ctx.check(ctx._lib.otip_result_copy(h, rows.ctypes.data, cols.ctypes.data,
+                                            vals.ctypes.data, y.ctypes.data, z.ctypes.data))
+        ctx._lib.otip_result_free(h)
+        results.append(SolveResult(d["status"], d, rows, cols, vals, y, z))
+    return results
+
+
+def otip_price(ctx: Context, xs, xt, y, z, bitmap, kmax: int, precision: int = OTIP_FP64):
+    """Pricing scan; returns (i, j, r) device tensors of the selected columns and
+    the count of negative reduced costs outside the support."""
+    torch = _torch()
+    XS, XT = _dev(xs, torch.int32, ctx.device), _dev(xt, torch.int32, ctx.device)
+    Y, Z = _dev(y, torch.float64, ctx.device), _dev(z, torch.float64, ctx.device)
+    BM = _dev(bitmap, torch.int32, ctx.device) if bitmap is not None else None
+    m, n = int(XS.shape[0]), int(XT.shape[0])
+    k = max(int(kmax), 1)
+    oi = torch.empty(k, dtype=torch.int32, device=Y.device)
+    oj = torch.empty(k, dtype=torch.int32, device=Y.device)
+    orr = torch.empty(k, dtype=torch.float64, device=Y.device)
+    cnt, nneg = ctypes.c_int64(), ctypes.c_int64()
+    ctx.check(ctx._lib.otip_price(ctx.handle, m, n, _ptr(XS), _ptr(XT), _ptr(Y), _ptr(Z),
+                                  _ptr(BM) if BM is not None else None, int(kmax), precision,
+                                  _ptr(oi), _ptr(oj), _ptr(orr), ctypes.byref(cnt),
+                                  ctypes.byref(nneg)))
+    c = int(cnt.value)
+    return oi[:c], oj[:c], orr[:c], int(nneg.value)
+
+
+def otip_rmin(ctx: Context, xs, xt, y, z):
+    torch = _torch()
+    XS, XT = _dev(xs, torch.int32, ctx.device), _dev(xt, torch.int32, ctx.device)
+    Y, Z = _dev(y, torch.float64, ctx.device), _dev(z, torch.float64, ctx.device)
+    v, arg = ctypes.c_double(), ctypes.c_int64()
+    ctx.check(ctx._lib.otip_rmin(ctx.handle, int(XS.shape[0]), int(XT.shape[0]), _ptr(XS),
+                                 _ptr(XT), _ptr(Y), _ptr(Z), ctypes.byref(v), ctypes.byref(arg)))
+    return float(v.value), int(arg.value)
+
+
+def otip_kron_apply(ctx: Context, X, rowsum, colsum):
+    """rowsum = X e_n, colsum = X^T e_m for a column-major m x n float64 tensor
+    (pass X as an (n, m) row-major tensor, i.e. vec(X) contiguous)."""
+    n, m = X.shape
+    ctx.check(ctx._lib.otip_kron_apply(ctx.handle, m, n, _ptr(X), _ptr(rowsum), _ptr(colsum)))
+
+
+def otip_kron_apply_t(ctx: Context, y, z, X):
+    n, m = X.shape
+    ctx.check(ctx._lib.otip_kron_apply_t(ctx.handle, m, n, _ptr(y), _ptr(z), _ptr(X)))
+
+
+def otip_schur(ctx: Context, m: int, n: int, idx, theta):
+    """S_M of the support idx (sorted variable indices) with weights theta;
+    returns (rowptr, colidx, vals, M, N) as device tensors."""
+    torch = _torch()
+    I = _dev(idx, torch.int64, ctx.device)
+    T = _dev(theta, torch.float64, ctx.device)
+    nnz = ctypes.c_int64()
+    ctx.check(ctx._lib.otip_schur(ctx.handle, m, n, int(I.shape[0]), _ptr(I), _ptr(T),
+                                  ctypes.byref(nnz), None, None, None, None, None))
+    dev = I.device
+    rp = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    ci = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev)
+    va = torch.empty(max(nnz.value, 1), dtype=torch.float64, device=dev)
+    M = torch.empty(m, dtype=torch.float64, device=dev)
+    N = torch.empty(n, dtype=torch.float64, device=dev)
+    ctx.check(ctx._lib.otip_schur(ctx.handle, m, n, int(I.shape[0]), _ptr(I), _ptr(T),
+                                  ctypes.byref(nnz), _ptr(rp), _ptr(ci), _ptr(va), _ptr(M),
+                                  _ptr(N)))
+    return rp, ci[:nnz.value], va[:nnz.value], M, N

@@ -1,0 +1,112 @@
+// Internal declarations shared by the otip HIP sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace otip {
+
+// Thrown inside the library, turned into a status code at the C boundary.
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &msg) : std::runtime_error(msg), code(c) {}
+};
+
+#define OTIP_HIP(call)                                                                        \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            throw ::otip::Error(3, std::string(#call) + ": " + hipGetErrorString(e_) + " (" + \
+                                     __FILE__ + ":" + std::to_string(__LINE__) + ")");        \
+    } while (0)
+
+#define OTIP_CHECK(cond, code, msg)                          \
+    do {                                                     \
+        if (!(cond)) throw ::otip::Error((code), (msg));     \
+    } while (0)
+
+// Growable device allocation owned by a context.  Contents are not preserved
+// across growth.
+template <typename T>
+struct DBuf {
+    T *ptr = nullptr;
+    size_t cap = 0;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    ~DBuf() { release(); }
+    void release() {
+        if (ptr) (void)hipFree(ptr);
+        ptr = nullptr;
+        cap = 0;
+    }
+    T *need(size_t n) {
+        if (n == 0) n = 1;
+        if (n > cap) {
+            release();
+            size_t c = n + n / 4;
+            hipError_t e = hipMalloc(&ptr, c * sizeof(T));
+            if (e != hipSuccess) {
+                ptr = nullptr;
+                throw Error(2, "device allocation of " + std::to_string(c * sizeof(T)) +
+                                   " bytes failed: " + hipGetErrorString(e));
+            }
+            cap = c;
+        }
+        return ptr;
+    }
+    T *get() const { return ptr; }
+};
+
+inline unsigned grid_for(int64_t n, int block) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > 0x7fffffff) g = 0x7fffffff;
+    return (unsigned)g;
+}
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- device helpers
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_sum_i(int v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Block-wide fixed-order sum of one double per thread (blockDim.x multiple of
+// 64, <= 1024).  Result valid in every thread.
+__device__ __forceinline__ double block_sum(double v, double *lds /* >= 16 */) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if (lane == 0) lds[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int k = 0; k < nw; ++k) t += lds[k];
+    return t;
+}
+
+// Ordered 64-bit key of a double: key(a) < key(b)  <=>  a < b (no NaNs).
+__device__ __forceinline__ uint64_t dkey(double r) {
+    uint64_t u = (uint64_t)__double_as_longlong(r);
+    return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double dkey_inv(uint64_t k) {
+    uint64_t u = (k & 0x8000000000000000ull) ? (k & 0x7fffffffffffffffull) : ~k;
+    return __longlong_as_double((long long)u);
+}
+
+}  // namespace otip

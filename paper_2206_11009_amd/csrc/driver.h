@@ -1,0 +1,97 @@
+// Solver state of one problem (internal).
+#pragma once
+
+#include <cstdarg>
+
+#include "../../include/otip.h"
+#include "internal.h"
+
+namespace otip {
+
+struct Result {
+    otip_info info{};
+    std::vector<int32_t> rows, cols;
+    std::vector<double> vals, y, z;
+};
+
+// Host-side purification of a plan to an acyclic support (purify.cpp).
+void purify_plan(int m, int n, const std::vector<int32_t> &rows, const std::vector<int32_t> &cols,
+                 const std::vector<double> &flows, const std::vector<int64_t> &costs,
+                 const std::vector<double> &a, const std::vector<double> &b, double drop_rel,
+                 std::vector<int32_t> &orows, std::vector<int32_t> &ocols,
+                 std::vector<double> &oflows);
+
+enum class Mode { PCG, Direct };
+
+struct Dir {
+    DBuf<double> dp, ds, dy, dz;
+};
+
+class Solver {
+  public:
+    explicit Solver(hipStream_t s) : st(s) {}
+    int run(const otip_problem &pr, const otip_params &prm, Result &res);
+    // normal-equation blocks and S_M for a given support and theta (parity checks)
+    int64_t schur_export(int m, int n, int64_t psi, const uint64_t *idx, const double *theta,
+                         int32_t *rowptr, int32_t *colidx, double *vals, double *Mout,
+                         double *Nout);
+
+  private:
+    void rebuild_views();
+    void alloc_support(int64_t cap);
+    void rowsum(const double *v, const double *base, double *out, double sign);
+    void colsum(const double *v, const double *base, double *out, double sign);
+    void newton(const double *r1a, const double *r1b, const double *r2, const double *r3,
+                double rtol, double atol, Dir &out);
+    void max_steps(const Dir &d, double &ap, double &ad);
+    void assemble();
+    void residuals(double &rel1, double &rel2, double &mu, double &primal, double &r1n);
+    int64_t price(int64_t kmax, uint64_t *out_idx, double *out_r, int64_t *nneg);
+    void update_support(const uint64_t *add_idx, int64_t nadd, double pin, const uint8_t *removed,
+                        int64_t nrem);
+    int64_t select_removals(uint8_t *removed);
+    void starting_point();
+    void finalize(Result &res);
+    static double now();
+    void log(const char *fmt, ...);
+
+    hipStream_t st;
+    otip_params P{};
+    Scanner scan;
+    Reducer red;
+    SchurSolver schur;
+    DenseLDL ldl;
+    DBuf<char> tmp;
+
+    int m = 0, n = 0;
+    const int32_t *xs = nullptr, *xt = nullptr;
+    int64_t cmax = 0;
+    double omega = 1.0, zeta = 1.0, fnorm = 0.0;
+    const double *a_in = nullptr, *b_in = nullptr;
+
+    int64_t psi_ = 0, psi_max = 0;
+    DBuf<uint64_t> idx;
+    DBuf<int32_t> si, sj, col_ptr, row_ptr, csr_pos;
+    DBuf<double> p, s, c, theta, r2, r3, w;
+    DBuf<uint8_t> prot;
+    DBuf<uint32_t> bitmap;
+    DBuf<double> a, b, y, z, M, invM, N, r1a, r1b, beta1, beta2, rhs, tmpn, tmpn2, zm, zn, zpsi;
+    DBuf<double> yun, zun;
+    Dir D[3];
+    DBuf<uint64_t> tmp_u64a, tmp_u64b, tmp_u64c, tmp_u64d;
+    DBuf<double> tmp_f64a, tmp_f64b, tmp_f64c, tmp_f64d;
+    DBuf<int32_t> tmp_i32a, tmp_i32b;
+    DBuf<uint32_t> tmp_u32a;
+    bool schur_valid = false;
+
+    Mode mode = Mode::PCG;
+    bool cg_failed = false;
+    int cg_its_iter = 0, max_cg_solve = 0;
+    int64_t cg_total = 0;
+    int direct_its = 0, iterations = 0;
+    int64_t pricing_passes = 0;
+    double max_fill = 0.0;
+    double t_pricing = 0, t_newton = 0, t_direct = 0, t_update = 0, t_setup = 0, t_final = 0;
+};
+
+}  // namespace otip

@@ -1,0 +1,1124 @@
+// The method's outer loop (Sections 3.1-3.4, 4.2-4.3) on one GPU.
+//
+// Device state: the support ("index", Section 3.2) as variable indices sorted
+// ascending -- i.e. grouped by target j, a compressed-column view of the plan --
+// with p, s, costs and (i, j); a compressed-row view through a permutation; a
+// bit per variable for the pricing scan; the duals y (m) and z (n).  All
+// per-element work runs in the kernels below and in scan/schur/dense; the host
+// only takes the scalar decisions (stop test, step lengths, corrector
+// acceptance, switch), each after one small device-to-host copy.
+#include <chrono>
+#include <cstring>
+
+#include "driver.h"
+
+namespace otip {
+
+// ============================================================== reductions
+template <int K, class F>
+__global__ __launch_bounds__(Reducer::kThreads) void rsum_k(int64_t N, F f, double *part) {
+    __shared__ double lds[16];
+    double acc[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) acc[q] = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < N;
+         t += (int64_t)gridDim.x * blockDim.x)
+        f(t, acc);
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        double v = block_sum(acc[q], lds);
+        if (threadIdx.x == 0) part[q * Reducer::kBlocks + blockIdx.x] = v;
+    }
+}
+
+template <int K, class F>
+__global__ __launch_bounds__(Reducer::kThreads) void rmin_k(int64_t N, F f, double *part) {
+    __shared__ double lds[16];
+    double acc[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) acc[q] = INFINITY;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < N;
+         t += (int64_t)gridDim.x * blockDim.x)
+        f(t, acc);
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        double v = wave_min(acc[q]);
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double b = lds[0];
+            for (int w = 1; w < (int)(blockDim.x >> 6); ++w) b = fmin(b, lds[w]);
+            part[q * Reducer::kBlocks + blockIdx.x] = b;
+        }
+    }
+}
+
+void Reducer::fetch_sum(hipStream_t st, int K, int nb, double *out) {
+    host_.resize((size_t)K * kBlocks);
+    OTIP_HIP(hipMemcpyAsync(host_.data(), part_.get(), sizeof(double) * K * kBlocks,
+                            hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipStreamSynchronize(st));
+    for (int q = 0; q < K; ++q) {
+        double s = 0.0;
+        for (int b = 0; b < nb; ++b) s += host_[(size_t)q * kBlocks + b];
+        out[q] = s;
+    }
+}
+
+void Reducer::fetch_min(hipStream_t st, int K, int nb, double *out) {
+    host_.resize((size_t)K * kBlocks);
+    OTIP_HIP(hipMemcpyAsync(host_.data(), part_.get(), sizeof(double) * K * kBlocks,
+                            hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipStreamSynchronize(st));
+    for (int q = 0; q < K; ++q) {
+        double s = INFINITY;
+        for (int b = 0; b < nb; ++b) s = std::min(s, host_[(size_t)q * kBlocks + b]);
+        out[q] = s;
+    }
+}
+
+static int red_blocks(int64_t N) {
+    return (int)std::min<int64_t>(Reducer::kBlocks, std::max<int64_t>(1, (N + 255) / 256));
+}
+
+template <int K, class F>
+static void reduce_sum(hipStream_t st, Reducer &R, int64_t N, F f, double *out) {
+    const int nb = red_blocks(N);
+    hipLaunchKernelGGL((rsum_k<K, F>), dim3(nb), dim3(Reducer::kThreads), 0, st, N, f, R.base());
+    OTIP_HIP(hipGetLastError());
+    R.fetch_sum(st, K, nb, out);
+}
+
+template <int K, class F>
+static void reduce_min(hipStream_t st, Reducer &R, int64_t N, F f, double *out) {
+    const int nb = red_blocks(N);
+    hipLaunchKernelGGL((rmin_k<K, F>), dim3(nb), dim3(Reducer::kThreads), 0, st, N, f, R.base());
+    OTIP_HIP(hipGetLastError());
+    R.fetch_min(st, K, nb, out);
+}
+
+// launch an element-wise functor over [0, N)
+template <class F>
+__global__ void foreach_k(int64_t N, F f) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < N;
+         t += (int64_t)gridDim.x * blockDim.x)
+        f(t);
+}
+template <class F>
+static void foreach(hipStream_t st, int64_t N, F f) {
+    if (N <= 0) return;
+    const unsigned g = (unsigned)std::min<int64_t>(4096, (N + 255) / 256);
+    hipLaunchKernelGGL((foreach_k<F>), dim3(g), dim3(256), 0, st, N, f);
+    OTIP_HIP(hipGetLastError());
+}
+
+// =============================================================== support views
+// idx sorted ascending -> (i, j), scaled costs
+struct FDerive {
+    const uint64_t *idx;
+    int32_t *si, *sj;
+    double *c;
+    const int32_t *xs, *xt;
+    int m;
+    double zeta;
+    __device__ void operator()(int64_t k) const {
+        const uint64_t v = idx[k];
+        const int i = (int)(v % (uint64_t)m), j = (int)(v / (uint64_t)m);
+        si[k] = i;
+        sj[k] = j;
+        const int64_t d0 = (int64_t)xs[2 * i] - xt[2 * j], d1 = (int64_t)xs[2 * i + 1] - xt[2 * j + 1];
+        c[k] = (double)(d0 * d0 + d1 * d1) * zeta;
+    }
+};
+
+// ptr[t] = first position whose key >= t (keys sorted ascending)
+struct FLowerBound {
+    const int32_t *key;
+    int64_t len;
+    int32_t *ptr;
+    __device__ void operator()(int64_t t) const {
+        int64_t lo = 0, hi = len;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if (key[mid] < (int32_t)t)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        ptr[t] = (int32_t)lo;
+    }
+};
+
+struct FIota {
+    int32_t *v;
+    __device__ void operator()(int64_t t) const { v[t] = (int32_t)t; }
+};
+
+struct FBits {
+    const uint64_t *idx;
+    uint32_t *bm;
+    bool set;
+    __device__ void operator()(int64_t k) const {
+        const uint64_t v = idx[k];
+        if (v == ~0ull) return;
+        if (set)
+            atomicOr(&bm[v >> 5], 1u << (v & 31u));
+        else
+            atomicAnd(&bm[v >> 5], ~(1u << (v & 31u)));
+    }
+};
+
+void Solver::rebuild_views() {
+    const int64_t psi = psi_;
+    foreach(st, psi, FDerive{idx.get(), si.get(), sj.get(), c.get(), xs, xt, m, zeta});
+    col_ptr.need((size_t)n + 1);
+    foreach(st, (int64_t)n + 1, FLowerBound{sj.get(), psi, col_ptr.get()});
+    // compressed-row view: stable sort of positions by source
+    tmp_i32a.need(psi);
+    tmp_u32a.need(psi);
+    foreach(st, psi, FIota{tmp_i32a.get()});
+    csr_pos.need(psi);
+    int bits = 1;
+    while ((1ll << bits) < m) ++bits;
+    sort_pairs_u32_i32(st, (const uint32_t *)si.get(), tmp_i32a.get(), tmp_u32a.get(),
+                       csr_pos.get(), psi, bits, tmp);
+    row_ptr.need((size_t)m + 1);
+    foreach(st, (int64_t)m + 1, FLowerBound{(const int32_t *)tmp_u32a.get(), psi, row_ptr.get()});
+    schur_valid = false;
+}
+
+void Solver::alloc_support(int64_t cap) {
+    idx.need(cap);
+    si.need(cap);
+    sj.need(cap);
+    p.need(cap);
+    s.need(cap);
+    c.need(cap);
+    theta.need(cap);
+    r2.need(cap);
+    r3.need(cap);
+    w.need(cap);
+    for (auto *d : {&D[0], &D[1], &D[2]}) {
+        d->dp.need(cap);
+        d->ds.need(cap);
+        d->dy.need(m);
+        d->dz.need(n);
+    }
+    prot.need(cap);
+}
+
+// ============================================================ segmented sums
+// out[i] = base[i] + sign * sum over row i of v (compressed-row view)
+struct FRowSum {
+    const int32_t *row_ptr, *csr_pos;
+    const double *v, *base;
+    double *out;
+    double sign;
+    __device__ void operator()(int64_t i) const {
+        double s = 0.0;
+        for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) s += v[csr_pos[e]];
+        out[i] = (base ? base[i] : 0.0) + sign * s;
+    }
+};
+struct FColSum {
+    const int32_t *col_ptr;
+    const double *v, *base;
+    double *out;
+    double sign;
+    __device__ void operator()(int64_t j) const {
+        double s = 0.0;
+        for (int e = col_ptr[j]; e < col_ptr[j + 1]; ++e) s += v[e];
+        out[j] = (base ? base[j] : 0.0) + sign * s;
+    }
+};
+
+void Solver::rowsum(const double *v, const double *base, double *out, double sign) {
+    foreach(st, m, FRowSum{row_ptr.get(), csr_pos.get(), v, base, out, sign});
+}
+void Solver::colsum(const double *v, const double *base, double *out, double sign) {
+    foreach(st, n, FColSum{col_ptr.get(), v, base, out, sign});
+}
+
+// ============================================================ Newton pieces
+struct FTheta {
+    const double *p, *s;
+    double *th;
+    __device__ void operator()(int64_t k) const { th[k] = p[k] / s[k]; }
+};
+struct FInv {
+    const double *v;
+    double *o;
+    __device__ void operator()(int64_t k) const { o[k] = 1.0 / v[k]; }
+};
+// w = theta (r2 - r3 / p)
+struct FW {
+    const double *th, *r2, *r3, *p;
+    double *w;
+    __device__ void operator()(int64_t k) const {
+        w[k] = th[k] * ((r2 ? r2[k] : 0.0) - r3[k] / p[k]);
+    }
+};
+// rhs_j = beta2_j - sum_{i in col j} theta_ij beta1_i / M_i
+struct FRhs {
+    const int32_t *col_ptr, *si;
+    const double *th, *beta1, *invM, *beta2;
+    double *rhs;
+    __device__ void operator()(int64_t j) const {
+        double s = 0.0;
+        for (int e = col_ptr[j]; e < col_ptr[j + 1]; ++e) s += th[e] * (beta1[si[e]] * invM[si[e]]);
+        rhs[j] = beta2[j] - s;
+    }
+};
+// dy_i = (beta1_i - sum_{j in row i} theta_ij dz_j) / M_i
+struct FDy {
+    const int32_t *row_ptr, *csr_pos, *sj;
+    const double *th, *beta1, *invM, *dz;
+    double *dy;
+    __device__ void operator()(int64_t i) const {
+        double s = 0.0;
+        for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            const int k = csr_pos[e];
+            s += th[k] * dz[sj[k]];
+        }
+        dy[i] = (beta1[i] - s) * invM[i];
+    }
+};
+// ds = r2 - (dy_i + dz_j); dp = (r3 - p ds) / s
+struct FDsDp {
+    const int32_t *si, *sj;
+    const double *r2, *r3, *p, *s, *dy, *dz;
+    double *ds, *dp;
+    __device__ void operator()(int64_t k) const {
+        const double d = (r2 ? r2[k] : 0.0) - (dy[si[k]] + dz[sj[k]]);
+        ds[k] = d;
+        dp[k] = (r3[k] - p[k] * d) / s[k];
+    }
+};
+struct FSub {
+    double *v;
+    double c;
+    __device__ void operator()(int64_t k) const { v[k] -= c; }
+};
+
+void Solver::newton(const double *r1a_, const double *r1b_, const double *r2_, const double *r3_,
+                    double rtol, double atol, Dir &out) {
+    foreach(st, psi_, FW{theta.get(), r2_, r3_, p.get(), w.get()});
+    rowsum(w.get(), r1a_, beta1.get(), 1.0);
+    colsum(w.get(), r1b_, beta2.get(), 1.0);
+    foreach(st, n, FRhs{col_ptr.get(), si.get(), theta.get(), beta1.get(), invM.get(),
+                        beta2.get(), rhs.get()});
+    if (mode == Mode::Direct) {
+        ldl.solve(st, rhs.get(), out.dz.get());
+        // one step of iterative refinement against S
+        schur.spmv(st, out.dz.get(), tmpn.get());
+        double *res = tmpn2.need(n);
+        double *rhsp = rhs.get();
+        double *tn = tmpn.get();
+        foreach(st, n, [=] __device__(int64_t j) { res[j] = rhsp[j] - tn[j]; });
+        ldl.solve(st, res, tmpn.get());
+        double *dz = out.dz.get();
+        foreach(st, n, [=] __device__(int64_t j) { dz[j] += tn[j]; });
+    } else {
+        // project on the range of S (orthogonal to e: the null vector of a
+        // connected support, Section 4)
+        double mean = 0.0;
+        const double *rp = rhs.get();
+        reduce_sum<1>(st, red, n, [=] __device__(int64_t j, double *acc) { acc[0] += rp[j]; },
+                      &mean);
+        foreach(st, n, FSub{rhs.get(), mean / n});
+        CGStats cs = schur.pcg(st, rhs.get(), out.dz.get(), rtol, atol, P.cg_max_iter);
+        cg_its_iter += cs.iterations;
+        max_cg_solve = std::max(max_cg_solve, cs.iterations);
+        if (!cs.converged) cg_failed = true;
+    }
+    foreach(st, m, FDy{row_ptr.get(), csr_pos.get(), sj.get(), theta.get(), beta1.get(),
+                       invM.get(), out.dz.get(), out.dy.get()});
+    foreach(st, psi_, FDsDp{si.get(), sj.get(), r2_, r3_, p.get(), s.get(), out.dy.get(),
+                            out.dz.get(), out.ds.get(), out.dp.get()});
+}
+
+// max step to the boundary for p and s
+void Solver::max_steps(const Dir &d, double &ap, double &ad) {
+    const double *pp = p.get(), *ss = s.get(), *dp = d.dp.get(), *ds = d.ds.get();
+    double r[2];
+    reduce_min<2>(st, red, psi_,
+                  [=] __device__(int64_t k, double *acc) {
+                      if (dp[k] < 0.0) acc[0] = fmin(acc[0], -pp[k] / dp[k]);
+                      if (ds[k] < 0.0) acc[1] = fmin(acc[1], -ss[k] / ds[k]);
+                  },
+                  r);
+    ap = r[0];
+    ad = r[1];
+}
+
+void Solver::assemble() {
+    foreach(st, psi_, FTheta{p.get(), s.get(), theta.get()});
+    rowsum(theta.get(), nullptr, M.get(), 1.0);
+    colsum(theta.get(), nullptr, N.get(), 1.0);
+    foreach(st, m, FInv{M.get(), invM.get()});
+    auto t0 = std::chrono::steady_clock::now();
+    if (!schur_valid) {
+        schur.symbolic(st, m, n, psi_, col_ptr.get(), si.get(), row_ptr.get(), csr_pos.get(),
+                       sj.get());
+        schur_valid = true;
+    }
+    schur.numeric(st, m, n, col_ptr.get(), si.get(), theta.get(), invM.get());
+    (void)t0;
+}
+
+// ============================================================ scaffolding
+double Solver::now() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+void Solver::log(const char *fmt, ...) {
+    if (!P.verbose) return;
+    va_list ap;
+    va_start(ap, fmt);
+    vfprintf(stderr, fmt, ap);
+    va_end(ap);
+}
+
+// ------------------------------------------------------------------ residuals
+void Solver::residuals(double &rel1, double &rel2, double &mu, double &primal, double &r1n) {
+    rowsum(p.get(), a.get(), r1a.get(), -1.0);
+    colsum(p.get(), b.get(), r1b.get(), -1.0);
+    const double *cc = c.get(), *pp = p.get(), *ss = s.get(), *yy = y.get(), *zz = z.get();
+    const int32_t *ii = si.get(), *jj = sj.get();
+    double *rr2 = r2.get();
+    double v[4];
+    reduce_sum<4>(st, red, psi_,
+                  [=] __device__(int64_t k, double *acc) {
+                      const double r = cc[k] - (yy[ii[k]] + zz[jj[k]]) - ss[k];
+                      rr2[k] = r;
+                      acc[0] = fma(r, r, acc[0]);
+                      acc[1] = fma(cc[k], cc[k], acc[1]);
+                      acc[2] = fma(pp[k], ss[k], acc[2]);
+                      acc[3] = fma(cc[k], pp[k], acc[3]);
+                  },
+                  v);
+    const double *ra = r1a.get(), *rb = r1b.get();
+    const int mm = m;
+    double q;
+    reduce_sum<1>(st, red, (int64_t)m + n,
+                  [=] __device__(int64_t t, double *acc) {
+                      const double r = t < mm ? ra[t] : rb[t - mm];
+                      acc[0] = fma(r, r, acc[0]);
+                  },
+                  &q);
+    r1n = std::sqrt(q);
+    rel1 = r1n / (1.0 + fnorm);
+    rel2 = std::sqrt(v[0]) / (1.0 + std::sqrt(v[1]));
+    mu = v[2] / (double)psi_;
+    primal = v[3];
+}
+
+// ------------------------------------------------------------------ pricing
+int64_t Solver::price(int64_t kmax, uint64_t *out_idx, double *out_r, int64_t *nneg) {
+    double t0 = now();
+    // pricing runs on the unscaled costs: duals divided by the power-of-two cost scale
+    double *yu = yun.need(m), *zu = zun.need(n);
+    const double *yy = y.get(), *zz = z.get();
+    const double iz = 1.0 / zeta;
+    foreach(st, m, [=] __device__(int64_t i) { yu[i] = yy[i] * iz; });
+    foreach(st, n, [=] __device__(int64_t j) { zu[j] = zz[j] * iz; });
+    PriceResult pr;
+    if (P.precision == OTIP_MIXED)
+        pr = scan.price_mixed(st, m, n, xs, xt, yu, zu, bitmap.get(), kmax, nullptr, nullptr,
+                              out_r, out_idx);
+    else
+        pr = scan.price(st, m, n, xs, xt, yu, zu, bitmap.get(), kmax, nullptr, nullptr, out_r,
+                        out_idx);
+    if (nneg) *nneg = pr.nneg;
+    pricing_passes += pr.passes;
+    OTIP_HIP(hipStreamSynchronize(st));
+    t_pricing += now() - t0;
+    return pr.count;
+}
+
+// --------------------------------------------------------- support update
+// New support = kept old entries plus entering ones (p = s = sqrt(mu)),
+// re-sorted by variable index; removed entries get the key ~0 and sort last.
+void Solver::update_support(const uint64_t *add_idx, int64_t nadd, double pin,
+                            const uint8_t *removed, int64_t nrem) {
+    const int64_t psi_new = psi_ - nrem + nadd;
+    const int64_t tot = psi_ + nadd;
+    uint64_t *kin = tmp_u64a.need(tot);
+    double *pin_ = tmp_f64a.need(tot), *sin_ = tmp_f64b.need(tot);
+    const uint64_t *id = idx.get();
+    const double *pp = p.get(), *ss = s.get();
+    const int64_t psi = psi_;
+    foreach(st, psi, [=] __device__(int64_t k) {
+        kin[k] = (removed && removed[k]) ? ~0ull : id[k];
+        pin_[k] = pp[k];
+        sin_[k] = ss[k];
+    });
+    if (nadd > 0) {
+        foreach(st, nadd, [=] __device__(int64_t k) {
+            kin[psi + k] = add_idx[k];
+            pin_[psi + k] = pin;
+            sin_[psi + k] = pin;
+        });
+        foreach(st, nadd, FBits{add_idx, bitmap.get(), true});
+    }
+    if (removed && nrem > 0) {
+        const uint8_t *rm = removed;
+        uint32_t *bm = bitmap.get();
+        foreach(st, psi, [=] __device__(int64_t k) {
+            if (rm[k]) {
+                const uint64_t v = id[k];
+                atomicAnd(&bm[v >> 5], ~(1u << (v & 31u)));
+            }
+        });
+    }
+    uint64_t *kout = tmp_u64b.need(tot);
+    double *pout = tmp_f64c.need(tot), *sout = tmp_f64d.need(tot);
+    sort_pairs_u64_f64x2(st, kin, pin_, sin_, kout, pout, sout, tot, 64, tmp, tmp_i32a, tmp_i32b);
+    psi_ = psi_new;
+    if ((size_t)psi_new > idx.cap) alloc_support(psi_new * 2);
+    OTIP_HIP(hipMemcpyAsync(idx.get(), kout, sizeof(uint64_t) * psi_new, hipMemcpyDeviceToDevice, st));
+    OTIP_HIP(hipMemcpyAsync(p.get(), pout, sizeof(double) * psi_new, hipMemcpyDeviceToDevice, st));
+    OTIP_HIP(hipMemcpyAsync(s.get(), sout, sizeof(double) * psi_new, hipMemcpyDeviceToDevice, st));
+    rebuild_views();
+    psi_max = std::max(psi_max, psi_);
+}
+
+// removal (Section 3.2): small p leave once near convergence; the largest p of
+// every row and column stays so that no row or column is left uncovered.
+int64_t Solver::select_removals(uint8_t *removed) {
+    const int64_t psi = psi_;
+    uint8_t *pr = prot.get();
+    OTIP_HIP(hipMemsetAsync(pr, 0, psi, st));
+    OTIP_HIP(hipMemsetAsync(removed, 0, psi, st));
+    const double *pp = p.get();
+    const uint64_t *id = idx.get();
+    const int32_t *rp = row_ptr.get(), *cp = csr_pos.get(), *cptr = col_ptr.get();
+    foreach(st, m, [=] __device__(int64_t i) {
+        int best = -1;
+        for (int e = rp[i]; e < rp[i + 1]; ++e) {
+            const int k = cp[e];
+            if (best < 0 || pp[k] > pp[best] || (pp[k] == pp[best] && id[k] < id[best])) best = k;
+        }
+        if (best >= 0) pr[best] = 1;
+    });
+    foreach(st, n, [=] __device__(int64_t j) {
+        int best = -1;
+        for (int k = cptr[j]; k < cptr[j + 1]; ++k)
+            if (best < 0 || pp[k] > pp[best] || (pp[k] == pp[best] && id[k] < id[best])) best = k;
+        if (best >= 0) pr[best] = 1;
+    });
+    const double *aa = a.get(), *bb = b.get();
+    const int32_t *ii = si.get(), *jj = sj.get();
+    const double rel = P.remove_rel;
+    double cnt;
+    reduce_sum<1>(st, red, psi,
+                  [=] __device__(int64_t k, double *acc) {
+                      const double thr = rel * fmin(aa[ii[k]], bb[jj[k]]);
+                      if (!pr[k] && pp[k] < thr) acc[0] += 1.0;
+                  },
+                  &cnt);
+    const int64_t ncand = (int64_t)cnt;
+    if (ncand == 0) return 0;
+    if (ncand <= m) {
+        foreach(st, psi, [=] __device__(int64_t k) {
+            const double thr = rel * fmin(aa[ii[k]], bb[jj[k]]);
+            removed[k] = (!pr[k] && pp[k] < thr) ? 1 : 0;
+        });
+        return ncand;
+    }
+    // more than m candidates: the m smallest by (p, idx)
+    uint64_t *keys = tmp_u64a.need(psi), *vals = tmp_u64c.need(psi);
+    foreach(st, psi, [=] __device__(int64_t k) {
+        const double thr = rel * fmin(aa[ii[k]], bb[jj[k]]);
+        const bool c = !pr[k] && pp[k] < thr;
+        keys[k] = c ? dkey(pp[k]) : ~0ull;
+        vals[k] = (uint64_t)k;  // position order == variable order
+    });
+    uint64_t *ko = tmp_u64b.need(psi), *vo = tmp_u64d.need(psi);
+    sort_pairs_u64(st, keys, vals, ko, vo, psi, 0, 64, tmp);  // stable: ties keep index order
+    const int64_t take = m;
+    foreach(st, take, [=] __device__(int64_t t) { removed[vo[t]] = 1; });
+    return take;
+}
+
+// ================================================================ the solve
+struct FScaleIn {
+    const double *src;
+    double *dst;
+    double f;
+    __device__ void operator()(int64_t k) const { dst[k] = src[k] * f; }
+};
+
+int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
+    const double T0 = now();
+    P = prm;
+    m = pr.m;
+    n = pr.n;
+    xs = pr.xs;
+    xt = pr.xt;
+    a_in = pr.a;
+    b_in = pr.b;
+    OTIP_CHECK(m >= 1 && n >= 1, OTIP_EINVAL, "m and n must be >= 1");
+    OTIP_CHECK(pr.a && pr.b && pr.xs && pr.xt, OTIP_EINVAL, "null problem array");
+    // ---- validation on the device data (masses > 0, balanced)
+    double sa, sb, mina, minb, bad;
+    {
+        const double *A = pr.a, *B = pr.b;
+        const int mm = m;
+        double v[3];
+        reduce_sum<3>(st, red, (int64_t)m + n,
+                      [=] __device__(int64_t t, double *acc) {
+                          const double x = t < mm ? A[t] : B[t - mm];
+                          if (t < mm)
+                              acc[0] += x;
+                          else
+                              acc[1] += x;
+                          if (!(x > 0.0) || isinf(x)) acc[2] += 1.0;
+                      },
+                      v);
+        sa = v[0];
+        sb = v[1];
+        bad = v[2];
+        (void)mina;
+        (void)minb;
+    }
+    OTIP_CHECK(bad == 0.0, OTIP_EINVAL, "masses must be finite and strictly positive");
+    OTIP_CHECK(std::fabs(sa - sb) <= 1e-12 * sa, OTIP_EINVAL, "sum(a) != sum(b)");
+    {
+        // coordinate range -> largest cost (for scaling and the initial support)
+        std::vector<int32_t> hx((size_t)2 * m), ht((size_t)2 * n);
+        OTIP_HIP(hipMemcpyAsync(hx.data(), xs, sizeof(int32_t) * 2 * m, hipMemcpyDeviceToHost, st));
+        OTIP_HIP(hipMemcpyAsync(ht.data(), xt, sizeof(int32_t) * 2 * n, hipMemcpyDeviceToHost, st));
+        OTIP_HIP(hipStreamSynchronize(st));
+        int64_t lo[2] = {INT64_MAX, INT64_MAX}, hi[2] = {INT64_MIN, INT64_MIN};
+        for (int q = 0; q < m; ++q)
+            for (int d = 0; d < 2; ++d) {
+                lo[d] = std::min<int64_t>(lo[d], hx[2 * q + d]);
+                hi[d] = std::max<int64_t>(hi[d], hx[2 * q + d]);
+            }
+        for (int q = 0; q < n; ++q)
+            for (int d = 0; d < 2; ++d) {
+                lo[d] = std::min<int64_t>(lo[d], ht[2 * q + d]);
+                hi[d] = std::max<int64_t>(hi[d], ht[2 * q + d]);
+            }
+        for (int d = 0; d < 2; ++d)
+            OTIP_CHECK(lo[d] >= -(1 << 14) && hi[d] <= (1 << 14), OTIP_EINVAL,
+                       "coordinates must lie in [-2^14, 2^14]");
+        cmax = (hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]);
+    }
+    omega = 1.0;
+    zeta = 1.0;
+    if (P.scale) {
+        omega = std::ldexp(1.0, (int)std::lround(std::log2((double)m / sa)));
+        zeta = std::ldexp(1.0, -(int)std::ceil(std::log2((double)std::max<int64_t>(1, cmax))));
+    }
+    a.need(m);
+    b.need(n);
+    foreach(st, m, FScaleIn{pr.a, a.get(), omega});
+    foreach(st, n, FScaleIn{pr.b, b.get(), omega});
+    fnorm = std::sqrt((sa * sa) * 0 + 0);  // replaced below with the exact norm
+    {
+        const double *A = a.get(), *B = b.get();
+        const int mm = m;
+        double q;
+        reduce_sum<1>(st, red, (int64_t)m + n,
+                      [=] __device__(int64_t t, double *acc) {
+                          const double x = t < mm ? A[t] : B[t - mm];
+                          acc[0] = fma(x, x, acc[0]);
+                      },
+                      &q);
+        fnorm = std::sqrt(q);
+    }
+    y.need(m);
+    z.need(n);
+    M.need(m);
+    invM.need(m);
+    N.need(n);
+    r1a.need(m);
+    r1b.need(n);
+    beta1.need(m);
+    beta2.need(n);
+    rhs.need(n);
+    tmpn.need(n);
+    tmpn2.need(n);
+    OTIP_HIP(hipMemsetAsync(zm.need(m), 0, sizeof(double) * m, st));
+    OTIP_HIP(hipMemsetAsync(zn.need(n), 0, sizeof(double) * n, st));
+    const size_t words = ((size_t)m * (size_t)n + 31) / 32;
+    bitmap.need(words);
+    OTIP_HIP(hipMemsetAsync(bitmap.get(), 0, words * sizeof(uint32_t), st));
+
+    // ---- initial support (Section 3.2, end)
+    double ts = now();
+    int64_t T = 0;
+    DBuf<uint64_t> init;
+    const int64_t psi0 = scan.initial_support(st, m, n, xs, xt, P.kappa, cmax, init, &T);
+    alloc_support(std::max<int64_t>(psi0 * 2, psi0 + 4 * (int64_t)std::max(m, n)));
+    OTIP_HIP(hipMemcpyAsync(idx.get(), init.get(), sizeof(uint64_t) * psi0, hipMemcpyDeviceToDevice, st));
+    psi_ = psi0;
+    psi_max = psi0;
+    rebuild_views();
+    foreach(st, psi_, FBits{idx.get(), bitmap.get(), true});
+    log("otip: m=%d n=%d psi0=%lld T=%lld omega=%g zeta=%g\n", m, n, (long long)psi0,
+        (long long)T, omega, zeta);
+    starting_point();
+    t_setup += now() - ts;
+
+    mode = (P.linear_solver == OTIP_LS_DIRECT) ? Mode::Direct : Mode::PCG;
+    if (mode == Mode::Direct)
+        OTIP_CHECK(n <= P.dense_max_n, OTIP_EUNSUPPORTED, "direct solver: n exceeds dense_max_n");
+    std::vector<int64_t> psi_hist;
+    const int64_t kcap = P.enter_cap > 0 ? P.enter_cap : m;
+    DBuf<uint64_t> sel_idx;
+    DBuf<double> sel_r;
+    sel_idx.need(kcap);
+    sel_r.need(kcap);
+    DBuf<uint8_t> removed;
+    int status = OTIP_EMAXITER;
+    int it = 0;
+    cg_failed = false;
+    for (it = 0; it < P.max_iter; ++it) {
+        double tn = now();
+        double rel1, rel2, mu, primal, r1n;
+        residuals(rel1, rel2, mu, primal, r1n);
+        const double relmu = (double)psi_ * mu / std::max(1.0, std::fabs(primal));
+        psi_hist.push_back(psi_);
+        if (std::max(std::max(rel1, rel2), relmu) < P.tol) {
+            t_newton += now() - tn;
+            std::vector<double> hr(1);
+            int64_t k = price(kcap, sel_idx.get(), sel_r.get(), nullptr);
+            int64_t nbig = 0;
+            if (k > 0) {
+                std::vector<double> rs(k);
+                OTIP_HIP(hipMemcpy(rs.data(), sel_r.get(), sizeof(double) * k, hipMemcpyDeviceToHost));
+                const double thr = P.cert_rel * std::max(1.0, std::fabs(primal));
+                for (int64_t q = 0; q < k; ++q)
+                    if (std::fabs(rs[q] * zeta) * (sa * omega) > thr) ++nbig;  // ordered by r
+            }
+            if (nbig == 0) {
+                status = OTIP_OK;
+                break;
+            }
+            double tu = now();
+            update_support(sel_idx.get(), nbig, std::sqrt(mu), nullptr, 0);
+            t_update += now() - tu;
+            log("otip: it %d certification re-entered %lld columns\n", it, (long long)nbig);
+            continue;
+        }
+        // ---- switch test (Section 4.3)
+        if (mode == Mode::PCG && P.linear_solver == OTIP_LS_AUTO && n <= P.dense_max_n) {
+            const int wdw = P.switch_window;
+            const bool force = (P.force_switch_at >= 0 && it >= P.force_switch_at) || cg_failed;
+            bool drop = false;
+            if ((int)psi_hist.size() > wdw) {
+                const double old = (double)psi_hist[psi_hist.size() - 1 - wdw];
+                drop = (old - (double)psi_) / old >= P.switch_drop;
+            }
+            if (force || drop) {
+                mode = Mode::Direct;
+                log("otip: it %d switch to the direct solver (%s)\n", it,
+                    force ? "forced/CG failure" : "support shrinking");
+            }
+        }
+        // ---- Newton direction
+        assemble();
+        double td = now();
+        if (mode == Mode::Direct) {
+            ldl.factor(st, schur.S, P.pivot_tol);
+            max_fill = std::max(max_fill, 100.0 * (double)ldl.nnz_L() / ((double)n * n));
+            direct_its++;
+        }
+        t_direct += (mode == Mode::Direct) ? now() - td : 0.0;
+        cg_its_iter = 0;
+        max_cg_solve = 0;
+        cg_failed = false;
+        const double atol = P.cg_eta * std::max(r1n, P.cg_floor * (1.0 + fnorm));
+        // predictor (sigma = 0)
+        double *rr3 = r3.get();
+        const double *pp = p.get(), *ss = s.get();
+        foreach(st, psi_, [=] __device__(int64_t k) { rr3[k] = -pp[k] * ss[k]; });
+        Dir &Da = D[0];
+        newton(r1a.get(), r1b.get(), r2.get(), r3.get(), P.cg_tol_pred, atol, Da);
+        double apa, ada;
+        max_steps(Da, apa, ada);
+        apa = std::min(1.0, apa);
+        ada = std::min(1.0, ada);
+        double mu_aff;
+        {
+            const double *dp = Da.dp.get(), *ds = Da.ds.get();
+            const double ap_ = apa, ad_ = ada;
+            reduce_sum<1>(st, red, psi_,
+                          [=] __device__(int64_t k, double *acc) {
+                              acc[0] = fma(pp[k] + ap_ * dp[k], ss[k] + ad_ * ds[k], acc[0]);
+                          },
+                          &mu_aff);
+            mu_aff /= (double)psi_;
+        }
+        const double sigma = mu > 0.0 ? std::pow(mu_aff / mu, 3.0) : 0.0;
+        // Mehrotra corrector
+        {
+            const double *dp = Da.dp.get(), *ds = Da.ds.get();
+            const double sm = sigma * mu;
+            foreach(st, psi_, [=] __device__(int64_t k) {
+                rr3[k] = sm - pp[k] * ss[k] - dp[k] * ds[k];
+            });
+        }
+        int cur = 1;
+        newton(r1a.get(), r1b.get(), r2.get(), r3.get(), P.cg_tol_pred, atol, D[cur]);
+        double ap, ad;
+        max_steps(D[cur], ap, ad);
+        ap = std::min(1.0, P.step_scale * ap);
+        ad = std::min(1.0, P.step_scale * ad);
+        // Gondzio centrality correctors
+        int ncorr = 0;
+        while (ncorr < P.max_corr && std::min(ap, ad) < 1.0) {
+            const double atp = std::min(1.0, ap + P.mcc_delta), atd = std::min(1.0, ad + P.mcc_delta);
+            const double lo = P.mcc_beta_min * sigma * mu, hi = P.mcc_beta_max * sigma * mu;
+            {
+                const double *dp = D[cur].dp.get(), *ds = D[cur].ds.get();
+                foreach(st, psi_, [=] __device__(int64_t k) {
+                    const double v = (pp[k] + atp * dp[k]) * (ss[k] + atd * ds[k]);
+                    double rc = fmin(fmax(v, lo), hi) - v;
+                    rr3[k] = fmax(rc, -hi);
+                });
+            }
+            const int tri = 3 - cur;  // the other of D[1], D[2]
+            newton(zm.get(), zn.get(), nullptr, r3.get(), P.cg_tol_corr, atol, D[tri]);
+            {
+                const double *dp = D[cur].dp.get(), *ds = D[cur].ds.get();
+                const double *dy = D[cur].dy.get(), *dz = D[cur].dz.get();
+                double *tp = D[tri].dp.get(), *ts_ = D[tri].ds.get();
+                double *ty = D[tri].dy.get(), *tz = D[tri].dz.get();
+                foreach(st, psi_, [=] __device__(int64_t k) {
+                    tp[k] += dp[k];
+                    ts_[k] += ds[k];
+                });
+                foreach(st, m, [=] __device__(int64_t i) { ty[i] += dy[i]; });
+                foreach(st, n, [=] __device__(int64_t j) { tz[j] += dz[j]; });
+            }
+            double nap, nad;
+            max_steps(D[tri], nap, nad);
+            nap = std::min(1.0, P.step_scale * nap);
+            nad = std::min(1.0, P.step_scale * nad);
+            if (std::min(nap, nad) >= std::min(ap, ad) + P.mcc_accept) {
+                cur = tri;
+                ap = nap;
+                ad = nad;
+                ++ncorr;
+            } else {
+                break;
+            }
+        }
+        cg_total += cg_its_iter;
+        const bool failed_now = cg_failed;
+        // ---- update
+        {
+            Dir &d = D[cur];
+            const double *dp = d.dp.get(), *ds = d.ds.get(), *dy = d.dy.get(), *dz = d.dz.get();
+            double *pw = p.get(), *sw = s.get(), *yw = y.get(), *zw = z.get();
+            const double ap_ = ap, ad_ = ad;
+            foreach(st, psi_, [=] __device__(int64_t k) {
+                pw[k] += ap_ * dp[k];
+                sw[k] += ad_ * ds[k];
+            });
+            foreach(st, m, [=] __device__(int64_t i) { yw[i] += ad_ * dy[i]; });
+            foreach(st, n, [=] __device__(int64_t j) { zw[j] += ad_ * dz[j]; });
+        }
+        double mu_new;
+        {
+            const double *pw = p.get(), *sw = s.get();
+            reduce_sum<1>(st, red, psi_,
+                          [=] __device__(int64_t k, double *acc) { acc[0] = fma(pw[k], sw[k], acc[0]); },
+                          &mu_new);
+            mu_new /= (double)psi_;
+        }
+        t_newton += now() - tn;
+        // ---- pricing and support update
+        int64_t nneg = 0;
+        const int64_t k = price(kcap, sel_idx.get(), sel_r.get(), &nneg);
+        double tu = now();
+        int64_t nrem = 0;
+        removed.need(psi_);
+        if (std::max(rel1, rel2) <= P.remove_gate) nrem = select_removals(removed.get());
+        if (k > 0 || nrem > 0)
+            update_support(sel_idx.get(), k, std::sqrt(mu_new), nrem ? removed.get() : nullptr, nrem);
+        t_update += now() - tu;
+        if (failed_now && mode == Mode::PCG) cg_failed = true;
+        log("otip: it %3d psi=%lld r1=%.2e r2=%.2e mu=%.2e ap=%.3f ad=%.3f sig=%.2e corr=%d cg=%d %s "
+            "add=%lld rem=%lld\n",
+            it, (long long)psi_hist.back(), rel1, rel2, relmu, ap, ad, sigma, ncorr, cg_its_iter,
+            mode == Mode::Direct ? "dir" : "pcg", (long long)k, (long long)nrem);
+    }
+    iterations = it + (status == OTIP_OK ? 1 : 0);
+    double tf = now();
+    finalize(res);
+    t_final += now() - tf;
+    res.info.status = status;
+    res.info.iterations = iterations;
+    res.info.cg_iterations = (int32_t)cg_total;
+    res.info.direct_iterations = direct_its;
+    res.info.psi_max = psi_max;
+    res.info.max_fill_pct = max_fill;
+    res.info.seconds_total = now() - T0;
+    res.info.seconds_pricing = t_pricing;
+    res.info.seconds_newton = t_newton;
+    res.info.seconds_direct = t_direct;
+    res.info.seconds_update = t_update;
+    res.info.seconds_setup = t_setup;
+    res.info.seconds_final = t_final;
+    return status;
+}
+
+// Mehrotra's starting-point heuristic on the restricted LP (Theta = I); the
+// paper leaves the starting point open.
+void Solver::starting_point() {
+    const int64_t psi = psi_;
+    double *pp = p.get(), *ss = s.get();
+    foreach(st, psi, [=] __device__(int64_t k) {
+        pp[k] = 1.0;
+        ss[k] = 1.0;
+    });
+    assemble();
+    const bool direct = n <= P.dense_max_n;
+    if (direct) ldl.factor(st, schur.S, P.pivot_tol);
+    auto normal_solve = [&](const double *b1, const double *b2, double *dy, double *dz) {
+        foreach(st, n, FRhs{col_ptr.get(), si.get(), theta.get(), b1, invM.get(), b2, rhs.get()});
+        if (direct) {
+            ldl.solve(st, rhs.get(), dz);
+        } else {
+            double mean = 0.0;
+            const double *rp = rhs.get();
+            reduce_sum<1>(st, red, n, [=] __device__(int64_t j, double *acc) { acc[0] += rp[j]; },
+                          &mean);
+            foreach(st, n, FSub{rhs.get(), mean / n});
+            schur.pcg(st, rhs.get(), dz, 1e-12, 0.0 + 1e300, std::max(P.cg_max_iter, 5000));
+        }
+        foreach(st, m, FDy{row_ptr.get(), csr_pos.get(), sj.get(), theta.get(), b1, invM.get(),
+                           dz, dy});
+    };
+    // least-norm p~ = A^T (A A^T)^-1 f
+    double *wy = D[0].dy.get(), *wz = D[0].dz.get();
+    normal_solve(a.get(), b.get(), wy, wz);
+    const int32_t *ii = si.get(), *jj = sj.get();
+    foreach(st, psi, [=] __device__(int64_t k) { pp[k] = wy[ii[k]] + wz[jj[k]]; });
+    // least-squares duals for c, s~ = c - A^T lambda
+    rowsum(c.get(), nullptr, beta1.get(), 1.0);
+    colsum(c.get(), nullptr, beta2.get(), 1.0);
+    double *ly = y.get(), *lz = z.get();
+    normal_solve(beta1.get(), beta2.get(), ly, lz);
+    const double *cc = c.get();
+    foreach(st, psi, [=] __device__(int64_t k) { ss[k] = cc[k] - (ly[ii[k]] + lz[jj[k]]); });
+    double mins[2];
+    reduce_min<2>(st, red, psi,
+                  [=] __device__(int64_t k, double *acc) {
+                      acc[0] = fmin(acc[0], pp[k]);
+                      acc[1] = fmin(acc[1], ss[k]);
+                  },
+                  mins);
+    const double dp = std::max(-1.5 * mins[0], 0.0), dsv = std::max(-1.5 * mins[1], 0.0);
+    double sums[3];
+    reduce_sum<3>(st, red, psi,
+                  [=] __device__(int64_t k, double *acc) {
+                      const double ph = pp[k] + dp, sh = ss[k] + dsv;
+                      acc[0] = fma(ph, sh, acc[0]);
+                      acc[1] += ph;
+                      acc[2] += sh;
+                  },
+                  sums);
+    const double dph = sums[2] > 0 ? 0.5 * sums[0] / sums[2] : 0.0;
+    const double dsh = sums[1] > 0 ? 0.5 * sums[0] / sums[1] : 0.0;
+    foreach(st, psi, [=] __device__(int64_t k) {
+        pp[k] = pp[k] + dp + dph;
+        ss[k] = ss[k] + dsv + dsh;
+    });
+    reduce_min<2>(st, red, psi,
+                  [=] __device__(int64_t k, double *acc) {
+                      acc[0] = fmin(acc[0], pp[k]);
+                      acc[1] = fmin(acc[1], ss[k]);
+                  },
+                  mins);
+    if (!(mins[0] > 0.0 && mins[1] > 0.0)) {
+        foreach(st, psi, [=] __device__(int64_t k) {
+            pp[k] = fmax(pp[k], 1e-8);
+            ss[k] = fmax(ss[k], 1e-8);
+        });
+    }
+}
+
+// ------------------------------------------------------------------ final
+// Primal projection onto A p = f on the support (dp = Theta A^T (A Theta A^T)^-1 r1,
+// the Newton step with r2 = r3 = 0), purification to a basic plan, dual
+// certificate from one full reduced-cost scan (Section 3.3: s_hat = c - A^T y_hat).
+void Solver::finalize(Result &res) {
+    const double fsum1 = 0.0;
+    (void)fsum1;
+    double *zp = zpsi.need(psi_);
+    OTIP_HIP(hipMemsetAsync(zp, 0, sizeof(double) * psi_, st));
+    for (int q = 0; q < P.polish_steps; ++q) {
+        rowsum(p.get(), a.get(), r1a.get(), -1.0);
+        colsum(p.get(), b.get(), r1b.get(), -1.0);
+        const double *ra = r1a.get(), *rb = r1b.get(), *A = a.get(), *B = b.get();
+        const int mm = m;
+        double v[2];
+        reduce_sum<2>(st, red, (int64_t)m + n,
+                      [=] __device__(int64_t t, double *acc) {
+                          acc[0] += fabs(t < mm ? ra[t] : rb[t - mm]);
+                          acc[1] += fabs(t < mm ? A[t] : B[t - mm]);
+                      },
+                      v);
+        if (v[0] / v[1] <= P.polish_tol) break;
+        assemble();
+        const bool direct = n <= P.dense_max_n;
+        Mode keep = mode;
+        mode = direct ? Mode::Direct : Mode::PCG;
+        if (direct) ldl.factor(st, schur.S, P.pivot_tol);
+        newton(r1a.get(), r1b.get(), nullptr, zp, 1e-14, 0.0, D[0]);
+        mode = keep;
+        double *pw = p.get();
+        const double *dp = D[0].dp.get();
+        foreach(st, psi_, [=] __device__(int64_t k) { pw[k] = fmax(pw[k] + dp[k], 0.0); });
+    }
+    // to the host, unscaled
+    const int64_t psi = psi_;
+    std::vector<uint64_t> hidx(psi);
+    std::vector<double> hp(psi), hy(m), hz(n), ha(m), hb(n);
+    std::vector<int32_t> hxs((size_t)2 * m), hxt((size_t)2 * n);
+    OTIP_HIP(hipMemcpyAsync(hidx.data(), idx.get(), sizeof(uint64_t) * psi, hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipMemcpyAsync(hp.data(), p.get(), sizeof(double) * psi, hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipMemcpyAsync(hy.data(), y.get(), sizeof(double) * m, hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipMemcpyAsync(hz.data(), z.get(), sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipMemcpyAsync(ha.data(), a_in, sizeof(double) * m, hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipMemcpyAsync(hb.data(), b_in, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipMemcpyAsync(hxs.data(), xs, sizeof(int32_t) * 2 * m, hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipMemcpyAsync(hxt.data(), xt, sizeof(int32_t) * 2 * n, hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipStreamSynchronize(st));
+    std::vector<int32_t> rows(psi), cols(psi);
+    std::vector<double> flows(psi);
+    std::vector<int64_t> costs(psi);
+    auto icost = [&](int i, int j) {
+        const int64_t d0 = (int64_t)hxs[2 * i] - hxt[2 * j], d1 = (int64_t)hxs[2 * i + 1] - hxt[2 * j + 1];
+        return d0 * d0 + d1 * d1;
+    };
+    for (int64_t k = 0; k < psi; ++k) {
+        rows[k] = (int32_t)(hidx[k] % (uint64_t)m);
+        cols[k] = (int32_t)(hidx[k] / (uint64_t)m);
+        flows[k] = hp[k] / omega;
+        costs[k] = icost(rows[k], cols[k]);
+    }
+    purify_plan(m, n, rows, cols, flows, costs, ha, hb, P.drop_rel, res.rows, res.cols, res.vals);
+    // gauge z_{n-1} = 0 on the unscaled duals
+    const double g = hz[n - 1] / zeta;
+    res.y.resize(m);
+    res.z.resize(n);
+    for (int i = 0; i < m; ++i) res.y[i] = hy[i] / zeta + g;
+    for (int j = 0; j < n; ++j) res.z[j] = hz[j] / zeta - g;
+    double *yu = yun.need(m), *zu = zun.need(n);
+    OTIP_HIP(hipMemcpyAsync(yu, res.y.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
+    OTIP_HIP(hipMemcpyAsync(zu, res.z.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+    double t0 = now();
+    double rmin = 0.0;
+    int64_t arg = 0;
+    scan.rmin(st, m, n, xs, xt, yu, zu, &rmin, &arg);
+    t_pricing += now() - t0;
+    // compensated sums on the host
+    auto ksum = [](const std::vector<double> &v) {
+        double s = 0.0, c = 0.0;
+        for (double x : v) {
+            const double t = s + x;
+            c += (std::fabs(s) >= std::fabs(x)) ? (s - t) + x : (x - t) + s;
+            s = t;
+        }
+        return s + c;
+    };
+    std::vector<double> terms;
+    terms.reserve(res.vals.size());
+    for (size_t k = 0; k < res.vals.size(); ++k)
+        terms.push_back((double)icost(res.rows[k], res.cols[k]) * res.vals[k]);
+    const double obj = ksum(terms);
+    std::vector<double> dt;
+    dt.reserve((size_t)m + n);
+    for (int i = 0; i < m; ++i) dt.push_back(ha[i] * res.y[i]);
+    for (int j = 0; j < n; ++j) dt.push_back(hb[j] * res.z[j]);
+    const double suma = ksum(ha);
+    const double dual = ksum(dt) + suma * std::min(0.0, rmin);
+    std::vector<double> rs(m, 0.0), cs(n, 0.0);
+    for (size_t k = 0; k < res.vals.size(); ++k) {
+        rs[res.rows[k]] += res.vals[k];
+        cs[res.cols[k]] += res.vals[k];
+    }
+    double num = 0.0, den = 0.0;
+    for (int i = 0; i < m; ++i) {
+        num += std::fabs(rs[i] - ha[i]);
+        den += std::fabs(ha[i]);
+    }
+    for (int j = 0; j < n; ++j) {
+        num += std::fabs(cs[j] - hb[j]);
+        den += std::fabs(hb[j]);
+    }
+    res.info.nnz = (int64_t)res.vals.size();
+    res.info.objective = obj;
+    res.info.dual_bound = dual;
+    res.info.rel_gap = (obj - dual) / std::max(1.0, std::fabs(obj));
+    res.info.marginal_residual = num / den;
+    res.info.r_min = rmin;
+}
+
+
+int64_t Solver::schur_export(int m_, int n_, int64_t psi, const uint64_t *idx_in,
+                             const double *theta_in, int32_t *rowptr, int32_t *colidx,
+                             double *vals, double *Mout, double *Nout) {
+    m = m_;
+    n = n_;
+    OTIP_CHECK(m >= 1 && n >= 1 && psi >= 1, OTIP_EINVAL, "schur: bad sizes");
+    // the views need coordinates only for costs; use a zero coordinate table
+    DBuf<int32_t> zc;
+    const int mx = std::max(m, n);
+    OTIP_HIP(hipMemsetAsync(zc.need((size_t)2 * mx), 0, sizeof(int32_t) * 2 * mx, st));
+    xs = zc.get();
+    xt = zc.get();
+    zeta = 1.0;
+    {
+        // the support must be sorted, duplicate-free and cover every row and column
+        std::vector<uint64_t> h(psi);
+        OTIP_HIP(hipMemcpyAsync(h.data(), idx_in, sizeof(uint64_t) * psi, hipMemcpyDeviceToHost, st));
+        OTIP_HIP(hipStreamSynchronize(st));
+        std::vector<char> rc((size_t)m, 0), cc((size_t)n, 0);
+        for (int64_t k = 0; k < psi; ++k) {
+            OTIP_CHECK(h[k] < (uint64_t)m * (uint64_t)n && (k == 0 || h[k] > h[k - 1]), OTIP_EINVAL,
+                       "schur: support must be sorted, unique and in range");
+            rc[h[k] % (uint64_t)m] = 1;
+            cc[h[k] / (uint64_t)m] = 1;
+        }
+        for (int i = 0; i < m; ++i) OTIP_CHECK(rc[i], OTIP_EINVAL, "schur: a row is not covered");
+        for (int j = 0; j < n; ++j) OTIP_CHECK(cc[j], OTIP_EINVAL, "schur: a column is not covered");
+    }
+    alloc_support(psi);
+    OTIP_HIP(hipMemcpyAsync(idx.get(), idx_in, sizeof(uint64_t) * psi, hipMemcpyDeviceToDevice, st));
+    psi_ = psi;
+    rebuild_views();
+    OTIP_HIP(hipMemcpyAsync(theta.get(), theta_in, sizeof(double) * psi, hipMemcpyDeviceToDevice, st));
+    M.need(m);
+    invM.need(m);
+    N.need(n);
+    rowsum(theta.get(), nullptr, M.get(), 1.0);
+    colsum(theta.get(), nullptr, N.get(), 1.0);
+    foreach(st, m, FInv{M.get(), invM.get()});
+    schur.symbolic(st, m, n, psi_, col_ptr.get(), si.get(), row_ptr.get(), csr_pos.get(), sj.get());
+    schur.numeric(st, m, n, col_ptr.get(), si.get(), theta.get(), invM.get());
+    const int64_t nnz = schur.S.nnz;
+    if (rowptr) {
+        OTIP_HIP(hipMemcpyAsync(rowptr, schur.S.rowptr.get(), sizeof(int32_t) * (n + 1),
+                                hipMemcpyDeviceToDevice, st));
+        OTIP_HIP(hipMemcpyAsync(colidx, schur.S.col.get(), sizeof(int32_t) * nnz,
+                                hipMemcpyDeviceToDevice, st));
+        OTIP_HIP(hipMemcpyAsync(vals, schur.S.val.get(), sizeof(double) * nnz,
+                                hipMemcpyDeviceToDevice, st));
+        if (Mout) OTIP_HIP(hipMemcpyAsync(Mout, M.get(), sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+        if (Nout) OTIP_HIP(hipMemcpyAsync(Nout, N.get(), sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    }
+    OTIP_HIP(hipStreamSynchronize(st));
+    return nnz;
+}
+
+}  // namespace otip

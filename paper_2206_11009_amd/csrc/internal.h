@@ -1,0 +1,140 @@
+// Internal interfaces between the otip sources (not part of the ABI).
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+
+namespace otip {
+
+// ------------------------------------------------------------ sort / scan (rocPRIM)
+void sort_pairs_u64(hipStream_t st, const uint64_t *kin, const uint64_t *vin, uint64_t *kout,
+                    uint64_t *vout, int64_t n, int begin_bit, int end_bit, DBuf<char> &tmp);
+void sort_pairs_u64_f64x2(hipStream_t st, const uint64_t *kin, const double *v1in,
+                          const double *v2in, uint64_t *kout, double *v1out, double *v2out,
+                          int64_t n, int end_bit, DBuf<char> &tmp, DBuf<int32_t> &perm_a,
+                          DBuf<int32_t> &perm_b);
+void sort_pairs_u32_i32(hipStream_t st, const uint32_t *kin, const int32_t *vin, uint32_t *kout,
+                        int32_t *vout, int64_t n, int end_bit, DBuf<char> &tmp);
+void sort_keys_u64(hipStream_t st, const uint64_t *kin, uint64_t *kout, int64_t n,
+                   DBuf<char> &tmp);
+int64_t unique_u64(hipStream_t st, const uint64_t *in, uint64_t *out, int64_t n, DBuf<char> &tmp,
+                   DBuf<unsigned long long> &cnt);
+void exclusive_scan_i64(hipStream_t st, const int64_t *in, int64_t *out, int64_t n,
+                        DBuf<char> &tmp);
+
+// ------------------------------------------------------------------- full scans
+struct PriceResult {
+    int64_t count;  // selected
+    int64_t nneg;   // negative reduced costs outside the support
+    int passes;     // full m*n passes used
+};
+
+class Scanner {
+  public:
+    // <= kmax most negative reduced costs outside the support, ordered by
+    // (r, idx); outputs may be null.
+    PriceResult price(hipStream_t st, int m, int n, const int32_t *xs, const int32_t *xt,
+                      const double *y, const double *z, const uint32_t *bitmap, int64_t kmax,
+                      int32_t *oi, int32_t *oj, double *orr, uint64_t *oidx);
+    // FP32 scan with an FP64 re-check of every candidate within the margin
+    PriceResult price_mixed(hipStream_t st, int m, int n, const int32_t *xs, const int32_t *xt,
+                            const double *y, const double *z, const uint32_t *bitmap,
+                            int64_t kmax, int32_t *oi, int32_t *oj, double *orr,
+                            uint64_t *oidx);
+    void rmin(hipStream_t st, int m, int n, const int32_t *xs, const int32_t *xt,
+              const double *y, const double *z, double *out, int64_t *arg);
+    int64_t initial_support(hipStream_t st, int m, int n, const int32_t *xs, const int32_t *xt,
+                            double kappa, int64_t cmax, DBuf<uint64_t> &out, int64_t *T);
+
+  private:
+    void prepare(hipStream_t st, int m, int n, const int32_t *xt, const double *z);
+    DBuf<char> jt_;
+    DBuf<unsigned long long> hist_, cnt_;
+    DBuf<uint64_t> ck_, ci_, ck2_, ci2_, u64a_, u64b_;
+    DBuf<int64_t> i64a_, i64b_;
+    DBuf<double> bmin_;
+    DBuf<uint64_t> barg_;
+    DBuf<char> tmp_;
+    DBuf<float> f32a_;
+};
+
+// ---------------------------------------------------------- fixed-order reductions
+// Sums (or minima) of up to 8 per-element quantities in a fixed, input-size
+// determined order: results are bitwise reproducible.
+class Reducer {
+  public:
+    static constexpr int kBlocks = 256;
+    static constexpr int kThreads = 256;
+    double *partial(int k) { return part_.need((size_t)kBlocks * 8) + (size_t)k * kBlocks; }
+    double *base() { return part_.need((size_t)kBlocks * 8); }
+    // fetch K totals of the partial sums written by a reduce kernel
+    void fetch_sum(hipStream_t st, int K, int nblocks, double *out);
+    void fetch_min(hipStream_t st, int K, int nblocks, double *out);
+
+  private:
+    DBuf<double> part_;
+    DBuf<double> out_;
+    std::vector<double> host_;
+};
+
+// ---------------------------------------------------------------- Schur / PCG
+struct SchurCSR {
+    int n = 0;
+    int64_t nnz = 0;
+    DBuf<int32_t> rowptr, col, row, diag;
+    DBuf<double> val, dinv;
+};
+
+struct CGStats {
+    int iterations = 0;
+    bool converged = false;
+    double res_norm = 0.0;
+};
+
+class SchurSolver {
+  public:
+    // pattern of S_M = N - V^T M^-1 V for the support (CSC arrays by column)
+    void symbolic(hipStream_t st, int m, int n, int64_t psi, const int32_t *col_ptr,
+                  const int32_t *si, const int32_t *row_ptr, const int32_t *csr_pos,
+                  const int32_t *sj);
+    // values: S_jk = -sum_{i in col j and col k} theta_ij theta_ik / M_i (j != k),
+    // S_jj = -sum_{k != j} S_jk; also the Jacobi inverse diagonal
+    void numeric(hipStream_t st, int m, int n, const int32_t *col_ptr, const int32_t *si,
+                 const double *theta, const double *invM);
+    // y = S x
+    void spmv(hipStream_t st, const double *x, double *y);
+    // Jacobi-preconditioned CG on S x = b (b projected on e-perp by the caller)
+    CGStats pcg(hipStream_t st, const double *b, double *x, double rtol, double atol, int maxit);
+    SchurCSR S;
+
+  private:
+    DBuf<int32_t> cnt_;
+    DBuf<char> tmp_;
+    DBuf<int64_t> off64_, cnt64_;
+    DBuf<double> r_, z_, p_, q_, part_, scal_;
+    DBuf<int> flag_;
+};
+
+// Dense LDL^T (FP64) of a Schur complement with the infinite-pivot rule.
+class DenseLDL {
+  public:
+    // factor the CSR matrix; returns number of infinite pivots
+    int factor(hipStream_t st, const SchurCSR &S, double pivtol);
+    void solve(hipStream_t st, const double *b, double *x);
+    int64_t nnz_L() const { return nnzL_; }
+    int n = 0;
+
+  private:
+    DBuf<double> A_, d_, orig_, W_, v_;
+    DBuf<int> ninf_;
+    int64_t nnzL_ = 0;
+};
+
+// dense Kronecker products (kron.hip)
+void kron_apply(hipStream_t st, int m, int n, const double *X, double *rowsum, double *colsum,
+                DBuf<double> &prow, DBuf<double> &pcol);
+void kron_apply_t(hipStream_t st, int m, int n, const double *y, const double *z, double *X);
+
+}  // namespace otip

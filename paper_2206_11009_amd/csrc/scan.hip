@@ -1,0 +1,570 @@
+// Full m x n scans: pricing (Sections 3.2 and 3.4), the reduced-cost minimum
+// of the dual certificate (Section 3.3), and the cheap-variable scans of the
+// initial support (Section 3.2, end).  Costs are generated on the fly from
+// integer coordinates and never stored.
+//
+// Thread mapping of every scan: a 256-thread block covers 256 consecutive
+// sources i (lanes along i, so the variable index i + j*m is contiguous across
+// a wave) and a run of TJ consecutive targets j.  Per-target data is
+// wave-uniform and is read through the scalar cache from a small table built
+// per call.
+#include "common.h"
+#include "internal.h"
+
+namespace otip {
+
+// Per-target table: B_j = |x_j|^2, -2 x_j0, -2 x_j1 and z_j, all exact doubles.
+struct __align__(32) JEntry {
+    double B, a2, b2, z;
+};
+
+__global__ void build_jtab(int n, const int32_t *__restrict__ xt, const double *__restrict__ z,
+                           JEntry *__restrict__ jt) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double a = (double)xt[2 * j], b = (double)xt[2 * j + 1];
+    JEntry e;
+    e.B = a * a + b * b;
+    e.a2 = -2.0 * a;
+    e.b2 = -2.0 * b;
+    e.z = z ? z[j] : 0.0;
+    jt[j] = e;
+}
+
+// Per-source data: A_i = |x_i|^2, x_i0, x_i1, y_i.  Rows past m get y = -inf so
+// that every reduced cost they produce is +inf (never selected).
+struct RowData {
+    double A, al, be, y;
+};
+
+__device__ __forceinline__ RowData load_row(int i, int m, const int32_t *__restrict__ xs,
+                                            const double *__restrict__ y) {
+    RowData d;
+    if (i < m) {
+        d.al = (double)xs[2 * i];
+        d.be = (double)xs[2 * i + 1];
+        d.A = d.al * d.al + d.be * d.be;
+        d.y = y ? y[i] : 0.0;
+    } else {
+        d.al = d.be = d.A = 0.0;
+        d.y = -INFINITY;
+    }
+    return d;
+}
+
+// C_ij exactly: |x_i|^2 + |x_j|^2 - 2 x_i.x_j; every intermediate is an integer
+// below 2^53, so the two fused multiply-adds are exact.
+__device__ __forceinline__ double cost_of(const RowData &r, const JEntry &t) {
+    return fma(r.be, t.b2, fma(r.al, t.a2, r.A + t.B));
+}
+
+__device__ __forceinline__ bool in_support(const uint32_t *__restrict__ bm, uint64_t idx) {
+    return bm && ((bm[idx >> 5] >> (idx & 31u)) & 1u);
+}
+
+constexpr int kScanBlock = 256;
+constexpr int kHistBins = 4096;
+
+struct PriceArgs {
+    int m, n, tj;
+    const int32_t *xs;
+    const double *y;
+    const JEntry *jt;
+    const uint32_t *bitmap;
+    // histogram mode: digit = (key >> shift) & 4095 over keys whose bits above
+    // shift+12 equal `prefix` (no filter when shift + 12 >= 64)
+    int shift;
+    uint64_t prefix;
+    unsigned long long *hist;
+    // compaction mode: every key <= key_max
+    uint64_t key_max;
+    unsigned long long *count;
+    uint64_t *out_key, *out_idx;
+    uint64_t cap;
+};
+
+// Pricing pass.  MODE 0: histogram of one 12-bit digit of the ordered key of
+// every strictly negative reduced cost outside the support.  MODE 1: append
+// (key, idx) of those with key <= key_max.
+template <int MODE>
+__global__ __launch_bounds__(kScanBlock) void price_pass(PriceArgs a) {
+    __shared__ unsigned int lh[MODE == 0 ? kHistBins : 1];
+    const int i = blockIdx.x * kScanBlock + threadIdx.x;
+    const int j0 = blockIdx.y * a.tj;
+    const int j1 = min(a.n, j0 + a.tj);
+    if (MODE == 0) {
+        for (int t = threadIdx.x; t < kHistBins; t += kScanBlock) lh[t] = 0u;
+        __syncthreads();
+    }
+    const RowData rd = load_row(i, a.m, a.xs, a.y);
+    const int pshift = a.shift + 12;
+    const JEntry *__restrict__ jt = a.jt;
+    for (int j = j0; j < j1; ++j) {
+        const JEntry t = jt[j];
+        const double r = (cost_of(rd, t) - rd.y) - t.z;
+        const bool neg = r < 0.0;
+        if (__ballot(neg) == 0ull) continue;
+        const uint64_t idx = (uint64_t)i + (uint64_t)j * (uint64_t)a.m;
+        bool take = neg && !in_support(a.bitmap, idx);
+        const uint64_t key = dkey(r);
+        if (MODE == 0) {
+            if (take && (pshift >= 64 || (key >> pshift) == a.prefix))
+                atomicAdd(&lh[(key >> a.shift) & 4095u], 1u);
+        } else {
+            take = take && key <= a.key_max;
+            const uint64_t mask = __ballot(take);
+            if (mask) {
+                const int lane = threadIdx.x & 63;
+                const int leader = __ffsll((long long)mask) - 1;
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd(a.count, (unsigned long long)__popcll(mask));
+                base = __shfl(base, leader, 64);
+                if (take) {
+                    const uint64_t pos = base + __popcll(mask & ((1ull << lane) - 1ull));
+                    if (pos < a.cap) {
+                        a.out_key[pos] = key;
+                        a.out_idx[pos] = idx;
+                    }
+                }
+            }
+        }
+    }
+    if (MODE == 0) {
+        __syncthreads();
+        for (int t = threadIdx.x; t < kHistBins; t += kScanBlock)
+            if (lh[t]) atomicAdd(&a.hist[t], (unsigned long long)lh[t]);
+    }
+}
+
+// Decode the selected (key, idx) into (i, j, r).
+__global__ void decode_selection(int64_t k, int m, const uint64_t *__restrict__ key,
+                                 const uint64_t *__restrict__ idx, int32_t *oi, int32_t *oj,
+                                 double *orr, uint64_t *oidx) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= k) return;
+    uint64_t v = idx[t];
+    if (oi) oi[t] = (int32_t)(v % (uint64_t)m);
+    if (oj) oj[t] = (int32_t)(v / (uint64_t)m);
+    if (orr) orr[t] = dkey_inv(key[t]);
+    if (oidx) oidx[t] = v;
+}
+
+static int pick_tj(int n) { return n >= 4096 ? 256 : (n >= 512 ? 64 : 16); }
+
+void Scanner::prepare(hipStream_t st, int m, int n, const int32_t *xt, const double *z) {
+    jt_.need((size_t)n * sizeof(JEntry));
+    hipLaunchKernelGGL(build_jtab, dim3(grid_for(n, 256)), dim3(256), 0, st, n, xt, z,
+                       (JEntry *)jt_.get());
+    OTIP_HIP(hipGetLastError());
+}
+
+PriceResult Scanner::price(hipStream_t st, int m, int n, const int32_t *xs, const int32_t *xt,
+                           const double *y, const double *z, const uint32_t *bitmap,
+                           int64_t kmax, int32_t *oi, int32_t *oj, double *orr,
+                           uint64_t *oidx) {
+    PriceResult res{0, 0, 0};
+    if (m <= 0 || n <= 0) return res;
+    prepare(st, m, n, xt, z);
+    const int tj = pick_tj(n);
+    dim3 grid(grid_for(m, kScanBlock), grid_for(n, tj));
+    hist_.need(kHistBins);
+    cnt_.need(1);
+    PriceArgs a{};
+    a.m = m;
+    a.n = n;
+    a.tj = tj;
+    a.xs = xs;
+    a.y = y;
+    a.jt = (const JEntry *)jt_.get();
+    a.bitmap = bitmap;
+    a.hist = hist_.get();
+    std::vector<unsigned long long> h(kHistBins);
+
+    auto histogram = [&](int shift, uint64_t prefix) {
+        OTIP_HIP(hipMemsetAsync(hist_.get(), 0, kHistBins * sizeof(unsigned long long), st));
+        a.shift = shift;
+        a.prefix = prefix;
+        hipLaunchKernelGGL(price_pass<0>, grid, dim3(kScanBlock), 0, st, a);
+        OTIP_HIP(hipGetLastError());
+        OTIP_HIP(hipMemcpyAsync(h.data(), hist_.get(), kHistBins * sizeof(unsigned long long),
+                                hipMemcpyDeviceToHost, st));
+        OTIP_HIP(hipStreamSynchronize(st));
+        res.passes++;
+    };
+
+    // radix select of the kmax smallest keys, 12 bits per level from the top
+    histogram(52, 0);
+    uint64_t total = 0;
+    for (auto v : h) total += v;
+    res.nneg = (int64_t)total;
+    if (kmax <= 0 || total == 0) return res;
+
+    uint64_t key_max;
+    uint64_t emit_bound;
+    if (total <= (uint64_t)kmax) {
+        key_max = ~0ull;
+        emit_bound = total;
+    } else {
+        uint64_t need = (uint64_t)kmax, less = 0, prefix = 0;
+        int shift = 52;
+        const uint64_t slack = (uint64_t)std::max<int64_t>(kmax, 1 << 16);
+        for (;;) {
+            uint64_t cum = 0;
+            int b = 0;
+            for (; b < kHistBins; ++b) {
+                if (cum + h[b] >= need) break;
+                cum += h[b];
+            }
+            OTIP_CHECK(b < kHistBins, 5, "pricing: histogram inconsistent");
+            less += cum;
+            need -= cum;
+            prefix = (prefix << 12) | (uint64_t)b;
+            const uint64_t bucket = h[b];
+            if (bucket <= slack || shift == 4) {
+                // every key whose top (64 - shift) bits are <= prefix
+                key_max = (shift == 0) ? prefix : (((prefix + 1) << shift) - 1);
+                if (shift == 4) key_max = ((prefix + 1) << 4) - 1;
+                emit_bound = less + bucket;
+                break;
+            }
+            shift = (shift >= 16) ? shift - 12 : 4;
+            if (shift == 4) {
+                // last level covers the remaining low bits in one digit
+                histogram(4, prefix);
+            } else {
+                histogram(shift, prefix);
+            }
+        }
+    }
+    // compaction
+    const uint64_t cap = emit_bound;
+    ck_.need(cap);
+    ci_.need(cap);
+    OTIP_HIP(hipMemsetAsync(cnt_.get(), 0, sizeof(unsigned long long), st));
+    a.key_max = key_max;
+    a.count = cnt_.get();
+    a.out_key = ck_.get();
+    a.out_idx = ci_.get();
+    a.cap = cap;
+    hipLaunchKernelGGL(price_pass<1>, grid, dim3(kScanBlock), 0, st, a);
+    OTIP_HIP(hipGetLastError());
+    unsigned long long emitted = 0;
+    OTIP_HIP(hipMemcpyAsync(&emitted, cnt_.get(), sizeof(emitted), hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipStreamSynchronize(st));
+    res.passes++;
+    OTIP_CHECK(emitted == cap, 5,
+               "pricing: compaction count " + std::to_string(emitted) + " != histogram count " +
+                   std::to_string(cap));
+    // order by (key, idx): sort by idx, then stably by key
+    ck2_.need(cap);
+    ci2_.need(cap);
+    sort_pairs_u64(st, ci_.get(), ck_.get(), ci2_.get(), ck2_.get(), (int64_t)cap, 0, 64, tmp_);
+    sort_pairs_u64(st, ck2_.get(), ci2_.get(), ck_.get(), ci_.get(), (int64_t)cap, 0, 64, tmp_);
+    const int64_t k = std::min<int64_t>(kmax, (int64_t)cap);
+    hipLaunchKernelGGL(decode_selection, dim3(grid_for(k, 256)), dim3(256), 0, st, k, m,
+                       ck_.get(), ci_.get(), oi, oj, orr, oidx);
+    OTIP_HIP(hipGetLastError());
+    res.count = k;
+    return res;
+}
+
+// ----------------------------------------------------------------- minimum scan
+struct MinArgs {
+    int m, n, tj;
+    const int32_t *xs;
+    const double *y;
+    const JEntry *jt;
+    double *bmin;
+    uint64_t *barg;
+};
+
+__global__ __launch_bounds__(kScanBlock) void rmin_pass(MinArgs a) {
+    __shared__ double sv[kScanBlock / 64];
+    __shared__ uint64_t si[kScanBlock / 64];
+    const int i = blockIdx.x * kScanBlock + threadIdx.x;
+    const int j0 = blockIdx.y * a.tj, j1 = min(a.n, j0 + a.tj);
+    const RowData rd = load_row(i, a.m, a.xs, a.y);
+    double best = INFINITY;
+    uint64_t arg = ~0ull;
+    for (int j = j0; j < j1; ++j) {
+        const JEntry t = a.jt[j];
+        const double r = (cost_of(rd, t) - rd.y) - t.z;
+        if (r < best) {  // first j attaining the minimum for this row
+            best = r;
+            arg = (uint64_t)i + (uint64_t)j * (uint64_t)a.m;
+        }
+    }
+    // (value, index) lexicographic minimum over the block
+    for (int o = 32; o > 0; o >>= 1) {
+        double ov = __shfl_xor(best, o, 64);
+        uint64_t oa = __shfl_xor(arg, o, 64);
+        if (ov < best || (ov == best && oa < arg)) {
+            best = ov;
+            arg = oa;
+        }
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sv[w] = best;
+        si[w] = arg;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < kScanBlock / 64; ++k)
+            if (sv[k] < best || (sv[k] == best && si[k] < arg)) {
+                best = sv[k];
+                arg = si[k];
+            }
+        const size_t b = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+        a.bmin[b] = best;
+        a.barg[b] = arg;
+    }
+}
+
+void Scanner::rmin(hipStream_t st, int m, int n, const int32_t *xs, const int32_t *xt,
+                   const double *y, const double *z, double *out, int64_t *arg) {
+    prepare(st, m, n, xt, z);
+    const int tj = pick_tj(n);
+    dim3 grid(grid_for(m, kScanBlock), grid_for(n, tj));
+    const size_t nb = (size_t)grid.x * grid.y;
+    bmin_.need(nb);
+    barg_.need(nb);
+    MinArgs a{m, n, tj, xs, y, (const JEntry *)jt_.get(), bmin_.get(), barg_.get()};
+    hipLaunchKernelGGL(rmin_pass, grid, dim3(kScanBlock), 0, st, a);
+    OTIP_HIP(hipGetLastError());
+    std::vector<double> v(nb);
+    std::vector<uint64_t> ai(nb);
+    OTIP_HIP(hipMemcpyAsync(v.data(), bmin_.get(), nb * sizeof(double), hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipMemcpyAsync(ai.data(), barg_.get(), nb * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                            st));
+    OTIP_HIP(hipStreamSynchronize(st));
+    double best = INFINITY;
+    uint64_t ba = ~0ull;
+    for (size_t b = 0; b < nb; ++b)
+        if (v[b] < best || (v[b] == best && ai[b] < ba)) {
+            best = v[b];
+            ba = ai[b];
+        }
+    *out = best;
+    if (arg) *arg = (int64_t)ba;
+}
+
+// ------------------------------------------------------- initial support scans
+__device__ __forceinline__ int64_t int_cost(const int32_t *xs, const int32_t *xt, int i, int j) {
+    int64_t d0 = (int64_t)xs[2 * i] - xt[2 * j];
+    int64_t d1 = (int64_t)xs[2 * i + 1] - xt[2 * j + 1];
+    return d0 * d0 + d1 * d1;
+}
+
+// histogram of (c - lo) >> shift for lo <= c <= hi; count of c < lo
+__global__ __launch_bounds__(kScanBlock) void cost_hist(int m, int n, int tj, const int32_t *xs,
+                                                        const int32_t *xt, int64_t lo, int64_t hi,
+                                                        int shift, unsigned long long *hist,
+                                                        unsigned long long *below) {
+    __shared__ unsigned int lh[kHistBins];
+    __shared__ unsigned int lbelow;
+    for (int t = threadIdx.x; t < kHistBins; t += kScanBlock) lh[t] = 0u;
+    if (threadIdx.x == 0) lbelow = 0u;
+    __syncthreads();
+    const int i = blockIdx.x * kScanBlock + threadIdx.x;
+    const int j0 = blockIdx.y * tj, j1 = min(n, j0 + tj);
+    if (i < m) {
+        unsigned int nb = 0;
+        for (int j = j0; j < j1; ++j) {
+            int64_t c = int_cost(xs, xt, i, j);
+            if (c < lo)
+                ++nb;
+            else if (c <= hi)
+                atomicAdd(&lh[(c - lo) >> shift], 1u);
+        }
+        if (nb) atomicAdd(&lbelow, nb);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < kHistBins; t += kScanBlock)
+        if (lh[t]) atomicAdd(&hist[t], (unsigned long long)lh[t]);
+    if (threadIdx.x == 0 && lbelow) atomicAdd(below, (unsigned long long)lbelow);
+}
+
+// number of c_ij <= T in each column j (one block per column)
+__global__ __launch_bounds__(kScanBlock) void count_le_col(int m, int n, const int32_t *xs,
+                                                           const int32_t *xt, int64_t T,
+                                                           int64_t *cnt) {
+    __shared__ double lds[16];
+    const int j = blockIdx.x;
+    int c = 0;
+    for (int i = threadIdx.x; i < m; i += kScanBlock) c += int_cost(xs, xt, i, j) <= T;
+    double t = block_sum((double)c, lds);
+    if (threadIdx.x == 0) cnt[j] = (int64_t)t;
+}
+
+// write the variable indices with c_ij <= T of column j in increasing i
+__global__ __launch_bounds__(kScanBlock) void collect_le_col(int m, int n, const int32_t *xs,
+                                                             const int32_t *xt, int64_t T,
+                                                             const int64_t *off,
+                                                             uint64_t *out) {
+    __shared__ int wcount[kScanBlock / 64];
+    const int j = blockIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int64_t base = off[j];
+    for (int i0 = 0; i0 < m; i0 += kScanBlock) {
+        const int i = i0 + threadIdx.x;
+        const bool take = i < m && int_cost(xs, xt, i, j) <= T;
+        const uint64_t mask = __ballot(take);
+        if (lane == 0) wcount[w] = __popcll(mask);
+        __syncthreads();
+        int before = 0, total = 0;
+        for (int k = 0; k < kScanBlock / 64; ++k) {
+            if (k < w) before += wcount[k];
+            total += wcount[k];
+        }
+        if (take)
+            out[base + before + __popcll(mask & ((1ull << lane) - 1ull))] =
+                (uint64_t)i + (uint64_t)j * (uint64_t)m;
+        base += total;
+        __syncthreads();
+    }
+}
+
+// cheapest target of each source (ties: smallest j) -> variable index
+__global__ __launch_bounds__(kScanBlock) void row_argmin(int m, int n, const int32_t *xs,
+                                                         const int32_t *xt, uint64_t *out) {
+    __shared__ int64_t sc[kScanBlock];
+    __shared__ int sj[kScanBlock];
+    const int i = blockIdx.x;
+    int64_t best = INT64_MAX;
+    int arg = n;
+    for (int j = threadIdx.x; j < n; j += kScanBlock) {
+        int64_t c = int_cost(xs, xt, i, j);
+        if (c < best) {
+            best = c;
+            arg = j;
+        }
+    }
+    sc[threadIdx.x] = best;
+    sj[threadIdx.x] = arg;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int t = 1; t < kScanBlock; ++t)
+            if (sc[t] < best || (sc[t] == best && sj[t] < arg)) {
+                best = sc[t];
+                arg = sj[t];
+            }
+        out[i] = (uint64_t)i + (uint64_t)arg * (uint64_t)m;
+    }
+}
+
+// cheapest source of each target (ties: smallest i) -> variable index
+__global__ __launch_bounds__(kScanBlock) void col_argmin(int m, int n, const int32_t *xs,
+                                                         const int32_t *xt, uint64_t *out) {
+    __shared__ int64_t sc[kScanBlock];
+    __shared__ int si[kScanBlock];
+    const int j = blockIdx.x;
+    int64_t best = INT64_MAX;
+    int arg = m;
+    for (int i = threadIdx.x; i < m; i += kScanBlock) {
+        int64_t c = int_cost(xs, xt, i, j);
+        if (c < best) {
+            best = c;
+            arg = i;
+        }
+    }
+    sc[threadIdx.x] = best;
+    si[threadIdx.x] = arg;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int t = 1; t < kScanBlock; ++t)
+            if (sc[t] < best || (sc[t] == best && si[t] < arg)) {
+                best = sc[t];
+                arg = si[t];
+            }
+        out[j] = (uint64_t)arg + (uint64_t)j * (uint64_t)m;
+    }
+}
+
+int64_t Scanner::initial_support(hipStream_t st, int m, int n, const int32_t *xs,
+                                 const int32_t *xt, double kappa, int64_t cmax,
+                                 DBuf<uint64_t> &out, int64_t *T_out) {
+    const int64_t target = std::min<int64_t>((int64_t)std::ceil(kappa * (double)(m + n - 1)),
+                                             (int64_t)m * (int64_t)n);
+    const int tj = pick_tj(n);
+    dim3 grid(grid_for(m, kScanBlock), grid_for(n, tj));
+    hist_.need(kHistBins);
+    cnt_.need(1);
+    std::vector<unsigned long long> h(kHistBins);
+    int64_t lo = 0, hi = cmax, below_total = 0, T = cmax;
+    for (;;) {
+        int shift = 0;
+        while (((hi - lo) >> shift) >= kHistBins) ++shift;
+        OTIP_HIP(hipMemsetAsync(hist_.get(), 0, kHistBins * sizeof(unsigned long long), st));
+        OTIP_HIP(hipMemsetAsync(cnt_.get(), 0, sizeof(unsigned long long), st));
+        hipLaunchKernelGGL(cost_hist, grid, dim3(kScanBlock), 0, st, m, n, tj, xs, xt, lo, hi,
+                           shift, hist_.get(), cnt_.get());
+        OTIP_HIP(hipGetLastError());
+        unsigned long long below = 0;
+        OTIP_HIP(hipMemcpyAsync(h.data(), hist_.get(), kHistBins * sizeof(unsigned long long),
+                                hipMemcpyDeviceToHost, st));
+        OTIP_HIP(hipMemcpyAsync(&below, cnt_.get(), sizeof(below), hipMemcpyDeviceToHost, st));
+        OTIP_HIP(hipStreamSynchronize(st));
+        below_total = (int64_t)below;
+        int64_t cum = below_total;
+        int b = 0;
+        for (; b < kHistBins; ++b) {
+            if (cum + (int64_t)h[b] >= target) break;
+            cum += (int64_t)h[b];
+        }
+        if (b >= kHistBins) {
+            T = hi;
+            break;
+        }
+        const int64_t nlo = lo + ((int64_t)b << shift);
+        const int64_t nhi = std::min(hi, lo + (((int64_t)b + 1) << shift) - 1);
+        if (shift == 0) {
+            T = nlo;
+            break;
+        }
+        lo = nlo;
+        hi = nhi;
+    }
+    *T_out = T;
+    // collect {c <= T} in variable order
+    DBuf<int64_t> &cnt = i64a_;
+    DBuf<int64_t> &off = i64b_;
+    cnt.need((size_t)n);
+    off.need((size_t)n + 1);
+    hipLaunchKernelGGL(count_le_col, dim3(n), dim3(kScanBlock), 0, st, m, n, xs, xt, T, cnt.get());
+    OTIP_HIP(hipGetLastError());
+    exclusive_scan_i64(st, cnt.get(), off.get(), n, tmp_);
+    int64_t last_off = 0, last_cnt = 0;
+    OTIP_HIP(hipMemcpyAsync(&last_off, off.get() + (n - 1), sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipMemcpyAsync(&last_cnt, cnt.get() + (n - 1), sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipStreamSynchronize(st));
+    const int64_t nle = last_off + last_cnt;
+    const int64_t tot = nle + m + n;
+    DBuf<uint64_t> &tmpk = u64a_;
+    tmpk.need((size_t)tot);
+    hipLaunchKernelGGL(collect_le_col, dim3(n), dim3(kScanBlock), 0, st, m, n, xs, xt, T, off.get(),
+                       tmpk.get());
+    hipLaunchKernelGGL(row_argmin, dim3(m), dim3(kScanBlock), 0, st, m, n, xs, xt,
+                       tmpk.get() + nle);
+    hipLaunchKernelGGL(col_argmin, dim3(n), dim3(kScanBlock), 0, st, m, n, xs, xt,
+                       tmpk.get() + nle + m);
+    OTIP_HIP(hipGetLastError());
+    // union: sort and drop duplicates
+    DBuf<uint64_t> &sorted = u64b_;
+    sorted.need((size_t)tot);
+    sort_keys_u64(st, tmpk.get(), sorted.get(), tot, tmp_);
+    out.need((size_t)tot);
+    int64_t nu = unique_u64(st, sorted.get(), out.get(), tot, tmp_, cnt_);
+    return nu;
+}
+
+}  // namespace otip
+
+namespace otip {
+PriceResult Scanner::price_mixed(hipStream_t st, int m, int n, const int32_t *xs,
+                                 const int32_t *xt, const double *y, const double *z,
+                                 const uint32_t *bitmap, int64_t kmax, int32_t *oi, int32_t *oj,
+                                 double *orr, uint64_t *oidx) {
+    throw Error(6, "mixed-precision pricing is not built yet");
+}
+}  // namespace otip

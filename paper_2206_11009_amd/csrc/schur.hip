@@ -1,0 +1,393 @@
+// Schur complement of the normal equations restricted to the support and its
+// preconditioned CG solve (Sections 3.5, 4 and 4.2).
+//
+// With vec(V) = theta on the support, M and N the row and column sums of V,
+// S_M = N - V^T M^-1 V is n x n and has entry (j, k), j != k, equal to
+// -sum over sources i adjacent to both j and k of theta_ij theta_ik / M_i.
+// Its diagonal equals minus the sum of the off-diagonal entries of its row
+// (eq. diagdom: the row sums of S_M vanish), which is how it is formed here:
+// the direct form N_jj - sum_i theta_ij^2 / M_i cancels catastrophically when
+// one entry dominates its row of V, as happens near optimality.
+#include "internal.h"
+
+namespace otip {
+
+// ---------------------------------------------------------------- symbolic
+// One wave per S row j.  The union of the targets of all sources adjacent to j
+// is marked in a per-wave LDS bitmap over [kmin, kmax]; the marked bits, read in
+// order, are the sorted column indices of row j.
+template <bool FILL>
+__global__ __launch_bounds__(64) void schur_pattern(int n, const int32_t *__restrict__ col_ptr,
+                                                    const int32_t *__restrict__ si,
+                                                    const int32_t *__restrict__ row_ptr,
+                                                    const int32_t *__restrict__ csr_pos,
+                                                    const int32_t *__restrict__ sj,
+                                                    int32_t *__restrict__ cnt,
+                                                    const int32_t *__restrict__ rowptr,
+                                                    int32_t *__restrict__ col,
+                                                    int32_t *__restrict__ row,
+                                                    int32_t *__restrict__ diag) {
+    extern __shared__ uint32_t bits[];
+    const int j = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int c0 = col_ptr[j], c1 = col_ptr[j + 1];
+    int kmin = n, kmax = -1;
+    for (int e = c0; e < c1; ++e) {
+        const int i = si[e];
+        const int r0 = row_ptr[i], r1 = row_ptr[i + 1];
+        kmin = min(kmin, sj[csr_pos[r0]]);
+        kmax = max(kmax, sj[csr_pos[r1 - 1]]);
+    }
+    const int w0 = kmin >> 5, w1 = kmax >> 5;
+    for (int w = w0 + lane; w <= w1; w += 64) bits[w - w0] = 0u;
+    __syncthreads();
+    for (int e = c0; e < c1; ++e) {
+        const int i = si[e];
+        const int r0 = row_ptr[i], r1 = row_ptr[i + 1];
+        for (int r = r0 + lane; r < r1; r += 64) {
+            const int k = sj[csr_pos[r]];
+            atomicOr(&bits[(k >> 5) - w0], 1u << (k & 31));
+        }
+    }
+    __syncthreads();
+    if (!FILL) {
+        int c = 0;
+        for (int w = w0 + lane; w <= w1; w += 64) c += __popc(bits[w - w0]);
+        c = wave_sum_i(c);
+        if (lane == 0) cnt[j] = c;
+        return;
+    }
+    int base = rowptr[j];
+    for (int wb = w0; wb <= w1; wb += 64) {
+        const int w = wb + lane;
+        uint32_t word = (w <= w1) ? bits[w - w0] : 0u;
+        int pc = __popc(word);
+        // inclusive prefix over the wave
+        int incl = pc;
+        for (int o = 1; o < 64; o <<= 1) {
+            int t = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += t;
+        }
+        int pos = base + incl - pc;
+        while (word) {
+            const int b = __ffs(word) - 1;
+            word &= word - 1u;
+            const int k = (w << 5) + b;
+            col[pos] = k;
+            row[pos] = j;
+            if (k == j) diag[j] = pos;
+            ++pos;
+        }
+        base += __shfl(incl, 63, 64);
+    }
+}
+
+__global__ void counts_to_i64(int n, const int32_t *c, int64_t *o) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) o[t] = c[t];
+}
+__global__ void i64_to_rowptr(int n, const int64_t *off, const int32_t *c, int32_t *rowptr) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) rowptr[t] = (int32_t)off[t];
+    if (t == n - 1) rowptr[n] = (int32_t)(off[t] + c[t]);
+}
+
+void SchurSolver::symbolic(hipStream_t st, int m, int n, int64_t psi, const int32_t *col_ptr,
+                           const int32_t *si, const int32_t *row_ptr, const int32_t *csr_pos,
+                           const int32_t *sj) {
+    const int words = (n + 31) / 32 + 1;
+    OTIP_CHECK(words * 4 <= 64 * 1024, 6, "Schur pattern: n too large for the LDS bitmap");
+    S.n = n;
+    cnt_.need((size_t)n);
+    hipLaunchKernelGGL(schur_pattern<false>, dim3(n), dim3(64), words * 4, st, n, col_ptr, si,
+                       row_ptr, csr_pos, sj, cnt_.get(), nullptr, nullptr, nullptr, nullptr);
+    OTIP_HIP(hipGetLastError());
+    cnt64_.need((size_t)n);
+    off64_.need((size_t)n);
+    hipLaunchKernelGGL(counts_to_i64, dim3(grid_for(n, 256)), dim3(256), 0, st, n, cnt_.get(),
+                       cnt64_.get());
+    exclusive_scan_i64(st, cnt64_.get(), off64_.get(), n, tmp_);
+    S.rowptr.need((size_t)n + 1);
+    hipLaunchKernelGGL(i64_to_rowptr, dim3(grid_for(n, 256)), dim3(256), 0, st, n, off64_.get(),
+                       cnt_.get(), S.rowptr.get());
+    int32_t nnz = 0;
+    OTIP_HIP(hipMemcpyAsync(&nnz, S.rowptr.get() + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipStreamSynchronize(st));
+    OTIP_CHECK(nnz >= n, 5, "Schur pattern: missing diagonal");
+    S.nnz = nnz;
+    S.col.need((size_t)nnz);
+    S.row.need((size_t)nnz);
+    S.diag.need((size_t)n);
+    S.val.need((size_t)nnz);
+    S.dinv.need((size_t)n);
+    hipLaunchKernelGGL(schur_pattern<true>, dim3(n), dim3(64), words * 4, st, n, col_ptr, si,
+                       row_ptr, csr_pos, sj, nullptr, S.rowptr.get(), S.col.get(), S.row.get(),
+                       S.diag.get());
+    OTIP_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- numeric
+// Off-diagonal entries by intersecting the (i-sorted) source lists of targets j
+// and k.  The product theta_ij * theta_ik is commutative, so S is exactly
+// symmetric; each entry is summed in increasing i (deterministic).
+__global__ void schur_offdiag(int64_t nnz, const int32_t *__restrict__ srow,
+                              const int32_t *__restrict__ scol,
+                              const int32_t *__restrict__ col_ptr, const int32_t *__restrict__ si,
+                              const double *__restrict__ theta, const double *__restrict__ invM,
+                              double *__restrict__ val) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    const int j = srow[e], k = scol[e];
+    if (j == k) {
+        val[e] = 0.0;
+        return;
+    }
+    int a = col_ptr[j], ae = col_ptr[j + 1];
+    int b = col_ptr[k], be = col_ptr[k + 1];
+    double acc = 0.0;
+    while (a < ae && b < be) {
+        const int ia = si[a], ib = si[b];
+        if (ia == ib) {
+            acc = fma(theta[a] * theta[b], invM[ia], acc);
+            ++a;
+            ++b;
+        } else if (ia < ib) {
+            ++a;
+        } else {
+            ++b;
+        }
+    }
+    val[e] = -acc;
+}
+
+__global__ void schur_diag(int n, const int32_t *__restrict__ rowptr,
+                           const int32_t *__restrict__ diag, double *__restrict__ val,
+                           double *__restrict__ dinv) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double s = 0.0;
+    const int d = diag[j];
+    for (int e = rowptr[j]; e < rowptr[j + 1]; ++e)
+        if (e != d) s += val[e];
+    val[d] = -s;
+    dinv[j] = (-s > 0.0) ? 1.0 / (-s) : 0.0;
+}
+
+void SchurSolver::numeric(hipStream_t st, int m, int n, const int32_t *col_ptr,
+                          const int32_t *si, const double *theta, const double *invM) {
+    hipLaunchKernelGGL(schur_offdiag, dim3(grid_for(S.nnz, 256)), dim3(256), 0, st, S.nnz,
+                       S.row.get(), S.col.get(), col_ptr, si, theta, invM, S.val.get());
+    hipLaunchKernelGGL(schur_diag, dim3(grid_for(n, 256)), dim3(256), 0, st, n, S.rowptr.get(),
+                       S.diag.get(), S.val.get(), S.dinv.get());
+    OTIP_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- SpMV + CG
+constexpr int kCGBlocks = 256;
+constexpr int kCGThreads = 256;
+
+// G lanes per row; rows distributed round-robin over a fixed grid.  If pdot,
+// partial[block] = sum over the block's rows of x_j * y_j.
+template <int G>
+__global__ __launch_bounds__(256) void spmv_rows(int n, const int32_t *__restrict__ rowptr,
+                                                 const int32_t *__restrict__ col,
+                                                 const double *__restrict__ val,
+                                                 const double *__restrict__ x,
+                                                 double *__restrict__ y, double *partial,
+                                                 const int *done) {
+    __shared__ double lds[16];
+    if (done && *done) return;
+    const int groups = 256 / G;
+    const int g = threadIdx.x / G, l = threadIdx.x % G;
+    double dot = 0.0;
+    for (int r = blockIdx.x * groups + g; r < n; r += gridDim.x * groups) {
+        double acc = 0.0;
+        for (int e = rowptr[r] + l; e < rowptr[r + 1]; e += G) acc = fma(val[e], x[col[e]], acc);
+        for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+        if (l == 0) {
+            y[r] = acc;
+            dot = fma(x[r], acc, dot);
+        }
+    }
+    if (partial) {
+        double t = block_sum(dot, lds);
+        if (threadIdx.x == 0) partial[blockIdx.x] = t;
+    }
+}
+
+struct CGScal {
+    double rho, rr, target, its;
+};
+
+__device__ __forceinline__ double sum_partials(const double *p, int nb) {
+    double s = 0.0;
+    for (int k = 0; k < nb; ++k) s += p[k];
+    return s;
+}
+
+__global__ __launch_bounds__(kCGThreads) void cg_init(int n, const double *__restrict__ b,
+                                                      const double *__restrict__ dinv, double *x,
+                                                      double *r, double *z, double *p,
+                                                      double *part) {
+    __shared__ double lds[16];
+    double rz = 0.0, rr = 0.0;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+        const double bj = b[j];
+        const double zj = dinv[j] * bj;
+        x[j] = 0.0;
+        r[j] = bj;
+        z[j] = zj;
+        p[j] = zj;
+        rz = fma(bj, zj, rz);
+        rr = fma(bj, bj, rr);
+    }
+    double t1 = block_sum(rz, lds);
+    double t2 = block_sum(rr, lds);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = t1;
+        part[kCGBlocks + blockIdx.x] = t2;
+    }
+}
+
+__global__ void cg_init_finish(int nb, const double *part, double rtol, double atol, CGScal *sc,
+                               int *done) {
+    double rz = sum_partials(part, nb), rr = sum_partials(part + kCGBlocks, nb);
+    double target = fmin(rtol * sqrt(rr), atol);
+    sc->rho = rz;
+    sc->rr = rr;
+    sc->target = target;
+    sc->its = 0.0;
+    *done = (sqrt(rr) <= target || rr == 0.0) ? 1 : 0;
+}
+
+// alpha = rho / (p.q); x += alpha p; r -= alpha q; z = D^-1 r; partial r.z, r.r
+__global__ __launch_bounds__(kCGThreads) void cg_update(int n, int nb1, const double *part1,
+                                                        const double *__restrict__ p,
+                                                        const double *__restrict__ q,
+                                                        const double *__restrict__ dinv,
+                                                        double *x, double *r, double *z,
+                                                        double *part2, const CGScal *sc,
+                                                        int *done) {
+    __shared__ double lds[16];
+    if (*done) return;
+    const double pq = sum_partials(part1, nb1);
+    if (!(pq > 0.0)) {  // breakdown (S is positive semidefinite)
+        if (blockIdx.x == 0 && threadIdx.x == 0) *done = 2;
+        return;
+    }
+    const double alpha = sc->rho / pq;
+    double rz = 0.0, rr = 0.0;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+        x[j] = fma(alpha, p[j], x[j]);
+        const double rj = fma(-alpha, q[j], r[j]);
+        r[j] = rj;
+        const double zj = dinv[j] * rj;
+        z[j] = zj;
+        rz = fma(rj, zj, rz);
+        rr = fma(rj, rj, rr);
+    }
+    double t1 = block_sum(rz, lds);
+    double t2 = block_sum(rr, lds);
+    if (threadIdx.x == 0) {
+        part2[blockIdx.x] = t1;
+        part2[kCGBlocks + blockIdx.x] = t2;
+    }
+}
+
+// beta = rho_new / rho; p = z + beta p; convergence flag
+__global__ __launch_bounds__(kCGThreads) void cg_direction(int n, int nb2, const double *part2,
+                                                           const double *__restrict__ z,
+                                                           double *p, CGScal *sc, int *done) {
+    if (*done) return;
+    const double rz = sum_partials(part2, nb2), rr = sum_partials(part2 + kCGBlocks, nb2);
+    const double beta = rz / sc->rho;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x)
+        p[j] = fma(beta, p[j], z[j]);
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // every block has read sc->rho before block 0 can overwrite it only if
+        // the update is deferred: keep rho_new in a separate slot
+        sc->rr = rr;
+        sc->its += 1.0;
+        if (sqrt(rr) <= sc->target) *done = 1;
+    }
+}
+
+__global__ void cg_commit_rho(int nb2, const double *part2, CGScal *sc, const int *done) {
+    if (*done == 2) return;
+    sc->rho = sum_partials(part2, nb2);
+}
+
+void SchurSolver::spmv(hipStream_t st, const double *x, double *y) {
+    const int n = S.n;
+    const double avg = (double)S.nnz / std::max(1, n);
+    const int G = avg >= 48 ? 64 : 16;
+    const unsigned nb = std::min<unsigned>(kCGBlocks, grid_for(n, 256 / G));
+    if (G == 64)
+        hipLaunchKernelGGL(spmv_rows<64>, dim3(nb), dim3(256), 0, st, n, S.rowptr.get(),
+                           S.col.get(), S.val.get(), x, y, nullptr, nullptr);
+    else
+        hipLaunchKernelGGL(spmv_rows<16>, dim3(nb), dim3(256), 0, st, n, S.rowptr.get(),
+                           S.col.get(), S.val.get(), x, y, nullptr, nullptr);
+    OTIP_HIP(hipGetLastError());
+}
+
+CGStats SchurSolver::pcg(hipStream_t st, const double *b, double *x, double rtol, double atol,
+                         int maxit) {
+    const int n = S.n;
+    CGStats out;
+    r_.need(n);
+    z_.need(n);
+    p_.need(n);
+    q_.need(n);
+    part_.need(4 * kCGBlocks);
+    scal_.need(4);
+    flag_.need(1);
+    double *part1 = part_.get();
+    double *part2 = part_.get() + 2 * kCGBlocks;
+    CGScal *sc = (CGScal *)scal_.get();
+    int *done = flag_.get();
+    const unsigned nbv = std::min<unsigned>(kCGBlocks, grid_for(n, kCGThreads));
+    const double avg = (double)S.nnz / std::max(1, n);
+    const int G = avg >= 48 ? 64 : 16;
+    const unsigned nbs = std::min<unsigned>(kCGBlocks, grid_for(n, 256 / G));
+    hipLaunchKernelGGL(cg_init, dim3(nbv), dim3(kCGThreads), 0, st, n, b, S.dinv.get(), x,
+                       r_.get(), z_.get(), p_.get(), part2);
+    hipLaunchKernelGGL(cg_init_finish, dim3(1), dim3(1), 0, st, (int)nbv, part2, rtol, atol, sc,
+                       done);
+    OTIP_HIP(hipGetLastError());
+    int its_done = 0;
+    int chunk = 4;
+    CGScal hs{};
+    int hdone = 0;
+    while (true) {
+        for (int c = 0; c < chunk; ++c) {
+            if (G == 64)
+                hipLaunchKernelGGL(spmv_rows<64>, dim3(nbs), dim3(256), 0, st, n, S.rowptr.get(),
+                                   S.col.get(), S.val.get(), p_.get(), q_.get(), part1, done);
+            else
+                hipLaunchKernelGGL(spmv_rows<16>, dim3(nbs), dim3(256), 0, st, n, S.rowptr.get(),
+                                   S.col.get(), S.val.get(), p_.get(), q_.get(), part1, done);
+            hipLaunchKernelGGL(cg_update, dim3(nbv), dim3(kCGThreads), 0, st, n, (int)nbs, part1,
+                               p_.get(), q_.get(), S.dinv.get(), x, r_.get(), z_.get(), part2, sc,
+                               done);
+            hipLaunchKernelGGL(cg_direction, dim3(nbv), dim3(kCGThreads), 0, st, n, (int)nbv,
+                               part2, z_.get(), p_.get(), sc, done);
+            hipLaunchKernelGGL(cg_commit_rho, dim3(1), dim3(1), 0, st, (int)nbv, part2, sc, done);
+        }
+        OTIP_HIP(hipGetLastError());
+        its_done += chunk;
+        OTIP_HIP(hipMemcpyAsync(&hs, sc, sizeof(CGScal), hipMemcpyDeviceToHost, st));
+        OTIP_HIP(hipMemcpyAsync(&hdone, done, sizeof(int), hipMemcpyDeviceToHost, st));
+        OTIP_HIP(hipStreamSynchronize(st));
+        if (hdone || (int)hs.its >= maxit) break;
+        chunk = std::min(std::min(chunk * 2, 64), maxit - (int)hs.its);
+        if (chunk <= 0) break;
+    }
+    out.iterations = (int)hs.its;
+    out.res_norm = std::sqrt(std::max(0.0, hs.rr));
+    out.converged = (hdone == 1);
+    return out;
+}
+
+}  // namespace otip

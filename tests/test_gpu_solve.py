@@ -1,0 +1,55 @@
+"""Whole solves through the C-ABI against the CPU oracle and exact optima."""
+import numpy as np
+import pytest
+
+import oracle
+from synthetic import config_instance
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2206_11009_amd as otip
+    c = otip.Context(0)
+    yield c
+    c.close()
+
+
+def check_result(res, a, b, xs, xt):
+    m, n = len(a), len(b)
+    assert res.status == 0, res.info
+    assert res.marginal_residual <= 1e-8
+    assert res.rel_gap <= 1e-6
+    assert len(res.flows) <= m + n - 1
+    assert oracle.is_forest(res.rows, res.cols, m, n)
+    # the reported numbers are those of the returned plan and duals
+    c = oracle.sq_costs(xs, xt, res.rows, res.cols)
+    assert abs(float((c * res.flows).sum()) - res.objective) <= 1e-12 * max(1, abs(res.objective))
+    rmin, _ = oracle._cscan.rmin(xs, xt, res.y, res.z)
+    assert rmin == pytest.approx(res.r_min, rel=1e-12, abs=1e-12)
+
+
+@pytest.mark.parametrize("k", range(10))
+def test_gaussian_16x16_matches_oracle(ctx, k):
+    import paper_2206_11009_amd as otip
+    inst = config_instance("c1", k)
+    res = otip.otip_solve(ctx, inst.a, inst.b, inst.xs, inst.xt)
+    ref = oracle.solve(inst.a, inst.b, inst.xs, inst.xt)
+    check_result(res, inst.a, inst.b, inst.xs, inst.xt)
+    assert abs(res.objective - ref.objective) <= 1e-6 * abs(ref.objective)
+
+
+def test_uniform_vs_enumeration(ctx):
+    import itertools
+    import paper_2206_11009_amd as otip
+    rng = np.random.default_rng(107)
+    n = 7
+    xs = rng.integers(0, 10, (n, 2)).astype(np.int32)
+    xt = rng.integers(0, 10, (n, 2)).astype(np.int32)
+    C = ((xs[:, None, :].astype(int) - xt[None, :, :]) ** 2).sum(-1)
+    best = min(sum(C[i, s[i]] for i in range(n)) for s in itertools.permutations(range(n)))
+    a = np.full(n, 1.0 / n)
+    res = otip.otip_solve(ctx, a, a.copy(), xs, xt)
+    assert abs(res.objective - best / n) <= 1e-9 * max(1.0, best / n)
+    check_result(res, a, a, xs, xt)
