@@ -1,0 +1,178 @@
+#!/usr/bin/env python
+"""Benchmark of the interior-point-inspired column-generation OT solver on one
+MI355X.
+
+A step is one complete solve of one Kantorovich LP to a certified relative
+duality gap <= 1e-6 (initial support, every Newton step and pricing scan, the
+CG -> LDL^T switch, purification and the final full-scan certificate).  The
+default workload is the 64 x 64 grid pair family (m = n = 4096, 16.8M
+variables, Gaussian-mixture histograms, squared-Euclidean cost generated on the
+fly, FP64); step k solves seed k mod 5.  Inputs are uploaded to HBM before the
+timed region.
+
+Prints one JSON line: seconds per LP (lower is better), the live roofline of
+the dominant kernel (HIP events around each of its launches on its stream),
+pricing throughput, and the CPU oracle timed on a bounded sample of the same
+workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_VECTOR_PEAK_TF = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+PRICE_FLOPS_PER_COST = 7.0     # C_ij: one add + two FMAs (5 flops); r: two subtractions
+WORKLOADS = {
+    "c1": "16x16 Gaussian-mixture grid pair (m=n=256, 65,536 variables), 3 bumps, FP64",
+    "c2": "64x64 Gaussian-mixture grid pair (m=n=4096, 16.8M variables), 5 bumps, FP64",
+    "c3": "128x128 white-noise grid pair (m=n=16384, 268M variables), FP64",
+    "c5": "256x256 Cauchy-bump grid pair (m=n=65536, 4.29e9 variables), FP64",
+}
+
+
+def baseline_metric():
+    with open(os.path.join(ROOT, "BASELINE.json")) as f:
+        return json.load(f)["metric"]
+
+
+def cpu_baseline(cfg, budget_s=20.0, fallback_its=None):
+    """Time the CPU oracle on seed 0 of the workload for about budget_s seconds
+    of outer iterations, then scale the mean time per outer iteration by the
+    number of outer iterations the oracle needs for the whole solve (stored by
+    tests/golden/make_golden.py)."""
+    import oracle
+    from synthetic import config_instance
+
+    class Stop(Exception):
+        pass
+
+    inst = config_instance(cfg, 0)
+    t0 = time.perf_counter()
+    marks = []
+
+    def log(rec):
+        marks.append(time.perf_counter())
+        if time.perf_counter() - t0 > budget_s:
+            raise Stop
+
+    try:
+        oracle.solve(inst.a, inst.b, inst.xs, inst.xt, log=log)
+        done = True
+    except Stop:
+        done = False
+    elapsed = (marks[-1] if marks else time.perf_counter()) - t0
+    its = len(marks)
+    golden = os.path.join(ROOT, "tests", "golden", f"oracle_{cfg}.json")
+    full_its = None
+    if os.path.exists(golden):
+        with open(golden) as f:
+            full_its = json.load(f)["results"][0]["iterations"]
+    if full_its is None and not done:
+        full_its = int(round(fallback_its or its))
+    if done:
+        value = elapsed
+        how = f"complete oracle solve of seed 0 ({its} outer iterations)"
+    else:
+        value = elapsed / its * full_its
+        how = (f"first {its} outer iterations of the seed-0 oracle solve ({elapsed:.1f} s), "
+               f"mean time per iteration x {full_its} iterations of the oracle's full solve")
+    return {"value": value, "unit": "s per LP (estimated)" if not done else "s per LP",
+            "cores": 1, "kind": "oracle", "sample": how}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures a single GPU; this build has no multi-GPU path "
+              "(each LP solve runs on one MI355X).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2206_11009_amd as otip
+    from synthetic import CONFIGS, config_instance
+
+    ctx = otip.Context(0)
+    seeds = CONFIGS[args.config]["seeds"]
+    dev = []
+    for k in range(args.warmup + args.steps):
+        inst = config_instance(args.config, k % seeds)
+        dev.append([torch.as_tensor(x, device="cuda:0") for x in (inst.a, inst.b, inst.xs, inst.xt)])
+    prm = otip.params(profile=1,
+                      precision=otip.OTIP_MIXED if args.precision == "mixed" else otip.OTIP_FP64)
+    for k in range(args.warmup):
+        otip.otip_solve(ctx, *dev[k], prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for k in range(args.steps):
+        r = otip.otip_solve(ctx, *dev[args.warmup + k], prm)
+        infos.append(r.info)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sec = (t1 - t0) / args.steps
+    for inf in infos:
+        if not (inf["rel_gap"] <= 1e-6 and inf["marginal_residual"] <= 1e-8):
+            raise SystemExit(f"solve not certified: {inf}")
+
+    spmv_ms = sum(i["spmv_ms"] for i in infos)
+    spmv_n = sum(i["spmv_launches"] for i in infos)
+    spmv_b = sum(i["spmv_bytes"] for i in infos)
+    pr_ms = sum(i["price_ms"] for i in infos)
+    pr_n = sum(i["price_launches"] for i in infos)
+    pr_e = sum(i["price_elems"] for i in infos)
+    spmv = {"bound": "hbm", "kernel": "spmv_rows (Schur SpMV in CG)",
+            "achieved": spmv_b / max(spmv_ms, 1e-12) / 1e6, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "avg_launch_us": 1e3 * spmv_ms / max(spmv_n, 1), "launches": spmv_n,
+            "total_ms": spmv_ms, "traffic": None}
+    price = {"bound": "alu", "kernel": "price_pass (pricing scan)",
+             "achieved": PRICE_FLOPS_PER_COST * pr_e / max(pr_ms, 1e-12) / 1e9,
+             "peak": FP64_VECTOR_PEAK_TF, "unit": "TFLOP/s",
+             "avg_launch_us": 1e3 * pr_ms / max(pr_n, 1), "launches": pr_n, "total_ms": pr_ms,
+             "traffic": None}
+    for r in (spmv, price):
+        r["frac"] = r["achieved"] / r["peak"]
+    dominant, other = (spmv, price) if spmv_ms >= pr_ms else (price, spmv)
+
+    out = {
+        "metric": baseline_metric(),
+        "value": sec,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * sec,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.config], "seeds": f"k mod {seeds}",
+                   "certified_rel_gap": 1e-6, "precision": args.precision},
+        "roofline": dominant,
+        "roofline_other": other,
+        "pricing_gcosts_per_s": pr_e / max(pr_ms, 1e-12) / 1e6,
+        "iterations_mean": sum(i["iterations"] for i in infos) / len(infos),
+        "cg_iterations_mean": sum(i["cg_iterations"] for i in infos) / len(infos),
+        "rel_gap_max": max(i["rel_gap"] for i in infos),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.config, fallback_its=out["iterations_mean"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

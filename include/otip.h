@@ -89,6 +89,9 @@ typedef struct otip_params {
     int32_t enter_cap;       /* max entering columns per iteration; <= 0 means m */
     int32_t scale;           /* power-of-two scaling of masses and costs (1 = on) */
     int32_t verbose;         /* 1: one line per iteration on stderr */
+    int32_t profile;         /* 1: time every SpMV and pricing launch with HIP events */
+    int32_t switch_cost;     /* 1: also switch once a dense factorisation is estimated (fixed
+                                cost model) to cost less than the last iteration's CG */
 } otip_params;
 
 /* Problem description.  All four arrays are DEVICE pointers.
@@ -126,6 +129,14 @@ typedef struct otip_info {
     double seconds_update;     /* support update and rebuild */
     double seconds_setup;      /* initial support, starting point */
     double seconds_final;      /* polish, purification, certificate */
+    int64_t pricing_scans;     /* full m*n passes of the pricing and certificate scans */
+    /* with params.profile: event-timed launches of the two hot kernels */
+    int64_t spmv_launches;     /* Schur SpMV launches inside CG */
+    double spmv_ms;            /* their summed durations */
+    double spmv_bytes;         /* their algorithmic bytes: 12 nnz + 20 n + 4 per launch */
+    int64_t price_launches;    /* pricing-pass launches */
+    double price_ms;
+    double price_elems;        /* reduced costs evaluated: m*n per launch */
 } otip_info;
 
 typedef struct otip_ctx otip_ctx;

@@ -491,7 +491,27 @@ def solve(a, b, xs, xt, params: OracleParams | None = None, log=None) -> OracleR
     status = "maxiter"
     cg_failed = False
     it = 0
-    for it in range(P.max_iter):
+    tol_int = P.tol
+    while True:
+        status, it, cg_failed, mode, cg_total, direct_its, max_fill = _iterate(
+            st, P, tol_int, it, mode, psi_hist, hist, cg_total, direct_its, max_fill, cg_failed,
+            f_norm, kcap, log)
+        result = _finalize(st, P, status, it, cg_total, direct_its, max_fill, hist, t0)
+        # the certified gap decides: tighten the internal tolerance and resume
+        if result.rel_gap <= P.tol or it >= P.max_iter or tol_int <= 1e-13:
+            if result.rel_gap > P.tol:
+                result.status = "maxiter"
+            return result
+        tol_int = max(tol_int * 0.1, 1e-13)
+
+
+def _iterate(st, P, tol_int, it, mode, psi_hist, hist, cg_total, direct_its, max_fill, cg_failed,
+             f_norm, kcap, log):
+    """Outer iterations from `it` until the stop test passes (and the
+    a-posteriori pricing finds nothing significant) or max_iter."""
+    m, n = st.m, st.n
+    status = "maxiter"
+    while it < P.max_iter:
         # 1. residuals of eq. redsystem
         ra, rb = A_apply(st.p, st.rows, st.cols, m, n)
         r1a, r1b = st.a - ra, st.b - rb
@@ -506,18 +526,18 @@ def solve(a, b, xs, xt, params: OracleParams | None = None, log=None) -> OracleR
                    solver=mode, primal=prim)
         hist.append(rec)
         # 2. stop test, then the a-posteriori pricing check
-        if max(rel1, rel2, relmu) < P.tol:
+        if max(rel1, rel2, relmu) < tol_int:
             sel, rsel, _ = _cscan.price(st.xs, st.xt, st.y / st.zeta, st.z / st.zeta,
                                         st.idx, kcap)
             big = np.abs(rsel * st.zeta) * st.a.sum() > P.cert_rel * max(1.0, abs(prim))
             if not big.any():
-                status = "optimal"
-                break
+                return "optimal", it + 1, cg_failed, mode, cg_total, direct_its, max_fill
             sm = math.sqrt(mu)
             rec["cert_added"] = int(big.sum())
             _set_support(st, np.concatenate([st.idx, sel[big]]),
                          np.concatenate([st.p, np.full(int(big.sum()), sm)]),
                          np.concatenate([st.s, np.full(int(big.sum()), sm)]))
+            it += 1
             continue
         # 6. switch test (Section 4.3)
         factor = None
@@ -615,38 +635,92 @@ def solve(a, b, xs, xt, params: OracleParams | None = None, log=None) -> OracleR
                      np.concatenate([st.s[keep], np.full(k, sm)]))
         if log:
             log(rec)
+        it += 1
+    return status, it, cg_failed, mode, cg_total, direct_its, max_fill
 
-    # final primal projection, purification, certificate
+
+def _finalize(st, P, status, it, cg_total, direct_its, max_fill, hist, t0):
+    """Final primal projection, purification to a basic plan, dual certificate.
+    Leaves the iterate scaled and usable for further iterations."""
+    m, n = st.m, st.n
+    saved = (st.a, st.b, st.p, st.y, st.z)
     _polish(st, P)
+    saved = (st.a, st.b, st.p.copy(), st.y, st.z)
     # undo the scaling
-    st.a, st.b = st.a / st.omega, st.b / st.omega
-    st.p = st.p / st.omega
-    st.y, st.z = st.y / st.zeta, st.z / st.zeta
-    rows, cols, flows = purify_to_forest(st.rows, st.cols, st.p,
-                                         sq_costs(st.xs, st.xt, st.rows, st.cols), m, n)
-    # numerically-zero remnants leave; the rest of the forest gets the flows
-    # the marginals determine (kept only if they stay nonnegative)
-    big = flows >= P.drop_rel * np.minimum(st.a[rows], st.b[cols])
-    exact, _imb = forest_flows(rows[big], cols[big], st.a, st.b)
-    if exact.size and exact.min() >= -1e-12 * exact.max():
-        rows, cols, flows = rows[big], cols[big], np.maximum(exact, 0.0)
+    a, b = st.a / st.omega, st.b / st.omega
+    pu = st.p / st.omega
+    yu, zu = st.y / st.zeta, st.z / st.zeta
+    st.a, st.b, st.p, st.y, st.z = saved
+    # purification to a basic plan: first with numerically-zero flows removed
+    # before any cycle is cancelled (fast); if the forest's exact flows are not
+    # nonnegative, again with every positive flow
+    for predrop in (True, False):
+        keep = pu > 0.0
+        if predrop:
+            keep &= pu >= P.drop_rel * np.minimum(a[st.rows], b[st.cols])
+        rows, cols, flows = purify_to_forest(st.rows[keep], st.cols[keep], pu[keep],
+                                             sq_costs(st.xs, st.xt, st.rows[keep],
+                                                      st.cols[keep]), m, n)
+        # the forest's flows as the marginals determine them, kept only if
+        # they stay nonnegative
+        big = flows >= P.drop_rel * np.minimum(a[rows], b[cols])
+        exact, _imb = forest_flows(rows[big], cols[big], a, b)
+        if exact.size and exact.min() >= -1e-12 * exact.max():
+            rows, cols, flows = rows[big], cols[big], np.maximum(exact, 0.0)
+            break
     order = np.argsort(rows + cols * m, kind="stable")
     rows, cols, flows = rows[order], cols[order], flows[order]
     costs = sq_costs(st.xs, st.xt, rows, cols).astype(np.float64)
     objective = math.fsum((costs * flows).tolist())
+    suma = a.sum()
+
+    def bound(yv, zv):
+        rm, _ = _cscan.rmin(st.xs, st.xt, yv, zv)
+        return math.fsum((a * yv).tolist()) + math.fsum((b * zv).tolist()) + suma * min(0.0, rm), rm
+
     # gauge: z_{n-1} = 0 (adding t to y and -t to z leaves c - A^T y unchanged)
-    g = st.z[n - 1]
-    y = st.y + g
-    z = st.z - g
-    r_min, _ = _cscan.rmin(st.xs, st.xt, y, z)
-    dual = math.fsum((st.a * y).tolist()) + math.fsum((st.b * z).tolist()) + \
-        st.a.sum() * min(0.0, r_min)
+    g = zu[n - 1]
+    y = yu + g
+    z = zu - g
+    dual, r_min = bound(y, z)
+    # dual recovery after termination (Section 3.3): duals of the basic plan,
+    # y_i + z_j = C_ij on its forest edges, each tree anchored at the
+    # interior-point dual of its smallest node; kept if their bound is stronger
+    yb, zb = basis_duals(rows, cols, costs, y, z, m, n)
+    dual_b, r_min_b = bound(yb, zb)
+    if dual_b > dual:
+        y, z, dual, r_min = yb, zb, dual_b, r_min_b
     ra, rb = A_apply(flows, rows, cols, m, n)
-    marg = (np.abs(ra - st.a).sum() + np.abs(rb - st.b).sum()) / (st.a.sum() + st.b.sum())
+    marg = (np.abs(ra - a).sum() + np.abs(rb - b).sum()) / (a.sum() + b.sum())
     rel_gap = (objective - dual) / max(1.0, abs(objective))
     return OracleResult(status=status, rows=rows, cols=cols, flows=flows, y=y, z=z,
                         objective=objective, dual_bound=dual, rel_gap=rel_gap,
-                        marginal_residual=float(marg), r_min=r_min, iterations=it + 1,
+                        marginal_residual=float(marg), r_min=r_min, iterations=it,
                         cg_iterations=cg_total, direct_iterations=direct_its,
                         max_fill_pct=max_fill, history=hist,
                         seconds=time.perf_counter() - t0)
+
+
+def basis_duals(rows, cols, costs, y0, z0, m, n):
+    """Duals of a basic plan: y_i + z_j = C_ij on every edge of its forest; the
+    smallest node of each tree keeps its value from (y0, z0); gauge z_{n-1} = 0."""
+    pot = np.concatenate([y0, z0]).astype(np.float64)
+    adj = [[] for _ in range(m + n)]
+    for k, (i, j) in enumerate(zip(rows.tolist(), cols.tolist())):
+        adj[i].append((m + j, k))
+        adj[m + j].append((i, k))
+    seen = np.zeros(m + n, bool)
+    for r in range(m + n):
+        if seen[r]:
+            continue
+        seen[r] = True
+        stack = [r]
+        while stack:
+            u = stack.pop()
+            for v, k in adj[u]:
+                if not seen[v]:
+                    seen[v] = True
+                    pot[v] = costs[k] - pot[u]
+                    stack.append(v)
+    g = pot[m + n - 1]
+    return pot[:m] + g, pot[m:] - g

@@ -29,7 +29,8 @@ class otip_params(ctypes.Structure):
         ("polish_tol", _c_f64), ("polish_steps", _c_i32), ("drop_rel", _c_f64),
         ("cg_eta", _c_f64), ("cg_floor", _c_f64), ("linear_solver", _c_i32),
         ("precision", _c_i32), ("dense_max_n", _c_i32), ("force_switch_at", _c_i32),
-        ("enter_cap", _c_i32), ("scale", _c_i32), ("verbose", _c_i32),
+        ("enter_cap", _c_i32), ("scale", _c_i32), ("verbose", _c_i32), ("profile", _c_i32),
+        ("switch_cost", _c_i32),
     ]
 
 
@@ -45,7 +46,9 @@ class otip_info(ctypes.Structure):
         ("marginal_residual", _c_f64), ("r_min", _c_f64), ("max_fill_pct", _c_f64),
         ("seconds_total", _c_f64), ("seconds_pricing", _c_f64), ("seconds_newton", _c_f64),
         ("seconds_direct", _c_f64), ("seconds_update", _c_f64), ("seconds_setup", _c_f64),
-        ("seconds_final", _c_f64),
+        ("seconds_final", _c_f64), ("pricing_scans", _c_i64), ("spmv_launches", _c_i64),
+        ("spmv_ms", _c_f64), ("spmv_bytes", _c_f64), ("price_launches", _c_i64),
+        ("price_ms", _c_f64), ("price_elems", _c_f64),
     ]
 
     def as_dict(self):

@@ -82,6 +82,8 @@ void otip_params_default(otip_params *p) {
     p->enter_cap = 0;
     p->scale = 1;
     p->verbose = 0;
+    p->profile = 0;
+    p->switch_cost = 1;
 }
 
 int otip_create(otip_ctx **ctx, int device, void *hip_stream) {

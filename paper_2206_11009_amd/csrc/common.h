@@ -63,6 +63,51 @@ struct DBuf {
     T *get() const { return ptr; }
 };
 
+// Event timing of individual kernel launches on their stream (opt-in).
+struct LaunchTimer {
+    bool on = false;
+    int64_t launches = 0;
+    double ms = 0.0, work = 0.0;
+    std::vector<hipEvent_t> ev;
+    std::vector<double> pending_work;
+    size_t used = 0;
+    ~LaunchTimer() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+    // record the start event of a launch carrying `w` units of work
+    void start(hipStream_t st, double w) {
+        if (!on) return;
+        if (used + 2 > ev.size()) {
+            for (int k = 0; k < 64; ++k) {
+                hipEvent_t e;
+                if (hipEventCreate(&e) != hipSuccess) throw Error(3, "hipEventCreate failed");
+                ev.push_back(e);
+            }
+        }
+        (void)hipEventRecord(ev[used], st);
+        pending_work.push_back(w);
+    }
+    void stop(hipStream_t st) {
+        if (!on) return;
+        (void)hipEventRecord(ev[used + 1], st);
+        used += 2;
+    }
+    // after the stream has been synchronised
+    void collect() {
+        if (!on) return;
+        for (size_t k = 0; k + 1 < used; k += 2) {
+            float t = 0.0f;
+            if (hipEventElapsedTime(&t, ev[k], ev[k + 1]) == hipSuccess) {
+                ms += t;
+                work += pending_work[k / 2];
+                ++launches;
+            }
+        }
+        used = 0;
+        pending_work.clear();
+    }
+};
+
 inline unsigned grid_for(int64_t n, int block) {
     int64_t g = (n + block - 1) / block;
     if (g < 1) g = 1;

@@ -33,20 +33,33 @@ __global__ void dense_zero(size_t total, double *A) {
         A[t] = 0.0;
 }
 
-// factor the diagonal block [kb, kb+nb) in LDS
+// Factor the diagonal block [kb, kb+nb): thread (i, q) keeps row i, columns
+// 16q..16q+15 of the block (t) and of its running inverse (x) in registers;
+// each step broadcasts the pivot, column k of L and row k of the inverse
+// through LDS.  L11 = prod_k (I + l_k e_k^T), so applying the row operations
+// X <- (I - l_k e_k^T) X to X = I in the same order leaves X = L11^-1, which
+// is written to Linv (nb x nb, column-major) for the panel product.
 __global__ __launch_bounds__(256) void ldl_diag(int n, int kb, int nb, double *A,
                                                 const double *orig, double *d, double pivtol,
-                                                int *ninf) {
-    __shared__ double T[NB][NB + 1];
+                                                int *ninf, double *Linv) {
+    __shared__ double colk[NB];
+    __shared__ double xrow[NB];
     __shared__ double dk;
-    for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) {
-        const int i = t % nb, j = t / nb;
-        T[i][j] = (i >= j) ? A[(size_t)(kb + i) + (size_t)(kb + j) * n] : 0.0;
+    const int i = threadIdx.x & 63, q = threadIdx.x >> 6;
+    double t[16], x[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        const int j = 16 * q + c;
+        t[c] = (i < nb && j < nb && i >= j) ? A[(size_t)(kb + i) + (size_t)(kb + j) * n] : 0.0;
+        x[c] = (i == j) ? 1.0 : 0.0;
     }
-    __syncthreads();
     for (int k = 0; k < nb; ++k) {
-        if (threadIdx.x == 0) {
-            double v = T[k][k];
+        const int kq = k >> 4, kc = k & 15;
+        if (q == kq && i == k) {
+            double v = 0.0;
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                if (c == kc) v = t[c];
             const double o = orig[kb + k];
             if (!(v > pivtol * o) || !(v > 0.0)) {
                 v = INFINITY;
@@ -55,57 +68,77 @@ __global__ __launch_bounds__(256) void ldl_diag(int n, int kb, int nb, double *A
             dk = v;
             d[kb + k] = v;
         }
-        __syncthreads();
-        const double dd = dk;
-        // column k of L
-        for (int i = k + 1 + threadIdx.x; i < nb; i += blockDim.x)
-            T[i][k] = isinf(dd) ? 0.0 : T[i][k] / dd;
-        __syncthreads();
-        // rank-1 update of the remaining lower triangle: A_ij -= l_ik d_k l_jk
-        if (!isinf(dd)) {
-            const int rem = nb - k - 1;
-            for (int t = threadIdx.x; t < rem * rem; t += blockDim.x) {
-                const int i = k + 1 + t % rem, j = k + 1 + t / rem;
-                if (i >= j) T[i][j] = fma(-T[i][k] * dd, T[j][k], T[i][j]);
-            }
+        if (i == k) {
+#pragma unroll
+            for (int c = 0; c < 16; ++c) xrow[16 * q + c] = x[c];
         }
         __syncthreads();
+        const double dd = dk;
+        if (q == kq) {
+            // column k of L (rows below k)
+            double l = 0.0;
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                if (c == kc) l = t[c];
+            l = (i > k && !isinf(dd)) ? l / dd : 0.0;
+            colk[i] = l;
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                if (c == kc && i > k) t[c] = l;
+        }
+        __syncthreads();
+        const double lik = colk[i];
+        if (!isinf(dd)) {
+            const double li = lik * dd;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const int j = 16 * q + c;
+                if (j > k && i >= j) t[c] = fma(-li, colk[j], t[c]);
+            }
+        }
+        // inverse: rows below k lose l_ik times row k
+#pragma unroll
+        for (int c = 0; c < 16; ++c) x[c] = fma(-lik, xrow[16 * q + c], x[c]);
+        __syncthreads();
     }
-    for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) {
-        const int i = t % nb, j = t / nb;
-        if (i > j) A[(size_t)(kb + i) + (size_t)(kb + j) * n] = T[i][j];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        const int j = 16 * q + c;
+        if (i < nb && j < nb && i > j) A[(size_t)(kb + i) + (size_t)(kb + j) * n] = t[c];
+        Linv[(size_t)i + (size_t)j * NB] = (i < nb && j < nb) ? x[c] : (i == j ? 1.0 : 0.0);
     }
 }
 
-// rows below the diagonal block: w_i solves w L11^T = a_i; l_i = w D^-1
+// Rows below the diagonal block: W21 = A21 L11^-T (so W21 = L21 D1) and
+// L21 = W21 D1^-1.  A 64-row tile of A21 and Linv are staged in LDS; each
+// thread forms 16 entries of W as dot products with rows of Linv.
 __global__ __launch_bounds__(256) void ldl_panel(int n, int kb, int nb, double *A,
-                                                 const double *d, double *W) {
-    __shared__ double L11[NB][NB + 1];
-    __shared__ double dd[NB];
-    for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) {
-        const int i = t % nb, j = t / nb;
-        L11[i][j] = (i > j) ? A[(size_t)(kb + i) + (size_t)(kb + j) * n] : 0.0;
+                                                 const double *d, double *W,
+                                                 const double *Linv) {
+    __shared__ double As[NB][NB + 1];
+    __shared__ double Li[NB][NB + 1];
+    const int r0 = kb + nb + blockIdx.x * NB;
+    const int rows = n - kb - nb;
+    for (int t = threadIdx.x; t < NB * NB; t += 256) {
+        const int a = t % NB, k = t / NB;
+        As[a][k] = (r0 + a < n && k < nb) ? A[(size_t)(r0 + a) + (size_t)(kb + k) * n] : 0.0;
+        Li[a][k] = Linv[(size_t)a + (size_t)k * NB];  // Linv(a, k)
     }
-    for (int t = threadIdx.x; t < nb; t += blockDim.x) dd[t] = d[kb + t];
     __syncthreads();
-    const int i = kb + nb + blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double w[NB];
+    const int a = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int i = r0 + a;
+    // W(i, k) = sum_t A(i, t) * Linv(k, t), t <= k
 #pragma unroll
-    for (int k = 0; k < NB; ++k) {
-        if (k < nb) {
-            double v = A[(size_t)i + (size_t)(kb + k) * n];
-            for (int t = 0; t < k; ++t) v = fma(-w[t], L11[k][t], v);
-            w[k] = v;
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < NB; ++k) {
-        if (k < nb) {
-            const bool inf = isinf(dd[k]);
-            const double wk = inf ? 0.0 : w[k];
-            W[(size_t)(i - kb - nb) + (size_t)k * (n - kb - nb)] = wk;
-            A[(size_t)i + (size_t)(kb + k) * n] = inf ? 0.0 : wk / dd[k];
+    for (int c = 0; c < 16; ++c) {
+        const int k = 16 * q + c;
+        double v = 0.0;
+        for (int tt = 0; tt <= k && tt < nb; ++tt) v = fma(As[a][tt], Li[k][tt], v);
+        if (i < n && k < nb) {
+            const double dd = d[kb + k];
+            const bool inf = isinf(dd);
+            const double wk = inf ? 0.0 : v;
+            W[(size_t)(i - kb - nb) + (size_t)k * rows] = wk;
+            A[(size_t)i + (size_t)(kb + k) * n] = inf ? 0.0 : wk / dd;
         }
     }
 }
@@ -156,48 +189,86 @@ __global__ __launch_bounds__(256) void ldl_update(int n, int kb, int nb, double 
         }
 }
 
-// single-workgroup triangular solves with the factor
-__global__ __launch_bounds__(1024) void ldl_solve_k(int n, const double *__restrict__ A,
-                                                   const double *__restrict__ d, double *x) {
-    // forward: L y = b (unit lower)
-    for (int kb = 0; kb < n; kb += NB) {
-        const int nb = min(NB, n - kb);
-        for (int k = 0; k < nb; ++k) {
-            __syncthreads();
-            const double xk = x[kb + k];
-            for (int i = kb + k + 1 + threadIdx.x; i < kb + nb; i += blockDim.x)
-                x[i] = fma(-A[(size_t)i + (size_t)(kb + k) * n], xk, x[i]);
+// Triangular solves, one launch per 64-wide block column.  Every workgroup
+// re-solves the 64 x 64 diagonal block in one wave (register shuffles) from
+// the final right-hand side entries of that block, then applies the block's
+// columns to its own rows of the remaining right-hand side; workgroup 0 stores
+// the solved block.  Right-hand side (w) and solution (x) are separate arrays,
+// so no workgroup reads an entry another one writes in the same launch.
+//
+// forward:  L y = b, unit lower, L column-major           (rows below the block)
+// backward: L^T x = y' (y' = D^-1 y) with U = L^T stored column-major (rows above)
+__device__ __forceinline__ double diag_solve_wave(int n, const double *__restrict__ T, int kb,
+                                                  int nb, double wt, bool lower) {
+    const int t = threadIdx.x & 63;
+    double row[NB];
+    // lane t's row of the 64 x 64 diagonal block, loaded before the recurrence
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+        row[k] = (t < nb && k < nb) ? T[(size_t)(kb + t) + (size_t)(kb + k) * n] : 0.0;
+    double x = wt;
+    if (lower) {
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            const double xk = __shfl(x, k, 64);
+            if (t > k && t < nb) x = fma(-row[k], xk, x);
         }
-        __syncthreads();
-        for (int i = kb + nb + threadIdx.x; i < n; i += blockDim.x) {
-            double v = x[i];
-            for (int k = 0; k < nb; ++k) v = fma(-A[(size_t)i + (size_t)(kb + k) * n], x[kb + k], v);
-            x[i] = v;
+    } else {
+#pragma unroll
+        for (int k = NB - 1; k >= 0; --k) {
+            const double xk = __shfl(x, k, 64);
+            if (t < k && k < nb) x = fma(-row[k], xk, x);
+        }
+    }
+    return x;
+}
+
+__global__ __launch_bounds__(256) void trsv_step(int n, int kb, int nb, const double *__restrict__ T,
+                                                 const double *__restrict__ d, double *w, double *x,
+                                                 int lower) {
+    __shared__ double xb[64];
+    if (threadIdx.x < 64) {
+        const int t = threadIdx.x;
+        const double wt = (t < nb) ? w[kb + t] : 0.0;
+        const double v = diag_solve_wave(n, T, kb, nb, wt, lower != 0);
+        if (t < nb) {
+            xb[t] = v;
+            if (blockIdx.x == 0) x[kb + t] = v;
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = isinf(d[i]) ? 0.0 : x[i] / d[i];
-    // backward: L^T x = y
-    for (int kb = ((n - 1) / NB) * NB; kb >= 0; kb -= NB) {
-        const int nb = min(NB, n - kb);
-        __syncthreads();
-        // x[kb..kb+nb) -= sum_{i >= kb+nb} L(i, k) x[i]
-        for (int k = threadIdx.x; k < nb; k += blockDim.x) {
-            double v = x[kb + k];
-            for (int i = kb + nb; i < n; ++i) v = fma(-A[(size_t)i + (size_t)(kb + k) * n], x[i], v);
-            x[kb + k] = v;
-        }
-        __syncthreads();
-        for (int k = nb - 1; k >= 0; --k) {
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                double v = x[kb + k];
-                for (int i = kb + k + 1; i < kb + nb; ++i)
-                    v = fma(-A[(size_t)i + (size_t)(kb + k) * n], x[i], v);
-                x[kb + k] = v;
-            }
-        }
-        __syncthreads();
+    // remaining rows: below the block (forward) or above it (backward)
+    const int r0 = lower ? kb + nb : 0;
+    const int r1 = lower ? n : kb;
+    const int i = r0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= r1) return;
+    double v = w[i];
+    for (int k = 0; k < nb; ++k) v = fma(-T[(size_t)i + (size_t)(kb + k) * n], xb[k], v);
+    w[i] = v;
+}
+
+// y = D^-1 y (an infinite pivot gives 0)
+__global__ void scale_by_pivots(int n, const double *__restrict__ d, double *y) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = isinf(d[i]) ? 0.0 : y[i] / d[i];
+}
+
+// U = L^T (64 x 64 tiles through LDS), unit diagonal implied
+__global__ __launch_bounds__(256) void transpose_lower(int n, const double *__restrict__ L,
+                                                       double *__restrict__ U) {
+    __shared__ double tile[64][65];
+    const int bi = blockIdx.x * 64, bj = blockIdx.y * 64;  // tile of L: rows bi.., cols bj..
+    if (blockIdx.y > blockIdx.x) return;
+    for (int t = threadIdx.x; t < 64 * 64; t += 256) {
+        const int r = t % 64, c = t / 64;
+        const int i = bi + r, j = bj + c;
+        tile[r][c] = (i < n && j < n && i > j) ? L[(size_t)i + (size_t)j * n] : 0.0;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < 64 * 64; t += 256) {
+        const int r = t % 64, c = t / 64;  // U(bj + r, bi + c) = L(bi + c, bj + r)
+        const int i = bj + r, j = bi + c;
+        if (i < n && j < n) U[(size_t)i + (size_t)j * n] = tile[c][r];
     }
 }
 
@@ -218,6 +289,7 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
     d_.need(n);
     orig_.need(n);
     W_.need((size_t)n * NB);
+    linv_.need((size_t)NB * NB);
     ninf_.need(1);
     hipLaunchKernelGGL(dense_zero, dim3(2048), dim3(256), 0, st, total, A);
     hipLaunchKernelGGL(dense_fill, dim3(n), dim3(64), 0, st, n, S.rowptr.get(), S.col.get(),
@@ -226,17 +298,20 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
     for (int kb = 0; kb < n; kb += NB) {
         const int nb = std::min(NB, n - kb);
         hipLaunchKernelGGL(ldl_diag, dim3(1), dim3(256), 0, st, n, kb, nb, A, orig_.get(),
-                           d_.get(), pivtol, ninf_.get());
+                           d_.get(), pivtol, ninf_.get(), linv_.get());
         const int rows = n - kb - nb;
         if (rows > 0) {
-            hipLaunchKernelGGL(ldl_panel, dim3(grid_for(rows, 256)), dim3(256), 0, st, n, kb, nb,
-                               A, d_.get(), W_.get());
+            hipLaunchKernelGGL(ldl_panel, dim3(grid_for(rows, NB)), dim3(256), 0, st, n, kb, nb,
+                               A, d_.get(), W_.get(), linv_.get());
             const unsigned tiles = grid_for(rows, NB);
             hipLaunchKernelGGL(ldl_update, dim3(tiles, tiles), dim3(256), 0, st, n, kb, nb, A,
                                W_.get());
         }
     }
     OTIP_HIP(hipGetLastError());
+    U_.need(total);
+    const unsigned tl = grid_for(n, 64);
+    hipLaunchKernelGGL(transpose_lower, dim3(tl, tl), dim3(256), 0, st, n, A, U_.get());
     DBuf<unsigned long long> c;
     c.need(1);
     OTIP_HIP(hipMemsetAsync(c.get(), 0, sizeof(unsigned long long), st));
@@ -251,8 +326,22 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
 }
 
 void DenseLDL::solve(hipStream_t st, const double *b, double *x) {
-    if (x != b) OTIP_HIP(hipMemcpyAsync(x, b, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-    hipLaunchKernelGGL(ldl_solve_k, dim3(1), dim3(1024), 0, st, n, A_.get(), d_.get(), x);
+    double *w = v_.need(n);
+    double *yv = W_.get();  // n doubles of the panel buffer (free after factor)
+    OTIP_HIP(hipMemcpyAsync(w, b, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    for (int kb = 0; kb < n; kb += NB) {
+        const int nb = std::min(NB, n - kb);
+        const int rows = n - kb - nb;
+        hipLaunchKernelGGL(trsv_step, dim3(std::max(1u, grid_for(rows, 256))), dim3(256), 0, st,
+                           n, kb, nb, A_.get(), d_.get(), w, yv, 1);
+    }
+    // yv = D^-1 L^-1 b; then backward on U = L^T
+    hipLaunchKernelGGL(scale_by_pivots, dim3(grid_for(n, 256)), dim3(256), 0, st, n, d_.get(), yv);
+    for (int kb = ((n - 1) / NB) * NB; kb >= 0; kb -= NB) {
+        const int nb = std::min(NB, n - kb);
+        hipLaunchKernelGGL(trsv_step, dim3(std::max(1u, grid_for(kb, 256))), dim3(256), 0, st, n,
+                           kb, nb, U_.get(), d_.get(), yv, x, 0);
+    }
     OTIP_HIP(hipGetLastError());
 }
 

@@ -62,6 +62,7 @@ class Solver {
     SchurSolver schur;
     DenseLDL ldl;
     DBuf<char> tmp;
+    LaunchTimer t_spmv, t_price;
 
     int m = 0, n = 0;
     const int32_t *xs = nullptr, *xt = nullptr;
@@ -91,6 +92,8 @@ class Solver {
     int direct_its = 0, iterations = 0;
     int64_t pricing_passes = 0;
     double max_fill = 0.0;
+    int cg_its_last = 0;
+    int solves_last = 2;
     double t_pricing = 0, t_newton = 0, t_direct = 0, t_update = 0, t_setup = 0, t_final = 0;
 };
 

@@ -209,35 +209,56 @@ void Solver::alloc_support(int64_t cap) {
 }
 
 // ============================================================ segmented sums
+// G lanes per segment (row of the compressed-row view or column of the
+// compressed-column view), fixed-order shuffle reduction: deterministic.
+template <int G, class F>
+__global__ __launch_bounds__(256) void segsum_k(int64_t rows, F f) {
+    constexpr int groups = 256 / G;
+    const int g = threadIdx.x / G, l = threadIdx.x % G;
+    for (int64_t r = (int64_t)blockIdx.x * groups + g; r < rows;
+         r += (int64_t)gridDim.x * groups) {
+        const int b = f.begin(r), e = f.end(r);
+        double acc = 0.0;
+        for (int k = b + l; k < e; k += G) acc += f.val(r, k);
+        for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+        if (l == 0) f.finish(r, acc);
+    }
+}
+template <class F>
+static void segsum(hipStream_t st, int64_t rows, F f) {
+    if (rows <= 0) return;
+    const unsigned g = (unsigned)std::min<int64_t>(4096, (rows + 15) / 16);
+    hipLaunchKernelGGL((segsum_k<16, F>), dim3(g), dim3(256), 0, st, rows, f);
+    OTIP_HIP(hipGetLastError());
+}
+
 // out[i] = base[i] + sign * sum over row i of v (compressed-row view)
 struct FRowSum {
     const int32_t *row_ptr, *csr_pos;
     const double *v, *base;
     double *out;
     double sign;
-    __device__ void operator()(int64_t i) const {
-        double s = 0.0;
-        for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) s += v[csr_pos[e]];
-        out[i] = (base ? base[i] : 0.0) + sign * s;
-    }
+    __device__ int begin(int64_t i) const { return row_ptr[i]; }
+    __device__ int end(int64_t i) const { return row_ptr[i + 1]; }
+    __device__ double val(int64_t, int k) const { return v[csr_pos[k]]; }
+    __device__ void finish(int64_t i, double s) const { out[i] = (base ? base[i] : 0.0) + sign * s; }
 };
 struct FColSum {
     const int32_t *col_ptr;
     const double *v, *base;
     double *out;
     double sign;
-    __device__ void operator()(int64_t j) const {
-        double s = 0.0;
-        for (int e = col_ptr[j]; e < col_ptr[j + 1]; ++e) s += v[e];
-        out[j] = (base ? base[j] : 0.0) + sign * s;
-    }
+    __device__ int begin(int64_t j) const { return col_ptr[j]; }
+    __device__ int end(int64_t j) const { return col_ptr[j + 1]; }
+    __device__ double val(int64_t, int k) const { return v[k]; }
+    __device__ void finish(int64_t j, double s) const { out[j] = (base ? base[j] : 0.0) + sign * s; }
 };
 
 void Solver::rowsum(const double *v, const double *base, double *out, double sign) {
-    foreach(st, m, FRowSum{row_ptr.get(), csr_pos.get(), v, base, out, sign});
+    segsum(st, m, FRowSum{row_ptr.get(), csr_pos.get(), v, base, out, sign});
 }
 void Solver::colsum(const double *v, const double *base, double *out, double sign) {
-    foreach(st, n, FColSum{col_ptr.get(), v, base, out, sign});
+    segsum(st, n, FColSum{col_ptr.get(), v, base, out, sign});
 }
 
 // ============================================================ Newton pieces
@@ -264,25 +285,23 @@ struct FRhs {
     const int32_t *col_ptr, *si;
     const double *th, *beta1, *invM, *beta2;
     double *rhs;
-    __device__ void operator()(int64_t j) const {
-        double s = 0.0;
-        for (int e = col_ptr[j]; e < col_ptr[j + 1]; ++e) s += th[e] * (beta1[si[e]] * invM[si[e]]);
-        rhs[j] = beta2[j] - s;
-    }
+    __device__ int begin(int64_t j) const { return col_ptr[j]; }
+    __device__ int end(int64_t j) const { return col_ptr[j + 1]; }
+    __device__ double val(int64_t, int e) const { return th[e] * (beta1[si[e]] * invM[si[e]]); }
+    __device__ void finish(int64_t j, double s) const { rhs[j] = beta2[j] - s; }
 };
 // dy_i = (beta1_i - sum_{j in row i} theta_ij dz_j) / M_i
 struct FDy {
     const int32_t *row_ptr, *csr_pos, *sj;
     const double *th, *beta1, *invM, *dz;
     double *dy;
-    __device__ void operator()(int64_t i) const {
-        double s = 0.0;
-        for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
-            const int k = csr_pos[e];
-            s += th[k] * dz[sj[k]];
-        }
-        dy[i] = (beta1[i] - s) * invM[i];
+    __device__ int begin(int64_t i) const { return row_ptr[i]; }
+    __device__ int end(int64_t i) const { return row_ptr[i + 1]; }
+    __device__ double val(int64_t, int e) const {
+        const int k = csr_pos[e];
+        return th[k] * dz[sj[k]];
     }
+    __device__ void finish(int64_t i, double s) const { dy[i] = (beta1[i] - s) * invM[i]; }
 };
 // ds = r2 - (dy_i + dz_j); dp = (r3 - p ds) / s
 struct FDsDp {
@@ -306,8 +325,8 @@ void Solver::newton(const double *r1a_, const double *r1b_, const double *r2_, c
     foreach(st, psi_, FW{theta.get(), r2_, r3_, p.get(), w.get()});
     rowsum(w.get(), r1a_, beta1.get(), 1.0);
     colsum(w.get(), r1b_, beta2.get(), 1.0);
-    foreach(st, n, FRhs{col_ptr.get(), si.get(), theta.get(), beta1.get(), invM.get(),
-                        beta2.get(), rhs.get()});
+    segsum(st, n, FRhs{col_ptr.get(), si.get(), theta.get(), beta1.get(), invM.get(),
+                       beta2.get(), rhs.get()});
     if (mode == Mode::Direct) {
         ldl.solve(st, rhs.get(), out.dz.get());
         // one step of iterative refinement against S
@@ -332,8 +351,8 @@ void Solver::newton(const double *r1a_, const double *r1b_, const double *r2_, c
         max_cg_solve = std::max(max_cg_solve, cs.iterations);
         if (!cs.converged) cg_failed = true;
     }
-    foreach(st, m, FDy{row_ptr.get(), csr_pos.get(), sj.get(), theta.get(), beta1.get(),
-                       invM.get(), out.dz.get(), out.dy.get()});
+    segsum(st, m, FDy{row_ptr.get(), csr_pos.get(), sj.get(), theta.get(), beta1.get(),
+                      invM.get(), out.dz.get(), out.dy.get()});
     foreach(st, psi_, FDsDp{si.get(), sj.get(), r2_, r3_, p.get(), s.get(), out.dy.get(),
                             out.dz.get(), out.ds.get(), out.dp.get()});
 }
@@ -554,6 +573,9 @@ struct FScaleIn {
 int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
     const double T0 = now();
     P = prm;
+    t_spmv.on = t_price.on = P.profile != 0;
+    schur.timer = &t_spmv;
+    scan.timer = &t_price;
     m = pr.m;
     n = pr.n;
     xs = pr.xs;
@@ -678,13 +700,16 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
     int status = OTIP_EMAXITER;
     int it = 0;
     cg_failed = false;
-    for (it = 0; it < P.max_iter; ++it) {
+    double tol_int = P.tol;
+    for (int round = 0;; ++round) {
+    status = OTIP_EMAXITER;
+    for (; it < P.max_iter; ++it) {
         double tn = now();
         double rel1, rel2, mu, primal, r1n;
         residuals(rel1, rel2, mu, primal, r1n);
         const double relmu = (double)psi_ * mu / std::max(1.0, std::fabs(primal));
         psi_hist.push_back(psi_);
-        if (std::max(std::max(rel1, rel2), relmu) < P.tol) {
+        if (std::max(std::max(rel1, rel2), relmu) < tol_int) {
             t_newton += now() - tn;
             std::vector<double> hr(1);
             int64_t k = price(kcap, sel_idx.get(), sel_r.get(), nullptr);
@@ -709,7 +734,19 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
         // ---- switch test (Section 4.3)
         if (mode == Mode::PCG && P.linear_solver == OTIP_LS_AUTO && n <= P.dense_max_n) {
             const int wdw = P.switch_window;
-            const bool force = (P.force_switch_at >= 0 && it >= P.force_switch_at) || cg_failed;
+            // fill "allows" a factorisation once it is cheaper than the CG it
+            // replaces.  A fixed cost model (not wall time, so the switch point
+            // is reproducible): CG iteration = SpMV bytes at 3 TB/s + three
+            // launches; dense = n^3/3 flops at 3 TF/s + its block launches +
+            // two 64-column triangular sweeps per solve.
+            const double nb = (double)((n + 63) / 64);
+            const double t_cg = cg_its_last * ((12.0 * (double)schur.S.nnz + 20.0 * n) / 3e12 +
+                                               3 * 4e-6);
+            const double t_dense = (double)n * n * n / 3.0 / 3e12 + nb * 3 * 8e-6 +
+                                   solves_last * 2.0 * nb * 6e-6;
+            const bool cheaper = P.switch_cost && it >= 1 && t_dense < t_cg;
+            const bool force = (P.force_switch_at >= 0 && it >= P.force_switch_at) || cg_failed ||
+                               cheaper;
             bool drop = false;
             if ((int)psi_hist.size() > wdw) {
                 const double old = (double)psi_hist[psi_hist.size() - 1 - wdw];
@@ -718,7 +755,8 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
             if (force || drop) {
                 mode = Mode::Direct;
                 log("otip: it %d switch to the direct solver (%s)\n", it,
-                    force ? "forced/CG failure" : "support shrinking");
+                    cheaper ? "factorisation cheaper than CG"
+                            : (force ? "forced/CG failure" : "support shrinking"));
             }
         }
         // ---- Newton direction
@@ -734,6 +772,8 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
         max_cg_solve = 0;
         cg_failed = false;
         const double atol = P.cg_eta * std::max(r1n, P.cg_floor * (1.0 + fnorm));
+        const double t_solves0 = now();
+        int nsolves = 2;
         // predictor (sigma = 0)
         double *rr3 = r3.get();
         const double *pp = p.get(), *ss = s.get();
@@ -785,6 +825,7 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
             }
             const int tri = 3 - cur;  // the other of D[1], D[2]
             newton(zm.get(), zn.get(), nullptr, r3.get(), P.cg_tol_corr, atol, D[tri]);
+            ++nsolves;
             {
                 const double *dp = D[cur].dp.get(), *ds = D[cur].ds.get();
                 const double *dy = D[cur].dy.get(), *dz = D[cur].dz.get();
@@ -811,6 +852,9 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
             }
         }
         cg_total += cg_its_iter;
+        if (mode == Mode::PCG) cg_its_last = cg_its_iter;
+        (void)t_solves0;
+        solves_last = nsolves;
         const bool failed_now = cg_failed;
         // ---- update
         {
@@ -850,10 +894,20 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
             it, (long long)psi_hist.back(), rel1, rel2, relmu, ap, ad, sigma, ncorr, cg_its_iter,
             mode == Mode::Direct ? "dir" : "pcg", (long long)k, (long long)nrem);
     }
-    iterations = it + (status == OTIP_OK ? 1 : 0);
+    if (status == OTIP_OK) ++it;
     double tf = now();
     finalize(res);
     t_final += now() - tf;
+    // the certified gap decides: tighten the internal tolerance and resume
+    if (res.info.rel_gap <= P.tol || it >= P.max_iter || tol_int <= 1e-13) {
+        if (res.info.rel_gap > P.tol) status = OTIP_EMAXITER;
+        break;
+    }
+    tol_int = std::max(tol_int * 0.1, 1e-13);
+    log("otip: certified gap %.3e above tolerance; resuming with stop tolerance %.1e\n",
+        res.info.rel_gap, tol_int);
+    }
+    iterations = it;
     res.info.status = status;
     res.info.iterations = iterations;
     res.info.cg_iterations = (int32_t)cg_total;
@@ -867,6 +921,13 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
     res.info.seconds_update = t_update;
     res.info.seconds_setup = t_setup;
     res.info.seconds_final = t_final;
+    res.info.pricing_scans = scan.scans;
+    res.info.spmv_launches = t_spmv.launches;
+    res.info.spmv_ms = t_spmv.ms;
+    res.info.spmv_bytes = t_spmv.work;
+    res.info.price_launches = t_price.launches;
+    res.info.price_ms = t_price.ms;
+    res.info.price_elems = t_price.work;
     return status;
 }
 
@@ -883,7 +944,7 @@ void Solver::starting_point() {
     const bool direct = n <= P.dense_max_n;
     if (direct) ldl.factor(st, schur.S, P.pivot_tol);
     auto normal_solve = [&](const double *b1, const double *b2, double *dy, double *dz) {
-        foreach(st, n, FRhs{col_ptr.get(), si.get(), theta.get(), b1, invM.get(), b2, rhs.get()});
+        segsum(st, n, FRhs{col_ptr.get(), si.get(), theta.get(), b1, invM.get(), b2, rhs.get()});
         if (direct) {
             ldl.solve(st, rhs.get(), dz);
         } else {
@@ -894,8 +955,8 @@ void Solver::starting_point() {
             foreach(st, n, FSub{rhs.get(), mean / n});
             schur.pcg(st, rhs.get(), dz, 1e-12, 0.0 + 1e300, std::max(P.cg_max_iter, 5000));
         }
-        foreach(st, m, FDy{row_ptr.get(), csr_pos.get(), sj.get(), theta.get(), b1, invM.get(),
-                           dz, dy});
+        segsum(st, m, FDy{row_ptr.get(), csr_pos.get(), sj.get(), theta.get(), b1, invM.get(),
+                          dz, dy});
     };
     // least-norm p~ = A^T (A A^T)^-1 f
     double *wy = D[0].dy.get(), *wz = D[0].dz.get();
@@ -1013,14 +1074,6 @@ void Solver::finalize(Result &res) {
     res.z.resize(n);
     for (int i = 0; i < m; ++i) res.y[i] = hy[i] / zeta + g;
     for (int j = 0; j < n; ++j) res.z[j] = hz[j] / zeta - g;
-    double *yu = yun.need(m), *zu = zun.need(n);
-    OTIP_HIP(hipMemcpyAsync(yu, res.y.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
-    OTIP_HIP(hipMemcpyAsync(zu, res.z.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
-    double t0 = now();
-    double rmin = 0.0;
-    int64_t arg = 0;
-    scan.rmin(st, m, n, xs, xt, yu, zu, &rmin, &arg);
-    t_pricing += now() - t0;
     // compensated sums on the host
     auto ksum = [](const std::vector<double> &v) {
         double s = 0.0, c = 0.0;
@@ -1036,12 +1089,64 @@ void Solver::finalize(Result &res) {
     for (size_t k = 0; k < res.vals.size(); ++k)
         terms.push_back((double)icost(res.rows[k], res.cols[k]) * res.vals[k]);
     const double obj = ksum(terms);
-    std::vector<double> dt;
-    dt.reserve((size_t)m + n);
-    for (int i = 0; i < m; ++i) dt.push_back(ha[i] * res.y[i]);
-    for (int j = 0; j < n; ++j) dt.push_back(hb[j] * res.z[j]);
     const double suma = ksum(ha);
-    const double dual = ksum(dt) + suma * std::min(0.0, rmin);
+    double *yu = yun.need(m), *zu = zun.need(n);
+    // certified bound a.y + b.z + sum(a) min(0, min_ij r_ij) of a dual pair
+    auto bound = [&](const std::vector<double> &yy, const std::vector<double> &zz, double &rmin) {
+        OTIP_HIP(hipMemcpyAsync(yu, yy.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
+        OTIP_HIP(hipMemcpyAsync(zu, zz.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+        double t0 = now();
+        int64_t arg = 0;
+        scan.rmin(st, m, n, xs, xt, yu, zu, &rmin, &arg);
+        t_pricing += now() - t0;
+        std::vector<double> dt;
+        dt.reserve((size_t)m + n);
+        for (int i = 0; i < m; ++i) dt.push_back(ha[i] * yy[i]);
+        for (int j = 0; j < n; ++j) dt.push_back(hb[j] * zz[j]);
+        return ksum(dt) + suma * std::min(0.0, rmin);
+    };
+    double rmin = 0.0;
+    double dual = bound(res.y, res.z, rmin);
+    // duals of the basic plan: y_i + z_j = C_ij on its (forest) edges, each
+    // tree anchored at the interior-point dual of its smallest node; kept when
+    // their certificate is the stronger one
+    {
+        std::vector<std::vector<std::pair<int, int>>> adj((size_t)m + n);
+        for (size_t k = 0; k < res.vals.size(); ++k) {
+            adj[res.rows[k]].push_back({m + res.cols[k], (int)k});
+            adj[m + res.cols[k]].push_back({res.rows[k], (int)k});
+        }
+        std::vector<double> pot((size_t)m + n, 0.0);
+        std::vector<char> seen((size_t)m + n, 0);
+        for (int r = 0; r < m + n; ++r) {
+            if (seen[r]) continue;
+            seen[r] = 1;
+            pot[r] = r < m ? res.y[r] : res.z[r - m];
+            std::vector<int> stack{r};
+            while (!stack.empty()) {
+                const int u = stack.back();
+                stack.pop_back();
+                for (auto [v, k] : adj[u])
+                    if (!seen[v]) {
+                        seen[v] = 1;
+                        pot[v] = (double)icost(res.rows[k], res.cols[k]) - pot[u];
+                        stack.push_back(v);
+                    }
+            }
+        }
+        const double g2 = pot[m + n - 1];
+        std::vector<double> yb(m), zb(n);
+        for (int i = 0; i < m; ++i) yb[i] = pot[i] + g2;
+        for (int j = 0; j < n; ++j) zb[j] = pot[m + j] - g2;
+        double rmin_b = 0.0;
+        const double dual_b = bound(yb, zb, rmin_b);
+        if (dual_b > dual) {
+            dual = dual_b;
+            rmin = rmin_b;
+            res.y.swap(yb);
+            res.z.swap(zb);
+        }
+    }
     std::vector<double> rs(m, 0.0), cs(n, 0.0);
     for (size_t k = 0; k < res.vals.size(); ++k) {
         rs[res.rows[k]] += res.vals[k];

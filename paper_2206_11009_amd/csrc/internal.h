@@ -33,6 +33,8 @@ struct PriceResult {
 
 class Scanner {
   public:
+    LaunchTimer *timer = nullptr;  // pricing-pass launches (optional)
+    int64_t scans = 0;             // full m*n passes so far
     // <= kmax most negative reduced costs outside the support, ordered by
     // (r, idx); outputs may be null.
     PriceResult price(hipStream_t st, int m, int n, const int32_t *xs, const int32_t *xt,
@@ -95,6 +97,7 @@ struct CGStats {
 
 class SchurSolver {
   public:
+    LaunchTimer *timer = nullptr;  // SpMV launches inside CG (optional)
     // pattern of S_M = N - V^T M^-1 V for the support (CSC arrays by column)
     void symbolic(hipStream_t st, int m, int n, int64_t psi, const int32_t *col_ptr,
                   const int32_t *si, const int32_t *row_ptr, const int32_t *csr_pos,
@@ -127,7 +130,7 @@ class DenseLDL {
     int n = 0;
 
   private:
-    DBuf<double> A_, d_, orig_, W_, v_;
+    DBuf<double> A_, U_, d_, orig_, W_, v_, linv_;
     DBuf<int> ninf_;
     int64_t nnzL_ = 0;
 };

@@ -71,16 +71,21 @@ struct Forest {
 
 }  // namespace
 
-void purify_plan(int m, int n, const std::vector<int32_t> &rows_in,
-                 const std::vector<int32_t> &cols_in, const std::vector<double> &flows_in,
-                 const std::vector<int64_t> &costs_in, const std::vector<double> &a,
-                 const std::vector<double> &b, double drop_rel, std::vector<int32_t> &orows,
-                 std::vector<int32_t> &ocols, std::vector<double> &oflows) {
+// One purification attempt; returns true when the forest flows recomputed from
+// the marginals are nonnegative (an exactly feasible basic plan).
+static bool purify_attempt(int m, int n, const std::vector<int32_t> &rows_in,
+                           const std::vector<int32_t> &cols_in, const std::vector<double> &flows_in,
+                           const std::vector<int64_t> &costs_in, const std::vector<double> &a,
+                           const std::vector<double> &b, double drop_rel, bool predrop,
+                           std::vector<int32_t> &orows, std::vector<int32_t> &ocols,
+                           std::vector<double> &oflows) {
     std::vector<int32_t> R, C;
     std::vector<double> F;
     std::vector<int64_t> W;
+    // with predrop, numerically-zero flows leave before any cycle is cancelled
     for (size_t k = 0; k < flows_in.size(); ++k)
-        if (flows_in[k] > 0.0) {
+        if (flows_in[k] > 0.0 &&
+            (!predrop || flows_in[k] >= drop_rel * std::min(a[rows_in[k]], b[cols_in[k]]))) {
             R.push_back(rows_in[k]);
             C.push_back(cols_in[k]);
             F.push_back(flows_in[k]);
@@ -240,6 +245,19 @@ void purify_plan(int m, int n, const std::vector<int32_t> &rows_in,
         ocols.push_back(C[e]);
         oflows.push_back(f);
     }
+    return use_exact;
+}
+
+void purify_plan(int m, int n, const std::vector<int32_t> &rows_in,
+                 const std::vector<int32_t> &cols_in, const std::vector<double> &flows_in,
+                 const std::vector<int64_t> &costs_in, const std::vector<double> &a,
+                 const std::vector<double> &b, double drop_rel, std::vector<int32_t> &orows,
+                 std::vector<int32_t> &ocols, std::vector<double> &oflows) {
+    if (purify_attempt(m, n, rows_in, cols_in, flows_in, costs_in, a, b, drop_rel, true, orows,
+                       ocols, oflows))
+        return;
+    purify_attempt(m, n, rows_in, cols_in, flows_in, costs_in, a, b, drop_rel, false, orows, ocols,
+                   oflows);
 }
 
 }  // namespace otip

@@ -83,27 +83,14 @@ struct PriceArgs {
     uint64_t cap;
 };
 
-// Pricing pass.  MODE 0: histogram of one 12-bit digit of the ordered key of
-// every strictly negative reduced cost outside the support.  MODE 1: append
-// (key, idx) of those with key <= key_max.
+// the per-variable part of a pricing pass (all lanes of the wave call it)
 template <int MODE>
-__global__ __launch_bounds__(kScanBlock) void price_pass(PriceArgs a) {
-    __shared__ unsigned int lh[MODE == 0 ? kHistBins : 1];
-    const int i = blockIdx.x * kScanBlock + threadIdx.x;
-    const int j0 = blockIdx.y * a.tj;
-    const int j1 = min(a.n, j0 + a.tj);
-    if (MODE == 0) {
-        for (int t = threadIdx.x; t < kHistBins; t += kScanBlock) lh[t] = 0u;
-        __syncthreads();
-    }
-    const RowData rd = load_row(i, a.m, a.xs, a.y);
-    const int pshift = a.shift + 12;
-    const JEntry *__restrict__ jt = a.jt;
-    for (int j = j0; j < j1; ++j) {
-        const JEntry t = jt[j];
-        const double r = (cost_of(rd, t) - rd.y) - t.z;
+__device__ __forceinline__ void price_one(const PriceArgs &a, int i, int j, double r,
+                                          unsigned int *lh) {
+    {
+        const int pshift = a.shift + 12;
         const bool neg = r < 0.0;
-        if (__ballot(neg) == 0ull) continue;
+        if (__ballot(neg) == 0ull) return;
         const uint64_t idx = (uint64_t)i + (uint64_t)j * (uint64_t)a.m;
         bool take = neg && !in_support(a.bitmap, idx);
         const uint64_t key = dkey(r);
@@ -129,6 +116,43 @@ __global__ __launch_bounds__(kScanBlock) void price_pass(PriceArgs a) {
             }
         }
     }
+}
+
+// Pricing pass.  MODE 0: histogram of one 12-bit digit of the ordered key of
+// every strictly negative reduced cost outside the support.  MODE 1: append
+// (key, idx) of those with key <= key_max.
+template <int MODE>
+__global__ __launch_bounds__(kScanBlock) void price_pass(PriceArgs a) {
+    __shared__ unsigned int lh[MODE == 0 ? kHistBins : 1];
+    const int i = blockIdx.x * kScanBlock + threadIdx.x;
+    const int j0 = blockIdx.y * a.tj;
+    const int j1 = min(a.n, j0 + a.tj);
+    if (MODE == 0) {
+        for (int t = threadIdx.x; t < kHistBins; t += kScanBlock) lh[t] = 0u;
+        __syncthreads();
+    }
+    const RowData rd = load_row(i, a.m, a.xs, a.y);
+    const JEntry *__restrict__ jt = a.jt;
+    int j = j0;
+    // four targets at a time: table loads issued together, and a whole group
+    // without a negative reduced cost costs one ballot
+    for (; j + 4 <= j1; j += 4) {
+        const JEntry t0 = jt[j], t1 = jt[j + 1], t2 = jt[j + 2], t3 = jt[j + 3];
+        const double r0 = (cost_of(rd, t0) - rd.y) - t0.z;
+        const double r1 = (cost_of(rd, t1) - rd.y) - t1.z;
+        const double r2 = (cost_of(rd, t2) - rd.y) - t2.z;
+        const double r3 = (cost_of(rd, t3) - rd.y) - t3.z;
+        if (__ballot(fmin(fmin(r0, r1), fmin(r2, r3)) < 0.0) == 0ull) continue;
+        price_one<MODE>(a, i, j, r0, lh);
+        price_one<MODE>(a, i, j + 1, r1, lh);
+        price_one<MODE>(a, i, j + 2, r2, lh);
+        price_one<MODE>(a, i, j + 3, r3, lh);
+    }
+    for (; j < j1; ++j) {
+        const JEntry t = jt[j];
+        const double r = (cost_of(rd, t) - rd.y) - t.z;
+        price_one<MODE>(a, i, j, r, lh);
+    }
     if (MODE == 0) {
         __syncthreads();
         for (int t = threadIdx.x; t < kHistBins; t += kScanBlock)
@@ -149,7 +173,14 @@ __global__ void decode_selection(int64_t k, int m, const uint64_t *__restrict__ 
     if (oidx) oidx[t] = v;
 }
 
-static int pick_tj(int n) { return n >= 4096 ? 256 : (n >= 512 ? 64 : 16); }
+// targets per block: enough blocks to fill 256 CUs several times over, but
+// enough work per block to amortise the histogram's LDS setup
+static int pick_tj(int m, int n) {
+    const int64_t rb = (m + 255) / 256;
+    int tj = 256;
+    while (tj > 16 && rb * ((n + tj - 1) / tj) < 2048) tj >>= 1;
+    return tj;
+}
 
 void Scanner::prepare(hipStream_t st, int m, int n, const int32_t *xt, const double *z) {
     jt_.need((size_t)n * sizeof(JEntry));
@@ -165,7 +196,7 @@ PriceResult Scanner::price(hipStream_t st, int m, int n, const int32_t *xs, cons
     PriceResult res{0, 0, 0};
     if (m <= 0 || n <= 0) return res;
     prepare(st, m, n, xt, z);
-    const int tj = pick_tj(n);
+    const int tj = pick_tj(m, n);
     dim3 grid(grid_for(m, kScanBlock), grid_for(n, tj));
     hist_.need(kHistBins);
     cnt_.need(1);
@@ -184,12 +215,16 @@ PriceResult Scanner::price(hipStream_t st, int m, int n, const int32_t *xs, cons
         OTIP_HIP(hipMemsetAsync(hist_.get(), 0, kHistBins * sizeof(unsigned long long), st));
         a.shift = shift;
         a.prefix = prefix;
+        if (timer) timer->start(st, (double)m * (double)n);
         hipLaunchKernelGGL(price_pass<0>, grid, dim3(kScanBlock), 0, st, a);
+        if (timer) timer->stop(st);
         OTIP_HIP(hipGetLastError());
         OTIP_HIP(hipMemcpyAsync(h.data(), hist_.get(), kHistBins * sizeof(unsigned long long),
                                 hipMemcpyDeviceToHost, st));
         OTIP_HIP(hipStreamSynchronize(st));
+        if (timer) timer->collect();
         res.passes++;
+        scans++;
     };
 
     // radix select of the kmax smallest keys, 12 bits per level from the top
@@ -246,12 +281,16 @@ PriceResult Scanner::price(hipStream_t st, int m, int n, const int32_t *xs, cons
     a.out_key = ck_.get();
     a.out_idx = ci_.get();
     a.cap = cap;
+    if (timer) timer->start(st, (double)m * (double)n);
     hipLaunchKernelGGL(price_pass<1>, grid, dim3(kScanBlock), 0, st, a);
+    if (timer) timer->stop(st);
     OTIP_HIP(hipGetLastError());
     unsigned long long emitted = 0;
     OTIP_HIP(hipMemcpyAsync(&emitted, cnt_.get(), sizeof(emitted), hipMemcpyDeviceToHost, st));
     OTIP_HIP(hipStreamSynchronize(st));
+    if (timer) timer->collect();
     res.passes++;
+    scans++;
     OTIP_CHECK(emitted == cap, 5,
                "pricing: compaction count " + std::to_string(emitted) + " != histogram count " +
                    std::to_string(cap));
@@ -324,7 +363,7 @@ __global__ __launch_bounds__(kScanBlock) void rmin_pass(MinArgs a) {
 void Scanner::rmin(hipStream_t st, int m, int n, const int32_t *xs, const int32_t *xt,
                    const double *y, const double *z, double *out, int64_t *arg) {
     prepare(st, m, n, xt, z);
-    const int tj = pick_tj(n);
+    const int tj = pick_tj(m, n);
     dim3 grid(grid_for(m, kScanBlock), grid_for(n, tj));
     const size_t nb = (size_t)grid.x * grid.y;
     bmin_.need(nb);
@@ -332,6 +371,7 @@ void Scanner::rmin(hipStream_t st, int m, int n, const int32_t *xs, const int32_
     MinArgs a{m, n, tj, xs, y, (const JEntry *)jt_.get(), bmin_.get(), barg_.get()};
     hipLaunchKernelGGL(rmin_pass, grid, dim3(kScanBlock), 0, st, a);
     OTIP_HIP(hipGetLastError());
+    scans++;
     std::vector<double> v(nb);
     std::vector<uint64_t> ai(nb);
     OTIP_HIP(hipMemcpyAsync(v.data(), bmin_.get(), nb * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -486,7 +526,7 @@ int64_t Scanner::initial_support(hipStream_t st, int m, int n, const int32_t *xs
                                  DBuf<uint64_t> &out, int64_t *T_out) {
     const int64_t target = std::min<int64_t>((int64_t)std::ceil(kappa * (double)(m + n - 1)),
                                              (int64_t)m * (int64_t)n);
-    const int tj = pick_tj(n);
+    const int tj = pick_tj(m, n);
     dim3 grid(grid_for(m, kScanBlock), grid_for(n, tj));
     hist_.need(kHistBins);
     cnt_.need(1);

@@ -160,24 +160,30 @@ __global__ void schur_offdiag(int64_t nnz, const int32_t *__restrict__ srow,
     val[e] = -acc;
 }
 
-__global__ void schur_diag(int n, const int32_t *__restrict__ rowptr,
-                           const int32_t *__restrict__ diag, double *__restrict__ val,
-                           double *__restrict__ dinv) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
+// one wave per row: S_jj = -(sum of the row's off-diagonal entries)
+__global__ __launch_bounds__(256) void schur_diag(int n, const int32_t *__restrict__ rowptr,
+                                                  const int32_t *__restrict__ diag,
+                                                  double *__restrict__ val,
+                                                  double *__restrict__ dinv) {
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int l = threadIdx.x & 63;
     if (j >= n) return;
-    double s = 0.0;
     const int d = diag[j];
-    for (int e = rowptr[j]; e < rowptr[j + 1]; ++e)
+    double s = 0.0;
+    for (int e = rowptr[j] + l; e < rowptr[j + 1]; e += 64)
         if (e != d) s += val[e];
-    val[d] = -s;
-    dinv[j] = (-s > 0.0) ? 1.0 / (-s) : 0.0;
+    s = wave_sum(s);
+    if (l == 0) {
+        val[d] = -s;
+        dinv[j] = (-s > 0.0) ? 1.0 / (-s) : 0.0;
+    }
 }
 
 void SchurSolver::numeric(hipStream_t st, int m, int n, const int32_t *col_ptr,
                           const int32_t *si, const double *theta, const double *invM) {
     hipLaunchKernelGGL(schur_offdiag, dim3(grid_for(S.nnz, 256)), dim3(256), 0, st, S.nnz,
                        S.row.get(), S.col.get(), col_ptr, si, theta, invM, S.val.get());
-    hipLaunchKernelGGL(schur_diag, dim3(grid_for(n, 256)), dim3(256), 0, st, n, S.rowptr.get(),
+    hipLaunchKernelGGL(schur_diag, dim3(grid_for(n, 4)), dim3(256), 0, st, n, S.rowptr.get(),
                        S.diag.get(), S.val.get(), S.dinv.get());
     OTIP_HIP(hipGetLastError());
 }
@@ -185,6 +191,7 @@ void SchurSolver::numeric(hipStream_t st, int m, int n, const int32_t *col_ptr,
 // ---------------------------------------------------------------- SpMV + CG
 constexpr int kCGBlocks = 256;
 constexpr int kCGThreads = 256;
+constexpr int kSpmvMaxBlocks = 4096;
 
 // G lanes per row; rows distributed round-robin over a fixed grid.  If pdot,
 // partial[block] = sum over the block's rows of x_j * y_j.
@@ -215,14 +222,25 @@ __global__ __launch_bounds__(256) void spmv_rows(int n, const int32_t *__restric
     }
 }
 
+// Device-side CG scalars.  rho is double-buffered by iteration parity: the
+// direction kernel reads rho[par] in every workgroup and workgroup 0 writes
+// rho[par ^ 1] for the next iteration, so no extra launch commits it.
 struct CGScal {
-    double rho, rr, target, its;
+    double rho[2], rr, target, its;
 };
 
-__device__ __forceinline__ double sum_partials(const double *p, int nb) {
-    double s = 0.0;
-    for (int k = 0; k < nb; ++k) s += p[k];
-    return s;
+// fixed-order sum of nb per-block partials, computed by wave 0 and broadcast
+__device__ __forceinline__ double sum_partials(const double *p, int nb, double *lds) {
+    if (threadIdx.x < 64) {
+        double s = 0.0;
+        for (int k = threadIdx.x; k < nb; k += 64) s += p[k];
+        s = wave_sum(s);
+        if (threadIdx.x == 0) lds[0] = s;
+    }
+    __syncthreads();
+    const double v = lds[0];
+    __syncthreads();
+    return v;
 }
 
 __global__ __launch_bounds__(kCGThreads) void cg_init(int n, const double *__restrict__ b,
@@ -249,15 +267,20 @@ __global__ __launch_bounds__(kCGThreads) void cg_init(int n, const double *__res
     }
 }
 
-__global__ void cg_init_finish(int nb, const double *part, double rtol, double atol, CGScal *sc,
-                               int *done) {
-    double rz = sum_partials(part, nb), rr = sum_partials(part + kCGBlocks, nb);
-    double target = fmin(rtol * sqrt(rr), atol);
-    sc->rho = rz;
-    sc->rr = rr;
-    sc->target = target;
-    sc->its = 0.0;
-    *done = (sqrt(rr) <= target || rr == 0.0) ? 1 : 0;
+__global__ __launch_bounds__(64) void cg_init_finish(int nb, const double *part, double rtol,
+                                                     double atol, CGScal *sc, int *done) {
+    __shared__ double lds[2];
+    const double rz = sum_partials(part, nb, lds);
+    const double rr = sum_partials(part + kCGBlocks, nb, lds);
+    if (threadIdx.x == 0) {
+        const double target = fmin(rtol * sqrt(rr), atol);
+        sc->rho[0] = rz;
+        sc->rho[1] = 0.0;
+        sc->rr = rr;
+        sc->target = target;
+        sc->its = 0.0;
+        *done = (sqrt(rr) <= target || rr == 0.0) ? 1 : 0;
+    }
 }
 
 // alpha = rho / (p.q); x += alpha p; r -= alpha q; z = D^-1 r; partial r.z, r.r
@@ -267,15 +290,15 @@ __global__ __launch_bounds__(kCGThreads) void cg_update(int n, int nb1, const do
                                                         const double *__restrict__ dinv,
                                                         double *x, double *r, double *z,
                                                         double *part2, const CGScal *sc,
-                                                        int *done) {
+                                                        int *done, int par) {
     __shared__ double lds[16];
     if (*done) return;
-    const double pq = sum_partials(part1, nb1);
+    const double pq = sum_partials(part1, nb1, lds);
     if (!(pq > 0.0)) {  // breakdown (S is positive semidefinite)
         if (blockIdx.x == 0 && threadIdx.x == 0) *done = 2;
         return;
     }
-    const double alpha = sc->rho / pq;
+    const double alpha = sc->rho[par] / pq;
     double rz = 0.0, rr = 0.0;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
         x[j] = fma(alpha, p[j], x[j]);
@@ -297,32 +320,28 @@ __global__ __launch_bounds__(kCGThreads) void cg_update(int n, int nb1, const do
 // beta = rho_new / rho; p = z + beta p; convergence flag
 __global__ __launch_bounds__(kCGThreads) void cg_direction(int n, int nb2, const double *part2,
                                                            const double *__restrict__ z,
-                                                           double *p, CGScal *sc, int *done) {
+                                                           double *p, CGScal *sc, int *done,
+                                                           int par) {
+    __shared__ double lds[2];
     if (*done) return;
-    const double rz = sum_partials(part2, nb2), rr = sum_partials(part2 + kCGBlocks, nb2);
-    const double beta = rz / sc->rho;
+    const double rz = sum_partials(part2, nb2, lds);
+    const double rr = sum_partials(part2 + kCGBlocks, nb2, lds);
+    const double beta = rz / sc->rho[par];
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x)
         p[j] = fma(beta, p[j], z[j]);
-    __syncthreads();
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        // every block has read sc->rho before block 0 can overwrite it only if
-        // the update is deferred: keep rho_new in a separate slot
+        sc->rho[par ^ 1] = rz;
         sc->rr = rr;
         sc->its += 1.0;
         if (sqrt(rr) <= sc->target) *done = 1;
     }
 }
 
-__global__ void cg_commit_rho(int nb2, const double *part2, CGScal *sc, const int *done) {
-    if (*done == 2) return;
-    sc->rho = sum_partials(part2, nb2);
-}
-
 void SchurSolver::spmv(hipStream_t st, const double *x, double *y) {
     const int n = S.n;
     const double avg = (double)S.nnz / std::max(1, n);
     const int G = avg >= 48 ? 64 : 16;
-    const unsigned nb = std::min<unsigned>(kCGBlocks, grid_for(n, 256 / G));
+    const unsigned nb = std::min<unsigned>(kSpmvMaxBlocks, grid_for(n, 256 / G));
     if (G == 64)
         hipLaunchKernelGGL(spmv_rows<64>, dim3(nb), dim3(256), 0, st, n, S.rowptr.get(),
                            S.col.get(), S.val.get(), x, y, nullptr, nullptr);
@@ -340,48 +359,51 @@ CGStats SchurSolver::pcg(hipStream_t st, const double *b, double *x, double rtol
     z_.need(n);
     p_.need(n);
     q_.need(n);
-    part_.need(4 * kCGBlocks);
-    scal_.need(4);
+    part_.need(kSpmvMaxBlocks + 2 * kCGBlocks);
+    scal_.need(sizeof(CGScal) / sizeof(double));
     flag_.need(1);
     double *part1 = part_.get();
-    double *part2 = part_.get() + 2 * kCGBlocks;
+    double *part2 = part_.get() + kSpmvMaxBlocks;
     CGScal *sc = (CGScal *)scal_.get();
     int *done = flag_.get();
     const unsigned nbv = std::min<unsigned>(kCGBlocks, grid_for(n, kCGThreads));
     const double avg = (double)S.nnz / std::max(1, n);
     const int G = avg >= 48 ? 64 : 16;
-    const unsigned nbs = std::min<unsigned>(kCGBlocks, grid_for(n, 256 / G));
+    const unsigned nbs = std::min<unsigned>(kSpmvMaxBlocks, grid_for(n, 256 / G));
     hipLaunchKernelGGL(cg_init, dim3(nbv), dim3(kCGThreads), 0, st, n, b, S.dinv.get(), x,
                        r_.get(), z_.get(), p_.get(), part2);
-    hipLaunchKernelGGL(cg_init_finish, dim3(1), dim3(1), 0, st, (int)nbv, part2, rtol, atol, sc,
+    hipLaunchKernelGGL(cg_init_finish, dim3(1), dim3(64), 0, st, (int)nbv, part2, rtol, atol, sc,
                        done);
     OTIP_HIP(hipGetLastError());
-    int its_done = 0;
-    int chunk = 4;
+    int chunk = std::min(4, std::max(1, maxit));
+    int launched = 0;
     CGScal hs{};
     int hdone = 0;
     while (true) {
         for (int c = 0; c < chunk; ++c) {
+            const int par = launched & 1;
+            if (timer) timer->start(st, 12.0 * (double)S.nnz + 20.0 * n + 4.0);
             if (G == 64)
                 hipLaunchKernelGGL(spmv_rows<64>, dim3(nbs), dim3(256), 0, st, n, S.rowptr.get(),
                                    S.col.get(), S.val.get(), p_.get(), q_.get(), part1, done);
             else
                 hipLaunchKernelGGL(spmv_rows<16>, dim3(nbs), dim3(256), 0, st, n, S.rowptr.get(),
                                    S.col.get(), S.val.get(), p_.get(), q_.get(), part1, done);
+            if (timer) timer->stop(st);
             hipLaunchKernelGGL(cg_update, dim3(nbv), dim3(kCGThreads), 0, st, n, (int)nbs, part1,
                                p_.get(), q_.get(), S.dinv.get(), x, r_.get(), z_.get(), part2, sc,
-                               done);
+                               done, par);
             hipLaunchKernelGGL(cg_direction, dim3(nbv), dim3(kCGThreads), 0, st, n, (int)nbv,
-                               part2, z_.get(), p_.get(), sc, done);
-            hipLaunchKernelGGL(cg_commit_rho, dim3(1), dim3(1), 0, st, (int)nbv, part2, sc, done);
+                               part2, z_.get(), p_.get(), sc, done, par);
+            ++launched;
         }
         OTIP_HIP(hipGetLastError());
-        its_done += chunk;
         OTIP_HIP(hipMemcpyAsync(&hs, sc, sizeof(CGScal), hipMemcpyDeviceToHost, st));
         OTIP_HIP(hipMemcpyAsync(&hdone, done, sizeof(int), hipMemcpyDeviceToHost, st));
         OTIP_HIP(hipStreamSynchronize(st));
-        if (hdone || (int)hs.its >= maxit) break;
-        chunk = std::min(std::min(chunk * 2, 64), maxit - (int)hs.its);
+        if (timer) timer->collect();
+        if (hdone || launched >= maxit) break;
+        chunk = std::min(std::min(chunk * 2, 64), maxit - launched);
         if (chunk <= 0) break;
     }
     out.iterations = (int)hs.its;

@@ -53,3 +53,43 @@ def test_uniform_vs_enumeration(ctx):
     res = otip.otip_solve(ctx, a, a.copy(), xs, xt)
     assert abs(res.objective - best / n) <= 1e-9 * max(1.0, best / n)
     check_result(res, a, a, xs, xt)
+
+
+@pytest.mark.parametrize("mode", ["paper_switch", "direct_only"])
+@pytest.mark.parametrize("k", [0, 3, 6])
+def test_solver_modes_16x16(ctx, k, mode):
+    """The CG -> LDL^T switch by the support-drop rule alone (Section 4.3), and
+    the direct solver throughout, reach the same certified optimum."""
+    import paper_2206_11009_amd as otip
+    inst = config_instance("c1", k)
+    if mode == "paper_switch":
+        prm = otip.params(switch_cost=0)
+    else:
+        prm = otip.params(linear_solver=otip.OTIP_LS_DIRECT)
+    res = otip.otip_solve(ctx, inst.a, inst.b, inst.xs, inst.xt, prm)
+    check_result(res, inst.a, inst.b, inst.xs, inst.xt)
+    if mode == "paper_switch":
+        assert res.cg_iterations > 0
+    golden = {r["seed"]: r for r in load_golden("c1")}
+    ref = golden[k]["objective"]
+    assert abs(res.objective - ref) <= 1e-6 * abs(ref)
+
+
+def load_golden(cfg):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"oracle_{cfg}.json")
+    with open(path) as f:
+        return json.load(f)["results"]
+
+
+@pytest.mark.parametrize("k", range(5))
+def test_gaussian_64x64_matches_stored_oracle(ctx, k):
+    """64x64 grids (16.8M variables): objective within 1e-6 of the oracle's
+    stored optimum, certified gap and marginals, basic plan."""
+    import paper_2206_11009_amd as otip
+    inst = config_instance("c2", k)
+    res = otip.otip_solve(ctx, inst.a, inst.b, inst.xs, inst.xt)
+    check_result(res, inst.a, inst.b, inst.xs, inst.xt)
+    ref = {r["seed"]: r for r in load_golden("c2")}[k]["objective"]
+    assert abs(res.objective - ref) <= 1e-6 * abs(ref)
