@@ -346,7 +346,9 @@ void Solver::newton(const double *r1a_, const double *r1b_, const double *r2_, c
         reduce_sum<1>(st, red, n, [=] __device__(int64_t j, double *acc) { acc[0] += rp[j]; },
                       &mean);
         foreach(st, n, FSub{rhs.get(), mean / n});
-        CGStats cs = schur.pcg(st, rhs.get(), out.dz.get(), rtol, atol, P.cg_max_iter);
+        CGStats cs = (P.precision == OTIP_MIXED)
+                         ? schur.pcg_mixed(st, rhs.get(), out.dz.get(), rtol, atol, P.cg_max_iter)
+                         : schur.pcg(st, rhs.get(), out.dz.get(), rtol, atol, P.cg_max_iter);
         cg_its_iter += cs.iterations;
         max_cg_solve = std::max(max_cg_solve, cs.iterations);
         if (!cs.converged) cg_failed = true;

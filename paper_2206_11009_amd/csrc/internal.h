@@ -110,13 +110,20 @@ class SchurSolver {
     void spmv(hipStream_t st, const double *x, double *y);
     // Jacobi-preconditioned CG on S x = b (b projected on e-perp by the caller)
     CGStats pcg(hipStream_t st, const double *b, double *x, double rtol, double atol, int maxit);
+    // the same in FP32 inside FP64 iterative refinement
+    CGStats pcg_mixed(hipStream_t st, const double *b, double *x, double rtol, double atol,
+                      int maxit);
     SchurCSR S;
 
   private:
+    template <typename T>
+    CGStats pcg_impl(hipStream_t st, const T *val, const T *dinv, const T *b, T *x, double rtol,
+                     double atol, int maxit, DBuf<T> &r, DBuf<T> &z, DBuf<T> &p, DBuf<T> &q);
     DBuf<int32_t> cnt_;
     DBuf<char> tmp_;
     DBuf<int64_t> off64_, cnt64_;
-    DBuf<double> r_, z_, p_, q_, part_, scal_;
+    DBuf<double> r_, z_, p_, q_, part_, scal_, rd_, sx_, rpart_;
+    DBuf<float> val32_, dinv32_, rf_, df_, rf2_, zf_, pf_, qf_;
     DBuf<int> flag_;
 };
 

@@ -601,10 +601,306 @@ int64_t Scanner::initial_support(hipStream_t st, int m, int n, const int32_t *xs
 }  // namespace otip
 
 namespace otip {
+
+// ------------------------------------------------------------ mixed precision
+// FP32 pricing with an FP64 re-check.  Costs are exact in FP32 when every
+// intermediate of |x_i|^2 + |x_j|^2 - 2 x_i.x_j stays below 2^24.  With
+// y32 = fl32(y), z32 = fl32(z) and two FP32 subtractions, the FP32 reduced cost
+// differs from the exact one by at most 3 u32 (C + Y + Z) (u32 = 2^-24, C, Y, Z
+// bounds on |C_ij|, |y|, |z|), and the FP64 one by at most 2 u64 (C + Y + Z);
+// margin = 8 u32 (C + Y + Z) covers twice their sum.  Hence
+//   r32 < -margin  =>  r64 < 0 (certainly negative);
+//   an entry of the FP64 top-k has r32 <= tau32 + 2 margin, tau32 the k-th
+//   smallest FP32 value among r32 < margin.
+// Every candidate with r32 <= min(margin, tau32 + 2 margin), and every entry of
+// the band -margin <= r32 < margin (for the exact negative count), is
+// re-evaluated in FP64 exactly as the FP64 scan does; the selection is then
+// identical to the FP64 one.
+struct __align__(16) JEntry32 {
+    float B, a2, b2, z;
+};
+
+__global__ void build_jtab32(int n, const int32_t *__restrict__ xt, const double *__restrict__ z,
+                             JEntry32 *__restrict__ jt) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    float a = (float)xt[2 * j], b = (float)xt[2 * j + 1];
+    JEntry32 e;
+    e.B = a * a + b * b;
+    e.a2 = -2.0f * a;
+    e.b2 = -2.0f * b;
+    e.z = (float)z[j];
+    jt[j] = e;
+}
+
+__device__ __forceinline__ uint32_t fkey(float r) {
+    uint32_t u = __float_as_uint(r);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+struct Price32Args {
+    int m, n, tj;
+    const int32_t *xs;
+    const double *y;
+    const JEntry32 *jt;
+    const uint32_t *bitmap;
+    float margin;
+    int shift;          // histogram digit (key >> shift) & 4095, keys r32 < margin
+    uint32_t prefix;    // bits above shift + 12 (no filter when shift + 12 >= 32)
+    unsigned long long *hist, *certain, *band;
+    float t32;          // compaction: r32 <= t32, or -margin <= r32 < margin
+    unsigned long long *count;
+    uint64_t *out_idx;
+    uint64_t cap;
+};
+
+template <int MODE>
+__global__ __launch_bounds__(kScanBlock) void price32_pass(Price32Args a) {
+    __shared__ unsigned int lh[MODE == 0 ? kHistBins : 1];
+    __shared__ unsigned int lc[2];
+    const int i = blockIdx.x * kScanBlock + threadIdx.x;
+    const int j0 = blockIdx.y * a.tj, j1 = min(a.n, j0 + a.tj);
+    if (MODE == 0) {
+        for (int t = threadIdx.x; t < kHistBins; t += kScanBlock) lh[t] = 0u;
+        if (threadIdx.x < 2) lc[threadIdx.x] = 0u;
+        __syncthreads();
+    }
+    float A = 0.f, al = 0.f, be = 0.f, yv = -INFINITY;
+    if (i < a.m) {
+        al = (float)a.xs[2 * i];
+        be = (float)a.xs[2 * i + 1];
+        A = al * al + be * be;
+        yv = (float)a.y[i];
+    }
+    const float mg = a.margin;
+    const int pshift = a.shift + 12;
+    unsigned int ncert = 0, nband = 0;
+    for (int j = j0; j < j1; ++j) {
+        const JEntry32 t = a.jt[j];
+        const float c = fmaf(be, t.b2, fmaf(al, t.a2, A + t.B));
+        const float r = (c - yv) - t.z;
+        const bool lo = r < mg;
+        if (__ballot(lo) == 0ull) continue;
+        const uint64_t idx = (uint64_t)i + (uint64_t)j * (uint64_t)a.m;
+        bool take = lo && !in_support(a.bitmap, idx);
+        if (MODE == 0) {
+            if (take) {
+                if (r < -mg)
+                    ++ncert;
+                else
+                    ++nband;
+                const uint32_t key = fkey(r);
+                if (pshift >= 32 || (key >> pshift) == a.prefix)
+                    atomicAdd(&lh[(key >> a.shift) & 4095u], 1u);
+            }
+        } else {
+            take = take && (r <= a.t32 || r >= -mg);
+            const uint64_t mask = __ballot(take);
+            if (mask) {
+                const int lane = threadIdx.x & 63;
+                const int leader = __ffsll((long long)mask) - 1;
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd(a.count, (unsigned long long)__popcll(mask));
+                base = __shfl(base, leader, 64);
+                if (take) {
+                    const uint64_t pos = base + __popcll(mask & ((1ull << lane) - 1ull));
+                    if (pos < a.cap) a.out_idx[pos] = idx;
+                }
+            }
+        }
+    }
+    if (MODE == 0) {
+        if (ncert) atomicAdd(&lc[0], ncert);
+        if (nband) atomicAdd(&lc[1], nband);
+        __syncthreads();
+        for (int t = threadIdx.x; t < kHistBins; t += kScanBlock)
+            if (lh[t]) atomicAdd(&a.hist[t], (unsigned long long)lh[t]);
+        if (threadIdx.x == 0) {
+            if (lc[0]) atomicAdd(a.certain, (unsigned long long)lc[0]);
+            if (lc[1]) atomicAdd(a.band, (unsigned long long)lc[1]);
+        }
+    }
+}
+
+// FP64 re-evaluation of the compacted candidates, exactly as the FP64 scan;
+// negative ones get their ordered key, others the key ~0 (sorted last).
+__global__ void recheck64(int64_t k, int m, const uint64_t *__restrict__ idx,
+                          const int32_t *__restrict__ xs, const int32_t *__restrict__ xt,
+                          const double *__restrict__ y, const double *__restrict__ z,
+                          float margin, uint64_t *__restrict__ key,
+                          unsigned long long *band_neg) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= k) return;
+    const uint64_t v = idx[t];
+    const int i = (int)(v % (uint64_t)m), j = (int)(v / (uint64_t)m);
+    const double al = (double)xs[2 * i], be = (double)xs[2 * i + 1];
+    const double aj = (double)xt[2 * j], bj = (double)xt[2 * j + 1];
+    const double c = fma(be, -2.0 * bj, fma(al, -2.0 * aj, (al * al + be * be) + (aj * aj + bj * bj)));
+    const double r = (c - y[i]) - z[j];
+    key[t] = r < 0.0 ? dkey(r) : ~0ull;
+    // the same FP32 value as the scan, to recognise the band
+    const float af = (float)al, bf = (float)be, ajf = (float)aj, bjf = (float)bj;
+    const float c32 = fmaf(bf, -2.0f * bjf, fmaf(af, -2.0f * ajf, (af * af + bf * bf) + (ajf * ajf + bjf * bjf)));
+    const float r32 = (c32 - (float)y[i]) - (float)z[j];
+    if (r32 >= -margin && r32 < margin && r < 0.0) atomicAdd(band_neg, 1ull);
+}
+
+__global__ void maxabs4(int m, int n, const int32_t *xs, const int32_t *xt, const double *y,
+                        const double *z, double *out) {
+    __shared__ double sm[4][16];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int t = threadIdx.x; t < 2 * m; t += blockDim.x) v[0] = fmax(v[0], fabs((double)xs[t]));
+    for (int t = threadIdx.x; t < 2 * n; t += blockDim.x) v[1] = fmax(v[1], fabs((double)xt[t]));
+    for (int t = threadIdx.x; t < m; t += blockDim.x) v[2] = fmax(v[2], fabs(y[t]));
+    for (int t = threadIdx.x; t < n; t += blockDim.x) v[3] = fmax(v[3], fabs(z[t]));
+    for (int q = 0; q < 4; ++q) {
+        double w = v[q];
+        for (int o = 32; o > 0; o >>= 1) w = fmax(w, __shfl_xor(w, o, 64));
+        if ((threadIdx.x & 63) == 0) sm[q][threadIdx.x >> 6] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double w = 0.0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) w = fmax(w, sm[threadIdx.x][k]);
+        out[threadIdx.x] = w;
+    }
+}
+
 PriceResult Scanner::price_mixed(hipStream_t st, int m, int n, const int32_t *xs,
                                  const int32_t *xt, const double *y, const double *z,
                                  const uint32_t *bitmap, int64_t kmax, int32_t *oi, int32_t *oj,
                                  double *orr, uint64_t *oidx) {
-    throw Error(6, "mixed-precision pricing is not built yet");
+    PriceResult res{0, 0, 0};
+    if (m <= 0 || n <= 0) return res;
+    // bounds for the margin and the exactness of FP32 costs
+    DBuf<double> &mx = bmin_;
+    mx.need(4);
+    hipLaunchKernelGGL(maxabs4, dim3(1), dim3(1024), 0, st, m, n, xs, xt, y, z, mx.get());
+    double h4[4];
+    OTIP_HIP(hipMemcpyAsync(h4, mx.get(), sizeof(h4), hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipStreamSynchronize(st));
+    const double X = h4[0], Xt = h4[1];
+    const double Cbound = 2.0 * (X + Xt) * (X + Xt);
+    const double inter = 2.0 * X * X + 2.0 * Xt * Xt + 4.0 * X * Xt;
+    if (!(inter < 16777216.0))  // FP32 costs would not be exact: FP64 scan (same result)
+        return price(st, m, n, xs, xt, y, z, bitmap, kmax, oi, oj, orr, oidx);
+    const double margin = 8.0 * std::ldexp(1.0, -24) * (Cbound + h4[2] + h4[3]);
+    const float mg = (float)margin;
+
+    jt_.need((size_t)n * sizeof(JEntry32));
+    hipLaunchKernelGGL(build_jtab32, dim3(grid_for(n, 256)), dim3(256), 0, st, n, xt, z,
+                       (JEntry32 *)jt_.get());
+    const int tj = pick_tj(m, n);
+    dim3 grid(grid_for(m, kScanBlock), grid_for(n, tj));
+    hist_.need(kHistBins + 3);
+    cnt_.need(2);
+    Price32Args a{};
+    a.m = m;
+    a.n = n;
+    a.tj = tj;
+    a.xs = xs;
+    a.y = y;
+    a.jt = (const JEntry32 *)jt_.get();
+    a.bitmap = bitmap;
+    a.margin = mg;
+    a.hist = hist_.get();
+    a.certain = hist_.get() + kHistBins;
+    a.band = hist_.get() + kHistBins + 1;
+    std::vector<unsigned long long> h(kHistBins + 2);
+    auto histogram = [&](int shift, uint32_t prefix) {
+        OTIP_HIP(hipMemsetAsync(hist_.get(), 0, (kHistBins + 2) * sizeof(unsigned long long), st));
+        a.shift = shift;
+        a.prefix = prefix;
+        if (timer) timer->start(st, (double)m * (double)n);
+        hipLaunchKernelGGL(price32_pass<0>, grid, dim3(kScanBlock), 0, st, a);
+        if (timer) timer->stop(st);
+        OTIP_HIP(hipGetLastError());
+        OTIP_HIP(hipMemcpyAsync(h.data(), hist_.get(), (kHistBins + 2) * sizeof(unsigned long long),
+                                hipMemcpyDeviceToHost, st));
+        OTIP_HIP(hipStreamSynchronize(st));
+        if (timer) timer->collect();
+        res.passes++;
+        scans++;
+    };
+    histogram(20, 0);
+    const uint64_t certain = h[kHistBins], band = h[kHistBins + 1];
+    const uint64_t total32 = certain + band;
+    // threshold of the FP64 candidates
+    float t32 = mg;
+    if (kmax > 0 && total32 > (uint64_t)kmax) {
+        // two 12-bit levels resolve the top 24 key bits; tau32 is taken as the
+        // largest value of the selected bucket (an upper bound: a larger
+        // threshold only adds candidates to the FP64 re-check)
+        uint64_t need = (uint64_t)kmax;
+        uint32_t prefix = 0;
+        int shift = 20;
+        for (;;) {
+            uint64_t cum = 0;
+            int b = 0;
+            for (; b < kHistBins; ++b) {
+                if (cum + h[b] >= need) break;
+                cum += h[b];
+            }
+            OTIP_CHECK(b < kHistBins, 5, "mixed pricing: histogram inconsistent");
+            need -= cum;
+            prefix = (prefix << 12) | (uint32_t)b;
+            if (shift == 8 || h[b] <= 1) {
+                const uint32_t kmaxkey = ((prefix + 1u) << shift) - 1u;
+                const uint32_t u = (kmaxkey & 0x80000000u) ? (kmaxkey & 0x7fffffffu) : ~kmaxkey;
+                const float tau = __builtin_bit_cast(float, u);
+                t32 = std::min(mg, (float)((double)tau + 2.0 * margin));
+                break;
+            }
+            shift = 8;
+            histogram(shift, prefix);
+        }
+    }
+    // compaction of the candidates and of the uncertain band
+    uint64_t cap = std::max<uint64_t>((uint64_t)std::max<int64_t>(kmax, 0) + band + 1024, 1 << 16);
+    OTIP_HIP(hipMemsetAsync(cnt_.get(), 0, sizeof(unsigned long long), st));
+    unsigned long long emitted = 0;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        ci_.need(cap);
+        OTIP_HIP(hipMemsetAsync(cnt_.get(), 0, sizeof(unsigned long long), st));
+        a.t32 = t32;
+        a.count = cnt_.get();
+        a.out_idx = ci_.get();
+        a.cap = cap;
+        if (timer) timer->start(st, (double)m * (double)n);
+        hipLaunchKernelGGL(price32_pass<1>, grid, dim3(kScanBlock), 0, st, a);
+        if (timer) timer->stop(st);
+        OTIP_HIP(hipGetLastError());
+        OTIP_HIP(hipMemcpyAsync(&emitted, cnt_.get(), sizeof(emitted), hipMemcpyDeviceToHost, st));
+        OTIP_HIP(hipStreamSynchronize(st));
+        if (timer) timer->collect();
+        res.passes++;
+        scans++;
+        if (emitted <= cap) break;
+        cap = emitted + 1024;
+    }
+    OTIP_CHECK(emitted <= cap, 5, "mixed pricing: compaction overflow");
+    const int64_t E = (int64_t)emitted;
+    ck_.need(std::max<int64_t>(E, 1));
+    unsigned long long *bneg = cnt_.get() + 1;
+    OTIP_HIP(hipMemsetAsync(bneg, 0, sizeof(unsigned long long), st));
+    if (E > 0)
+        hipLaunchKernelGGL(recheck64, dim3(grid_for(E, 256)), dim3(256), 0, st, E, m, ci_.get(), xs,
+                           xt, y, z, mg, ck_.get(), bneg);
+    unsigned long long hb = 0;
+    OTIP_HIP(hipMemcpyAsync(&hb, bneg, sizeof(hb), hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipStreamSynchronize(st));
+    res.nneg = (int64_t)(certain + hb);
+    if (kmax <= 0 || E == 0) return res;
+    ck2_.need(E);
+    ci2_.need(E);
+    sort_pairs_u64(st, ci_.get(), ck_.get(), ci2_.get(), ck2_.get(), E, 0, 64, tmp_);
+    sort_pairs_u64(st, ck2_.get(), ci2_.get(), ck_.get(), ci_.get(), E, 0, 64, tmp_);
+    const int64_t k = std::min<int64_t>(kmax, res.nneg);
+    hipLaunchKernelGGL(decode_selection, dim3(grid_for(std::max<int64_t>(k, 1), 256)), dim3(256), 0,
+                       st, k, m, ck_.get(), ci_.get(), oi, oj, orr, oidx);
+    OTIP_HIP(hipGetLastError());
+    res.count = k;
+    return res;
 }
+
 }  // namespace otip

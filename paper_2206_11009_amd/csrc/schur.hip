@@ -193,27 +193,28 @@ constexpr int kCGBlocks = 256;
 constexpr int kCGThreads = 256;
 constexpr int kSpmvMaxBlocks = 4096;
 
-// G lanes per row; rows distributed round-robin over a fixed grid.  If pdot,
-// partial[block] = sum over the block's rows of x_j * y_j.
-template <int G>
+// G lanes per row; rows distributed round-robin over a fixed grid.  If
+// partial, partial[block] = sum over the block's rows of x_j * y_j (in FP64).
+// T is the storage type of the values and vectors (double, or float for the
+// inner solves of the mixed-precision mode).
+template <int G, typename T>
 __global__ __launch_bounds__(256) void spmv_rows(int n, const int32_t *__restrict__ rowptr,
                                                  const int32_t *__restrict__ col,
-                                                 const double *__restrict__ val,
-                                                 const double *__restrict__ x,
-                                                 double *__restrict__ y, double *partial,
-                                                 const int *done) {
+                                                 const T *__restrict__ val,
+                                                 const T *__restrict__ x, T *__restrict__ y,
+                                                 double *partial, const int *done) {
     __shared__ double lds[16];
     if (done && *done) return;
     const int groups = 256 / G;
     const int g = threadIdx.x / G, l = threadIdx.x % G;
     double dot = 0.0;
     for (int r = blockIdx.x * groups + g; r < n; r += gridDim.x * groups) {
-        double acc = 0.0;
+        T acc = (T)0;
         for (int e = rowptr[r] + l; e < rowptr[r + 1]; e += G) acc = fma(val[e], x[col[e]], acc);
         for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
         if (l == 0) {
             y[r] = acc;
-            dot = fma(x[r], acc, dot);
+            dot = fma((double)x[r], (double)acc, dot);
         }
     }
     if (partial) {
@@ -243,21 +244,21 @@ __device__ __forceinline__ double sum_partials(const double *p, int nb, double *
     return v;
 }
 
-__global__ __launch_bounds__(kCGThreads) void cg_init(int n, const double *__restrict__ b,
-                                                      const double *__restrict__ dinv, double *x,
-                                                      double *r, double *z, double *p,
-                                                      double *part) {
+template <typename T>
+__global__ __launch_bounds__(kCGThreads) void cg_init(int n, const T *__restrict__ b,
+                                                      const T *__restrict__ dinv, T *x, T *r,
+                                                      T *z, T *p, double *part) {
     __shared__ double lds[16];
     double rz = 0.0, rr = 0.0;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
-        const double bj = b[j];
-        const double zj = dinv[j] * bj;
-        x[j] = 0.0;
+        const T bj = b[j];
+        const T zj = dinv[j] * bj;
+        x[j] = (T)0;
         r[j] = bj;
         z[j] = zj;
         p[j] = zj;
-        rz = fma(bj, zj, rz);
-        rr = fma(bj, bj, rr);
+        rz = fma((double)bj, (double)zj, rz);
+        rr = fma((double)bj, (double)bj, rr);
     }
     double t1 = block_sum(rz, lds);
     double t2 = block_sum(rr, lds);
@@ -284,12 +285,12 @@ __global__ __launch_bounds__(64) void cg_init_finish(int nb, const double *part,
 }
 
 // alpha = rho / (p.q); x += alpha p; r -= alpha q; z = D^-1 r; partial r.z, r.r
+template <typename T>
 __global__ __launch_bounds__(kCGThreads) void cg_update(int n, int nb1, const double *part1,
-                                                        const double *__restrict__ p,
-                                                        const double *__restrict__ q,
-                                                        const double *__restrict__ dinv,
-                                                        double *x, double *r, double *z,
-                                                        double *part2, const CGScal *sc,
+                                                        const T *__restrict__ p,
+                                                        const T *__restrict__ q,
+                                                        const T *__restrict__ dinv, T *x, T *r,
+                                                        T *z, double *part2, const CGScal *sc,
                                                         int *done, int par) {
     __shared__ double lds[16];
     if (*done) return;
@@ -298,16 +299,16 @@ __global__ __launch_bounds__(kCGThreads) void cg_update(int n, int nb1, const do
         if (blockIdx.x == 0 && threadIdx.x == 0) *done = 2;
         return;
     }
-    const double alpha = sc->rho[par] / pq;
+    const T alpha = (T)(sc->rho[par] / pq);
     double rz = 0.0, rr = 0.0;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
         x[j] = fma(alpha, p[j], x[j]);
-        const double rj = fma(-alpha, q[j], r[j]);
+        const T rj = fma(-alpha, q[j], r[j]);
         r[j] = rj;
-        const double zj = dinv[j] * rj;
+        const T zj = dinv[j] * rj;
         z[j] = zj;
-        rz = fma(rj, zj, rz);
-        rr = fma(rj, rj, rr);
+        rz = fma((double)rj, (double)zj, rz);
+        rr = fma((double)rj, (double)rj, rr);
     }
     double t1 = block_sum(rz, lds);
     double t2 = block_sum(rr, lds);
@@ -318,15 +319,15 @@ __global__ __launch_bounds__(kCGThreads) void cg_update(int n, int nb1, const do
 }
 
 // beta = rho_new / rho; p = z + beta p; convergence flag
+template <typename T>
 __global__ __launch_bounds__(kCGThreads) void cg_direction(int n, int nb2, const double *part2,
-                                                           const double *__restrict__ z,
-                                                           double *p, CGScal *sc, int *done,
-                                                           int par) {
+                                                           const T *__restrict__ z, T *p,
+                                                           CGScal *sc, int *done, int par) {
     __shared__ double lds[2];
     if (*done) return;
     const double rz = sum_partials(part2, nb2, lds);
     const double rr = sum_partials(part2 + kCGBlocks, nb2, lds);
-    const double beta = rz / sc->rho[par];
+    const T beta = (T)(rz / sc->rho[par]);
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x)
         p[j] = fma(beta, p[j], z[j]);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -337,22 +338,33 @@ __global__ __launch_bounds__(kCGThreads) void cg_direction(int n, int nb2, const
     }
 }
 
-void SchurSolver::spmv(hipStream_t st, const double *x, double *y) {
+template <typename T>
+static void launch_spmv(hipStream_t st, const SchurCSR &S, const T *val, const T *x, T *y,
+                        double *partial, const int *done, unsigned &nb_out) {
     const int n = S.n;
     const double avg = (double)S.nnz / std::max(1, n);
     const int G = avg >= 48 ? 64 : 16;
     const unsigned nb = std::min<unsigned>(kSpmvMaxBlocks, grid_for(n, 256 / G));
+    nb_out = nb;
     if (G == 64)
-        hipLaunchKernelGGL(spmv_rows<64>, dim3(nb), dim3(256), 0, st, n, S.rowptr.get(),
-                           S.col.get(), S.val.get(), x, y, nullptr, nullptr);
+        hipLaunchKernelGGL((spmv_rows<64, T>), dim3(nb), dim3(256), 0, st, n, S.rowptr.get(),
+                           S.col.get(), val, x, y, partial, done);
     else
-        hipLaunchKernelGGL(spmv_rows<16>, dim3(nb), dim3(256), 0, st, n, S.rowptr.get(),
-                           S.col.get(), S.val.get(), x, y, nullptr, nullptr);
+        hipLaunchKernelGGL((spmv_rows<16, T>), dim3(nb), dim3(256), 0, st, n, S.rowptr.get(),
+                           S.col.get(), val, x, y, partial, done);
+}
+
+void SchurSolver::spmv(hipStream_t st, const double *x, double *y) {
+    unsigned nb;
+    launch_spmv<double>(st, S, S.val.get(), x, y, nullptr, nullptr, nb);
     OTIP_HIP(hipGetLastError());
 }
 
-CGStats SchurSolver::pcg(hipStream_t st, const double *b, double *x, double rtol, double atol,
-                         int maxit) {
+// Jacobi-preconditioned CG in storage type T on S x = b.
+template <typename T>
+CGStats SchurSolver::pcg_impl(hipStream_t st, const T *val, const T *dinv, const T *b, T *x,
+                              double rtol, double atol, int maxit, DBuf<T> &r_, DBuf<T> &z_,
+                              DBuf<T> &p_, DBuf<T> &q_) {
     const int n = S.n;
     CGStats out;
     r_.need(n);
@@ -367,11 +379,8 @@ CGStats SchurSolver::pcg(hipStream_t st, const double *b, double *x, double rtol
     CGScal *sc = (CGScal *)scal_.get();
     int *done = flag_.get();
     const unsigned nbv = std::min<unsigned>(kCGBlocks, grid_for(n, kCGThreads));
-    const double avg = (double)S.nnz / std::max(1, n);
-    const int G = avg >= 48 ? 64 : 16;
-    const unsigned nbs = std::min<unsigned>(kSpmvMaxBlocks, grid_for(n, 256 / G));
-    hipLaunchKernelGGL(cg_init, dim3(nbv), dim3(kCGThreads), 0, st, n, b, S.dinv.get(), x,
-                       r_.get(), z_.get(), p_.get(), part2);
+    hipLaunchKernelGGL((cg_init<T>), dim3(nbv), dim3(kCGThreads), 0, st, n, b, dinv, x, r_.get(),
+                       z_.get(), p_.get(), part2);
     hipLaunchKernelGGL(cg_init_finish, dim3(1), dim3(64), 0, st, (int)nbv, part2, rtol, atol, sc,
                        done);
     OTIP_HIP(hipGetLastError());
@@ -379,21 +388,18 @@ CGStats SchurSolver::pcg(hipStream_t st, const double *b, double *x, double rtol
     int launched = 0;
     CGScal hs{};
     int hdone = 0;
+    const double bytes = (2.0 * sizeof(T) + 4.0) * (double)S.nnz + (16.0 + 4.0) * n + 4.0;
     while (true) {
         for (int c = 0; c < chunk; ++c) {
             const int par = launched & 1;
-            if (timer) timer->start(st, 12.0 * (double)S.nnz + 20.0 * n + 4.0);
-            if (G == 64)
-                hipLaunchKernelGGL(spmv_rows<64>, dim3(nbs), dim3(256), 0, st, n, S.rowptr.get(),
-                                   S.col.get(), S.val.get(), p_.get(), q_.get(), part1, done);
-            else
-                hipLaunchKernelGGL(spmv_rows<16>, dim3(nbs), dim3(256), 0, st, n, S.rowptr.get(),
-                                   S.col.get(), S.val.get(), p_.get(), q_.get(), part1, done);
+            unsigned nbs;
+            if (timer) timer->start(st, sizeof(T) == 8 ? 12.0 * (double)S.nnz + 20.0 * n + 4.0 : bytes);
+            launch_spmv<T>(st, S, val, p_.get(), q_.get(), part1, done, nbs);
             if (timer) timer->stop(st);
-            hipLaunchKernelGGL(cg_update, dim3(nbv), dim3(kCGThreads), 0, st, n, (int)nbs, part1,
-                               p_.get(), q_.get(), S.dinv.get(), x, r_.get(), z_.get(), part2, sc,
+            hipLaunchKernelGGL((cg_update<T>), dim3(nbv), dim3(kCGThreads), 0, st, n, (int)nbs,
+                               part1, p_.get(), q_.get(), dinv, x, r_.get(), z_.get(), part2, sc,
                                done, par);
-            hipLaunchKernelGGL(cg_direction, dim3(nbv), dim3(kCGThreads), 0, st, n, (int)nbv,
+            hipLaunchKernelGGL((cg_direction<T>), dim3(nbv), dim3(kCGThreads), 0, st, n, (int)nbv,
                                part2, z_.get(), p_.get(), sc, done, par);
             ++launched;
         }
@@ -409,6 +415,79 @@ CGStats SchurSolver::pcg(hipStream_t st, const double *b, double *x, double rtol
     out.iterations = (int)hs.its;
     out.res_norm = std::sqrt(std::max(0.0, hs.rr));
     out.converged = (hdone == 1);
+    return out;
+}
+
+CGStats SchurSolver::pcg(hipStream_t st, const double *b, double *x, double rtol, double atol,
+                         int maxit) {
+    return pcg_impl<double>(st, S.val.get(), S.dinv.get(), b, x, rtol, atol, maxit, r_, z_, p_, q_);
+}
+
+__global__ void to_f32(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x)
+        b[t] = (float)a[t];
+}
+__global__ void resid64(int n, const double *__restrict__ b, const double *__restrict__ Sx,
+                        double *__restrict__ r, float *__restrict__ r32, double *part) {
+    __shared__ double lds[16];
+    double s = 0.0;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+        const double v = b[j] - Sx[j];
+        r[j] = v;
+        r32[j] = (float)v;
+        s = fma(v, v, s);
+    }
+    const double t = block_sum(s, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+__global__ void add_f32(int n, const float *__restrict__ d, double *__restrict__ x) {
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x)
+        x[j] += (double)d[j];
+}
+
+// Mixed precision: FP64 iterative refinement around FP32 Jacobi-CG.  Each
+// outer step forms the FP64 residual r = b - S x and solves S d = r in FP32 to
+// a relative 1e-4 (or the remaining target); x += d.  Stops on the FP64
+// residual, so the accuracy is that of an FP64 solve.
+CGStats SchurSolver::pcg_mixed(hipStream_t st, const double *b, double *x, double rtol,
+                               double atol, int maxit) {
+    const int n = S.n;
+    CGStats out;
+    val32_.need((size_t)S.nnz);
+    dinv32_.need(n);
+    hipLaunchKernelGGL(to_f32, dim3(std::min<unsigned>(4096, grid_for(S.nnz, 256))), dim3(256), 0,
+                       st, S.nnz, S.val.get(), val32_.get());
+    hipLaunchKernelGGL(to_f32, dim3(grid_for(n, 256)), dim3(256), 0, st, (int64_t)n,
+                       S.dinv.get(), dinv32_.get());
+    double *r = rd_.need(n), *Sx = sx_.need(n);
+    float *r32 = rf_.need(n), *d32 = df_.need(n);
+    double *part = rpart_.need(256);
+    OTIP_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, st));
+    const unsigned nbv = std::min<unsigned>(256, grid_for(n, 256));
+    double target = -1.0;
+    std::vector<double> hp(nbv);
+    for (int outer = 0; outer < 12; ++outer) {
+        spmv(st, x, Sx);
+        hipLaunchKernelGGL(resid64, dim3(nbv), dim3(256), 0, st, n, b, Sx, r, r32, part);
+        OTIP_HIP(hipMemcpyAsync(hp.data(), part, sizeof(double) * nbv, hipMemcpyDeviceToHost, st));
+        OTIP_HIP(hipStreamSynchronize(st));
+        double rr = 0.0;
+        for (double v : hp) rr += v;
+        const double rn = std::sqrt(rr);
+        if (target < 0.0) target = std::min(rtol * rn, atol);
+        out.res_norm = rn;
+        if (rn <= target || rn == 0.0) {
+            out.converged = true;
+            break;
+        }
+        if (out.iterations >= maxit) break;
+        const double inner = std::max(1e-4, 0.5 * target / rn);
+        CGStats cs = pcg_impl<float>(st, val32_.get(), dinv32_.get(), r32, d32, inner, 1e300,
+                                     maxit - out.iterations, rf2_, zf_, pf_, qf_);
+        out.iterations += std::max(cs.iterations, 1);
+        hipLaunchKernelGGL(add_f32, dim3(nbv), dim3(256), 0, st, n, d32, x);
+    }
     return out;
 }
 

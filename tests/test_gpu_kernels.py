@@ -146,3 +146,40 @@ def test_schur_matches_oracle(ctx):
     for j in range(n):
         assert np.all(np.diff(ci[rp[j]:rp[j + 1]]) > 0)
     assert np.array_equal(G, G.T)   # exactly symmetric
+
+
+@pytest.mark.parametrize("m,n,kmax,seed", [(300, 257, 300, 1), (1000, 700, 50, 2), (64, 64, 100000, 3),
+                                           (257, 129, 0, 4)])
+def test_mixed_pricing_identical_to_fp64(ctx, m, n, kmax, seed):
+    """FP32 scan + FP64 re-check returns exactly the FP64 selection and count."""
+    import paper_2206_11009_amd as otip
+    rng = np.random.default_rng(seed)
+    xs = rng.integers(0, 60, (m, 2)).astype(np.int32)
+    xt = rng.integers(0, 60, (n, 2)).astype(np.int32)
+    y, z = rng.uniform(0, 900, m), rng.uniform(0, 900, n)
+    support = rng.choice(m * n, size=min(m * n // 3, 5000), replace=False)
+    bm = bitmap_of(support, m, n)
+    oi, oj, orr, nneg = otip.otip_price(ctx, xs, xt, y, z, bm, kmax, otip.OTIP_MIXED)
+    o_idx, o_r, o_neg = _cscan.price(xs, xt, y, z, np.sort(support.astype(np.int64)), kmax)
+    assert nneg == o_neg
+    g_idx = oi.cpu().numpy().astype(np.int64) + oj.cpu().numpy().astype(np.int64) * m
+    np.testing.assert_array_equal(g_idx, o_idx)
+    np.testing.assert_array_equal(orr.cpu().numpy(), o_r)
+
+
+def test_mixed_pricing_near_zero_band(ctx):
+    """Duals placed so that many reduced costs sit inside the FP32 margin of 0."""
+    import paper_2206_11009_amd as otip
+    inst = config_instance("c2", 1)
+    m = inst.m
+    rng = np.random.default_rng(8)
+    c0 = oracle.sq_costs(inst.xs, inst.xt, np.arange(m), np.arange(m)).astype(float)
+    y = c0 + rng.integers(0, 3, m).astype(float) + rng.uniform(-1e-6, 1e-6, m)
+    z = np.zeros(m)
+    for kmax in (0, 7, m):
+        oi, oj, orr, nneg = otip.otip_price(ctx, inst.xs, inst.xt, y, z, None, kmax, otip.OTIP_MIXED)
+        o_idx, o_r, o_neg = _cscan.price(inst.xs, inst.xt, y, z, np.zeros(0, np.int64), kmax)
+        assert nneg == o_neg
+        g_idx = oi.cpu().numpy().astype(np.int64) + oj.cpu().numpy().astype(np.int64) * m
+        np.testing.assert_array_equal(g_idx, o_idx)
+        np.testing.assert_array_equal(orr.cpu().numpy(), o_r)

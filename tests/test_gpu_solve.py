@@ -93,3 +93,16 @@ def test_gaussian_64x64_matches_stored_oracle(ctx, k):
     check_result(res, inst.a, inst.b, inst.xs, inst.xt)
     ref = {r["seed"]: r for r in load_golden("c2")}[k]["objective"]
     assert abs(res.objective - ref) <= 1e-6 * abs(ref)
+
+
+@pytest.mark.parametrize("cfg,k", [("c1", 0), ("c1", 5), ("c2", 2)])
+def test_mixed_precision_solve(ctx, cfg, k):
+    """FP32 pricing with FP64 re-check and FP32 CG inside FP64 refinement reach
+    the oracle's optimum with an FP64 certificate."""
+    import paper_2206_11009_amd as otip
+    inst = config_instance(cfg, k)
+    res = otip.otip_solve(ctx, inst.a, inst.b, inst.xs, inst.xt,
+                          otip.params(precision=otip.OTIP_MIXED, switch_cost=0))
+    check_result(res, inst.a, inst.b, inst.xs, inst.xt)
+    ref = {r["seed"]: r for r in load_golden(cfg)}[k]["objective"]
+    assert abs(res.objective - ref) <= 1e-6 * abs(ref)
