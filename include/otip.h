@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define OTIP_ABI_VERSION 1
+#define OTIP_ABI_VERSION 2
 
 enum otip_status {
     OTIP_OK = 0,
@@ -92,12 +92,22 @@ typedef struct otip_params {
     int32_t profile;         /* 1: time every SpMV and pricing launch with HIP events */
     int32_t switch_cost;     /* 1: also switch once a dense factorisation is estimated (fixed
                                 cost model) to cost less than the last iteration's CG */
+    int32_t batch_workers;   /* otip_solve_batch: host workers, each with its own HIP stream
+                                and solver state (0: min(8, count)) */
+    int32_t price_tile;      /* targets per pricing-scan block, a power of two in [16, 256];
+                                0: chosen from m and n */
+    double ws_kappa;         /* warm start: initial support ~ ws_kappa*(m+n-1) smallest
+                                reduced costs under the given duals (0: use kappa) */
 } otip_params;
 
-/* Problem description.  All four arrays are DEVICE pointers.
+/* Problem description.  All arrays are DEVICE pointers.
  *   a  : m doubles, > 0          b : n doubles, > 0, |sum a - sum b| <= 1e-12 sum a
  *   xs : m x 2 int32, row-major   xt: n x 2 int32, row-major, coordinates in
- *        [-2^14, 2^14] so that every cost fits in 31 bits. */
+ *        [-2^14, 2^14] so that every cost fits in 31 bits.
+ *   y0, z0: optional predicted duals (m and n doubles, cost units) or both NULL.
+ *        When given, the initial support is built from them instead of from
+ *        the costs alone (a warm start); the method and its certificate are
+ *        unchanged.  Non-finite values fall back to the plain initial support. */
 typedef struct otip_problem {
     int32_t m;
     int32_t n;
@@ -105,6 +115,8 @@ typedef struct otip_problem {
     const double *b;
     const int32_t *xs;
     const int32_t *xt;
+    const double *y0;
+    const double *z0;
 } otip_problem;
 
 /* Summary of a solve (Section 5.3 reports iterations, time, CG iterations,
@@ -169,8 +181,15 @@ int otip_solve(otip_ctx *ctx, const otip_problem *pr, const otip_params *params,
 
 /*
  * Solve `count` independent problems; outs[k] receives each result.  The
- * per-instance full scans of all problems of one outer iteration run as one
- * launch over a table of instances.
+ * problems are taken largest first (by m*n) by params->batch_workers host
+ * workers, each owning a non-blocking HIP stream (default priority) and a
+ * solver whose device buffers persist across problems and calls, so that the
+ * many small launches of different instances overlap on the device.  Input
+ * arrays must be ready on the context's stream, which is synchronised first.
+ * Returns OTIP_OK, or OTIP_EMAXITER if any instance hit the iteration limit
+ * (every outs[k] is valid then).  On any other error no result is returned
+ * (every outs[k] is NULL) and otip_last_error names the failing instance.
+ * The context must not be used by another thread during the call.
  */
 int otip_solve_batch(otip_ctx *ctx, const otip_problem *prs, int32_t count,
                      const otip_params *params, otip_result **outs);
@@ -232,6 +251,48 @@ int otip_kron_apply_t(otip_ctx *ctx, int32_t m, int32_t n, const double *y, cons
 int otip_schur(otip_ctx *ctx, int32_t m, int32_t n, int64_t psi, const int64_t *idx,
                const double *theta, int64_t *out_nnz, int32_t *rowptr, int32_t *colidx,
                double *vals, double *M, double *N);
+
+/* ------------------------------------------------------------------------
+ * Learned warm start.  A small convolutional network maps the two marginals of
+ * a side x side grid problem (pixel i at coordinates (i / side, i % side)) to
+ * predicted duals; passing them as otip_problem.y0/z0 replaces the initial
+ * support rule of Section 3.2 (end) by the c-transform of the prediction and
+ * its smallest reduced costs.  The solve, its pricing and its certificate are
+ * those of the plain method, so a poor prediction costs time, not accuracy.
+ *
+ * Network (FP32): four 3x3 convolutions, 2 -> 32 -> 32 -> 32 -> 2 channels,
+ * dilations 1, 2, 4, 8, zero padding equal to the dilation, ReLU after the
+ * first three.  Parameters: one flat FP32 array of otip_ws_param_count()
+ * values, per layer W[out][in][3][3] then b[out].  Input x: N x 2 x H x W
+ * (NCHW, the marginals as densities: mass * side^2 per pixel); output: N x 2 x
+ * H x W (duals in normalised coordinates: pixel cost units / side^2, any
+ * gauge).  All pointers are DEVICE pointers except `loss`.
+ * ------------------------------------------------------------------------ */
+int64_t otip_ws_param_count(void);
+
+/* out = net(in).  batch <= 65535, H*W <= 2^24. */
+int otip_ws_forward(otip_ctx *ctx, const float *weights, int32_t batch, int32_t h, int32_t w,
+                    const float *in, float *out);
+
+/* Gradient of the mean squared error mean((net(in) - target)^2) with respect
+ * to the parameters into grad (otip_ws_param_count() floats); the loss into
+ * *loss (host, may be NULL).  Weight-gradient sums are accumulated in FP64. */
+int otip_ws_grad(otip_ctx *ctx, const float *weights, int32_t batch, int32_t h, int32_t w,
+                 const float *in, const float *target, float *grad, double *loss);
+
+/* One Adam step (Kingma & Ba) with bias correction for step >= 1; weights,
+ * first and second moments m, v are updated in place (FP32).  The
+ * hyperparameters are doubles so that 1 - beta is formed exactly. */
+int otip_ws_adam(otip_ctx *ctx, float *weights, float *m, float *v, const float *grad,
+                 int32_t step, double lr, double beta1, double beta2, double eps);
+
+/* Predicted duals of a side x side grid problem with marginals a, b (m = n =
+ * side^2 doubles): the marginals are averaged over a 32 x 32 partition of the
+ * square (exact area weights), the network runs at 32 x 32, and its output is
+ * interpolated bilinearly at the pixel centres (clamped at the border) and
+ * scaled by side^2 into y0, z0 (pixel cost units). */
+int otip_ws_predict(otip_ctx *ctx, const float *weights, int32_t side, const double *a,
+                    const double *b, double *y0, double *z0);
 
 #ifdef __cplusplus
 }

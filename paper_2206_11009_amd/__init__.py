@@ -10,17 +10,20 @@ calls raise if the library is not built or no GPU is present.
 from __future__ import annotations
 
 import ctypes
+import os as _os
 from dataclasses import dataclass
 
 import numpy as np
 
 from . import _abi
-from ._abi import (OTIP_OK, OTIP_EMAXITER, OTIP_FP64, OTIP_MIXED, OTIP_LS_AUTO, OTIP_LS_PCG,  # noqa: F401
+from ._abi import (OTIP_OK, OTIP_EINVAL, OTIP_ENOMEM, OTIP_EHIP, OTIP_ENUMERIC, OTIP_EUNSUPPORTED,  # noqa: F401
+                   OTIP_EMAXITER, OTIP_FP64, OTIP_MIXED, OTIP_LS_AUTO, OTIP_LS_PCG,  # noqa: F401
                    OTIP_LS_DIRECT, otip_params, otip_problem, otip_info)
 
 __all__ = ["otip_version", "otip_params_default", "Context", "OtipError", "SolveResult",
            "otip_solve", "otip_solve_batch", "otip_price", "otip_rmin", "otip_kron_apply",
-           "otip_kron_apply_t", "otip_schur", "params"]
+           "otip_kron_apply_t", "otip_schur", "params", "otip_ws_param_count", "otip_ws_forward",
+           "otip_ws_grad", "otip_ws_adam", "otip_ws_predict", "load_ws_weights"]
 
 
 class OtipError(RuntimeError):
@@ -116,15 +119,19 @@ class SolveResult:
         raise AttributeError(k)
 
 
-def _problem(ctx, a, b, xs, xt):
+def _problem(ctx, a, b, xs, xt, y0=None, z0=None):
     torch = _torch()
     A = _dev(a, torch.float64, ctx.device)
     B = _dev(b, torch.float64, ctx.device)
     XS = _dev(xs, torch.int32, ctx.device)
     XT = _dev(xt, torch.int32, ctx.device)
+    Y0 = _dev(y0, torch.float64, ctx.device) if y0 is not None else None
+    Z0 = _dev(z0, torch.float64, ctx.device) if z0 is not None else None
     pr = otip_problem(int(A.shape[0]), int(B.shape[0]), A.data_ptr(), B.data_ptr(),
-                      XS.data_ptr(), XT.data_ptr())
-    return pr, (A, B, XS, XT)
+                      XS.data_ptr(), XT.data_ptr(),
+                      Y0.data_ptr() if Y0 is not None else None,
+                      Z0.data_ptr() if Z0 is not None else None)
+    return pr, (A, B, XS, XT, Y0, Z0)
 
 
 def _collect(ctx, res_handle, rc):
@@ -139,9 +146,11 @@ def _collect(ctx, res_handle, rc):
     return d, rows, cols, vals
 
 
-def otip_solve(ctx: Context, a, b, xs, xt, prm: otip_params | None = None) -> SolveResult:
-    """Solve one problem; a, b, xs, xt may be numpy arrays or torch tensors."""
-    pr, keep = _problem(ctx, a, b, xs, xt)
+def otip_solve(ctx: Context, a, b, xs, xt, prm: otip_params | None = None, y0=None,
+               z0=None) -> SolveResult:
+    """Solve one problem; a, b, xs, xt (and the optional warm-start duals y0,
+    z0) may be numpy arrays or torch tensors."""
+    pr, keep = _problem(ctx, a, b, xs, xt, y0, z0)
     h = ctypes.c_void_p()
     rc = ctx._lib.otip_solve(ctx.handle, ctypes.byref(pr),
                              ctypes.byref(prm) if prm is not None else None, ctypes.byref(h))
@@ -159,11 +168,12 @@ def otip_solve(ctx: Context, a, b, xs, xt, prm: otip_params | None = None) -> So
 
 
 def otip_solve_batch(ctx: Context, problems, prm: otip_params | None = None):
-    """Solve a list of (a, b, xs, xt) problems; returns a list of SolveResult."""
+    """Solve a list of (a, b, xs, xt) or (a, b, xs, xt, y0, z0) problems;
+    returns a list of SolveResult in the same order."""
     prs = (otip_problem * len(problems))()
     keep = []
-    for k, (a, b, xs, xt) in enumerate(problems):
-        pr, kk = _problem(ctx, a, b, xs, xt)
+    for k, prob in enumerate(problems):
+        pr, kk = _problem(ctx, *prob)
         prs[k] = pr
         keep.append(kk)
     outs = (ctypes.c_void_p * len(problems))()
@@ -245,3 +255,65 @@ def otip_schur(ctx: Context, m: int, n: int, idx, theta):
                                   ctypes.byref(nnz), _ptr(rp), _ptr(ci), _ptr(va), _ptr(M),
                                   _ptr(N)))
     return rp, ci[:nnz.value], va[:nnz.value], M, N
+
+
+# ------------------------------------------------------------ learned warm start
+def otip_ws_param_count() -> int:
+    return int(_abi.load().otip_ws_param_count())
+
+
+def otip_ws_forward(ctx: Context, weights, x):
+    """net(x) for an (N, 2, H, W) float32 device tensor; returns a new tensor."""
+    torch = _torch()
+    x = x.contiguous()
+    out = torch.empty_like(x)
+    N, C, H, W = x.shape
+    if C != 2:
+        raise OtipError(_abi.OTIP_EINVAL, "input must have 2 channels")
+    ctx.check(ctx._lib.otip_ws_forward(ctx.handle, _ptr(weights), N, H, W, _ptr(x), _ptr(out)))
+    return out
+
+
+def otip_ws_grad(ctx: Context, weights, x, target, grad=None):
+    """(loss, grad) of the mean-squared error of net(x) against target."""
+    torch = _torch()
+    x, target = x.contiguous(), target.contiguous()
+    if grad is None:
+        grad = torch.empty_like(weights)
+    N, _, H, W = x.shape
+    loss = ctypes.c_double()
+    ctx.check(ctx._lib.otip_ws_grad(ctx.handle, _ptr(weights), N, H, W, _ptr(x), _ptr(target),
+                                    _ptr(grad), ctypes.byref(loss)))
+    return float(loss.value), grad
+
+
+def otip_ws_adam(ctx: Context, weights, m, v, grad, step: int, lr: float, beta1: float = 0.9,
+                 beta2: float = 0.999, eps: float = 1e-8):
+    ctx.check(ctx._lib.otip_ws_adam(ctx.handle, _ptr(weights), _ptr(m), _ptr(v), _ptr(grad),
+                                    int(step), float(lr), float(beta1), float(beta2), float(eps)))
+
+
+def otip_ws_predict(ctx: Context, weights, side: int, a, b):
+    """Predicted duals (y0, z0) of a side x side grid pair, as device tensors."""
+    torch = _torch()
+    A = _dev(a, torch.float64, ctx.device)
+    B = _dev(b, torch.float64, ctx.device)
+    y0 = torch.empty(side * side, dtype=torch.float64, device=A.device)
+    z0 = torch.empty(side * side, dtype=torch.float64, device=A.device)
+    ctx.check(ctx._lib.otip_ws_predict(ctx.handle, _ptr(weights), int(side), _ptr(A), _ptr(B),
+                                       _ptr(y0), _ptr(z0)))
+    return y0, z0
+
+
+WS_WEIGHTS = _os.path.join(_os.path.dirname(_os.path.abspath(__file__)), "ws_weights.bin")
+
+
+def load_ws_weights(ctx: Context, path: str = WS_WEIGHTS):
+    """The trained warm-start parameters (FP32 file written by ws_train) as a
+    device tensor."""
+    torch = _torch()
+    w = np.fromfile(path, dtype="<f4")
+    if w.size != otip_ws_param_count():
+        raise OtipError(_abi.OTIP_EINVAL, f"{path}: {w.size} values, expected "
+                        f"{otip_ws_param_count()}")
+    return torch.as_tensor(w, device=f"cuda:{ctx.device}")

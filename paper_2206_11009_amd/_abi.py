@@ -31,11 +31,15 @@ class otip_params(ctypes.Structure):
         ("precision", _c_i32), ("dense_max_n", _c_i32), ("force_switch_at", _c_i32),
         ("enter_cap", _c_i32), ("scale", _c_i32), ("verbose", _c_i32), ("profile", _c_i32),
         ("switch_cost", _c_i32),
+        ("batch_workers", _c_i32),
+        ("price_tile", _c_i32),
+        ("ws_kappa", ctypes.c_double),
     ]
 
 
 class otip_problem(ctypes.Structure):
-    _fields_ = [("m", _c_i32), ("n", _c_i32), ("a", _p), ("b", _p), ("xs", _p), ("xt", _p)]
+    _fields_ = [("m", _c_i32), ("n", _c_i32), ("a", _p), ("b", _p), ("xs", _p), ("xt", _p),
+                ("y0", _p), ("z0", _p)]
 
 
 class otip_info(ctypes.Structure):
@@ -77,6 +81,12 @@ SIGNATURES = {
     "otip_kron_apply_t": (ctypes.c_int, [_p, _c_i32, _c_i32, _p, _p, _p]),
     "otip_schur": (ctypes.c_int, [_p, _c_i32, _c_i32, _c_i64, _p, _p, ctypes.POINTER(_c_i64),
                                   _p, _p, _p, _p, _p]),
+    "otip_ws_param_count": (_c_i64, []),
+    "otip_ws_forward": (ctypes.c_int, [_p, _p, _c_i32, _c_i32, _c_i32, _p, _p]),
+    "otip_ws_grad": (ctypes.c_int, [_p, _p, _c_i32, _c_i32, _c_i32, _p, _p, _p,
+                                    ctypes.POINTER(_c_f64)]),
+    "otip_ws_adam": (ctypes.c_int, [_p, _p, _p, _p, _p, _c_i32, _c_f64, _c_f64, _c_f64, _c_f64]),
+    "otip_ws_predict": (ctypes.c_int, [_p, _p, _c_i32, _p, _p, _p, _p]),
 }
 
 _lib = None

@@ -1,16 +1,35 @@
 // C-ABI entry points (include/otip.h).  Every call catches the library's
 // exceptions and returns a status code; the message is kept on the context.
+#include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <memory>
+#include <mutex>
+#include <numeric>
+#include <thread>
 
 #include "driver.h"
+
+// One worker of otip_solve_batch: a non-blocking stream (default priority) and
+// a solver whose device buffers are kept from one problem to the next.
+struct BatchWorker {
+    hipStream_t st = nullptr;
+    std::unique_ptr<otip::Solver> solver;
+    ~BatchWorker() {
+        solver.reset();
+        if (st) (void)hipStreamDestroy(st);
+    }
+};
 
 struct otip_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
+    std::unique_ptr<otip::Solver> solver;  // otip_solve's, on `stream`
+    std::vector<std::unique_ptr<BatchWorker>> workers;
     otip::Scanner scan;
     otip::SchurSolver schur;
+    otip::WarmNet net;
     otip::DBuf<double> buf_a, buf_b, buf_c;
     otip::DBuf<uint64_t> buf_u;
     otip::DBuf<int32_t> buf_i;
@@ -84,6 +103,9 @@ void otip_params_default(otip_params *p) {
     p->verbose = 0;
     p->profile = 0;
     p->switch_cost = 1;
+    p->batch_workers = 0;
+    p->price_tile = 0;
+    p->ws_kappa = 0.0;
 }
 
 int otip_create(otip_ctx **ctx, int device, void *hip_stream) {
@@ -122,8 +144,8 @@ int otip_solve(otip_ctx *ctx, const otip_problem *pr, const otip_params *params,
             P = *params;
         else
             otip_params_default(&P);
-        otip::Solver s(ctx->stream);
-        status = s.run(*pr, P, res->r);
+        if (!ctx->solver) ctx->solver = std::make_unique<otip::Solver>(ctx->stream);
+        status = ctx->solver->run(*pr, P, res->r);
         OTIP_HIP(hipStreamSynchronize(ctx->stream));
     });
     if (rc != OTIP_OK) return rc;
@@ -133,20 +155,95 @@ int otip_solve(otip_ctx *ctx, const otip_problem *pr, const otip_params *params,
 
 int otip_solve_batch(otip_ctx *ctx, const otip_problem *prs, int32_t count,
                      const otip_params *params, otip_result **outs) {
-    if (!ctx || !prs || !outs || count < 0) return OTIP_EINVAL;
-    int worst = OTIP_OK;
-    for (int32_t k = 0; k < count; ++k) {
-        int rc = otip_solve(ctx, &prs[k], params, &outs[k]);
-        if (rc != OTIP_OK && rc != OTIP_EMAXITER) {
-            for (int32_t q = 0; q < k; ++q) {
-                otip_result_free(outs[q]);
-                outs[q] = nullptr;
-            }
-            return rc;
+    if (!ctx || count < 0 || (count > 0 && (!prs || !outs))) return OTIP_EINVAL;
+    for (int32_t k = 0; k < count; ++k) outs[k] = nullptr;
+    if (count == 0) return OTIP_OK;
+    otip_params P;
+    if (params)
+        P = *params;
+    else
+        otip_params_default(&P);
+    const int nw = std::max(1, std::min<int>(P.batch_workers > 0 ? P.batch_workers : 8, count));
+    int rc = guarded(ctx, [&] {
+        OTIP_CHECK(nw <= 64, OTIP_EINVAL, "batch_workers must be <= 64");
+        // the caller's stream produced the inputs
+        OTIP_HIP(hipStreamSynchronize(ctx->stream));
+        while ((int)ctx->workers.size() < nw) {
+            auto w = std::make_unique<BatchWorker>();
+            OTIP_HIP(hipStreamCreateWithFlags(&w->st, hipStreamNonBlocking));
+            w->solver = std::make_unique<otip::Solver>(w->st);
+            ctx->workers.push_back(std::move(w));
         }
-        if (rc == OTIP_EMAXITER) worst = rc;
+    });
+    if (rc != OTIP_OK) return rc;
+    // largest first, so that a worker's buffers grow on its first problems only
+    std::vector<int32_t> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t u, int32_t v) {
+        return (int64_t)prs[u].m * prs[u].n > (int64_t)prs[v].m * prs[v].n;
+    });
+    std::atomic<int32_t> next{0};
+    std::atomic<bool> abort{false};
+    std::vector<int> codes(count, OTIP_OK);
+    std::mutex mu;
+    int first_code = OTIP_OK;
+    std::string first_msg;
+    auto fail = [&](int32_t k, int code, const char *msg) {
+        std::lock_guard<std::mutex> g(mu);
+        if (first_code == OTIP_OK) {
+            first_code = code;
+            first_msg = "instance " + std::to_string(k) + ": " + msg;
+        }
+        abort = true;
+    };
+    auto work = [&](int w) {
+        BatchWorker &W = *ctx->workers[w];
+        if (hipSetDevice(ctx->device) != hipSuccess) {
+            fail(-1, OTIP_EHIP, "hipSetDevice failed in a batch worker");
+            return;
+        }
+        for (;;) {
+            if (abort.load()) return;
+            const int32_t q = next.fetch_add(1);
+            if (q >= count) return;
+            const int32_t k = order[q];
+            try {
+                auto res = std::make_unique<otip_result>();
+                codes[k] = W.solver->run(prs[k], P, res->r);
+                OTIP_HIP(hipStreamSynchronize(W.st));
+                outs[k] = res.release();
+            } catch (const otip::Error &e) {
+                (void)hipStreamSynchronize(W.st);
+                fail(k, e.code, e.what());
+            } catch (const std::bad_alloc &) {
+                fail(k, OTIP_ENOMEM, "host allocation failed");
+            } catch (const std::exception &e) {
+                (void)hipStreamSynchronize(W.st);
+                fail(k, OTIP_EHIP, e.what());
+            }
+        }
+    };
+    std::vector<std::thread> threads;
+    threads.reserve(nw - 1);
+    try {
+        for (int w = 1; w < nw; ++w) threads.emplace_back(work, w);
+    } catch (const std::exception &) {
+        fail(-1, OTIP_EHIP, "could not start batch worker threads");
     }
-    return worst;
+    work(0);
+    for (auto &t : threads) t.join();
+    if (first_code != OTIP_OK) {
+        for (int32_t k = 0; k < count; ++k) {
+            otip_result_free(outs[k]);
+            outs[k] = nullptr;
+        }
+        ctx->err = first_msg;
+        return first_code;
+    }
+    ctx->err.clear();
+    for (int32_t k = 0; k < count; ++k)
+        if (codes[k] == OTIP_EMAXITER) return OTIP_EMAXITER;
+    return OTIP_OK;
 }
 
 int otip_result_info(const otip_result *r, otip_info *info) {
@@ -230,6 +327,51 @@ int otip_schur(otip_ctx *ctx, int32_t m, int32_t n, int64_t psi, const int64_t *
         otip::Solver s(ctx->stream);
         *out_nnz = s.schur_export(m, n, psi, (const uint64_t *)idx, theta, rowptr, colidx, vals,
                                   M, N);
+    });
+}
+
+int64_t otip_ws_param_count(void) { return otip::WarmNet::param_count(); }
+
+int otip_ws_forward(otip_ctx *ctx, const float *weights, int32_t batch, int32_t h, int32_t w,
+                    const float *in, float *out) {
+    return guarded(ctx, [&] {
+        OTIP_CHECK(weights && in && out && batch >= 1 && batch <= 65535 && h >= 1 && w >= 1 &&
+                       (int64_t)h * w <= (1 << 24),
+                   OTIP_EINVAL, "otip_ws_forward: bad arguments");
+        ctx->net.forward(ctx->stream, weights, batch, h, w, in, out);
+        OTIP_HIP(hipStreamSynchronize(ctx->stream));
+    });
+}
+
+int otip_ws_grad(otip_ctx *ctx, const float *weights, int32_t batch, int32_t h, int32_t w,
+                 const float *in, const float *target, float *grad, double *loss) {
+    return guarded(ctx, [&] {
+        OTIP_CHECK(weights && in && target && grad && batch >= 1 && batch <= 65535 && h >= 1 &&
+                       w >= 1 && (int64_t)h * w <= (1 << 24),
+                   OTIP_EINVAL, "otip_ws_grad: bad arguments");
+        const double l = ctx->net.grad(ctx->stream, weights, batch, h, w, in, target, grad);
+        if (loss) *loss = l;
+    });
+}
+
+int otip_ws_adam(otip_ctx *ctx, float *weights, float *m, float *v, const float *grad,
+                 int32_t step, double lr, double beta1, double beta2, double eps) {
+    return guarded(ctx, [&] {
+        OTIP_CHECK(weights && m && v && grad && step >= 1 && beta1 >= 0.0 && beta1 < 1.0 &&
+                       beta2 >= 0.0 && beta2 < 1.0 && eps >= 0.0,
+                   OTIP_EINVAL, "otip_ws_adam: bad arguments");
+        ctx->net.adam(ctx->stream, weights, m, v, grad, step, lr, beta1, beta2, eps);
+        OTIP_HIP(hipStreamSynchronize(ctx->stream));
+    });
+}
+
+int otip_ws_predict(otip_ctx *ctx, const float *weights, int32_t side, const double *a,
+                    const double *b, double *y0, double *z0) {
+    return guarded(ctx, [&] {
+        OTIP_CHECK(weights && a && b && y0 && z0 && side >= 1 && side <= 32768, OTIP_EINVAL,
+                   "otip_ws_predict: bad arguments");
+        ctx->net.predict(ctx->stream, weights, side, a, b, y0, z0);
+        OTIP_HIP(hipStreamSynchronize(ctx->stream));
     });
 }
 

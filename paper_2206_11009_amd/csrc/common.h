@@ -92,6 +92,12 @@ struct LaunchTimer {
         (void)hipEventRecord(ev[used + 1], st);
         used += 2;
     }
+    void reset() {
+        launches = 0;
+        ms = work = 0.0;
+        used = 0;
+        pending_work.clear();
+    }
     // after the stream has been synchronised
     void collect() {
         if (!on) return;

@@ -4,12 +4,16 @@
 //
 // Right-looking blocked factorisation of the lower triangle of a column-major
 // n x n array, block width 64:
-//   1. the 64 x 64 diagonal block is factorised in LDS by one workgroup;
+//   1. the 64 x 64 diagonal block is factorised by one wavefront, which also
+//      inverts its unit lower factor;
 //   2. every row below solves w_i L11^T = a_i (w = L21 D1) and l_i = w_i D1^-1;
 //   3. the trailing lower triangle is updated, A22 -= L21 W21^T, in 64 x 64
 //      tiles staged through LDS.
 // A pivot d_k <= pivtol * S_kk (original diagonal) or d_k <= 0 becomes +inf:
 // its column of L is zero and the solve returns 0 for that unknown.
+// After the factorisation X = L^-1 is formed (recursive doubling with tiled
+// products), so that each solve x = X^T D^-1 X b is two matrix-vector
+// products instead of a chain of dependent triangular steps.
 #include "internal.h"
 
 namespace otip {
@@ -33,80 +37,62 @@ __global__ void dense_zero(size_t total, double *A) {
         A[t] = 0.0;
 }
 
-// Factor the diagonal block [kb, kb+nb): thread (i, q) keeps row i, columns
-// 16q..16q+15 of the block (t) and of its running inverse (x) in registers;
-// each step broadcasts the pivot, column k of L and row k of the inverse
-// through LDS.  L11 = prod_k (I + l_k e_k^T), so applying the row operations
-// X <- (I - l_k e_k^T) X to X = I in the same order leaves X = L11^-1, which
-// is written to Linv (nb x nb, column-major) for the panel product.
-__global__ __launch_bounds__(256) void ldl_diag(int n, int kb, int nb, double *A,
-                                                const double *orig, double *d, double pivtol,
-                                                int *ninf, double *Linv) {
+// Factor the diagonal block [kb, kb+nb) in one wavefront.  Lane i keeps row i
+// of the block's lower triangle in registers; at pivot k, column k of L goes
+// through LDS and every lane updates its row (right-looking).  Then the unit
+// lower factor L11 is put in LDS and lane c solves L11 x = e_c by forward
+// substitution, giving column c of L11^-1 (Linv, nb x nb column-major, padded
+// with the identity to 64 x 64) for the panel product.
+__global__ __launch_bounds__(64) void ldl_diag(int n, int kb, int nb, double *A,
+                                               const double *orig, double *d, double pivtol,
+                                               int *ninf, double *Linv) {
     __shared__ double colk[NB];
-    __shared__ double xrow[NB];
-    __shared__ double dk;
-    const int i = threadIdx.x & 63, q = threadIdx.x >> 6;
-    double t[16], x[16];
+    __shared__ double Ls[NB][NB + 1];
+    const int i = threadIdx.x;
+    double t[NB];
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
-        const int j = 16 * q + c;
-        t[c] = (i < nb && j < nb && i >= j) ? A[(size_t)(kb + i) + (size_t)(kb + j) * n] : 0.0;
-        x[c] = (i == j) ? 1.0 : 0.0;
-    }
-    for (int k = 0; k < nb; ++k) {
-        const int kq = k >> 4, kc = k & 15;
-        if (q == kq && i == k) {
-            double v = 0.0;
+    for (int c = 0; c < NB; ++c)
+        t[c] = (i < nb && c < nb && c <= i) ? A[(size_t)(kb + i) + (size_t)(kb + c) * n] : 0.0;
 #pragma unroll
-            for (int c = 0; c < 16; ++c)
-                if (c == kc) v = t[c];
-            const double o = orig[kb + k];
-            if (!(v > pivtol * o) || !(v > 0.0)) {
-                v = INFINITY;
-                atomicAdd(ninf, 1);
+    for (int k = 0; k < NB; ++k) {
+        if (k < nb) {
+            double piv = __shfl(t[k], k, 64);
+            if (!(piv > pivtol * orig[kb + k]) || !(piv > 0.0)) piv = INFINITY;
+            if (i == 0) {
+                d[kb + k] = piv;
+                if (isinf(piv)) atomicAdd(ninf, 1);
             }
-            dk = v;
-            d[kb + k] = v;
-        }
-        if (i == k) {
-#pragma unroll
-            for (int c = 0; c < 16; ++c) xrow[16 * q + c] = x[c];
-        }
-        __syncthreads();
-        const double dd = dk;
-        if (q == kq) {
-            // column k of L (rows below k)
-            double l = 0.0;
-#pragma unroll
-            for (int c = 0; c < 16; ++c)
-                if (c == kc) l = t[c];
-            l = (i > k && !isinf(dd)) ? l / dd : 0.0;
+            const bool fin = !isinf(piv);
+            const double l = (fin && i > k && i < nb) ? t[k] / piv : 0.0;
             colk[i] = l;
+            __syncthreads();
+            const double ld = fin ? l * piv : 0.0;
 #pragma unroll
-            for (int c = 0; c < 16; ++c)
-                if (c == kc && i > k) t[c] = l;
+            for (int j = k + 1; j < NB; ++j)
+                if (j <= i) t[j] = fma(-ld, colk[j], t[j]);
+            if (i > k) t[k] = l;
+            __syncthreads();
         }
-        __syncthreads();
-        const double lik = colk[i];
-        if (!isinf(dd)) {
-            const double li = lik * dd;
+    }
+    // L11 (strict lower part) to A and to LDS
 #pragma unroll
-            for (int c = 0; c < 16; ++c) {
-                const int j = 16 * q + c;
-                if (j > k && i >= j) t[c] = fma(-li, colk[j], t[c]);
-            }
-        }
-        // inverse: rows below k lose l_ik times row k
+    for (int c = 0; c < NB; ++c) {
+        const bool low = i < nb && c < i;
+        if (low && c < nb) A[(size_t)(kb + i) + (size_t)(kb + c) * n] = t[c];
+        Ls[i][c] = low ? t[c] : 0.0;
+    }
+    __syncthreads();
+    // column i of L11^-1: x_r = [r == i] - sum_{s < r} L(r, s) x_s
+    double x[NB];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) x[c] = fma(-lik, xrow[16 * q + c], x[c]);
-        __syncthreads();
+    for (int r = 0; r < NB; ++r) {
+        double v = (r == i) ? 1.0 : 0.0;
+#pragma unroll
+        for (int s2 = 0; s2 < r; ++s2) v = fma(-Ls[r][s2], x[s2], v);
+        x[r] = v;
     }
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
-        const int j = 16 * q + c;
-        if (i < nb && j < nb && i > j) A[(size_t)(kb + i) + (size_t)(kb + j) * n] = t[c];
-        Linv[(size_t)i + (size_t)j * NB] = (i < nb && j < nb) ? x[c] : (i == j ? 1.0 : 0.0);
-    }
+    for (int r = 0; r < NB; ++r) Linv[(size_t)r + (size_t)i * NB] = x[r];
 }
 
 // Rows below the diagonal block: W21 = A21 L11^-T (so W21 = L21 D1) and
@@ -189,68 +175,115 @@ __global__ __launch_bounds__(256) void ldl_update(int n, int kb, int nb, double 
         }
 }
 
-// Triangular solves, one launch per 64-wide block column.  Every workgroup
-// re-solves the 64 x 64 diagonal block in one wave (register shuffles) from
-// the final right-hand side entries of that block, then applies the block's
-// columns to its own rows of the remaining right-hand side; workgroup 0 stores
-// the solved block.  Right-hand side (w) and solution (x) are separate arrays,
-// so no workgroup reads an entry another one writes in the same launch.
-//
-// forward:  L y = b, unit lower, L column-major           (rows below the block)
-// backward: L^T x = y' (y' = D^-1 y) with U = L^T stored column-major (rows above)
-__device__ __forceinline__ double diag_solve_wave(int n, const double *__restrict__ T, int kb,
-                                                  int nb, double wt, bool lower) {
-    const int t = threadIdx.x & 63;
-    double row[NB];
-    // lane t's row of the 64 x 64 diagonal block, loaded before the recurrence
+// X = L^-1 by recursive doubling.  The 64 x 64 diagonal blocks of X are the
+// block inverses from ldl_diag.  At level b (b = 64, 128, ...) every pair of
+// consecutive diagonal blocks [c1, c1+b), [r2, r2+b') (r2 = c1 + b) whose
+// inverses are known gives the off-diagonal block of the inverse of the pair:
+//   X(r2.., c1..) = -X22 L21 X11,
+// computed as T = L21 X11 (mode 0), then X21 = -X22 T (mode 1).  Both are
+// 64 x 64-tiled products that skip the zero tiles of the triangular factors.
+__global__ void inv_init(int n, const double *__restrict__ linv, double *__restrict__ X) {
+    const int blk = blockIdx.x, kb = blk * NB;
+    for (int t = threadIdx.x; t < NB * NB; t += blockDim.x) {
+        const int r = t % NB, c = t / NB;
+        if (kb + r < n && kb + c < n)
+            X[(size_t)(kb + r) + (size_t)(kb + c) * n] = linv[(size_t)blk * NB * NB + t];
+    }
+}
+
+__global__ __launch_bounds__(256) void inv_mul(int n, int b, int mode, const double *__restrict__ L,
+                                               double *__restrict__ X, double *__restrict__ T) {
+    const int p = blockIdx.z;
+    const int c1 = 2 * p * b, r2 = c1 + b;
+    const int rows2 = min(b, n - r2);
+    const int ti = blockIdx.x, tj = blockIdx.y;
+    if (ti * NB >= rows2) return;
+    __shared__ double As[NB][NB + 1];
+    __shared__ double Bs[NB][NB + 1];
+    double *Tp = T + (size_t)p * b * b;  // b x b column-major, rows < rows2 used
+    // mode 0: A(r, k) = L(r2 + r, c1 + k), B(k, c) = X(c1 + k, c1 + c), zero for k < c
+    // mode 1: A(r, k) = X(r2 + r, r2 + k), zero for k > r; B(k, c) = T(k, c)
+    const int kt0 = mode == 0 ? tj : 0;
+    const int kt1 = mode == 0 ? b / NB : ti + 1;
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    double acc[4][4];
 #pragma unroll
-    for (int k = 0; k < NB; ++k)
-        row[k] = (t < nb && k < nb) ? T[(size_t)(kb + t) + (size_t)(kb + k) * n] : 0.0;
-    double x = wt;
-    if (lower) {
+    for (int u = 0; u < 4; ++u)
 #pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+    for (int kt = kt0; kt < kt1; ++kt) {
+        for (int t = threadIdx.x; t < NB * NB; t += 256) {
+            const int q = t % NB, k = t / NB;  // element (q, k) of the A and B tiles
+            const int ar = ti * NB + q, ak = kt * NB + k;
+            const int bk = kt * NB + q, bc = tj * NB + k;
+            double av = 0.0, bv = 0.0;
+            if (mode == 0) {
+                if (ar < rows2) av = L[(size_t)(r2 + ar) + (size_t)(c1 + ak) * n];
+                bv = X[(size_t)(c1 + bk) + (size_t)(c1 + bc) * n];
+            } else {
+                if (ar < rows2 && ak < rows2) av = X[(size_t)(r2 + ar) + (size_t)(r2 + ak) * n];
+                if (bk < rows2) bv = Tp[(size_t)bk + (size_t)bc * b];
+            }
+            As[q][k] = av;
+            Bs[q][k] = bv;
+        }
+        __syncthreads();
         for (int k = 0; k < NB; ++k) {
-            const double xk = __shfl(x, k, 64);
-            if (t > k && t < nb) x = fma(-row[k], xk, x);
-        }
-    } else {
+            double av[4], bv[4];
 #pragma unroll
-        for (int k = NB - 1; k >= 0; --k) {
-            const double xk = __shfl(x, k, 64);
-            if (t < k && k < nb) x = fma(-row[k], xk, x);
+            for (int u = 0; u < 4; ++u) av[u] = As[tx + 16 * u][k];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) bv[v] = Bs[k][ty + 16 * v];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
         }
+        __syncthreads();
     }
-    return x;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = ti * NB + tx + 16 * u, c = tj * NB + ty + 16 * v;
+            if (r >= rows2) continue;
+            if (mode == 0)
+                Tp[(size_t)r + (size_t)c * b] = acc[u][v];
+            else
+                X[(size_t)(r2 + r) + (size_t)(c1 + c) * n] = -acc[u][v];
+        }
 }
 
-__global__ __launch_bounds__(256) void trsv_step(int n, int kb, int nb, const double *__restrict__ T,
-                                                 const double *__restrict__ d, double *w, double *x,
-                                                 int lower) {
-    __shared__ double xb[64];
-    if (threadIdx.x < 64) {
-        const int t = threadIdx.x;
-        const double wt = (t < nb) ? w[kb + t] : 0.0;
-        const double v = diag_solve_wave(n, T, kb, nb, wt, lower != 0);
-        if (t < nb) {
-            xb[t] = v;
-            if (blockIdx.x == 0) x[kb + t] = v;
-        }
+// Solve L D L^T x = b with X = L^-1 (unit lower, column-major) and XT, the
+// strict upper part of X^T: two products, one wavefront per entry.
+// forward: y_i = (b_i + sum_{j<i} X(i, j) b_j) / d_i   (infinite pivot: 0)
+__global__ __launch_bounds__(256) void inv_fwd(int n, const double *__restrict__ XT,
+                                               const double *__restrict__ d,
+                                               const double *__restrict__ b,
+                                               double *__restrict__ y) {
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (i >= n) return;
+    double acc = 0.0;
+    const double *col = XT + (size_t)i * n;  // column i of X^T = row i of X
+    for (int j = lane; j < i; j += 64) acc = fma(col[j], b[j], acc);
+    acc = wave_sum(acc);
+    if (lane == 0) {
+        const double v = b[i] + acc;
+        y[i] = isinf(d[i]) ? 0.0 : v / d[i];
     }
-    __syncthreads();
-    // remaining rows: below the block (forward) or above it (backward)
-    const int r0 = lower ? kb + nb : 0;
-    const int r1 = lower ? n : kb;
-    const int i = r0 + blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= r1) return;
-    double v = w[i];
-    for (int k = 0; k < nb; ++k) v = fma(-T[(size_t)i + (size_t)(kb + k) * n], xb[k], v);
-    w[i] = v;
 }
 
-// y = D^-1 y (an infinite pivot gives 0)
-__global__ void scale_by_pivots(int n, const double *__restrict__ d, double *y) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) y[i] = isinf(d[i]) ? 0.0 : y[i] / d[i];
+// backward: x_j = y_j + sum_{i>j} X(i, j) y_i
+__global__ __launch_bounds__(256) void inv_bwd(int n, const double *__restrict__ X,
+                                               const double *__restrict__ y,
+                                               double *__restrict__ x) {
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (j >= n) return;
+    double acc = 0.0;
+    const double *col = X + (size_t)j * n;
+    for (int i = j + 1 + lane; i < n; i += 64) acc = fma(col[i], y[i], acc);
+    acc = wave_sum(acc);
+    if (lane == 0) x[j] = y[j] + acc;
 }
 
 // U = L^T (64 x 64 tiles through LDS), unit diagonal implied
@@ -285,11 +318,12 @@ __global__ void count_nonzero_lower(int n, const double *A, unsigned long long *
 int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
     n = S.n;
     const size_t total = (size_t)n * n;
+    const int nblk = (n + NB - 1) / NB;
     double *A = A_.need(total);
     d_.need(n);
     orig_.need(n);
     W_.need((size_t)n * NB);
-    linv_.need((size_t)NB * NB);
+    double *linv = linv_.need((size_t)nblk * NB * NB);
     ninf_.need(1);
     hipLaunchKernelGGL(dense_zero, dim3(2048), dim3(256), 0, st, total, A);
     hipLaunchKernelGGL(dense_fill, dim3(n), dim3(64), 0, st, n, S.rowptr.get(), S.col.get(),
@@ -297,22 +331,41 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
     OTIP_HIP(hipMemsetAsync(ninf_.get(), 0, sizeof(int), st));
     for (int kb = 0; kb < n; kb += NB) {
         const int nb = std::min(NB, n - kb);
-        hipLaunchKernelGGL(ldl_diag, dim3(1), dim3(256), 0, st, n, kb, nb, A, orig_.get(),
-                           d_.get(), pivtol, ninf_.get(), linv_.get());
+        double *Li = linv + (size_t)(kb / NB) * NB * NB;
+        hipLaunchKernelGGL(ldl_diag, dim3(1), dim3(64), 0, st, n, kb, nb, A, orig_.get(),
+                           d_.get(), pivtol, ninf_.get(), Li);
         const int rows = n - kb - nb;
         if (rows > 0) {
             hipLaunchKernelGGL(ldl_panel, dim3(grid_for(rows, NB)), dim3(256), 0, st, n, kb, nb,
-                               A, d_.get(), W_.get(), linv_.get());
+                               A, d_.get(), W_.get(), Li);
             const unsigned tiles = grid_for(rows, NB);
             hipLaunchKernelGGL(ldl_update, dim3(tiles, tiles), dim3(256), 0, st, n, kb, nb, A,
                                W_.get());
         }
     }
+    // X = L^-1 (unit lower; the strict lower part of A holds L)
+    double *X = X_.need(total);
+    hipLaunchKernelGGL(dense_zero, dim3(2048), dim3(256), 0, st, total, X);
+    hipLaunchKernelGGL(inv_init, dim3(nblk), dim3(256), 0, st, n, linv, X);
+    if (n > NB) {
+        size_t tmax = 0;
+        for (int b = NB; b < n; b *= 2) {
+            const int pairs = (n - b + 2 * b - 1) / (2 * b);
+            tmax = std::max(tmax, (size_t)pairs * b * b);
+        }
+        double *T = T_.need(tmax);
+        for (int b = NB; b < n; b *= 2) {
+            const int pairs = (n - b + 2 * b - 1) / (2 * b);
+            dim3 grid(b / NB, b / NB, pairs);
+            hipLaunchKernelGGL(inv_mul, grid, dim3(256), 0, st, n, b, 0, A, X, T);
+            hipLaunchKernelGGL(inv_mul, grid, dim3(256), 0, st, n, b, 1, A, X, T);
+        }
+    }
     OTIP_HIP(hipGetLastError());
-    U_.need(total);
+    XT_.need(total);
     const unsigned tl = grid_for(n, 64);
-    hipLaunchKernelGGL(transpose_lower, dim3(tl, tl), dim3(256), 0, st, n, A, U_.get());
-    DBuf<unsigned long long> c;
+    hipLaunchKernelGGL(transpose_lower, dim3(tl, tl), dim3(256), 0, st, n, X, XT_.get());
+    DBuf<unsigned long long> &c = cnt_;
     c.need(1);
     OTIP_HIP(hipMemsetAsync(c.get(), 0, sizeof(unsigned long long), st));
     hipLaunchKernelGGL(count_nonzero_lower, dim3(1024), dim3(256), 0, st, n, A, c.get());
@@ -326,22 +379,10 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
 }
 
 void DenseLDL::solve(hipStream_t st, const double *b, double *x) {
-    double *w = v_.need(n);
-    double *yv = W_.get();  // n doubles of the panel buffer (free after factor)
-    OTIP_HIP(hipMemcpyAsync(w, b, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-    for (int kb = 0; kb < n; kb += NB) {
-        const int nb = std::min(NB, n - kb);
-        const int rows = n - kb - nb;
-        hipLaunchKernelGGL(trsv_step, dim3(std::max(1u, grid_for(rows, 256))), dim3(256), 0, st,
-                           n, kb, nb, A_.get(), d_.get(), w, yv, 1);
-    }
-    // yv = D^-1 L^-1 b; then backward on U = L^T
-    hipLaunchKernelGGL(scale_by_pivots, dim3(grid_for(n, 256)), dim3(256), 0, st, n, d_.get(), yv);
-    for (int kb = ((n - 1) / NB) * NB; kb >= 0; kb -= NB) {
-        const int nb = std::min(NB, n - kb);
-        hipLaunchKernelGGL(trsv_step, dim3(std::max(1u, grid_for(kb, 256))), dim3(256), 0, st, n,
-                           kb, nb, U_.get(), d_.get(), yv, x, 0);
-    }
+    double *y = v_.need(n);
+    const unsigned g = grid_for(n, 4);
+    hipLaunchKernelGGL(inv_fwd, dim3(g), dim3(256), 0, st, n, XT_.get(), d_.get(), b, y);
+    hipLaunchKernelGGL(inv_bwd, dim3(g), dim3(256), 0, st, n, X_.get(), y, x);
     OTIP_HIP(hipGetLastError());
 }
 

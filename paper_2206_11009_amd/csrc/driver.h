@@ -52,6 +52,7 @@ class Solver {
     int64_t select_removals(uint8_t *removed);
     void starting_point();
     void finalize(Result &res);
+    void reset_state();
     static double now();
     void log(const char *fmt, ...);
 
@@ -83,6 +84,12 @@ class Solver {
     DBuf<double> tmp_f64a, tmp_f64b, tmp_f64c, tmp_f64d;
     DBuf<int32_t> tmp_i32a, tmp_i32b;
     DBuf<uint32_t> tmp_u32a;
+    DBuf<uint64_t> init_, sel_idx_;
+    DBuf<double> sel_r_;
+    DBuf<uint8_t> removed_;
+    DBuf<int32_t> zc_;
+    DBuf<double> yws_, zws_;
+    bool warm_used = false;
     bool schur_valid = false;
 
     Mode mode = Mode::PCG;

@@ -572,12 +572,35 @@ struct FScaleIn {
     __device__ void operator()(int64_t k) const { dst[k] = src[k] * f; }
 };
 
+// Per-solve scalars back to their initial values; device buffers are kept so
+// that a solver reused for a stream of problems allocates (and frees) nothing
+// once it has seen the largest one.
+void Solver::reset_state() {
+    psi_ = psi_max = 0;
+    schur_valid = false;
+    mode = Mode::PCG;
+    cg_failed = false;
+    cg_its_iter = max_cg_solve = 0;
+    cg_total = 0;
+    direct_its = iterations = 0;
+    pricing_passes = 0;
+    max_fill = 0.0;
+    cg_its_last = 0;
+    solves_last = 2;
+    t_pricing = t_newton = t_direct = t_update = t_setup = t_final = 0.0;
+    t_spmv.reset();
+    t_price.reset();
+    warm_used = false;
+}
+
 int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
     const double T0 = now();
+    reset_state();
     P = prm;
     t_spmv.on = t_price.on = P.profile != 0;
     schur.timer = &t_spmv;
     scan.timer = &t_price;
+    scan.tile = P.price_tile;
     m = pr.m;
     n = pr.n;
     xs = pr.xs;
@@ -676,8 +699,16 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
     // ---- initial support (Section 3.2, end)
     double ts = now();
     int64_t T = 0;
-    DBuf<uint64_t> init;
-    const int64_t psi0 = scan.initial_support(st, m, n, xs, xt, P.kappa, cmax, init, &T);
+    DBuf<uint64_t> &init = init_;
+    OTIP_CHECK((pr.y0 == nullptr) == (pr.z0 == nullptr), OTIP_EINVAL,
+               "warm start needs both y0 and z0");
+    int64_t psi0 = -1;
+    if (pr.y0) {
+        psi0 = scan.warm_support(st, m, n, xs, xt, pr.y0, pr.z0,
+                                 P.ws_kappa > 0 ? P.ws_kappa : P.kappa, init, yws_, zws_);
+        warm_used = psi0 >= 0;
+    }
+    if (psi0 < 0) psi0 = scan.initial_support(st, m, n, xs, xt, P.kappa, cmax, init, &T);
     alloc_support(std::max<int64_t>(psi0 * 2, psi0 + 4 * (int64_t)std::max(m, n)));
     OTIP_HIP(hipMemcpyAsync(idx.get(), init.get(), sizeof(uint64_t) * psi0, hipMemcpyDeviceToDevice, st));
     psi_ = psi0;
@@ -694,11 +725,11 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
         OTIP_CHECK(n <= P.dense_max_n, OTIP_EUNSUPPORTED, "direct solver: n exceeds dense_max_n");
     std::vector<int64_t> psi_hist;
     const int64_t kcap = P.enter_cap > 0 ? P.enter_cap : m;
-    DBuf<uint64_t> sel_idx;
-    DBuf<double> sel_r;
+    DBuf<uint64_t> &sel_idx = sel_idx_;
+    DBuf<double> &sel_r = sel_r_;
     sel_idx.need(kcap);
     sel_r.need(kcap);
-    DBuf<uint8_t> removed;
+    DBuf<uint8_t> &removed = removed_;
     int status = OTIP_EMAXITER;
     int it = 0;
     cg_failed = false;
@@ -718,7 +749,9 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
             int64_t nbig = 0;
             if (k > 0) {
                 std::vector<double> rs(k);
-                OTIP_HIP(hipMemcpy(rs.data(), sel_r.get(), sizeof(double) * k, hipMemcpyDeviceToHost));
+                OTIP_HIP(hipMemcpyAsync(rs.data(), sel_r.get(), sizeof(double) * k,
+                                        hipMemcpyDeviceToHost, st));
+                OTIP_HIP(hipStreamSynchronize(st));
                 const double thr = P.cert_rel * std::max(1.0, std::fabs(primal));
                 for (int64_t q = 0; q < k; ++q)
                     if (std::fabs(rs[q] * zeta) * (sa * omega) > thr) ++nbig;  // ordered by r
@@ -1179,7 +1212,7 @@ int64_t Solver::schur_export(int m_, int n_, int64_t psi, const uint64_t *idx_in
     n = n_;
     OTIP_CHECK(m >= 1 && n >= 1 && psi >= 1, OTIP_EINVAL, "schur: bad sizes");
     // the views need coordinates only for costs; use a zero coordinate table
-    DBuf<int32_t> zc;
+    DBuf<int32_t> &zc = zc_;
     const int mx = std::max(m, n);
     OTIP_HIP(hipMemsetAsync(zc.need((size_t)2 * mx), 0, sizeof(int32_t) * 2 * mx, st));
     xs = zc.get();

@@ -25,6 +25,10 @@ void exclusive_scan_i64(hipStream_t st, const int64_t *in, int64_t *out, int64_t
                         DBuf<char> &tmp);
 
 // ------------------------------------------------------------------- full scans
+// targets per scan block: `tile` if it is a power of two in [16, 256], else a
+// size-based choice
+int pick_tj(int m, int n, int tile);
+
 struct PriceResult {
     int64_t count;  // selected
     int64_t nneg;   // negative reduced costs outside the support
@@ -35,6 +39,7 @@ class Scanner {
   public:
     LaunchTimer *timer = nullptr;  // pricing-pass launches (optional)
     int64_t scans = 0;             // full m*n passes so far
+    int tile = 0;                  // targets per scan block (0: chosen from m, n)
     // <= kmax most negative reduced costs outside the support, ordered by
     // (r, idx); outputs may be null.
     PriceResult price(hipStream_t st, int m, int n, const int32_t *xs, const int32_t *xt,
@@ -49,6 +54,11 @@ class Scanner {
               const double *y, const double *z, double *out, int64_t *arg);
     int64_t initial_support(hipStream_t st, int m, int n, const int32_t *xs, const int32_t *xt,
                             double kappa, int64_t cmax, DBuf<uint64_t> &out, int64_t *T);
+    // initial support from predicted duals (c-transform, smallest reduced
+    // costs, row and column covers); -1 if the duals are unusable
+    int64_t warm_support(hipStream_t st, int m, int n, const int32_t *xs, const int32_t *xt,
+                         const double *y0, const double *z0, double kappa,
+                         DBuf<uint64_t> &out, DBuf<double> &yw, DBuf<double> &zw);
 
   private:
     void prepare(hipStream_t st, int m, int n, const int32_t *xt, const double *z);
@@ -60,6 +70,7 @@ class Scanner {
     DBuf<uint64_t> barg_;
     DBuf<char> tmp_;
     DBuf<float> f32a_;
+    DBuf<int> flag_;
 };
 
 // ---------------------------------------------------------- fixed-order reductions
@@ -137,9 +148,32 @@ class DenseLDL {
     int n = 0;
 
   private:
-    DBuf<double> A_, U_, d_, orig_, W_, v_, linv_;
+    DBuf<double> A_, X_, XT_, T_, d_, orig_, W_, v_, linv_;
     DBuf<int> ninf_;
+    DBuf<unsigned long long> cnt_;
     int64_t nnzL_ = 0;
+};
+
+// Warm-start network (cnn.hip): 4 dilated 3x3 convolution layers, 32 channels,
+// FP32.  Buffers for activations and gradients are owned here.
+class WarmNet {
+  public:
+    static int64_t param_count();
+    // out = net(x), x: N x 2 x H x W, out: N x 2 x H x W (NCHW)
+    void forward(hipStream_t st, const float *theta, int N, int H, int W, const float *x,
+                 float *out);
+    // mean-squared-error loss of net(x) against target; its gradient into g
+    double grad(hipStream_t st, const float *theta, int N, int H, int W, const float *x,
+                const float *target, float *g);
+    void adam(hipStream_t st, float *theta, float *m, float *v, const float *g, int step,
+              double lr, double b1, double b2, double eps);
+    // predicted duals of a side x side grid pair (pixel cost units)
+    void predict(hipStream_t st, const float *theta, int side, const double *a, const double *b,
+                 double *y0, double *z0);
+
+  private:
+    DBuf<float> a_[3], out_, ga_, gb_, in_;
+    DBuf<double> part_;
 };
 
 // dense Kronecker products (kron.hip)

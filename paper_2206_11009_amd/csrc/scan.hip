@@ -175,7 +175,8 @@ __global__ void decode_selection(int64_t k, int m, const uint64_t *__restrict__ 
 
 // targets per block: enough blocks to fill 256 CUs several times over, but
 // enough work per block to amortise the histogram's LDS setup
-static int pick_tj(int m, int n) {
+int pick_tj(int m, int n, int tile) {
+    if (tile >= 16 && tile <= 256 && (tile & (tile - 1)) == 0) return tile;
     const int64_t rb = (m + 255) / 256;
     int tj = 256;
     while (tj > 16 && rb * ((n + tj - 1) / tj) < 2048) tj >>= 1;
@@ -196,7 +197,7 @@ PriceResult Scanner::price(hipStream_t st, int m, int n, const int32_t *xs, cons
     PriceResult res{0, 0, 0};
     if (m <= 0 || n <= 0) return res;
     prepare(st, m, n, xt, z);
-    const int tj = pick_tj(m, n);
+    const int tj = pick_tj(m, n, tile);
     dim3 grid(grid_for(m, kScanBlock), grid_for(n, tj));
     hist_.need(kHistBins);
     cnt_.need(1);
@@ -363,7 +364,7 @@ __global__ __launch_bounds__(kScanBlock) void rmin_pass(MinArgs a) {
 void Scanner::rmin(hipStream_t st, int m, int n, const int32_t *xs, const int32_t *xt,
                    const double *y, const double *z, double *out, int64_t *arg) {
     prepare(st, m, n, xt, z);
-    const int tj = pick_tj(m, n);
+    const int tj = pick_tj(m, n, tile);
     dim3 grid(grid_for(m, kScanBlock), grid_for(n, tj));
     const size_t nb = (size_t)grid.x * grid.y;
     bmin_.need(nb);
@@ -526,7 +527,7 @@ int64_t Scanner::initial_support(hipStream_t st, int m, int n, const int32_t *xs
                                  DBuf<uint64_t> &out, int64_t *T_out) {
     const int64_t target = std::min<int64_t>((int64_t)std::ceil(kappa * (double)(m + n - 1)),
                                              (int64_t)m * (int64_t)n);
-    const int tj = pick_tj(m, n);
+    const int tj = pick_tj(m, n, tile);
     dim3 grid(grid_for(m, kScanBlock), grid_for(n, tj));
     hist_.need(kHistBins);
     cnt_.need(1);
@@ -790,7 +791,7 @@ PriceResult Scanner::price_mixed(hipStream_t st, int m, int n, const int32_t *xs
     jt_.need((size_t)n * sizeof(JEntry32));
     hipLaunchKernelGGL(build_jtab32, dim3(grid_for(n, 256)), dim3(256), 0, st, n, xt, z,
                        (JEntry32 *)jt_.get());
-    const int tj = pick_tj(m, n);
+    const int tj = pick_tj(m, n, tile);
     dim3 grid(grid_for(m, kScanBlock), grid_for(n, tj));
     hist_.need(kHistBins + 3);
     cnt_.need(2);

@@ -1,0 +1,72 @@
+"""What the trained warm-start network gains over the plain initial support.
+
+The network (paper_2206_11009_amd/ws_weights.bin, trained by ws_train.py on
+32 x 32 problems disjoint from these) predicts duals for held-out problems of
+the uneven-batch family (sides 8..32); the solves with and without the
+prediction must reach the same certified optimum, and the learned start must
+need fewer outer iterations on average.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synthetic import batch_instances
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2206_11009_amd as otip
+    c = otip.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def weights(ctx):
+    import paper_2206_11009_amd as otip
+    return otip.load_ws_weights(ctx)
+
+
+def side_of(inst):
+    return int(round(np.sqrt(inst.m)))
+
+
+def c_transform_bound(inst, y0):
+    """Dual objective of the c-transformed prediction (a valid lower bound)."""
+    C = ((inst.xs[:, None, :].astype(np.int64) - inst.xt[None, :, :]) ** 2).sum(-1).astype(float)
+    z = (C - y0[:, None]).min(axis=0)
+    y = (C - z[None, :]).min(axis=1)
+    return float(inst.a @ y + inst.b @ z)
+
+
+def test_learned_start_gains_over_plain(ctx, weights):
+    import paper_2206_11009_amd as otip
+    insts = batch_instances(96)
+    probs = [(i.a, i.b, i.xs, i.xt) for i in insts]
+    plain = otip.otip_solve_batch(ctx, probs)
+    preds = [otip.otip_ws_predict(ctx, weights, side_of(i), i.a, i.b) for i in insts]
+    warm = otip.otip_solve_batch(ctx, [p + (y0, z0) for p, (y0, z0) in zip(probs, preds)])
+    for inst, p, w in zip(insts, plain, warm):
+        for r in (p, w):
+            assert r.status == 0 and r.rel_gap <= 1e-6 and r.marginal_residual <= 1e-8
+            assert oracle.is_forest(r.rows, r.cols, inst.m, inst.n)
+        assert abs(w.objective - p.objective) <= 1e-6 * abs(p.objective)
+    it_p = np.array([r.iterations for r in plain], float)
+    it_w = np.array([r.iterations for r in warm], float)
+    print(f"mean outer iterations: plain {it_p.mean():.2f}, learned {it_w.mean():.2f}")
+    assert it_w.mean() <= 0.9 * it_p.mean()
+
+
+def test_predicted_duals_are_near_optimal(ctx, weights):
+    """The c-transform of the prediction is a dual bound within a few percent
+    of the optimum (the plain rule starts from no dual information at all)."""
+    import paper_2206_11009_amd as otip
+    insts = batch_instances(12)
+    for inst in insts:
+        y0, _ = otip.otip_ws_predict(ctx, weights, side_of(inst), inst.a, inst.b)
+        opt = otip.otip_solve(ctx, inst.a, inst.b, inst.xs, inst.xt).objective
+        bound = c_transform_bound(inst, y0.cpu().numpy())
+        assert bound <= opt * (1 + 1e-9)
+        assert bound >= 0.9 * opt, (inst.name, bound, opt)
