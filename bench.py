@@ -10,10 +10,13 @@ variables, Gaussian-mixture histograms, squared-Euclidean cost generated on the
 fly, FP64); step k solves seed k mod 5.  Inputs are uploaded to HBM before the
 timed region.
 
-Prints one JSON line: seconds per LP (lower is better), the live roofline of
-the dominant kernel (HIP events around each of its launches on its stream),
-pricing throughput, and the CPU oracle timed on a bounded sample of the same
-workload.
+Prints one JSON line: seconds per LP (lower is better) of the plain FP64
+method, the live roofline of the dominant kernel (HIP events around each of its
+launches on its stream), pricing throughput, the same instances solved by the
+mixed-precision and learned-warm-start forms ("forms"; the network's prediction
+is inside the timed region), and the CPU oracle timed on a bounded sample of the
+same workload.  --config c4 times whole batches of 512 uneven instances
+(otip_solve_batch) and reports seconds per LP of the batch.
 """
 from __future__ import annotations
 
@@ -33,6 +36,7 @@ WORKLOADS = {
     "c1": "16x16 Gaussian-mixture grid pair (m=n=256, 65,536 variables), 3 bumps, FP64",
     "c2": "64x64 Gaussian-mixture grid pair (m=n=4096, 16.8M variables), 5 bumps, FP64",
     "c3": "128x128 white-noise grid pair (m=n=16384, 268M variables), FP64",
+    "c4": "512 Gaussian-mixture grid pairs of side U{8..32} (1-5 bumps), batched",
     "c5": "256x256 Cauchy-bump grid pair (m=n=65536, 4.29e9 variables), FP64",
 }
 
@@ -87,47 +91,75 @@ def cpu_baseline(cfg, budget_s=20.0, fallback_its=None):
             "cores": 1, "kind": "oracle", "sample": how}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures a single GPU; this build has no multi-GPU path "
-              "(each LP solve runs on one MI355X).", file=sys.stderr)
-        sys.exit(2)
+def upload(insts):
+    import torch
+    return [[torch.as_tensor(x, device="cuda:0") for x in (i.a, i.b, i.xs, i.xt)] for i in insts]
 
+
+def side_of(inst):
+    side = int(round(inst.m ** 0.5))
+    return side if side * side == inst.m == inst.n else None
+
+
+def run_single(ctx, dev, insts, prm, weights, steps, warmup):
+    """Seconds per LP over `steps` solves (after `warmup`), with the learned
+    prediction (inside the timed region) when weights are given."""
     import torch
     import paper_2206_11009_amd as otip
-    from synthetic import CONFIGS, config_instance
 
-    ctx = otip.Context(0)
-    seeds = CONFIGS[args.config]["seeds"]
-    dev = []
-    for k in range(args.warmup + args.steps):
-        inst = config_instance(args.config, k % seeds)
-        dev.append([torch.as_tensor(x, device="cuda:0") for x in (inst.a, inst.b, inst.xs, inst.xt)])
-    prm = otip.params(profile=1,
-                      precision=otip.OTIP_MIXED if args.precision == "mixed" else otip.OTIP_FP64)
-    for k in range(args.warmup):
-        otip.otip_solve(ctx, *dev[k], prm)
+    def one(k):
+        a, b, xs, xt = dev[k]
+        if weights is None:
+            return otip.otip_solve(ctx, a, b, xs, xt, prm)
+        y0, z0 = otip.otip_ws_predict(ctx, weights, side_of(insts[k]), a, b)
+        return otip.otip_solve(ctx, a, b, xs, xt, prm, y0=y0, z0=z0)
+
+    for k in range(warmup):
+        one(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [one(warmup + k).info for k in range(steps)]
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, infos
+
+
+def run_batch(ctx, dev, insts, prm, weights, steps, warmup):
+    """Seconds per LP of whole-batch solves (otip_solve_batch)."""
+    import torch
+    import paper_2206_11009_amd as otip
+
+    def one():
+        if weights is None:
+            return otip.otip_solve_batch(ctx, dev, prm)
+        probs = []
+        for (a, b, xs, xt), inst in zip(dev, insts):
+            y0, z0 = otip.otip_ws_predict(ctx, weights, side_of(inst), a, b)
+            probs.append((a, b, xs, xt, y0, z0))
+        return otip.otip_solve_batch(ctx, probs, prm)
+
+    for _ in range(warmup):
+        one()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
-    for k in range(args.steps):
-        r = otip.otip_solve(ctx, *dev[args.warmup + k], prm)
-        infos.append(r.info)
+    for _ in range(steps):
+        infos += [r.info for r in one()]
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    sec = (t1 - t0) / args.steps
-    for inf in infos:
-        if not (inf["rel_gap"] <= 1e-6 and inf["marginal_residual"] <= 1e-8):
-            raise SystemExit(f"solve not certified: {inf}")
+    return (time.perf_counter() - t0) / (steps * len(dev)), infos
 
+
+def summary(sec, infos):
+    n = len(infos)
+    return {"s_per_lp": sec,
+            "iterations_mean": sum(i["iterations"] for i in infos) / n,
+            "cg_iterations_mean": sum(i["cg_iterations"] for i in infos) / n,
+            "direct_iterations_mean": sum(i["direct_iterations"] for i in infos) / n,
+            "rel_gap_max": max(i["rel_gap"] for i in infos),
+            "certified": all(i["rel_gap"] <= 1e-6 and i["marginal_residual"] <= 1e-8
+                             for i in infos)}
+
+
+def rooflines(infos):
     spmv_ms = sum(i["spmv_ms"] for i in infos)
     spmv_n = sum(i["spmv_launches"] for i in infos)
     spmv_b = sum(i["spmv_bytes"] for i in infos)
@@ -146,6 +178,61 @@ def main():
     for r in (spmv, price):
         r["frac"] = r["achieved"] / r["peak"]
     dominant, other = (spmv, price) if spmv_ms >= pr_ms else (price, spmv)
+    return dominant, other, pr_e / max(pr_ms, 1e-12) / 1e6
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
+                    help="precision of the headline (plain) measurement")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the mixed-precision and learned-warm-start forms")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures a single GPU; this build has no multi-GPU path "
+              "(each LP solve runs on one MI355X).", file=sys.stderr)
+        sys.exit(2)
+
+    import paper_2206_11009_amd as otip
+    from paper_2206_11009_amd.autotune import tuned
+    from synthetic import CONFIGS, batch_instances, config_instance
+
+    ctx = otip.Context(0)
+    batched = args.config == "c4"
+    if batched:
+        insts = batch_instances(512)
+        run = run_batch
+    else:
+        seeds = CONFIGS[args.config]["seeds"]
+        insts = [config_instance(args.config, k % seeds) for k in range(args.warmup + args.steps)]
+        run = run_single
+    dev = upload(insts)
+    prec = otip.OTIP_MIXED if args.precision == "mixed" else otip.OTIP_FP64
+    tune = tuned(max(i.m for i in insts), max(i.n for i in insts), batched)
+    sec, infos = run(ctx, dev, insts, otip.params(profile=1, precision=prec, **tune), None,
+                     args.steps, args.warmup)
+    if not summary(sec, infos)["certified"]:
+        raise SystemExit(f"solve not certified: {infos}")
+    dominant, other, gcosts = rooflines(infos)
+
+    forms = {f"{args.precision}_plain": summary(sec, infos)}
+    weights = None
+    if not args.no_forms and all(side_of(i) for i in insts) and os.path.exists(otip.WS_WEIGHTS):
+        weights = otip.load_ws_weights(ctx)
+        for name, p, w in [("mixed_plain", otip.OTIP_MIXED, None),
+                           (f"{args.precision}_learned", prec, weights),
+                           ("mixed_learned", otip.OTIP_MIXED, weights)]:
+            if name in forms:
+                continue
+            s2, inf2 = run(ctx, dev, insts, otip.params(precision=p, **tune), w, args.steps,
+                           args.warmup)
+            forms[name] = summary(s2, inf2)
+            forms[name]["speedup_vs_plain"] = sec / s2
 
     out = {
         "metric": baseline_metric(),
@@ -154,22 +241,26 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * sec,
+        "ms_per_step": 1e3 * sec * (len(dev) if batched else 1),
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.config], "seeds": f"k mod {seeds}",
-                   "certified_rel_gap": 1e-6, "precision": args.precision},
+        "config": {"workload": WORKLOADS[args.config],
+                   "instances": (f"512 per step" if batched else
+                                 f"step k solves seed k mod {CONFIGS[args.config]['seeds']}"),
+                   "certified_rel_gap": 1e-6, "precision": args.precision,
+                   "form": "plain initial support", "tuned": tune},
         "roofline": dominant,
         "roofline_other": other,
-        "pricing_gcosts_per_s": pr_e / max(pr_ms, 1e-12) / 1e6,
-        "iterations_mean": sum(i["iterations"] for i in infos) / len(infos),
-        "cg_iterations_mean": sum(i["cg_iterations"] for i in infos) / len(infos),
-        "rel_gap_max": max(i["rel_gap"] for i in infos),
+        "pricing_gcosts_per_s": gcosts,
+        "iterations_mean": forms[f"{args.precision}_plain"]["iterations_mean"],
+        "cg_iterations_mean": forms[f"{args.precision}_plain"]["cg_iterations_mean"],
+        "rel_gap_max": forms[f"{args.precision}_plain"]["rel_gap_max"],
+        "forms": forms,
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not batched:
         out["cpu_baseline"] = cpu_baseline(args.config, fallback_its=out["iterations_mean"])
     print(json.dumps(out), flush=True)
 

@@ -42,7 +42,7 @@ enum otip_status {
     OTIP_EINVAL = 1,      /* bad argument: sizes, null pointers, masses */
     OTIP_ENOMEM = 2,      /* device allocation failed */
     OTIP_EHIP = 3,        /* HIP runtime error */
-    OTIP_EMAXITER = 4,    /* iteration limit: result valid, gap may exceed tol */
+    OTIP_EMAXITER = 4,    /* iteration limit: result valid but not certified to tol */
     OTIP_ENUMERIC = 5,    /* NaN or breakdown */
     OTIP_EUNSUPPORTED = 6 /* request outside what this build supports */
 };
@@ -122,7 +122,7 @@ typedef struct otip_problem {
 /* Summary of a solve (Section 5.3 reports iterations, time, CG iterations,
  * fill and iterative/direct iteration counts; Table 3). */
 typedef struct otip_info {
-    int32_t status;            /* OTIP_OK or OTIP_EMAXITER */
+    int32_t status;            /* OTIP_OK (certified), OTIP_EMAXITER or OTIP_ENUMERIC */
     int32_t iterations;        /* outer iterations */
     int32_t cg_iterations;     /* total CG iterations */
     int32_t direct_iterations; /* iterations solved by the direct factorisation */
@@ -173,8 +173,12 @@ const char *otip_last_error(const otip_ctx *ctx);
  * Solve one problem (the whole method of Sections 3-4: initial support,
  * Newton steps on the restricted problem, pricing and support updates, the
  * CG -> LDL^T switch; then a final primal projection, purification to a basic
- * plan and the dual certificate).  params may be NULL (defaults).  On OTIP_OK or
- * OTIP_EMAXITER *out holds a result to query and free.
+ * plan and the dual certificate).  params may be NULL (defaults).
+ * OTIP_OK means certified: the plan meets the marginals to 1e-9 (relative, 1-norm)
+ * and its gap to the certified dual bound is at most params->tol.  On OTIP_OK,
+ * OTIP_EMAXITER (limits reached before that) or OTIP_ENUMERIC (the iterate
+ * became non-finite) *out holds a result to query and free; only OTIP_OK's is
+ * certified.
  */
 int otip_solve(otip_ctx *ctx, const otip_problem *pr, const otip_params *params,
                otip_result **out);
@@ -186,8 +190,9 @@ int otip_solve(otip_ctx *ctx, const otip_problem *pr, const otip_params *params,
  * solver whose device buffers persist across problems and calls, so that the
  * many small launches of different instances overlap on the device.  Input
  * arrays must be ready on the context's stream, which is synchronised first.
- * Returns OTIP_OK, or OTIP_EMAXITER if any instance hit the iteration limit
- * (every outs[k] is valid then).  On any other error no result is returned
+ * Returns OTIP_OK if every instance is certified, else OTIP_EMAXITER or
+ * OTIP_ENUMERIC (the worse of the instances' statuses); every outs[k] is valid
+ * then and its info.status tells its own.  On any other error no result is returned
  * (every outs[k] is NULL) and otip_last_error names the failing instance.
  * The context must not be used by another thread during the call.
  */
@@ -214,10 +219,11 @@ void otip_result_free(otip_result *r);
  *   outside the support): HOST.
  *   precision: OTIP_FP64, or OTIP_MIXED (FP32 scan with an FP64 re-check of
  *   every candidate within a proven margin; same result).
+ *   tile: targets per workgroup (as otip_params.price_tile; 0 = by size).
  */
 int otip_price(otip_ctx *ctx, int32_t m, int32_t n, const int32_t *xs, const int32_t *xt,
-               const double *y, const double *z, const uint32_t *support_bitmap,
-               int64_t kmax, int32_t precision, int32_t *out_i, int32_t *out_j, double *out_r,
+               const double *y, const double *z, const uint32_t *support_bitmap, int64_t kmax,
+               int32_t precision, int32_t tile, int32_t *out_i, int32_t *out_j, double *out_r,
                int64_t *out_count, int64_t *out_nneg);
 
 /* min over ALL (i, j) of ((double)C_ij - y_i) - z_j and the first variable index

@@ -154,7 +154,7 @@ def otip_solve(ctx: Context, a, b, xs, xt, prm: otip_params | None = None, y0=No
     h = ctypes.c_void_p()
     rc = ctx._lib.otip_solve(ctx.handle, ctypes.byref(pr),
                              ctypes.byref(prm) if prm is not None else None, ctypes.byref(h))
-    ctx.check(rc, (OTIP_OK, OTIP_EMAXITER))
+    ctx.check(rc, (OTIP_OK, OTIP_EMAXITER, OTIP_ENUMERIC))
     try:
         d, rows, cols, vals = _collect(ctx, h, rc)
         y = np.empty(pr.m, np.float64)
@@ -179,7 +179,7 @@ def otip_solve_batch(ctx: Context, problems, prm: otip_params | None = None):
     outs = (ctypes.c_void_p * len(problems))()
     rc = ctx._lib.otip_solve_batch(ctx.handle, prs, len(problems),
                                    ctypes.byref(prm) if prm is not None else None, outs)
-    ctx.check(rc, (OTIP_OK, OTIP_EMAXITER))
+    ctx.check(rc, (OTIP_OK, OTIP_EMAXITER, OTIP_ENUMERIC))
     results = []
     for k in range(len(problems)):
         h = ctypes.c_void_p(outs[k])
@@ -193,7 +193,8 @@ def otip_solve_batch(ctx: Context, problems, prm: otip_params | None = None):
     return results
 
 
-def otip_price(ctx: Context, xs, xt, y, z, bitmap, kmax: int, precision: int = OTIP_FP64):
+def otip_price(ctx: Context, xs, xt, y, z, bitmap, kmax: int, precision: int = OTIP_FP64,
+               tile: int = 0):
     """Pricing scan; returns (i, j, r) device tensors of the selected columns and
     the count of negative reduced costs outside the support."""
     torch = _torch()
@@ -208,7 +209,7 @@ def otip_price(ctx: Context, xs, xt, y, z, bitmap, kmax: int, precision: int = O
     cnt, nneg = ctypes.c_int64(), ctypes.c_int64()
     ctx.check(ctx._lib.otip_price(ctx.handle, m, n, _ptr(XS), _ptr(XT), _ptr(Y), _ptr(Z),
                                   _ptr(BM) if BM is not None else None, int(kmax), precision,
-                                  _ptr(oi), _ptr(oj), _ptr(orr), ctypes.byref(cnt),
+                                  int(tile), _ptr(oi), _ptr(oj), _ptr(orr), ctypes.byref(cnt),
                                   ctypes.byref(nneg)))
     c = int(cnt.value)
     return oi[:c], oj[:c], orr[:c], int(nneg.value)

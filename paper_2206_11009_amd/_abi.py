@@ -73,7 +73,7 @@ SIGNATURES = {
     "otip_result_info": (ctypes.c_int, [_p, ctypes.POINTER(otip_info)]),
     "otip_result_copy": (ctypes.c_int, [_p, _p, _p, _p, _p, _p]),
     "otip_result_free": (None, [_p]),
-    "otip_price": (ctypes.c_int, [_p, _c_i32, _c_i32, _p, _p, _p, _p, _p, _c_i64, _c_i32,
+    "otip_price": (ctypes.c_int, [_p, _c_i32, _c_i32, _p, _p, _p, _p, _p, _c_i64, _c_i32, _c_i32,
                                   _p, _p, _p, ctypes.POINTER(_c_i64), ctypes.POINTER(_c_i64)]),
     "otip_rmin": (ctypes.c_int, [_p, _c_i32, _c_i32, _p, _p, _p, _p,
                                  ctypes.POINTER(_c_f64), ctypes.POINTER(_c_i64)]),

@@ -241,9 +241,12 @@ int otip_solve_batch(otip_ctx *ctx, const otip_problem *prs, int32_t count,
         return first_code;
     }
     ctx->err.clear();
-    for (int32_t k = 0; k < count; ++k)
-        if (codes[k] == OTIP_EMAXITER) return OTIP_EMAXITER;
-    return OTIP_OK;
+    int worst = OTIP_OK;
+    for (int32_t k = 0; k < count; ++k) {
+        if (codes[k] == OTIP_ENUMERIC) worst = OTIP_ENUMERIC;
+        if (codes[k] == OTIP_EMAXITER && worst == OTIP_OK) worst = OTIP_EMAXITER;
+    }
+    return worst;
 }
 
 int otip_result_info(const otip_result *r, otip_info *info) {
@@ -268,9 +271,10 @@ void otip_result_free(otip_result *r) { delete r; }
 
 int otip_price(otip_ctx *ctx, int32_t m, int32_t n, const int32_t *xs, const int32_t *xt,
                const double *y, const double *z, const uint32_t *support_bitmap, int64_t kmax,
-               int32_t precision, int32_t *out_i, int32_t *out_j, double *out_r,
+               int32_t precision, int32_t tile, int32_t *out_i, int32_t *out_j, double *out_r,
                int64_t *out_count, int64_t *out_nneg) {
     return guarded(ctx, [&] {
+        ctx->scan.tile = tile;
         OTIP_CHECK(m >= 1 && n >= 1 && xs && xt && y && z && kmax >= 0, OTIP_EINVAL,
                    "otip_price: bad arguments");
         OTIP_CHECK(kmax == 0 || (out_i && out_j && out_r), OTIP_EINVAL,

@@ -49,20 +49,23 @@ __global__ __launch_bounds__(64) void ldl_diag(int n, int kb, int nb, double *A,
     __shared__ double colk[NB];
     __shared__ double Ls[NB][NB + 1];
     const int i = threadIdx.x;
+    // lane i holds row i of the block and the original diagonal entry i (the
+    // pivot test of step k reads lane k's value through a shuffle)
+    const double oi = i < nb ? orig[kb + i] : 1.0;
     double t[NB];
 #pragma unroll
     for (int c = 0; c < NB; ++c)
         t[c] = (i < nb && c < nb && c <= i) ? A[(size_t)(kb + i) + (size_t)(kb + c) * n] : 0.0;
+    int ninf_local = 0;
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
         if (k < nb) {
             double piv = __shfl(t[k], k, 64);
-            if (!(piv > pivtol * orig[kb + k]) || !(piv > 0.0)) piv = INFINITY;
-            if (i == 0) {
-                d[kb + k] = piv;
-                if (isinf(piv)) atomicAdd(ninf, 1);
-            }
+            const double ok = __shfl(oi, k, 64);
+            if (!(piv > pivtol * ok) || !(piv > 0.0)) piv = INFINITY;
             const bool fin = !isinf(piv);
+            ninf_local += fin ? 0 : 1;
+            if (i == k) d[kb + k] = piv;
             const double l = (fin && i > k && i < nb) ? t[k] / piv : 0.0;
             colk[i] = l;
             __syncthreads();
@@ -74,6 +77,7 @@ __global__ __launch_bounds__(64) void ldl_diag(int n, int kb, int nb, double *A,
             __syncthreads();
         }
     }
+    if (i == 0 && ninf_local) atomicAdd(ninf, ninf_local);
     // L11 (strict lower part) to A and to LDS
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
@@ -82,17 +86,22 @@ __global__ __launch_bounds__(64) void ldl_diag(int n, int kb, int nb, double *A,
         Ls[i][c] = low ? t[c] : 0.0;
     }
     __syncthreads();
-    // column i of L11^-1: x_r = [r == i] - sum_{s < r} L(r, s) x_s
+    // lane i: column i of L11^-1.  Right-looking: once x_s is final, every
+    // x_r (r > s) loses L(r, s) x_s, so the dependent chains are 64 long.
     double x[NB];
 #pragma unroll
-    for (int r = 0; r < NB; ++r) {
-        double v = (r == i) ? 1.0 : 0.0;
+    for (int r = 0; r < NB; ++r) x[r] = (r == i) ? 1.0 : 0.0;
 #pragma unroll
-        for (int s2 = 0; s2 < r; ++s2) v = fma(-Ls[r][s2], x[s2], v);
-        x[r] = v;
-    }
+    for (int s2 = 0; s2 < NB; ++s2)
 #pragma unroll
-    for (int r = 0; r < NB; ++r) Linv[(size_t)r + (size_t)i * NB] = x[r];
+        for (int r = s2 + 1; r < NB; ++r) x[r] = fma(-Ls[r][s2], x[s2], x[r]);
+    __syncthreads();
+    // through LDS so that the store of the column-major block is coalesced
+#pragma unroll
+    for (int r = 0; r < NB; ++r) Ls[r][i] = x[r];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NB; ++c) Linv[(size_t)i + (size_t)c * NB] = Ls[i][c];
 }
 
 // Rows below the diagonal block: W21 = A21 L11^-T (so W21 = L21 D1) and
@@ -286,6 +295,71 @@ __global__ __launch_bounds__(256) void inv_bwd(int n, const double *__restrict__
     if (lane == 0) x[j] = y[j] + acc;
 }
 
+// Substitution solves, one launch per 64-wide block column (used for a
+// factorisation whose explicit inverse is not finite).  Every workgroup
+// re-solves the 64 x 64 diagonal block in one wave (register shuffles) from
+// the final right-hand side entries of that block, then applies the block's
+// columns to its own rows of the remaining right-hand side; workgroup 0 stores
+// the solved block.  Right-hand side (w) and solution (x) are separate arrays,
+// so no workgroup reads an entry another one writes in the same launch.
+//
+// forward:  L y = b, unit lower, L column-major           (rows below the block)
+// backward: L^T x = y' (y' = D^-1 y) with U = L^T stored column-major (rows above)
+__device__ __forceinline__ double diag_solve_wave(int n, const double *__restrict__ T, int kb,
+                                                  int nb, double wt, bool lower) {
+    const int t = threadIdx.x & 63;
+    double row[NB];
+    // lane t's row of the 64 x 64 diagonal block, loaded before the recurrence
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+        row[k] = (t < nb && k < nb) ? T[(size_t)(kb + t) + (size_t)(kb + k) * n] : 0.0;
+    double x = wt;
+    if (lower) {
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            const double xk = __shfl(x, k, 64);
+            if (t > k && t < nb) x = fma(-row[k], xk, x);
+        }
+    } else {
+#pragma unroll
+        for (int k = NB - 1; k >= 0; --k) {
+            const double xk = __shfl(x, k, 64);
+            if (t < k && k < nb) x = fma(-row[k], xk, x);
+        }
+    }
+    return x;
+}
+
+__global__ __launch_bounds__(256) void trsv_step(int n, int kb, int nb, const double *__restrict__ T,
+                                                 const double *__restrict__ d, double *w, double *x,
+                                                 int lower) {
+    __shared__ double xb[64];
+    if (threadIdx.x < 64) {
+        const int t = threadIdx.x;
+        const double wt = (t < nb) ? w[kb + t] : 0.0;
+        const double v = diag_solve_wave(n, T, kb, nb, wt, lower != 0);
+        if (t < nb) {
+            xb[t] = v;
+            if (blockIdx.x == 0) x[kb + t] = v;
+        }
+    }
+    __syncthreads();
+    // remaining rows: below the block (forward) or above it (backward)
+    const int r0 = lower ? kb + nb : 0;
+    const int r1 = lower ? n : kb;
+    const int i = r0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= r1) return;
+    double v = w[i];
+    for (int k = 0; k < nb; ++k) v = fma(-T[(size_t)i + (size_t)(kb + k) * n], xb[k], v);
+    w[i] = v;
+}
+
+// y = D^-1 y (an infinite pivot gives 0)
+__global__ void scale_by_pivots(int n, const double *__restrict__ d, double *y) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = isinf(d[i]) ? 0.0 : y[i] / d[i];
+}
+
 // U = L^T (64 x 64 tiles through LDS), unit diagonal implied
 __global__ __launch_bounds__(256) void transpose_lower(int n, const double *__restrict__ L,
                                                        double *__restrict__ U) {
@@ -303,6 +377,14 @@ __global__ __launch_bounds__(256) void transpose_lower(int n, const double *__re
         const int i = bj + r, j = bi + c;
         if (i < n && j < n) U[(size_t)i + (size_t)j * n] = tile[c][r];
     }
+}
+
+__global__ void any_nonfinite(size_t total, const double *__restrict__ X, int *flag) {
+    bool bad = false;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (size_t)gridDim.x * blockDim.x)
+        bad |= !isfinite(X[t]);
+    if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
 }
 
 __global__ void count_nonzero_lower(int n, const double *A, unsigned long long *cnt) {
@@ -369,20 +451,48 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
     c.need(1);
     OTIP_HIP(hipMemsetAsync(c.get(), 0, sizeof(unsigned long long), st));
     hipLaunchKernelGGL(count_nonzero_lower, dim3(1024), dim3(256), 0, st, n, A, c.get());
-    int hn = 0;
+    // an explicit inverse can overflow where the factor itself is finite
+    // (products of large multipliers): then solve by substitution
+    OTIP_HIP(hipMemsetAsync(bad_.need(1), 0, sizeof(int), st));
+    hipLaunchKernelGGL(any_nonfinite, dim3(1024), dim3(256), 0, st, total, X, bad_.get());
+    int hn = 0, hbad = 0;
     unsigned long long hc = 0;
     OTIP_HIP(hipMemcpyAsync(&hn, ninf_.get(), sizeof(int), hipMemcpyDeviceToHost, st));
     OTIP_HIP(hipMemcpyAsync(&hc, c.get(), sizeof(hc), hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipMemcpyAsync(&hbad, bad_.get(), sizeof(int), hipMemcpyDeviceToHost, st));
     OTIP_HIP(hipStreamSynchronize(st));
     nnzL_ = (int64_t)hc + n;
+    inverse_ok_ = hbad == 0;
+    if (!inverse_ok_)  // U = L^T for the backward substitution
+        hipLaunchKernelGGL(transpose_lower, dim3(tl, tl), dim3(256), 0, st, n, A, XT_.get());
     return hn;
 }
 
 void DenseLDL::solve(hipStream_t st, const double *b, double *x) {
     double *y = v_.need(n);
-    const unsigned g = grid_for(n, 4);
-    hipLaunchKernelGGL(inv_fwd, dim3(g), dim3(256), 0, st, n, XT_.get(), d_.get(), b, y);
-    hipLaunchKernelGGL(inv_bwd, dim3(g), dim3(256), 0, st, n, X_.get(), y, x);
+    if (inverse_ok_) {
+        const unsigned g = grid_for(n, 4);
+        hipLaunchKernelGGL(inv_fwd, dim3(g), dim3(256), 0, st, n, XT_.get(), d_.get(), b, y);
+        hipLaunchKernelGGL(inv_bwd, dim3(g), dim3(256), 0, st, n, X_.get(), y, x);
+        OTIP_HIP(hipGetLastError());
+        return;
+    }
+    // substitution on L (in A_) and U = L^T (in XT_)
+    double *w = X_.get();  // n doubles of scratch: X is not used on this path
+    double *yv = y;
+    OTIP_HIP(hipMemcpyAsync(w, b, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    for (int kb = 0; kb < n; kb += NB) {
+        const int nb = std::min(NB, n - kb);
+        const int rows = n - kb - nb;
+        hipLaunchKernelGGL(trsv_step, dim3(std::max(1u, grid_for(rows, 256))), dim3(256), 0, st,
+                           n, kb, nb, A_.get(), d_.get(), w, yv, 1);
+    }
+    hipLaunchKernelGGL(scale_by_pivots, dim3(grid_for(n, 256)), dim3(256), 0, st, n, d_.get(), yv);
+    for (int kb = ((n - 1) / NB) * NB; kb >= 0; kb -= NB) {
+        const int nb = std::min(NB, n - kb);
+        hipLaunchKernelGGL(trsv_step, dim3(std::max(1u, grid_for(kb, 256))), dim3(256), 0, st, n,
+                           kb, nb, XT_.get(), d_.get(), yv, x, 0);
+    }
     OTIP_HIP(hipGetLastError());
 }
 

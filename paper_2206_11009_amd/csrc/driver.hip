@@ -590,6 +590,7 @@ void Solver::reset_state() {
     t_pricing = t_newton = t_direct = t_update = t_setup = t_final = 0.0;
     t_spmv.reset();
     t_price.reset();
+    scan.scans = 0;
     warm_used = false;
 }
 
@@ -740,6 +741,11 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
         double tn = now();
         double rel1, rel2, mu, primal, r1n;
         residuals(rel1, rel2, mu, primal, r1n);
+        if (!std::isfinite(rel1) || !std::isfinite(rel2) || !std::isfinite(mu)) {
+            log("otip: it %d non-finite iterate\n", it);
+            status = OTIP_ENUMERIC;
+            break;
+        }
         const double relmu = (double)psi_ * mu / std::max(1.0, std::fabs(primal));
         psi_hist.push_back(psi_);
         if (std::max(std::max(rel1, rel2), relmu) < tol_int) {
@@ -933,9 +939,14 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
     double tf = now();
     finalize(res);
     t_final += now() - tf;
-    // the certified gap decides: tighten the internal tolerance and resume
-    if (res.info.rel_gap <= P.tol || it >= P.max_iter || tol_int <= 1e-13) {
-        if (res.info.rel_gap > P.tol) status = OTIP_EMAXITER;
+    // the certificate decides: a feasible plan (marginals to 1e-9) whose gap to
+    // the certified bound is within the tolerance; a negative gap beyond it
+    // means an infeasible plan.  Otherwise tighten the internal tolerance and
+    // resume.
+    const bool certified = std::isfinite(res.info.rel_gap) && res.info.rel_gap <= P.tol &&
+                           res.info.rel_gap >= -P.tol && res.info.marginal_residual <= 1e-9;
+    if (certified || status == OTIP_ENUMERIC || it >= P.max_iter || tol_int <= 1e-13) {
+        if (!certified && status != OTIP_ENUMERIC) status = OTIP_EMAXITER;
         break;
     }
     tol_int = std::max(tol_int * 0.1, 1e-13);
@@ -1073,6 +1084,14 @@ void Solver::finalize(Result &res) {
         mode = keep;
         double *pw = p.get();
         const double *dp = D[0].dp.get();
+        double bad = 0.0;
+        reduce_sum<1>(st, red, psi_,
+                      [=] __device__(int64_t k, double *acc) { acc[0] += isfinite(dp[k]) ? 0.0 : 1.0; },
+                      &bad);
+        if (bad != 0.0) {
+            log("otip: polish step %d not finite; plan kept as it was\n", q);
+            break;
+        }
         foreach(st, psi_, [=] __device__(int64_t k) { pw[k] = fmax(pw[k] + dp[k], 0.0); });
     }
     // to the host, unscaled

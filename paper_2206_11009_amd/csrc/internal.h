@@ -149,9 +149,10 @@ class DenseLDL {
 
   private:
     DBuf<double> A_, X_, XT_, T_, d_, orig_, W_, v_, linv_;
-    DBuf<int> ninf_;
+    DBuf<int> ninf_, bad_;
     DBuf<unsigned long long> cnt_;
     int64_t nnzL_ = 0;
+    bool inverse_ok_ = true;
 };
 
 // Warm-start network (cnn.hip): 4 dilated 3x3 convolution layers, 32 channels,

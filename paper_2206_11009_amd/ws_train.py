@@ -45,14 +45,16 @@ def he_uniform(seed: int) -> np.ndarray:
     return np.concatenate(parts).astype(np.float32)
 
 
-def solve_duals(ctx, first: int, count: int, chunk: int, workers: int, log):
-    """Inputs (count, 2, 32, 32) and targets of the training instances."""
+def solve_duals(ctx, first: int, count: int, chunk: int, workers: int, log, budget=None):
+    """Inputs (count, 2, 32, 32) and targets of the training instances; stops
+    after the chunk that exceeds `budget` seconds and returns what it has."""
     import torch
     import paper_2206_11009_amd as otip
     from synthetic import batch_instances
     X = np.empty((count, 2, SIDE, SIDE), np.float32)
     T = np.empty((count, 2, SIDE, SIDE), np.float32)
     prm = otip.params(batch_workers=workers)
+    keep = np.zeros(count, bool)
     t0 = time.perf_counter()
     for c0 in range(0, count, chunk):
         cn = min(chunk, count - c0)
@@ -61,8 +63,11 @@ def solve_duals(ctx, first: int, count: int, chunk: int, workers: int, log):
                  for i in insts]
         res = otip.otip_solve_batch(ctx, probs, prm)
         for q, (inst, r) in enumerate(zip(insts, res)):
-            if not (r.rel_gap <= 1e-6 and r.marginal_residual <= 1e-8):
-                raise RuntimeError(f"training instance {first + c0 + q} not certified: {r.info}")
+            if not (r.status == otip.OTIP_OK and r.rel_gap <= 1e-6 and
+                    r.marginal_residual <= 1e-8):
+                log(f"training instance {first + c0 + q} not certified, left out: {r.info}")
+                continue
+            keep[c0 + q] = True
             shift = 0.5 * (r.z.mean() - r.y.mean())
             X[c0 + q, 0] = (inst.a * SIDE * SIDE).reshape(SIDE, SIDE)
             X[c0 + q, 1] = (inst.b * SIDE * SIDE).reshape(SIDE, SIDE)
@@ -71,7 +76,10 @@ def solve_duals(ctx, first: int, count: int, chunk: int, workers: int, log):
         el = time.perf_counter() - t0
         log(f"solved {c0 + cn}/{count} training problems, {el:.0f} s "
             f"({(c0 + cn) / el:.1f}/s)")
-    return X, T
+        if budget is not None and el > budget and c0 + cn < count:
+            log(f"time budget reached after the first {c0 + cn} problems")
+            break
+    return X[keep], T[keep]
 
 
 def train(ctx, X, T, epochs: int, batch: int, lr: float, seed: int, log):
@@ -126,6 +134,8 @@ def main():
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--chunk", type=int, default=1024)
     ap.add_argument("--out", default=os.path.dirname(os.path.abspath(__file__)))
+    ap.add_argument("--budget", type=float, default=None,
+                    help="seconds of solving after which the data set is cut")
     args = ap.parse_args()
     import paper_2206_11009_amd as otip
 
@@ -134,13 +144,13 @@ def main():
 
     ctx = otip.Context(0)
     t0 = time.perf_counter()
-    X, T = solve_duals(ctx, FIRST, args.count, args.chunk, args.workers, log)
+    X, T = solve_duals(ctx, FIRST, args.count, args.chunk, args.workers, log, args.budget)
     t1 = time.perf_counter()
     w, hist, nval = train(ctx, X, T, args.epochs, args.batch, args.lr, args.seed, log)
     t2 = time.perf_counter()
     os.makedirs(args.out, exist_ok=True)
     w.astype("<f4").tofile(os.path.join(args.out, "ws_weights.bin"))
-    meta = {"grid": SIDE, "training_problems": args.count, "first_index": FIRST,
+    meta = {"grid": SIDE, "training_problems": int(X.shape[0]), "first_index": FIRST,
             "held_out": nval, "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
             "seed": args.seed, "params": int(w.size), "solve_seconds": t1 - t0,
             "train_seconds": t2 - t1, "history": hist,
