@@ -20,6 +20,14 @@ namespace otip {
 
 constexpr int NB = 64;
 
+// FP64 matrix core: D(16x16) += A(16x4) B(4x16).  Lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16]; it receives D[mfma_row(l, q)][l % 16] in register q.
+typedef double d4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ int mfma_row(int lane, int q) { return (lane >> 4) + 4 * q; }
+__device__ __forceinline__ d4 mfma4(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 __global__ void dense_fill(int n, const int32_t *__restrict__ rowptr,
                            const int32_t *__restrict__ col, const double *__restrict__ val,
                            double *__restrict__ A, double *__restrict__ orig) {
@@ -38,19 +46,25 @@ __global__ void dense_zero(size_t total, double *A) {
 }
 
 // Factor the diagonal block [kb, kb+nb) in one wavefront.  Lane i keeps row i
-// of the block's lower triangle in registers; at pivot k, column k of L goes
-// through LDS and every lane updates its row (right-looking).  Then the unit
-// lower factor L11 is put in LDS and lane c solves L11 x = e_c by forward
-// substitution, giving column c of L11^-1 (Linv, nb x nb column-major, padded
-// with the identity to 64 x 64) for the panel product.
+// of the block in registers.  Every value one lane needs from another (the
+// pivot, column k of L, an entry of L11 for the inverse) is read with
+// v_readlane at a compile-time lane index into a scalar register, so the
+// recurrence runs without LDS round trips.  Right-looking: at pivot k each
+// lane applies the rank-one update to its row (entries right of its diagonal
+// receive values that are never read).  Then lane c solves L11 x = e_c for
+// column c of L11^-1 (right-looking, dependent chains 64 long), which goes to
+// Linv (64 x 64 column-major, identity-padded) through LDS for a coalesced store.
+__device__ __forceinline__ double rdlane(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
 __global__ __launch_bounds__(64) void ldl_diag(int n, int kb, int nb, double *A,
                                                const double *orig, double *d, double pivtol,
                                                int *ninf, double *Linv) {
-    __shared__ double colk[NB];
     __shared__ double Ls[NB][NB + 1];
     const int i = threadIdx.x;
-    // lane i holds row i of the block and the original diagonal entry i (the
-    // pivot test of step k reads lane k's value through a shuffle)
     const double oi = i < nb ? orig[kb + i] : 1.0;
     double t[NB];
 #pragma unroll
@@ -60,43 +74,35 @@ __global__ __launch_bounds__(64) void ldl_diag(int n, int kb, int nb, double *A,
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
         if (k < nb) {
-            double piv = __shfl(t[k], k, 64);
-            const double ok = __shfl(oi, k, 64);
-            if (!(piv > pivtol * ok) || !(piv > 0.0)) piv = INFINITY;
+            double piv = rdlane(t[k], k);
+            if (!(piv > pivtol * rdlane(oi, k)) || !(piv > 0.0)) piv = INFINITY;
             const bool fin = !isinf(piv);
             ninf_local += fin ? 0 : 1;
             if (i == k) d[kb + k] = piv;
-            const double l = (fin && i > k && i < nb) ? t[k] / piv : 0.0;
-            colk[i] = l;
-            __syncthreads();
-            const double ld = fin ? l * piv : 0.0;
+            if (fin) {
+                const double l = (i > k && i < nb) ? t[k] / piv : 0.0;
+                const double ld = l * piv;
 #pragma unroll
-            for (int j = k + 1; j < NB; ++j)
-                if (j <= i) t[j] = fma(-ld, colk[j], t[j]);
-            if (i > k) t[k] = l;
-            __syncthreads();
+                for (int j = k + 1; j < NB; ++j) t[j] = fma(-ld, rdlane(l, j), t[j]);
+                if (i > k) t[k] = l;
+            } else if (i > k) {
+                t[k] = 0.0;  // infinite pivot: the column of L is zero
+            }
         }
     }
     if (i == 0 && ninf_local) atomicAdd(ninf, ninf_local);
-    // L11 (strict lower part) to A and to LDS
 #pragma unroll
-    for (int c = 0; c < NB; ++c) {
-        const bool low = i < nb && c < i;
-        if (low && c < nb) A[(size_t)(kb + i) + (size_t)(kb + c) * n] = t[c];
-        Ls[i][c] = low ? t[c] : 0.0;
-    }
-    __syncthreads();
-    // lane i: column i of L11^-1.  Right-looking: once x_s is final, every
-    // x_r (r > s) loses L(r, s) x_s, so the dependent chains are 64 long.
+    for (int c = 0; c < NB; ++c)
+        if (i < nb && c < i && c < nb) A[(size_t)(kb + i) + (size_t)(kb + c) * n] = t[c];
+    // lane i: column i of L11^-1; L(r, s) (s < r) is t[s] of lane r, and it is
+    // zero outside the block (rows and columns >= nb stayed zero above)
     double x[NB];
 #pragma unroll
     for (int r = 0; r < NB; ++r) x[r] = (r == i) ? 1.0 : 0.0;
 #pragma unroll
     for (int s2 = 0; s2 < NB; ++s2)
 #pragma unroll
-        for (int r = s2 + 1; r < NB; ++r) x[r] = fma(-Ls[r][s2], x[s2], x[r]);
-    __syncthreads();
-    // through LDS so that the store of the column-major block is coalesced
+        for (int r = s2 + 1; r < NB; ++r) x[r] = fma(-rdlane(t[s2], r), x[s2], x[r]);
 #pragma unroll
     for (int r = 0; r < NB; ++r) Ls[r][i] = x[r];
     __syncthreads();
@@ -138,7 +144,8 @@ __global__ __launch_bounds__(256) void ldl_panel(int n, int kb, int nb, double *
     }
 }
 
-// A22 -= L21 W21^T on lower-triangular 64x64 tiles
+// A22 -= L21 W21^T on lower-triangular 64x64 tiles; each wave forms a 32x32
+// quarter of the tile as 2x2 blocks of 16x16 matrix-core products
 __global__ __launch_bounds__(256) void ldl_update(int n, int kb, int nb, double *A,
                                                   const double *W) {
     const int r0 = kb + nb;
@@ -155,33 +162,36 @@ __global__ __launch_bounds__(256) void ldl_update(int n, int kb, int nb, double 
         Ws[a][k] = (jj < rows && k < nb) ? W[(size_t)jj + (size_t)k * rows] : 0.0;
     }
     __syncthreads();
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    double acc[4][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+    d4 acc[2][2];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-    for (int k = 0; k < nb; ++k) {
-        double lv[4], wv[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) lv[a] = Ls[tx + 16 * a][k];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) wv[b] = Ws[ty + 16 * b][k];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = fma(lv[a], wv[b], acc[a][b]);
+        for (int v = 0; v < 2; ++v) acc[u][v] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k = 0; k < NB; k += 4) {
+        const double a0 = Ls[wr + li][k + lk], a1 = Ls[wr + 16 + li][k + lk];
+        const double b0 = Ws[wc + li][k + lk], b1 = Ws[wc + 16 + li][k + lk];
+        acc[0][0] = mfma4(a0, b0, acc[0][0]);
+        acc[0][1] = mfma4(a0, b1, acc[0][1]);
+        acc[1][0] = mfma4(a1, b0, acc[1][0]);
+        acc[1][1] = mfma4(a1, b1, acc[1][1]);
     }
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int ii = i0 + tx + 16 * a, jj = j0 + ty + 16 * b;
-            if (ii < rows && jj < rows && ii >= jj) {
-                double *p = &A[(size_t)(r0 + ii) + (size_t)(r0 + jj) * n];
-                *p -= acc[a][b];
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int ii = i0 + wr + 16 * u + mfma_row(lane, q);
+                const int jj = j0 + wc + 16 * v + li;
+                if (ii < rows && jj < rows && ii >= jj) {
+                    double *p = &A[(size_t)(r0 + ii) + (size_t)(r0 + jj) * n];
+                    *p -= acc[u][v][q];
+                }
             }
-        }
 }
 
 // X = L^-1 by recursive doubling.  The 64 x 64 diagonal blocks of X are the
@@ -214,12 +224,14 @@ __global__ __launch_bounds__(256) void inv_mul(int n, int b, int mode, const dou
     // mode 1: A(r, k) = X(r2 + r, r2 + k), zero for k > r; B(k, c) = T(k, c)
     const int kt0 = mode == 0 ? tj : 0;
     const int kt1 = mode == 0 ? b / NB : ti + 1;
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    double acc[4][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+    d4 acc[2][2];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+        for (int v = 0; v < 2; ++v) acc[u][v] = d4{0.0, 0.0, 0.0, 0.0};
     for (int kt = kt0; kt < kt1; ++kt) {
         for (int t = threadIdx.x; t < NB * NB; t += 256) {
             const int q = t % NB, k = t / NB;  // element (q, k) of the A and B tiles
@@ -237,30 +249,31 @@ __global__ __launch_bounds__(256) void inv_mul(int n, int b, int mode, const dou
             Bs[q][k] = bv;
         }
         __syncthreads();
-        for (int k = 0; k < NB; ++k) {
-            double av[4], bv[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) av[u] = As[tx + 16 * u][k];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) bv[v] = Bs[k][ty + 16 * v];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
+#pragma unroll 4
+        for (int k = 0; k < NB; k += 4) {
+            const double a0 = As[wr + li][k + lk], a1 = As[wr + 16 + li][k + lk];
+            const double b0 = Bs[k + lk][wc + li], b1 = Bs[k + lk][wc + 16 + li];
+            acc[0][0] = mfma4(a0, b0, acc[0][0]);
+            acc[0][1] = mfma4(a0, b1, acc[0][1]);
+            acc[1][0] = mfma4(a1, b0, acc[1][0]);
+            acc[1][1] = mfma4(a1, b1, acc[1][1]);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = ti * NB + tx + 16 * u, c = tj * NB + ty + 16 * v;
-            if (r >= rows2) continue;
-            if (mode == 0)
-                Tp[(size_t)r + (size_t)c * b] = acc[u][v];
-            else
-                X[(size_t)(r2 + r) + (size_t)(c1 + c) * n] = -acc[u][v];
-        }
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = ti * NB + wr + 16 * u + mfma_row(lane, q);
+                const int c = tj * NB + wc + 16 * v + li;
+                if (r >= rows2) continue;
+                if (mode == 0)
+                    Tp[(size_t)r + (size_t)c * b] = acc[u][v][q];
+                else
+                    X[(size_t)(r2 + r) + (size_t)(c1 + c) * n] = -acc[u][v][q];
+            }
 }
 
 // Solve L D L^T x = b with X = L^-1 (unit lower, column-major) and XT, the

@@ -277,7 +277,8 @@ struct FW {
     const double *th, *r2, *r3, *p;
     double *w;
     __device__ void operator()(int64_t k) const {
-        w[k] = th[k] * ((r2 ? r2[k] : 0.0) - r3[k] / p[k]);
+        // r3 null: zero (the projection of the final polish, where p may be 0)
+        w[k] = th[k] * ((r2 ? r2[k] : 0.0) - (r3 ? r3[k] / p[k] : 0.0));
     }
 };
 // rhs_j = beta2_j - sum_{i in col j} theta_ij beta1_i / M_i
@@ -306,12 +307,13 @@ struct FDy {
 // ds = r2 - (dy_i + dz_j); dp = (r3 - p ds) / s
 struct FDsDp {
     const int32_t *si, *sj;
-    const double *r2, *r3, *p, *s, *dy, *dz;
+    const double *r2, *r3, *p, *s, *dy, *dz, *th;
     double *ds, *dp;
     __device__ void operator()(int64_t k) const {
         const double d = (r2 ? r2[k] : 0.0) - (dy[si[k]] + dz[sj[k]]);
         ds[k] = d;
-        dp[k] = (r3[k] - p[k] * d) / s[k];
+        // r3 null: dp = -Theta ds with the assembled Theta
+        dp[k] = r3 ? (r3[k] - p[k] * d) / s[k] : -th[k] * d;
     }
 };
 struct FSub {
@@ -327,7 +329,8 @@ void Solver::newton(const double *r1a_, const double *r1b_, const double *r2_, c
     colsum(w.get(), r1b_, beta2.get(), 1.0);
     segsum(st, n, FRhs{col_ptr.get(), si.get(), theta.get(), beta1.get(), invM.get(),
                        beta2.get(), rhs.get()});
-    if (mode == Mode::Direct) {
+    bool use_cg = mode != Mode::Direct;
+    if (!use_cg) {
         ldl.solve(st, rhs.get(), out.dz.get());
         // one step of iterative refinement against S
         schur.spmv(st, out.dz.get(), tmpn.get());
@@ -338,7 +341,18 @@ void Solver::newton(const double *r1a_, const double *r1b_, const double *r2_, c
         ldl.solve(st, res, tmpn.get());
         double *dz = out.dz.get();
         foreach(st, n, [=] __device__(int64_t j) { dz[j] += tn[j]; });
-    } else {
+        // a factorisation of a nearly singular S can lose all accuracy (huge
+        // multipliers); CG on the same system degrades gracefully instead
+        double bad = 0.0;
+        reduce_sum<1>(st, red, n,
+                      [=] __device__(int64_t j, double *acc) { acc[0] += isfinite(dz[j]) ? 0.0 : 1.0; },
+                      &bad);
+        if (bad != 0.0) {
+            log("otip: direct solve not finite; this solve by CG\n");
+            use_cg = true;
+        }
+    }
+    if (use_cg) {
         // project on the range of S (orthogonal to e: the null vector of a
         // connected support, Section 4)
         double mean = 0.0;
@@ -356,7 +370,7 @@ void Solver::newton(const double *r1a_, const double *r1b_, const double *r2_, c
     segsum(st, m, FDy{row_ptr.get(), csr_pos.get(), sj.get(), theta.get(), beta1.get(),
                       invM.get(), out.dz.get(), out.dy.get()});
     foreach(st, psi_, FDsDp{si.get(), sj.get(), r2_, r3_, p.get(), s.get(), out.dy.get(),
-                            out.dz.get(), out.ds.get(), out.dp.get()});
+                            out.dz.get(), theta.get(), out.ds.get(), out.dp.get()});
 }
 
 // max step to the boundary for p and s
@@ -778,13 +792,17 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
             // fill "allows" a factorisation once it is cheaper than the CG it
             // replaces.  A fixed cost model (not wall time, so the switch point
             // is reproducible): CG iteration = SpMV bytes at 3 TB/s + three
-            // launches; dense = n^3/3 flops at 3 TF/s + its block launches +
-            // two 64-column triangular sweeps per solve.
+            // launches of 6 us; dense = factor and inverse (2 n^3/3 flops at
+            // 12 TF/s) + their dependent launches (3 per 64-column block, 2 per
+            // doubling level, 20 us each) + per solve two products over n^2/2
+            // entries each at 2 TB/s and two launches of 6 us.
             const double nb = (double)((n + 63) / 64);
+            const double levels = std::ceil(std::log2(std::max(1.0, nb)));
             const double t_cg = cg_its_last * ((12.0 * (double)schur.S.nnz + 20.0 * n) / 3e12 +
-                                               3 * 4e-6);
-            const double t_dense = (double)n * n * n / 3.0 / 3e12 + nb * 3 * 8e-6 +
-                                   solves_last * 2.0 * nb * 6e-6;
+                                               3 * 6e-6);
+            const double t_dense = 2.0 * (double)n * n * n / 3.0 / 12e12 +
+                                   (3.0 * nb + 2.0 * levels) * 20e-6 +
+                                   solves_last * (8.0 * (double)n * n / 2e12 + 2 * 6e-6);
             const bool cheaper = P.switch_cost && it >= 1 && t_dense < t_cg;
             const bool force = (P.force_switch_at >= 0 && it >= P.force_switch_at) || cg_failed ||
                                cheaper;
@@ -1060,8 +1078,11 @@ void Solver::starting_point() {
 void Solver::finalize(Result &res) {
     const double fsum1 = 0.0;
     (void)fsum1;
-    double *zp = zpsi.need(psi_);
-    OTIP_HIP(hipMemsetAsync(zp, 0, sizeof(double) * psi_, st));
+    // the projection below moves p off the interior; keep the interior
+    // iterate for a resumed iteration
+    double *pkeep = zpsi.need(psi_);
+    OTIP_HIP(hipMemcpyAsync(pkeep, p.get(), sizeof(double) * psi_, hipMemcpyDeviceToDevice, st));
+    bool assembled = false;
     for (int q = 0; q < P.polish_steps; ++q) {
         rowsum(p.get(), a.get(), r1a.get(), -1.0);
         colsum(p.get(), b.get(), r1b.get(), -1.0);
@@ -1075,12 +1096,16 @@ void Solver::finalize(Result &res) {
                       },
                       v);
         if (v[0] / v[1] <= P.polish_tol) break;
-        assemble();
+        // Theta of the interior iterate, assembled and factorised once
         const bool direct = n <= P.dense_max_n;
+        if (!assembled) {
+            assemble();
+            if (direct) ldl.factor(st, schur.S, P.pivot_tol);
+            assembled = true;
+        }
         Mode keep = mode;
         mode = direct ? Mode::Direct : Mode::PCG;
-        if (direct) ldl.factor(st, schur.S, P.pivot_tol);
-        newton(r1a.get(), r1b.get(), nullptr, zp, 1e-14, 0.0, D[0]);
+        newton(r1a.get(), r1b.get(), nullptr, nullptr, 1e-14, 0.0, D[0]);
         mode = keep;
         double *pw = p.get();
         const double *dp = D[0].dp.get();
@@ -1108,6 +1133,7 @@ void Solver::finalize(Result &res) {
     OTIP_HIP(hipMemcpyAsync(hxs.data(), xs, sizeof(int32_t) * 2 * m, hipMemcpyDeviceToHost, st));
     OTIP_HIP(hipMemcpyAsync(hxt.data(), xt, sizeof(int32_t) * 2 * n, hipMemcpyDeviceToHost, st));
     OTIP_HIP(hipStreamSynchronize(st));
+    OTIP_HIP(hipMemcpyAsync(p.get(), pkeep, sizeof(double) * psi_, hipMemcpyDeviceToDevice, st));
     std::vector<int32_t> rows(psi), cols(psi);
     std::vector<double> flows(psi);
     std::vector<int64_t> costs(psi);
