@@ -9,6 +9,8 @@
 // wave-uniform and is read through the scalar cache from a small table built
 // per call.
 #include "common.h"
+#include <cstring>
+
 #include "internal.h"
 
 namespace otip {
@@ -17,6 +19,21 @@ namespace otip {
 struct __align__(32) JEntry {
     double B, a2, b2, z;
 };
+
+// The per-target tables are read-only during a scan and every lane of a wave
+// reads the same entry: reading them through the constant address space lets
+// the compiler use scalar loads even in kernels that also store to memory.
+typedef const __attribute__((address_space(4))) double *cdptr;
+typedef const __attribute__((address_space(4))) float *cfptr;
+__device__ __forceinline__ JEntry ldj(const JEntry *p, int j) {
+    const cdptr q = (cdptr)(p + j);
+    JEntry e;
+    e.B = q[0];
+    e.a2 = q[1];
+    e.b2 = q[2];
+    e.z = q[3];
+    return e;
+}
 
 __global__ void build_jtab(int n, const int32_t *__restrict__ xt, const double *__restrict__ z,
                            JEntry *__restrict__ jt) {
@@ -78,6 +95,9 @@ struct PriceArgs {
     unsigned long long *hist;
     // compaction mode: every key <= key_max
     uint64_t key_max;
+    // no key of interest belongs to an r above rcut (the double whose key is
+    // the largest one of interest, or +inf): groups with no r <= rcut skip
+    double rcut;
     unsigned long long *count;
     uint64_t *out_key, *out_idx;
     uint64_t cap;
@@ -89,7 +109,7 @@ __device__ __forceinline__ void price_one(const PriceArgs &a, int i, int j, doub
                                           unsigned int *lh) {
     {
         const int pshift = a.shift + 12;
-        const bool neg = r < 0.0;
+        const bool neg = r < 0.0 && r <= a.rcut;
         if (__ballot(neg) == 0ull) return;
         const uint64_t idx = (uint64_t)i + (uint64_t)j * (uint64_t)a.m;
         bool take = neg && !in_support(a.bitmap, idx);
@@ -132,24 +152,26 @@ __global__ __launch_bounds__(kScanBlock) void price_pass(PriceArgs a) {
         __syncthreads();
     }
     const RowData rd = load_row(i, a.m, a.xs, a.y);
-    const JEntry *__restrict__ jt = a.jt;
+    const JEntry *jt = a.jt;
     int j = j0;
     // four targets at a time: table loads issued together, and a whole group
     // without a negative reduced cost costs one ballot
     for (; j + 4 <= j1; j += 4) {
-        const JEntry t0 = jt[j], t1 = jt[j + 1], t2 = jt[j + 2], t3 = jt[j + 3];
+        const JEntry t0 = ldj(jt, j), t1 = ldj(jt, j + 1), t2 = ldj(jt, j + 2),
+                     t3 = ldj(jt, j + 3);
         const double r0 = (cost_of(rd, t0) - rd.y) - t0.z;
         const double r1 = (cost_of(rd, t1) - rd.y) - t1.z;
         const double r2 = (cost_of(rd, t2) - rd.y) - t2.z;
         const double r3 = (cost_of(rd, t3) - rd.y) - t3.z;
-        if (__ballot(fmin(fmin(r0, r1), fmin(r2, r3)) < 0.0) == 0ull) continue;
+        const double lo = fmin(fmin(r0, r1), fmin(r2, r3));
+        if (__ballot(lo < 0.0 && lo <= a.rcut) == 0ull) continue;
         price_one<MODE>(a, i, j, r0, lh);
         price_one<MODE>(a, i, j + 1, r1, lh);
         price_one<MODE>(a, i, j + 2, r2, lh);
         price_one<MODE>(a, i, j + 3, r3, lh);
     }
     for (; j < j1; ++j) {
-        const JEntry t = jt[j];
+        const JEntry t = ldj(jt, j);
         const double r = (cost_of(rd, t) - rd.y) - t.z;
         price_one<MODE>(a, i, j, r, lh);
     }
@@ -175,6 +197,14 @@ __global__ void decode_selection(int64_t k, int m, const uint64_t *__restrict__ 
 
 // targets per block: enough blocks to fill 256 CUs several times over, but
 // enough work per block to amortise the histogram's LDS setup
+// the double with ordered key k (host side), or +inf where k is not a number's key
+static double rcut_of_key(uint64_t k) {
+    const uint64_t u = (k & 0x8000000000000000ull) ? (k & 0x7fffffffffffffffull) : ~k;
+    double d;
+    std::memcpy(&d, &u, sizeof d);
+    return std::isnan(d) ? INFINITY : d;
+}
+
 int pick_tj(int m, int n, int tile) {
     if (tile >= 16 && tile <= 256 && (tile & (tile - 1)) == 0) return tile;
     const int64_t rb = (m + 255) / 256;
@@ -216,6 +246,8 @@ PriceResult Scanner::price(hipStream_t st, int m, int n, const int32_t *xs, cons
         OTIP_HIP(hipMemsetAsync(hist_.get(), 0, kHistBins * sizeof(unsigned long long), st));
         a.shift = shift;
         a.prefix = prefix;
+        a.rcut = (shift + 12 >= 64) ? INFINITY
+                                    : rcut_of_key(((prefix + 1) << (shift + 12)) - 1);
         if (timer) timer->start(st, (double)m * (double)n);
         hipLaunchKernelGGL(price_pass<0>, grid, dim3(kScanBlock), 0, st, a);
         if (timer) timer->stop(st);
@@ -278,6 +310,7 @@ PriceResult Scanner::price(hipStream_t st, int m, int n, const int32_t *xs, cons
     ci_.need(cap);
     OTIP_HIP(hipMemsetAsync(cnt_.get(), 0, sizeof(unsigned long long), st));
     a.key_max = key_max;
+    a.rcut = key_max == ~0ull ? INFINITY : rcut_of_key(key_max);
     a.count = cnt_.get();
     a.out_key = ck_.get();
     a.out_idx = ci_.get();
@@ -327,7 +360,7 @@ __global__ __launch_bounds__(kScanBlock) void rmin_pass(MinArgs a) {
     double best = INFINITY;
     uint64_t arg = ~0ull;
     for (int j = j0; j < j1; ++j) {
-        const JEntry t = a.jt[j];
+        const JEntry t = ldj(a.jt, j);
         const double r = (cost_of(rd, t) - rd.y) - t.z;
         if (r < best) {  // first j attaining the minimum for this row
             best = r;
@@ -621,6 +654,16 @@ struct __align__(16) JEntry32 {
     float B, a2, b2, z;
 };
 
+__device__ __forceinline__ JEntry32 ldj32(const JEntry32 *p, int j) {
+    const cfptr q = (cfptr)(p + j);
+    JEntry32 e;
+    e.B = q[0];
+    e.a2 = q[1];
+    e.b2 = q[2];
+    e.z = q[3];
+    return e;
+}
+
 __global__ void build_jtab32(int n, const int32_t *__restrict__ xt, const double *__restrict__ z,
                              JEntry32 *__restrict__ jt) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -677,7 +720,7 @@ __global__ __launch_bounds__(kScanBlock) void price32_pass(Price32Args a) {
     const int pshift = a.shift + 12;
     unsigned int ncert = 0, nband = 0;
     for (int j = j0; j < j1; ++j) {
-        const JEntry32 t = a.jt[j];
+        const JEntry32 t = ldj32(a.jt, j);
         const float c = fmaf(be, t.b2, fmaf(al, t.a2, A + t.B));
         const float r = (c - yv) - t.z;
         const bool lo = r < mg;
