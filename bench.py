@@ -166,7 +166,7 @@ def rooflines(infos):
     pr_ms = sum(i["price_ms"] for i in infos)
     pr_n = sum(i["price_launches"] for i in infos)
     pr_e = sum(i["price_elems"] for i in infos)
-    spmv = {"bound": "hbm", "kernel": "spmv_rows (Schur SpMV in CG)",
+    spmv = {"bound": "hbm", "kernel": "spmv_dir (Schur SpMV fused with the CG direction update)",
             "achieved": spmv_b / max(spmv_ms, 1e-12) / 1e6, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "avg_launch_us": 1e3 * spmv_ms / max(spmv_n, 1), "launches": spmv_n,
             "total_ms": spmv_ms, "traffic": None}

@@ -143,9 +143,11 @@ typedef struct otip_info {
     double seconds_final;      /* polish, purification, certificate */
     int64_t pricing_scans;     /* full m*n passes of the pricing and certificate scans */
     /* with params.profile: event-timed launches of the two hot kernels */
-    int64_t spmv_launches;     /* Schur SpMV launches inside CG */
+    int64_t spmv_launches;     /* Schur SpMV launches inside CG (fused with the direction
+                                  update p = z + beta p) */
     double spmv_ms;            /* their summed durations */
-    double spmv_bytes;         /* their algorithmic bytes: 12 nnz + 20 n + 4 per launch */
+    double spmv_bytes;         /* their algorithmic bytes: 12 nnz + 36 n per launch (FP64;
+                                  8 nnz + 20 n for the FP32 inner solves) */
     int64_t price_launches;    /* pricing-pass launches */
     double price_ms;
     double price_elems;        /* reduced costs evaluated: m*n per launch */

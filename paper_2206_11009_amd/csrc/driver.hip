@@ -398,7 +398,8 @@ void Solver::assemble() {
                        sj.get());
         schur_valid = true;
     }
-    schur.numeric(st, m, n, col_ptr.get(), si.get(), theta.get(), invM.get());
+    schur.numeric(st, m, n, col_ptr.get(), si.get(), row_ptr.get(), csr_pos.get(), sj.get(),
+                  theta.get(), invM.get());
     (void)t0;
 }
 
@@ -1290,7 +1291,8 @@ int64_t Solver::schur_export(int m_, int n_, int64_t psi, const uint64_t *idx_in
     colsum(theta.get(), nullptr, N.get(), 1.0);
     foreach(st, m, FInv{M.get(), invM.get()});
     schur.symbolic(st, m, n, psi_, col_ptr.get(), si.get(), row_ptr.get(), csr_pos.get(), sj.get());
-    schur.numeric(st, m, n, col_ptr.get(), si.get(), theta.get(), invM.get());
+    schur.numeric(st, m, n, col_ptr.get(), si.get(), row_ptr.get(), csr_pos.get(), sj.get(),
+                  theta.get(), invM.get());
     const int64_t nnz = schur.S.nnz;
     if (rowptr) {
         OTIP_HIP(hipMemcpyAsync(rowptr, schur.S.rowptr.get(), sizeof(int32_t) * (n + 1),

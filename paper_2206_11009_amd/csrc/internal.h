@@ -116,6 +116,7 @@ class SchurSolver {
     // values: S_jk = -sum_{i in col j and col k} theta_ij theta_ik / M_i (j != k),
     // S_jj = -sum_{k != j} S_jk; also the Jacobi inverse diagonal
     void numeric(hipStream_t st, int m, int n, const int32_t *col_ptr, const int32_t *si,
+                 const int32_t *row_ptr, const int32_t *csr_pos, const int32_t *sj,
                  const double *theta, const double *invM);
     // y = S x
     void spmv(hipStream_t st, const double *x, double *y);

@@ -160,6 +160,42 @@ __global__ void schur_offdiag(int64_t nnz, const int32_t *__restrict__ srow,
     val[e] = -acc;
 }
 
+// Off-diagonal values by rows, for n <= kRowAccMax: one wavefront per row j of
+// S accumulates sum_i theta_ij theta_ik / M_i into a dense LDS row over the
+// sources i of column j in increasing i (each source's targets k are distinct,
+// and successive sources are ordered by the wave's program order), then
+// gathers the row's pattern.  Same products and summation order as
+// schur_offdiag, so the values are identical; the work is
+// sum_j sum_{i in col j} deg(i) instead of a merge per nonzero.
+constexpr int kRowAccMax = 8192;
+
+__global__ __launch_bounds__(64) void schur_offdiag_rows(
+    int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ scol,
+    const int32_t *__restrict__ col_ptr, const int32_t *__restrict__ si,
+    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ csr_pos,
+    const int32_t *__restrict__ sj, const double *__restrict__ theta,
+    const double *__restrict__ invM, double *__restrict__ val) {
+    extern __shared__ double acc[];
+    const int j = blockIdx.x, l = threadIdx.x;
+    const int e0 = rowptr[j], e1 = rowptr[j + 1];
+    for (int e = e0 + l; e < e1; e += 64) acc[scol[e]] = 0.0;
+    __syncthreads();
+    for (int a = col_ptr[j]; a < col_ptr[j + 1]; ++a) {
+        const int i = si[a];
+        const double ta = theta[a], im = invM[i];
+        for (int t = row_ptr[i] + l; t < row_ptr[i + 1]; t += 64) {
+            const int q = csr_pos[t];
+            const int k = sj[q];
+            acc[k] = fma(ta * theta[q], im, acc[k]);
+        }
+        __syncthreads();
+    }
+    for (int e = e0 + l; e < e1; e += 64) {
+        const int k = scol[e];
+        val[e] = (k == j) ? 0.0 : -acc[k];
+    }
+}
+
 // one wave per row: S_jj = -(sum of the row's off-diagonal entries)
 __global__ __launch_bounds__(256) void schur_diag(int n, const int32_t *__restrict__ rowptr,
                                                   const int32_t *__restrict__ diag,
@@ -180,9 +216,15 @@ __global__ __launch_bounds__(256) void schur_diag(int n, const int32_t *__restri
 }
 
 void SchurSolver::numeric(hipStream_t st, int m, int n, const int32_t *col_ptr,
-                          const int32_t *si, const double *theta, const double *invM) {
-    hipLaunchKernelGGL(schur_offdiag, dim3(grid_for(S.nnz, 256)), dim3(256), 0, st, S.nnz,
-                       S.row.get(), S.col.get(), col_ptr, si, theta, invM, S.val.get());
+                          const int32_t *si, const int32_t *row_ptr, const int32_t *csr_pos,
+                          const int32_t *sj, const double *theta, const double *invM) {
+    if (n <= kRowAccMax)
+        hipLaunchKernelGGL(schur_offdiag_rows, dim3(n), dim3(64), sizeof(double) * n, st, n,
+                           S.rowptr.get(), S.col.get(), col_ptr, si, row_ptr, csr_pos, sj, theta,
+                           invM, S.val.get());
+    else
+        hipLaunchKernelGGL(schur_offdiag, dim3(grid_for(S.nnz, 256)), dim3(256), 0, st, S.nnz,
+                           S.row.get(), S.col.get(), col_ptr, si, theta, invM, S.val.get());
     hipLaunchKernelGGL(schur_diag, dim3(grid_for(n, 4)), dim3(256), 0, st, n, S.rowptr.get(),
                        S.diag.get(), S.val.get(), S.dinv.get());
     OTIP_HIP(hipGetLastError());
@@ -256,7 +298,7 @@ __global__ __launch_bounds__(kCGThreads) void cg_init(int n, const T *__restrict
         x[j] = (T)0;
         r[j] = bj;
         z[j] = zj;
-        p[j] = zj;
+        p[j] = (T)0;  // the first direction is z itself (beta = 0)
         rz = fma((double)bj, (double)zj, rz);
         rr = fma((double)bj, (double)bj, rr);
     }
@@ -275,12 +317,64 @@ __global__ __launch_bounds__(64) void cg_init_finish(int nb, const double *part,
     const double rr = sum_partials(part + kCGBlocks, nb, lds);
     if (threadIdx.x == 0) {
         const double target = fmin(rtol * sqrt(rr), atol);
-        sc->rho[0] = rz;
-        sc->rho[1] = 0.0;
+        sc->rho[0] = 0.0;
+        sc->rho[1] = 1.0;  // previous rho of the first iteration (its beta is 0)
         sc->rr = rr;
         sc->target = target;
         sc->its = 0.0;
         *done = (sqrt(rr) <= target || rr == 0.0) ? 1 : 0;
+    }
+}
+
+// One CG iteration's first half.  From the previous update's partials:
+// rho = r.z and r.r (convergence test); beta = rho / rho_prev (0 on the first
+// iteration); the new direction p_new = z + beta p_old is formed where the
+// SpMV gathers it, q = S p_new, and the rows' p_new . q go to partial.  rho is
+// double-buffered by parity: every workgroup reads rho[par ^ 1] (the previous
+// one) and workgroup 0 writes rho[par].  G lanes per row.
+template <int G, typename T>
+__global__ __launch_bounds__(256) void spmv_dir(int n, const int32_t *__restrict__ rowptr,
+                                                const int32_t *__restrict__ col,
+                                                const T *__restrict__ val,
+                                                const T *__restrict__ z,
+                                                const T *__restrict__ pold, T *__restrict__ pnew,
+                                                T *__restrict__ q, int nb2, const double *part2,
+                                                double *partial, CGScal *sc, int *done, int first,
+                                                int par) {
+    __shared__ double lds[16];
+    if (*done) return;
+    const double rz = sum_partials(part2, nb2, lds);
+    const double rr = sum_partials(part2 + kCGBlocks, nb2, lds);
+    if (sqrt(rr) <= sc->target || rr == 0.0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc->rr = rr;
+            *done = 1;
+        }
+        return;
+    }
+    const T beta = first ? (T)0 : (T)(rz / sc->rho[par ^ 1]);
+    const int groups = 256 / G;
+    const int g = threadIdx.x / G, l = threadIdx.x % G;
+    double dot = 0.0;
+    for (int r = blockIdx.x * groups + g; r < n; r += gridDim.x * groups) {
+        T acc = (T)0;
+        for (int e = rowptr[r] + l; e < rowptr[r + 1]; e += G) {
+            const int c = col[e];
+            acc = fma(val[e], fma(beta, pold[c], z[c]), acc);
+        }
+        for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+        if (l == 0) {
+            const T pr = fma(beta, pold[r], z[r]);
+            pnew[r] = pr;
+            q[r] = acc;
+            dot = fma((double)pr, (double)acc, dot);
+        }
+    }
+    const double t = block_sum(dot, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->rho[par] = rz;
+        sc->rr = rr;
     }
 }
 
@@ -290,7 +384,7 @@ __global__ __launch_bounds__(kCGThreads) void cg_update(int n, int nb1, const do
                                                         const T *__restrict__ p,
                                                         const T *__restrict__ q,
                                                         const T *__restrict__ dinv, T *x, T *r,
-                                                        T *z, double *part2, const CGScal *sc,
+                                                        T *z, double *part2, CGScal *sc,
                                                         int *done, int par) {
     __shared__ double lds[16];
     if (*done) return;
@@ -316,25 +410,19 @@ __global__ __launch_bounds__(kCGThreads) void cg_update(int n, int nb1, const do
         part2[blockIdx.x] = t1;
         part2[kCGBlocks + blockIdx.x] = t2;
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->its += 1.0;
 }
 
-// beta = rho_new / rho; p = z + beta p; convergence flag
-template <typename T>
-__global__ __launch_bounds__(kCGThreads) void cg_direction(int n, int nb2, const double *part2,
-                                                           const T *__restrict__ z, T *p,
-                                                           CGScal *sc, int *done, int par) {
+// convergence test on the last update's partials (end of a chunk of
+// iterations, so that a converged last iteration is reported as such)
+__global__ __launch_bounds__(64) void cg_check(int nb2, const double *part2, CGScal *sc,
+                                               int *done) {
     __shared__ double lds[2];
     if (*done) return;
-    const double rz = sum_partials(part2, nb2, lds);
     const double rr = sum_partials(part2 + kCGBlocks, nb2, lds);
-    const T beta = (T)(rz / sc->rho[par]);
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x)
-        p[j] = fma(beta, p[j], z[j]);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        sc->rho[par ^ 1] = rz;
+    if (threadIdx.x == 0) {
         sc->rr = rr;
-        sc->its += 1.0;
-        if (sqrt(rr) <= sc->target) *done = 1;
+        if (sqrt(rr) <= sc->target || rr == 0.0) *done = 1;
     }
 }
 
@@ -354,6 +442,26 @@ static void launch_spmv(hipStream_t st, const SchurCSR &S, const T *val, const T
                            S.col.get(), val, x, y, partial, done);
 }
 
+template <typename T>
+static void launch_spmv_dir(hipStream_t st, const SchurCSR &S, const T *val, const T *z,
+                            const T *pold, T *pnew, T *q, int nb2, const double *part2,
+                            double *partial, CGScal *sc, int *done, int first, int par,
+                            unsigned &nb_out) {
+    const int n = S.n;
+    const double avg = (double)S.nnz / std::max(1, n);
+    const int G = avg >= 48 ? 64 : 16;
+    const unsigned nb = std::min<unsigned>(kSpmvMaxBlocks, grid_for(n, 256 / G));
+    nb_out = nb;
+    if (G == 64)
+        hipLaunchKernelGGL((spmv_dir<64, T>), dim3(nb), dim3(256), 0, st, n, S.rowptr.get(),
+                           S.col.get(), val, z, pold, pnew, q, nb2, part2, partial, sc, done,
+                           first, par);
+    else
+        hipLaunchKernelGGL((spmv_dir<16, T>), dim3(nb), dim3(256), 0, st, n, S.rowptr.get(),
+                           S.col.get(), val, z, pold, pnew, q, nb2, part2, partial, sc, done,
+                           first, par);
+}
+
 void SchurSolver::spmv(hipStream_t st, const double *x, double *y) {
     unsigned nb;
     launch_spmv<double>(st, S, S.val.get(), x, y, nullptr, nullptr, nb);
@@ -369,7 +477,7 @@ CGStats SchurSolver::pcg_impl(hipStream_t st, const T *val, const T *dinv, const
     CGStats out;
     r_.need(n);
     z_.need(n);
-    p_.need(n);
+    p_.need(2 * (size_t)n);  // two directions, alternating by iteration parity
     q_.need(n);
     part_.need(kSpmvMaxBlocks + 2 * kCGBlocks);
     scal_.need(sizeof(CGScal) / sizeof(double));
@@ -378,9 +486,10 @@ CGStats SchurSolver::pcg_impl(hipStream_t st, const T *val, const T *dinv, const
     double *part2 = part_.get() + kSpmvMaxBlocks;
     CGScal *sc = (CGScal *)scal_.get();
     int *done = flag_.get();
+    T *P[2] = {p_.get(), p_.get() + n};
     const unsigned nbv = std::min<unsigned>(kCGBlocks, grid_for(n, kCGThreads));
     hipLaunchKernelGGL((cg_init<T>), dim3(nbv), dim3(kCGThreads), 0, st, n, b, dinv, x, r_.get(),
-                       z_.get(), p_.get(), part2);
+                       z_.get(), P[1], part2);
     hipLaunchKernelGGL(cg_init_finish, dim3(1), dim3(64), 0, st, (int)nbv, part2, rtol, atol, sc,
                        done);
     OTIP_HIP(hipGetLastError());
@@ -388,21 +497,24 @@ CGStats SchurSolver::pcg_impl(hipStream_t st, const T *val, const T *dinv, const
     int launched = 0;
     CGScal hs{};
     int hdone = 0;
-    const double bytes = (2.0 * sizeof(T) + 4.0) * (double)S.nnz + (16.0 + 4.0) * n + 4.0;
+    // algorithmic bytes of one fused launch: values and columns, row pointers,
+    // the two gathered vectors read once, the new direction and q written
+    const double bytes = ((double)sizeof(T) + 4.0) * (double)S.nnz +
+                         (4.0 + 4.0 * (double)sizeof(T)) * n;
     while (true) {
         for (int c = 0; c < chunk; ++c) {
             const int par = launched & 1;
             unsigned nbs;
-            if (timer) timer->start(st, sizeof(T) == 8 ? 12.0 * (double)S.nnz + 20.0 * n + 4.0 : bytes);
-            launch_spmv<T>(st, S, val, p_.get(), q_.get(), part1, done, nbs);
+            if (timer) timer->start(st, bytes);
+            launch_spmv_dir<T>(st, S, val, z_.get(), P[par ^ 1], P[par], q_.get(), (int)nbv,
+                               part2, part1, sc, done, launched == 0 ? 1 : 0, par, nbs);
             if (timer) timer->stop(st);
             hipLaunchKernelGGL((cg_update<T>), dim3(nbv), dim3(kCGThreads), 0, st, n, (int)nbs,
-                               part1, p_.get(), q_.get(), dinv, x, r_.get(), z_.get(), part2, sc,
+                               part1, P[par], q_.get(), dinv, x, r_.get(), z_.get(), part2, sc,
                                done, par);
-            hipLaunchKernelGGL((cg_direction<T>), dim3(nbv), dim3(kCGThreads), 0, st, n, (int)nbv,
-                               part2, z_.get(), p_.get(), sc, done, par);
             ++launched;
         }
+        hipLaunchKernelGGL(cg_check, dim3(1), dim3(64), 0, st, (int)nbv, part2, sc, done);
         OTIP_HIP(hipGetLastError());
         OTIP_HIP(hipMemcpyAsync(&hs, sc, sizeof(CGScal), hipMemcpyDeviceToHost, st));
         OTIP_HIP(hipMemcpyAsync(&hdone, done, sizeof(int), hipMemcpyDeviceToHost, st));
