@@ -30,6 +30,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+# HBM traffic of the fused Schur SpMV measured by rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE (separate runs) on `bench.py --steps 1 --warmup 0 --no-cpu-baseline
+# --no-forms`, scaled by what the counters read for a 1 GiB device copy; valid
+# only for the kernel source it was measured on (the SHA-256 of spmv_dir's text).
+SPMV_TRAFFIC = {"source": "paper_2206_11009_amd/csrc/schur.hip",
+                "sha256": "5d16a05004c09ca953f0ca7e30520c6a45f7111a6fba72bba28a1c5da99dbfd1",
+                "bytes_per_launch": 11666362.0}
 FP64_VECTOR_PEAK_TF = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 PRICE_FLOPS_PER_COST = 7.0     # C_ij: one add + two FMAs (5 flops); r: two subtractions
 WORKLOADS = {
@@ -159,6 +166,29 @@ def summary(sec, infos):
                              for i in infos)}
 
 
+def kernel_source_sha256(path, name):
+    """SHA-256 of one kernel's source text: from its signature to the first
+    line that closes a top-level block."""
+    import hashlib
+    with open(os.path.join(ROOT, path)) as f:
+        src = f.read()
+    start = src.find(f"void {name}(")
+    if start < 0:
+        return None
+    end = src.find("\n}\n", start)
+    return hashlib.sha256(src[start:end + 3].encode()).hexdigest()
+
+
+def measured_traffic():
+    """Counter-measured SpMV bytes per launch, or None once the kernel's
+    source differs from the one the counters were taken on."""
+    if SPMV_TRAFFIC["sha256"] is None:
+        return None
+    if kernel_source_sha256(SPMV_TRAFFIC["source"], "spmv_dir") != SPMV_TRAFFIC["sha256"]:
+        return None
+    return SPMV_TRAFFIC["bytes_per_launch"]
+
+
 def rooflines(infos):
     spmv_ms = sum(i["spmv_ms"] for i in infos)
     spmv_n = sum(i["spmv_launches"] for i in infos)
@@ -169,7 +199,8 @@ def rooflines(infos):
     spmv = {"bound": "hbm", "kernel": "spmv_dir (Schur SpMV fused with the CG direction update)",
             "achieved": spmv_b / max(spmv_ms, 1e-12) / 1e6, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "avg_launch_us": 1e3 * spmv_ms / max(spmv_n, 1), "launches": spmv_n,
-            "total_ms": spmv_ms, "traffic": None}
+            "total_ms": spmv_ms, "traffic": measured_traffic(),
+            "algorithmic_bytes_per_launch": spmv_b / max(spmv_n, 1)}
     price = {"bound": "alu", "kernel": "price_pass (pricing scan)",
              "achieved": PRICE_FLOPS_PER_COST * pr_e / max(pr_ms, 1e-12) / 1e9,
              "peak": FP64_VECTOR_PEAK_TF, "unit": "TFLOP/s",

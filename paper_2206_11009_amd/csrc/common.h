@@ -1,6 +1,7 @@
 // Internal declarations shared by the otip HIP sources (not part of the ABI).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -91,6 +92,23 @@ struct LaunchTimer {
         if (!on) return;
         (void)hipEventRecord(ev[used + 1], st);
         used += 2;
+    }
+    // events for one launch of `w` units made with hipExtLaunchKernelGGL, which
+    // records them at the dispatch's own start and end; null when timing is off
+    void arm(double w, hipEvent_t *a, hipEvent_t *b) {
+        *a = *b = nullptr;
+        if (!on) return;
+        if (used + 2 > ev.size()) {
+            for (int k = 0; k < 64; ++k) {
+                hipEvent_t e;
+                if (hipEventCreate(&e) != hipSuccess) throw Error(3, "hipEventCreate failed");
+                ev.push_back(e);
+            }
+        }
+        *a = ev[used];
+        *b = ev[used + 1];
+        used += 2;
+        pending_work.push_back(w);
     }
     void reset() {
         launches = 0;

@@ -248,9 +248,10 @@ PriceResult Scanner::price(hipStream_t st, int m, int n, const int32_t *xs, cons
         a.prefix = prefix;
         a.rcut = (shift + 12 >= 64) ? INFINITY
                                     : rcut_of_key(((prefix + 1) << (shift + 12)) - 1);
-        if (timer) timer->start(st, (double)m * (double)n);
-        hipLaunchKernelGGL(price_pass<0>, grid, dim3(kScanBlock), 0, st, a);
-        if (timer) timer->stop(st);
+        hipEvent_t e0_, e1_;
+        if (timer) timer->arm((double)m * (double)n, &e0_, &e1_);
+        else e0_ = e1_ = nullptr;
+        hipExtLaunchKernelGGL(price_pass<0>, grid, dim3(kScanBlock), 0, st, e0_, e1_, 0, a);
         OTIP_HIP(hipGetLastError());
         OTIP_HIP(hipMemcpyAsync(h.data(), hist_.get(), kHistBins * sizeof(unsigned long long),
                                 hipMemcpyDeviceToHost, st));
@@ -315,9 +316,10 @@ PriceResult Scanner::price(hipStream_t st, int m, int n, const int32_t *xs, cons
     a.out_key = ck_.get();
     a.out_idx = ci_.get();
     a.cap = cap;
-    if (timer) timer->start(st, (double)m * (double)n);
-    hipLaunchKernelGGL(price_pass<1>, grid, dim3(kScanBlock), 0, st, a);
-    if (timer) timer->stop(st);
+    hipEvent_t e0_, e1_;
+    if (timer) timer->arm((double)m * (double)n, &e0_, &e1_);
+    else e0_ = e1_ = nullptr;
+    hipExtLaunchKernelGGL(price_pass<1>, grid, dim3(kScanBlock), 0, st, e0_, e1_, 0, a);
     OTIP_HIP(hipGetLastError());
     unsigned long long emitted = 0;
     OTIP_HIP(hipMemcpyAsync(&emitted, cnt_.get(), sizeof(emitted), hipMemcpyDeviceToHost, st));
@@ -855,9 +857,10 @@ PriceResult Scanner::price_mixed(hipStream_t st, int m, int n, const int32_t *xs
         OTIP_HIP(hipMemsetAsync(hist_.get(), 0, (kHistBins + 2) * sizeof(unsigned long long), st));
         a.shift = shift;
         a.prefix = prefix;
-        if (timer) timer->start(st, (double)m * (double)n);
-        hipLaunchKernelGGL(price32_pass<0>, grid, dim3(kScanBlock), 0, st, a);
-        if (timer) timer->stop(st);
+        hipEvent_t e0_, e1_;
+        if (timer) timer->arm((double)m * (double)n, &e0_, &e1_);
+        else e0_ = e1_ = nullptr;
+        hipExtLaunchKernelGGL(price32_pass<0>, grid, dim3(kScanBlock), 0, st, e0_, e1_, 0, a);
         OTIP_HIP(hipGetLastError());
         OTIP_HIP(hipMemcpyAsync(h.data(), hist_.get(), (kHistBins + 2) * sizeof(unsigned long long),
                                 hipMemcpyDeviceToHost, st));
@@ -910,9 +913,10 @@ PriceResult Scanner::price_mixed(hipStream_t st, int m, int n, const int32_t *xs
         a.count = cnt_.get();
         a.out_idx = ci_.get();
         a.cap = cap;
-        if (timer) timer->start(st, (double)m * (double)n);
-        hipLaunchKernelGGL(price32_pass<1>, grid, dim3(kScanBlock), 0, st, a);
-        if (timer) timer->stop(st);
+        hipEvent_t e0_, e1_;
+        if (timer) timer->arm((double)m * (double)n, &e0_, &e1_);
+        else e0_ = e1_ = nullptr;
+        hipExtLaunchKernelGGL(price32_pass<1>, grid, dim3(kScanBlock), 0, st, e0_, e1_, 0, a);
         OTIP_HIP(hipGetLastError());
         OTIP_HIP(hipMemcpyAsync(&emitted, cnt_.get(), sizeof(emitted), hipMemcpyDeviceToHost, st));
         OTIP_HIP(hipStreamSynchronize(st));

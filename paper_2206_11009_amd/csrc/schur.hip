@@ -442,24 +442,24 @@ static void launch_spmv(hipStream_t st, const SchurCSR &S, const T *val, const T
                            S.col.get(), val, x, y, partial, done);
 }
 
+// e0, e1: events recorded at the dispatch's own start and end (may be null)
 template <typename T>
 static void launch_spmv_dir(hipStream_t st, const SchurCSR &S, const T *val, const T *z,
                             const T *pold, T *pnew, T *q, int nb2, const double *part2,
                             double *partial, CGScal *sc, int *done, int first, int par,
-                            unsigned &nb_out) {
+                            unsigned &nb_out, hipEvent_t e0, hipEvent_t e1) {
     const int n = S.n;
     const double avg = (double)S.nnz / std::max(1, n);
     const int G = avg >= 48 ? 64 : 16;
     const unsigned nb = std::min<unsigned>(kSpmvMaxBlocks, grid_for(n, 256 / G));
     nb_out = nb;
+    const int32_t *rp = S.rowptr.get(), *cl = S.col.get();
     if (G == 64)
-        hipLaunchKernelGGL((spmv_dir<64, T>), dim3(nb), dim3(256), 0, st, n, S.rowptr.get(),
-                           S.col.get(), val, z, pold, pnew, q, nb2, part2, partial, sc, done,
-                           first, par);
+        hipExtLaunchKernelGGL(spmv_dir<64, T>, dim3(nb), dim3(256), 0, st, e0, e1, 0, n, rp, cl,
+                              val, z, pold, pnew, q, nb2, part2, partial, sc, done, first, par);
     else
-        hipLaunchKernelGGL((spmv_dir<16, T>), dim3(nb), dim3(256), 0, st, n, S.rowptr.get(),
-                           S.col.get(), val, z, pold, pnew, q, nb2, part2, partial, sc, done,
-                           first, par);
+        hipExtLaunchKernelGGL(spmv_dir<16, T>, dim3(nb), dim3(256), 0, st, e0, e1, 0, n, rp, cl,
+                              val, z, pold, pnew, q, nb2, part2, partial, sc, done, first, par);
 }
 
 void SchurSolver::spmv(hipStream_t st, const double *x, double *y) {
@@ -505,10 +505,10 @@ CGStats SchurSolver::pcg_impl(hipStream_t st, const T *val, const T *dinv, const
         for (int c = 0; c < chunk; ++c) {
             const int par = launched & 1;
             unsigned nbs;
-            if (timer) timer->start(st, bytes);
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (timer) timer->arm(bytes, &e0, &e1);
             launch_spmv_dir<T>(st, S, val, z_.get(), P[par ^ 1], P[par], q_.get(), (int)nbv,
-                               part2, part1, sc, done, launched == 0 ? 1 : 0, par, nbs);
-            if (timer) timer->stop(st);
+                               part2, part1, sc, done, launched == 0 ? 1 : 0, par, nbs, e0, e1);
             hipLaunchKernelGGL((cg_update<T>), dim3(nbv), dim3(kCGThreads), 0, st, n, (int)nbs,
                                part1, P[par], q_.get(), dinv, x, r_.get(), z_.get(), part2, sc,
                                done, par);
