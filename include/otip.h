@@ -39,7 +39,8 @@ extern "C" {
 
 enum otip_status {
     OTIP_OK = 0,
-    OTIP_EINVAL = 1,      /* bad argument: sizes, null pointers, masses */
+    OTIP_EINVAL = 1,      /* bad argument: sizes, null pointers, masses (negative, non-finite,
+                             unbalanced, all zero), coordinates out of range */
     OTIP_ENOMEM = 2,      /* device allocation failed */
     OTIP_EHIP = 3,        /* HIP runtime error */
     OTIP_EMAXITER = 4,    /* iteration limit: result valid but not certified to tol */
@@ -101,7 +102,10 @@ typedef struct otip_params {
 } otip_params;
 
 /* Problem description.  All arrays are DEVICE pointers.
- *   a  : m doubles, > 0          b : n doubles, > 0, |sum a - sum b| <= 1e-12 sum a
+ *   a  : m doubles, >= 0         b : n doubles, >= 0, |sum a - sum b| <= 1e-12 sum a,
+ *        sums > 0.  Rows and columns of zero mass are dropped before solving and
+ *        returned with zero flow and c-transform duals (every reduced cost of
+ *        theirs >= 0), so the certificate covers the whole problem.
  *   xs : m x 2 int32, row-major   xt: n x 2 int32, row-major, coordinates in
  *        [-2^14, 2^14] so that every cost fits in 31 bits.
  *   y0, z0: optional predicted duals (m and n doubles, cost units) or both NULL.

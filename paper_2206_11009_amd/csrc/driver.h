@@ -53,6 +53,7 @@ class Solver {
     void starting_point();
     void finalize(Result &res);
     void reset_state();
+    int run_without_zeros(const otip_problem &pr, const otip_params &prm, Result &res);
     static double now();
     void log(const char *fmt, ...);
 
@@ -88,7 +89,8 @@ class Solver {
     DBuf<double> sel_r_;
     DBuf<uint8_t> removed_;
     DBuf<int32_t> zc_;
-    DBuf<double> yws_, zws_;
+    DBuf<double> yws_, zws_, zmass_, zdual_;
+    DBuf<int32_t> zcoord_;
     bool warm_used = false;
     bool schur_valid = false;
 

@@ -587,6 +587,117 @@ struct FScaleIn {
     __device__ void operator()(int64_t k) const { dst[k] = src[k] * f; }
 };
 
+// Zero masses (the marginals lie in R+): the rows and columns with zero mass
+// carry no flow, so they are dropped, the problem without them is solved, and
+// they come back with zero flow and c-transform duals (y_i = min_j C_ij - z_j
+// over the kept targets, then z_j = min_i C_ij - y_i over all sources), which
+// keep every reduced cost of the added rows and columns >= 0: the certificate
+// of the smaller problem holds for the whole one.
+int Solver::run_without_zeros(const otip_problem &pr, const otip_params &prm, Result &res) {
+    const int M = pr.m, Nn = pr.n;
+    std::vector<double> ha(M), hb(Nn);
+    std::vector<int32_t> hxs((size_t)2 * M), hxt((size_t)2 * Nn);
+    std::vector<double> hy0, hz0;
+    OTIP_HIP(hipMemcpyAsync(ha.data(), pr.a, sizeof(double) * M, hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipMemcpyAsync(hb.data(), pr.b, sizeof(double) * Nn, hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipMemcpyAsync(hxs.data(), pr.xs, sizeof(int32_t) * 2 * M, hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipMemcpyAsync(hxt.data(), pr.xt, sizeof(int32_t) * 2 * Nn, hipMemcpyDeviceToHost, st));
+    if (pr.y0 && pr.z0) {
+        hy0.resize(M);
+        hz0.resize(Nn);
+        OTIP_HIP(hipMemcpyAsync(hy0.data(), pr.y0, sizeof(double) * M, hipMemcpyDeviceToHost, st));
+        OTIP_HIP(hipMemcpyAsync(hz0.data(), pr.z0, sizeof(double) * Nn, hipMemcpyDeviceToHost, st));
+    }
+    OTIP_HIP(hipStreamSynchronize(st));
+    std::vector<int32_t> ki, kj;
+    for (int i = 0; i < M; ++i)
+        if (ha[i] > 0.0) ki.push_back(i);
+    for (int j = 0; j < Nn; ++j)
+        if (hb[j] > 0.0) kj.push_back(j);
+    const int mk = (int)ki.size(), nk = (int)kj.size();
+    std::vector<double> cm((size_t)mk + nk), cy((size_t)mk + nk);
+    std::vector<int32_t> cx((size_t)2 * (mk + nk));
+    for (int q = 0; q < mk; ++q) {
+        cm[q] = ha[ki[q]];
+        cx[2 * q] = hxs[2 * ki[q]];
+        cx[2 * q + 1] = hxs[2 * ki[q] + 1];
+        if (!hy0.empty()) cy[q] = hy0[ki[q]];
+    }
+    for (int q = 0; q < nk; ++q) {
+        cm[mk + q] = hb[kj[q]];
+        cx[2 * (mk + q)] = hxt[2 * kj[q]];
+        cx[2 * (mk + q) + 1] = hxt[2 * kj[q] + 1];
+        if (!hz0.empty()) cy[mk + q] = hz0[kj[q]];
+    }
+    double *dm = zmass_.need(cm.size()), *dy = zdual_.need(cy.size());
+    int32_t *dx = zcoord_.need(cx.size());
+    OTIP_HIP(hipMemcpyAsync(dm, cm.data(), sizeof(double) * cm.size(), hipMemcpyHostToDevice, st));
+    OTIP_HIP(hipMemcpyAsync(dy, cy.data(), sizeof(double) * cy.size(), hipMemcpyHostToDevice, st));
+    OTIP_HIP(hipMemcpyAsync(dx, cx.data(), sizeof(int32_t) * cx.size(), hipMemcpyHostToDevice, st));
+    otip_problem sub{mk, nk, dm, dm + mk, dx, dx + 2 * (size_t)mk,
+                     hy0.empty() ? nullptr : dy, hz0.empty() ? nullptr : dy + mk};
+    Result r;
+    const int status = run(sub, prm, r);  // no zero masses left: no further recursion
+    res.info = r.info;
+    res.rows.resize(r.rows.size());
+    res.cols.resize(r.cols.size());
+    for (size_t k = 0; k < r.rows.size(); ++k) {
+        res.rows[k] = ki[r.rows[k]];
+        res.cols[k] = kj[r.cols[k]];
+    }
+    res.vals = r.vals;
+    // order of the expanded plan: by variable index i + j*M
+    {
+        std::vector<size_t> ord(res.vals.size());
+        for (size_t k = 0; k < ord.size(); ++k) ord[k] = k;
+        std::sort(ord.begin(), ord.end(), [&](size_t u, size_t v) {
+            const int64_t iu = res.rows[u] + (int64_t)res.cols[u] * M;
+            const int64_t iv = res.rows[v] + (int64_t)res.cols[v] * M;
+            return iu < iv;
+        });
+        std::vector<int32_t> rr(ord.size()), cc(ord.size());
+        std::vector<double> vv(ord.size());
+        for (size_t k = 0; k < ord.size(); ++k) {
+            rr[k] = res.rows[ord[k]];
+            cc[k] = res.cols[ord[k]];
+            vv[k] = res.vals[ord[k]];
+        }
+        res.rows.swap(rr);
+        res.cols.swap(cc);
+        res.vals.swap(vv);
+    }
+    std::vector<double> yf(M, 0.0), zf(Nn, -INFINITY);
+    for (int q = 0; q < mk; ++q) yf[ki[q]] = r.y[q];
+    for (int q = 0; q < nk; ++q) zf[kj[q]] = r.z[q];
+    double *gy = zdual_.need((size_t)2 * (M + Nn));
+    double *gz = gy + M, *ty = gz + Nn, *tz = ty + M;
+    OTIP_HIP(hipMemcpyAsync(gz, zf.data(), sizeof(double) * Nn, hipMemcpyHostToDevice, st));
+    if (mk < M) {
+        std::vector<double> h(M);
+        scan.ctransform_rows(st, M, Nn, pr.xs, pr.xt, gz, ty);
+        OTIP_HIP(hipMemcpyAsync(h.data(), ty, sizeof(double) * M, hipMemcpyDeviceToHost, st));
+        OTIP_HIP(hipStreamSynchronize(st));
+        for (int i = 0; i < M; ++i)
+            if (!(ha[i] > 0.0)) yf[i] = h[i];
+    }
+    if (nk < Nn) {
+        std::vector<double> h(Nn);
+        OTIP_HIP(hipMemcpyAsync(gy, yf.data(), sizeof(double) * M, hipMemcpyHostToDevice, st));
+        scan.ctransform_cols(st, M, Nn, pr.xs, pr.xt, gy, tz);
+        OTIP_HIP(hipMemcpyAsync(h.data(), tz, sizeof(double) * Nn, hipMemcpyDeviceToHost, st));
+        OTIP_HIP(hipStreamSynchronize(st));
+        for (int j = 0; j < Nn; ++j)
+            if (!(hb[j] > 0.0)) zf[j] = h[j];
+    }
+    const double g = zf[Nn - 1];  // gauge z_{n-1} = 0
+    for (auto &v : yf) v += g;
+    for (auto &v : zf) v -= g;
+    res.y.swap(yf);
+    res.z.swap(zf);
+    res.info.nnz = (int64_t)res.vals.size();
+    return status;
+}
+
 // Per-solve scalars back to their initial values; device buffers are kept so
 // that a solver reused for a stream of problems allocates (and frees) nothing
 // once it has seen the largest one.
@@ -626,29 +737,33 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
     OTIP_CHECK(m >= 1 && n >= 1, OTIP_EINVAL, "m and n must be >= 1");
     OTIP_CHECK(pr.a && pr.b && pr.xs && pr.xt, OTIP_EINVAL, "null problem array");
     // ---- validation on the device data (masses > 0, balanced)
-    double sa, sb, mina, minb, bad;
+    double sa, sb, mina, minb, bad, zeros;
     {
         const double *A = pr.a, *B = pr.b;
         const int mm = m;
-        double v[3];
-        reduce_sum<3>(st, red, (int64_t)m + n,
+        double v[4];
+        reduce_sum<4>(st, red, (int64_t)m + n,
                       [=] __device__(int64_t t, double *acc) {
                           const double x = t < mm ? A[t] : B[t - mm];
                           if (t < mm)
                               acc[0] += x;
                           else
                               acc[1] += x;
-                          if (!(x > 0.0) || isinf(x)) acc[2] += 1.0;
+                          if (!(x >= 0.0) || isinf(x)) acc[2] += 1.0;
+                          if (x == 0.0) acc[3] += 1.0;
                       },
                       v);
         sa = v[0];
         sb = v[1];
         bad = v[2];
+        zeros = v[3];
         (void)mina;
         (void)minb;
     }
-    OTIP_CHECK(bad == 0.0, OTIP_EINVAL, "masses must be finite and strictly positive");
+    OTIP_CHECK(bad == 0.0, OTIP_EINVAL, "masses must be finite and nonnegative");
+    OTIP_CHECK(sa > 0.0 && sb > 0.0, OTIP_EINVAL, "total mass must be positive");
     OTIP_CHECK(std::fabs(sa - sb) <= 1e-12 * sa, OTIP_EINVAL, "sum(a) != sum(b)");
+    if (zeros > 0.0) return run_without_zeros(pr, prm, res);
     {
         // coordinate range -> largest cost (for scaling and the initial support)
         std::vector<int32_t> hx((size_t)2 * m), ht((size_t)2 * n);

@@ -54,6 +54,12 @@ class Scanner {
               const double *y, const double *z, double *out, int64_t *arg);
     int64_t initial_support(hipStream_t st, int m, int n, const int32_t *xs, const int32_t *xt,
                             double kappa, int64_t cmax, DBuf<uint64_t> &out, int64_t *T);
+    // c-transforms: y_i = min_j (C_ij - z_j), z_j = min_i (C_ij - y_i) (an entry
+    // of -inf in the given duals excludes its row or column)
+    void ctransform_rows(hipStream_t st, int m, int n, const int32_t *xs, const int32_t *xt,
+                         const double *z, double *y);
+    void ctransform_cols(hipStream_t st, int m, int n, const int32_t *xs, const int32_t *xt,
+                         const double *y, double *z);
     // initial support from predicted duals (c-transform, smallest reduced
     // costs, row and column covers); -1 if the duals are unusable
     int64_t warm_support(hipStream_t st, int m, int n, const int32_t *xs, const int32_t *xt,

@@ -74,7 +74,7 @@ __global__ __launch_bounds__(kWB) void ctrans_row(int m, int n, const int32_t *x
     }
     if (threadIdx.x == 0) {
         y[i] = sv[0];
-        cover[i] = (uint64_t)i + (uint64_t)min(sa[0], n - 1) * (uint64_t)m;
+        if (cover) cover[i] = (uint64_t)i + (uint64_t)min(sa[0], n - 1) * (uint64_t)m;
     }
 }
 
@@ -188,6 +188,19 @@ __global__ void nonfinite_flag(int64_t len, const double *v, int *flag) {
 }
 
 }  // namespace
+
+void Scanner::ctransform_rows(hipStream_t st, int m, int n, const int32_t *xs, const int32_t *xt,
+                              const double *z, double *y) {
+    hipLaunchKernelGGL(ctrans_row, dim3(m), dim3(kWB), 0, st, m, n, xs, xt, z, y,
+                       (uint64_t *)nullptr);
+    OTIP_HIP(hipGetLastError());
+}
+
+void Scanner::ctransform_cols(hipStream_t st, int m, int n, const int32_t *xs, const int32_t *xt,
+                              const double *y, double *z) {
+    hipLaunchKernelGGL(ctrans_col, dim3(n), dim3(kWB), 0, st, m, n, xs, xt, y, z);
+    OTIP_HIP(hipGetLastError());
+}
 
 int64_t Scanner::warm_support(hipStream_t st, int m, int n, const int32_t *xs, const int32_t *xt,
                               const double *y0, const double *z0, double kappa,
