@@ -35,8 +35,8 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 # --no-forms`, scaled by what the counters read for a 1 GiB device copy; valid
 # only for the kernel source it was measured on (the SHA-256 of spmv_dir's text).
 SPMV_TRAFFIC = {"source": "paper_2206_11009_amd/csrc/schur.hip",
-                "sha256": "5d16a05004c09ca953f0ca7e30520c6a45f7111a6fba72bba28a1c5da99dbfd1",
-                "bytes_per_launch": 11666362.0}
+                "sha256": "43d84d2e35c30395e1c72a321017adcc6068042e438eb6afad49501af23448c3",
+                "bytes_per_launch": 11667382.0}
 FP64_VECTOR_PEAK_TF = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 PRICE_FLOPS_PER_COST = 7.0     # C_ij: one add + two FMAs (5 flops); r: two subtractions
 WORKLOADS = {

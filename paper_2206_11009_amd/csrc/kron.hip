@@ -5,8 +5,9 @@
 // Both stream X once through HBM; every other access stays on chip.
 //
 // kron_apply: a 256-thread block owns a tile of 1024 rows x 64 columns; each
-// thread reads 4 rows of each column (coalesced along the column), keeps its 4
-// running row sums in registers and reduces each column over the block.
+// thread reads 2 x 2 adjacent rows of each column with 16-byte loads (a wave
+// covers 1 KB contiguous per load), keeps its 4 running row sums in registers
+// and reduces each column over the block.
 // Partial sums per tile go to small side arrays that a second, fixed-order
 // pass adds up, so the result is bitwise reproducible.
 #include "internal.h"
@@ -14,6 +15,7 @@
 namespace otip {
 
 constexpr int KR_ROWS = 1024;  // rows per tile (4 per thread)
+typedef double dv2 __attribute__((ext_vector_type(2)));
 constexpr int KR_COLS = 64;    // columns per tile
 
 __global__ __launch_bounds__(256) void kron_tile(int m, int n, const double *__restrict__ X,
@@ -21,24 +23,31 @@ __global__ __launch_bounds__(256) void kron_tile(int m, int n, const double *__r
                                                  double *__restrict__ pcol) {
     __shared__ double cs[4][KR_COLS];
     const int rt = blockIdx.x, ct = blockIdx.y;
-    const int i0 = rt * KR_ROWS + threadIdx.x;
+    const int r0 = rt * KR_ROWS;
     const int j0 = ct * KR_COLS;
     const int jn = min(KR_COLS, n - j0);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // rows of this thread: r0 + 2t, r0 + 2t + 1 and the same 512 rows further
+    const int ia = r0 + 2 * threadIdx.x, ib = ia + 512;
     double rs[4] = {0.0, 0.0, 0.0, 0.0};
-    const bool full = (rt + 1) * KR_ROWS <= m;
+    // 16-byte loads when every column of the tile starts 16-byte aligned (X
+    // aligned, m even) and the tile has all its rows
+    const bool wide = (m % 2 == 0) && r0 + KR_ROWS <= m && ((uintptr_t)X % 16 == 0);
     for (int c = 0; c < jn; ++c) {
         const double *col = X + (size_t)(j0 + c) * (size_t)m;
         double v[4];
-        if (full) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) v[q] = __builtin_nontemporal_load(&col[i0 + 256 * q]);
+        if (wide) {
+            const dv2 va = __builtin_nontemporal_load((const dv2 *)(col + ia));
+            const dv2 vb = __builtin_nontemporal_load((const dv2 *)(col + ib));
+            v[0] = va.x;
+            v[1] = va.y;
+            v[2] = vb.x;
+            v[3] = vb.y;
         } else {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int i = i0 + 256 * q;
-                v[q] = i < m ? __builtin_nontemporal_load(&col[i]) : 0.0;
-            }
+            v[0] = ia < m ? col[ia] : 0.0;
+            v[1] = ia + 1 < m ? col[ia + 1] : 0.0;
+            v[2] = ib < m ? col[ib] : 0.0;
+            v[3] = ib + 1 < m ? col[ib + 1] : 0.0;
         }
         double t = 0.0;
 #pragma unroll
@@ -52,11 +61,10 @@ __global__ __launch_bounds__(256) void kron_tile(int m, int n, const double *__r
     __syncthreads();
     for (int c = threadIdx.x; c < jn; c += 256)
         pcol[(size_t)rt * n + j0 + c] = ((cs[0][c] + cs[1][c]) + cs[2][c]) + cs[3][c];
+    const int rows[4] = {ia, ia + 1, ib, ib + 1};
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int i = i0 + 256 * q;
-        if (i < m) prow[(size_t)ct * m + i] = rs[q];
-    }
+    for (int q = 0; q < 4; ++q)
+        if (rows[q] < m) prow[(size_t)ct * m + rows[q]] = rs[q];
 }
 
 __global__ void kron_finish(int len, int parts, const double *__restrict__ part,
@@ -82,26 +90,30 @@ void kron_apply(hipStream_t st, int m, int n, const double *X, double *rowsum, d
     OTIP_HIP(hipGetLastError());
 }
 
-// X_ij = y_i + z_j: each block writes a 1024 x 64 tile, rows along the lanes
+// X_ij = y_i + z_j: each block writes a 1024 x 64 tile, 16 bytes per lane and
+// store when the columns are 16-byte aligned (m even) and the tile is full
 __global__ __launch_bounds__(256) void kron_t_tile(int m, int n, const double *__restrict__ y,
                                                    const double *__restrict__ z,
                                                    double *__restrict__ X) {
-    const int i0 = blockIdx.x * KR_ROWS + threadIdx.x;
+    const int r0 = blockIdx.x * KR_ROWS;
+    const int ia = r0 + 2 * threadIdx.x, ib = ia + 512;
     const int j0 = blockIdx.y * KR_COLS;
     const int jn = min(KR_COLS, n - j0);
+    const int rows[4] = {ia, ia + 1, ib, ib + 1};
     double yv[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int i = i0 + 256 * q;
-        yv[q] = i < m ? y[i] : 0.0;
-    }
+    for (int q = 0; q < 4; ++q) yv[q] = rows[q] < m ? y[rows[q]] : 0.0;
+    const bool wide = (m % 2 == 0) && r0 + KR_ROWS <= m && ((uintptr_t)X % 16 == 0);
     for (int c = 0; c < jn; ++c) {
         const double zj = z[j0 + c];
         double *col = X + (size_t)(j0 + c) * (size_t)m;
+        if (wide) {
+            *(dv2 *)(col + ia) = dv2{yv[0] + zj, yv[1] + zj};
+            *(dv2 *)(col + ib) = dv2{yv[2] + zj, yv[3] + zj};
+        } else {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int i = i0 + 256 * q;
-            if (i < m) __builtin_nontemporal_store(yv[q] + zj, &col[i]);
+            for (int q = 0; q < 4; ++q)
+                if (rows[q] < m) col[rows[q]] = yv[q] + zj;
         }
     }
 }

@@ -252,7 +252,18 @@ __global__ __launch_bounds__(256) void spmv_rows(int n, const int32_t *__restric
     double dot = 0.0;
     for (int r = blockIdx.x * groups + g; r < n; r += gridDim.x * groups) {
         T acc = (T)0;
-        for (int e = rowptr[r] + l; e < rowptr[r + 1]; e += G) acc = fma(val[e], x[col[e]], acc);
+        const int e1 = rowptr[r + 1];
+        int e = rowptr[r] + l;
+        for (; e + 3 * G < e1; e += 4 * G) {
+            const int c0 = col[e], c1 = col[e + G], c2 = col[e + 2 * G], c3 = col[e + 3 * G];
+            const T v0 = val[e], v1 = val[e + G], v2 = val[e + 2 * G], v3 = val[e + 3 * G];
+            const T x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
+            acc = fma(v0, x0, acc);
+            acc = fma(v1, x1, acc);
+            acc = fma(v2, x2, acc);
+            acc = fma(v3, x3, acc);
+        }
+        for (; e < e1; e += G) acc = fma(val[e], x[col[e]], acc);
         for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
         if (l == 0) {
             y[r] = acc;
@@ -358,7 +369,21 @@ __global__ __launch_bounds__(256) void spmv_dir(int n, const int32_t *__restrict
     double dot = 0.0;
     for (int r = blockIdx.x * groups + g; r < n; r += gridDim.x * groups) {
         T acc = (T)0;
-        for (int e = rowptr[r] + l; e < rowptr[r + 1]; e += G) {
+        const int e1 = rowptr[r + 1];
+        int e = rowptr[r] + l;
+        // four strides at a time: the column loads, then the gathers, are all
+        // in flight before the products (same summation order as one by one)
+        for (; e + 3 * G < e1; e += 4 * G) {
+            const int c0 = col[e], c1 = col[e + G], c2 = col[e + 2 * G], c3 = col[e + 3 * G];
+            const T v0 = val[e], v1 = val[e + G], v2 = val[e + 2 * G], v3 = val[e + 3 * G];
+            const T g0 = fma(beta, pold[c0], z[c0]), g1 = fma(beta, pold[c1], z[c1]);
+            const T g2 = fma(beta, pold[c2], z[c2]), g3 = fma(beta, pold[c3], z[c3]);
+            acc = fma(v0, g0, acc);
+            acc = fma(v1, g1, acc);
+            acc = fma(v2, g2, acc);
+            acc = fma(v3, g3, acc);
+        }
+        for (; e < e1; e += G) {
             const int c = col[e];
             acc = fma(val[e], fma(beta, pold[c], z[c]), acc);
         }
