@@ -264,6 +264,34 @@ int otip_schur(otip_ctx *ctx, int32_t m, int32_t n, int64_t psi, const int64_t *
                const double *theta, int64_t *out_nnz, int32_t *rowptr, int32_t *colidx,
                double *vals, double *M, double *N);
 
+/*
+ * Preconditioned conjugate gradients of the Newton step (Section 4, eq. for
+ * the Schur complement; tolerances of Section 5.2), on a caller's matrix:
+ * solves S x = b for a symmetric positive (semi)definite n x n CSR matrix with
+ * the Jacobi preconditioner, stopping when ||b - S x||_2 <= rtol ||b||_2 (as
+ * the iteration's recurrence tracks it) or after maxit iterations.  Each
+ * iteration is one fused launch (SpMV with the direction update) and one
+ * vector update, as inside otip_solve.
+ *   rowptr (n+1 int32), colidx (nnz int32, in [0, n)), vals (nnz), b (n):
+ *   DEVICE, read only (copied; rowptr is validated on the host, colidx on the
+ *   device).  x (n): DEVICE, output (the iteration starts from 0).  A row
+ *   whose diagonal is absent or not positive gets preconditioner 0.  For a
+ *   singular S (as the Schur complement, whose rows sum to 0) b must lie in
+ *   its range.
+ *   precision: OTIP_FP64, or OTIP_MIXED (FP32 CG inside FP64 iterative
+ *   refinement on the FP64 residual).
+ *   iterations, res_norm: HOST, optional.  spmv_stats: HOST, optional, 3
+ *   values: fused SpMV launches that did work, their mean duration in seconds
+ *   (events recorded at the dispatches' own start and end), and their
+ *   algorithmic bytes per launch ((w + 4) nnz + (4 + 4 w) n, w = 8 in FP64
+ *   and 4 in the FP32 inner solves).
+ * Returns OTIP_OK when converged, OTIP_EMAXITER when maxit was reached,
+ * OTIP_ENUMERIC on a breakdown (p'Sp <= 0).
+ */
+int otip_pcg(otip_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr, const int32_t *colidx,
+             const double *vals, const double *b, double *x, double rtol, int32_t maxit,
+             int32_t precision, int32_t *iterations, double *res_norm, double *spmv_stats);
+
 /* ------------------------------------------------------------------------
  * Learned warm start.  A small convolutional network maps the two marginals of
  * a side x side grid problem (pixel i at coordinates (i / side, i % side)) to

@@ -22,7 +22,7 @@ from ._abi import (OTIP_OK, OTIP_EINVAL, OTIP_ENOMEM, OTIP_EHIP, OTIP_ENUMERIC, 
 
 __all__ = ["otip_version", "otip_params_default", "Context", "OtipError", "SolveResult",
            "otip_solve", "otip_solve_batch", "otip_price", "otip_rmin", "otip_kron_apply",
-           "otip_kron_apply_t", "otip_schur", "params", "otip_ws_param_count", "otip_ws_forward",
+           "otip_kron_apply_t", "otip_schur", "otip_pcg", "PCGResult", "params", "otip_ws_param_count", "otip_ws_forward",
            "otip_ws_grad", "otip_ws_adam", "otip_ws_predict", "load_ws_weights"]
 
 
@@ -256,6 +256,47 @@ def otip_schur(ctx: Context, m: int, n: int, idx, theta):
                                   ctypes.byref(nnz), _ptr(rp), _ptr(ci), _ptr(va), _ptr(M),
                                   _ptr(N)))
     return rp, ci[:nnz.value], va[:nnz.value], M, N
+
+
+class PCGResult:
+    """Outcome of otip_pcg: status (OTIP_OK, OTIP_EMAXITER or OTIP_ENUMERIC),
+    iterations, final residual norm, and the fused SpMV launches that did work
+    with their mean duration (s) and algorithmic bytes per launch."""
+
+    def __init__(self, status, iterations, res_norm, stats):
+        self.status = status
+        self.iterations = iterations
+        self.res_norm = res_norm
+        self.spmv_launches = int(stats[0])
+        self.spmv_seconds = stats[1]
+        self.spmv_bytes = stats[2]
+
+
+def otip_pcg(ctx: Context, rowptr, colidx, vals, b, x=None, rtol=1e-6, maxit=1000,
+             precision=0):
+    """Jacobi-PCG on the CSR matrix (device tensors); x (device, n) is
+    written.  Returns (x, PCGResult); errors other than the iteration limit
+    and a breakdown raise."""
+    torch = _torch()
+    n = int(rowptr.shape[0]) - 1
+    nnz = int(vals.shape[0])
+    rp = _dev(rowptr, torch.int32, ctx.device)
+    ci = _dev(colidx, torch.int32, ctx.device)
+    va = _dev(vals, torch.float64, ctx.device)
+    bb = _dev(b, torch.float64, ctx.device)
+    if x is None:
+        x = torch.empty(n, dtype=torch.float64, device=bb.device)
+    elif not (x.dtype == torch.float64 and x.is_contiguous() and x.numel() == n
+              and x.device == bb.device):
+        raise OtipError(_abi.OTIP_EINVAL, "x must be a contiguous float64 device tensor of n")
+    its = ctypes.c_int32()
+    rn = ctypes.c_double()
+    st = (ctypes.c_double * 3)()
+    rc = ctx._lib.otip_pcg(ctx.handle, n, nnz, _ptr(rp), _ptr(ci), _ptr(va), _ptr(bb), _ptr(x),
+                           float(rtol), int(maxit), int(precision), ctypes.byref(its),
+                           ctypes.byref(rn), st)
+    ctx.check(rc, allow=(_abi.OTIP_OK, _abi.OTIP_EMAXITER, _abi.OTIP_ENUMERIC))
+    return x, PCGResult(rc, its.value, rn.value, list(st))
 
 
 # ------------------------------------------------------------ learned warm start

@@ -81,6 +81,8 @@ SIGNATURES = {
     "otip_kron_apply_t": (ctypes.c_int, [_p, _c_i32, _c_i32, _p, _p, _p]),
     "otip_schur": (ctypes.c_int, [_p, _c_i32, _c_i32, _c_i64, _p, _p, ctypes.POINTER(_c_i64),
                                   _p, _p, _p, _p, _p]),
+    "otip_pcg": (ctypes.c_int, [_p, _c_i32, _c_i64, _p, _p, _p, _p, _p, _c_f64, _c_i32, _c_i32,
+                                ctypes.POINTER(_c_i32), ctypes.POINTER(_c_f64), _p]),
     "otip_ws_param_count": (_c_i64, []),
     "otip_ws_forward": (ctypes.c_int, [_p, _p, _c_i32, _c_i32, _c_i32, _p, _p]),
     "otip_ws_grad": (ctypes.c_int, [_p, _p, _c_i32, _c_i32, _c_i32, _p, _p, _p,

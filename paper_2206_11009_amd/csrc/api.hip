@@ -334,6 +334,37 @@ int otip_schur(otip_ctx *ctx, int32_t m, int32_t n, int64_t psi, const int64_t *
     });
 }
 
+int otip_pcg(otip_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr, const int32_t *colidx,
+             const double *vals, const double *b, double *x, double rtol, int32_t maxit,
+             int32_t precision, int32_t *iterations, double *res_norm, double *spmv_stats) {
+    otip::CGStats cs;
+    int rc = guarded(ctx, [&] {
+        OTIP_CHECK(n >= 1 && nnz >= 0 && nnz <= 0x7fffffff && rowptr && b && x &&
+                       (nnz == 0 || (colidx && vals)) && rtol > 0.0 && maxit >= 1 &&
+                       (precision == OTIP_FP64 || precision == OTIP_MIXED),
+                   OTIP_EINVAL, "otip_pcg: bad arguments");
+        otip::SchurSolver s;
+        otip::LaunchTimer t;
+        t.on = spmv_stats != nullptr;
+        s.timer = &t;
+        s.load_csr(ctx->stream, n, nnz, rowptr, colidx, vals);
+        cs = precision == OTIP_MIXED ? s.pcg_mixed(ctx->stream, b, x, rtol, INFINITY, maxit)
+                                     : s.pcg(ctx->stream, b, x, rtol, INFINITY, maxit);
+        OTIP_HIP(hipStreamSynchronize(ctx->stream));
+        if (iterations) *iterations = cs.iterations;
+        if (res_norm) *res_norm = cs.res_norm;
+        if (spmv_stats) {
+            const double w = precision == OTIP_MIXED ? 4.0 : 8.0;
+            spmv_stats[0] = (double)t.launches;
+            spmv_stats[1] = t.launches ? t.ms * 1e-3 / (double)t.launches : 0.0;
+            spmv_stats[2] = (w + 4.0) * (double)nnz + (4.0 + 4.0 * w) * n;
+        }
+    });
+    if (rc != OTIP_OK) return rc;
+    if (cs.converged) return OTIP_OK;
+    return cs.iterations >= maxit ? OTIP_EMAXITER : OTIP_ENUMERIC;
+}
+
 int64_t otip_ws_param_count(void) { return otip::WarmNet::param_count(); }
 
 int otip_ws_forward(otip_ctx *ctx, const float *weights, int32_t batch, int32_t h, int32_t w,

@@ -116,10 +116,13 @@ struct LaunchTimer {
         used = 0;
         pending_work.clear();
     }
-    // after the stream has been synchronised
-    void collect() {
+    // after the stream has been synchronised; only the first `keep` launches
+    // armed since the last collect count (launches that found their work
+    // already done are dropped from both the time and the work)
+    void collect(size_t keep = SIZE_MAX) {
         if (!on) return;
-        for (size_t k = 0; k + 1 < used; k += 2) {
+        const size_t lim = keep >= used / 2 ? used : 2 * keep;
+        for (size_t k = 0; k + 1 < lim; k += 2) {
             float t = 0.0f;
             if (hipEventElapsedTime(&t, ev[k], ev[k + 1]) == hipSuccess) {
                 ms += t;

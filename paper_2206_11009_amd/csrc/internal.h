@@ -124,6 +124,10 @@ class SchurSolver {
     void numeric(hipStream_t st, int m, int n, const int32_t *col_ptr, const int32_t *si,
                  const int32_t *row_ptr, const int32_t *csr_pos, const int32_t *sj,
                  const double *theta, const double *invM);
+    // S from a caller's CSR matrix (device arrays, copied; row pointers and
+    // column indices validated) with its Jacobi inverse diagonal
+    void load_csr(hipStream_t st, int n, int64_t nnz, const int32_t *rowptr, const int32_t *col,
+                  const double *val);
     // y = S x
     void spmv(hipStream_t st, const double *x, double *y);
     // Jacobi-preconditioned CG on S x = b (b projected on e-perp by the caller)
@@ -136,12 +140,12 @@ class SchurSolver {
   private:
     template <typename T>
     CGStats pcg_impl(hipStream_t st, const T *val, const T *dinv, const T *b, T *x, double rtol,
-                     double atol, int maxit, DBuf<T> &r, DBuf<T> &z, DBuf<T> &p, DBuf<T> &q);
+                     double atol, int maxit, DBuf<T> &r, DBuf<T> &p, DBuf<T> &q);
     DBuf<int32_t> cnt_;
     DBuf<char> tmp_;
     DBuf<int64_t> off64_, cnt64_;
-    DBuf<double> r_, z_, p_, q_, part_, scal_, rd_, sx_, rpart_;
-    DBuf<float> val32_, dinv32_, rf_, df_, rf2_, zf_, pf_, qf_;
+    DBuf<double> r_, p_, q_, part_, scal_, rd_, sx_, rpart_;
+    DBuf<float> val32_, dinv32_, rf_, df_, rf2_, pf_, qf_;
     DBuf<int> flag_;
 };
 

@@ -234,6 +234,7 @@ void SchurSolver::numeric(hipStream_t st, int m, int n, const int32_t *col_ptr,
 constexpr int kCGBlocks = 256;
 constexpr int kCGThreads = 256;
 constexpr int kSpmvMaxBlocks = 4096;
+constexpr int kSpmvDirBlocks = 768;
 
 // G lanes per row; rows distributed round-robin over a fixed grid.  If
 // partial, partial[block] = sum over the block's rows of x_j * y_j (in FP64).
@@ -277,8 +278,9 @@ __global__ __launch_bounds__(256) void spmv_rows(int n, const int32_t *__restric
 }
 
 // Device-side CG scalars.  rho is double-buffered by iteration parity: the
-// direction kernel reads rho[par] in every workgroup and workgroup 0 writes
-// rho[par ^ 1] for the next iteration, so no extra launch commits it.
+// direction kernel of iteration parity par reads the previous rho from
+// rho[par ^ 1] in every workgroup and workgroup 0 writes the new one to
+// rho[par], so no extra launch commits it.
 struct CGScal {
     double rho[2], rr, target, its;
 };
@@ -297,10 +299,17 @@ __device__ __forceinline__ double sum_partials(const double *p, int nb, double *
     return v;
 }
 
+// The preconditioned residual z and the search direction p of one iteration
+// parity, interleaved so that the SpMV gathers both with one load per nonzero.
+template <typename T>
+struct __attribute__((aligned(2 * sizeof(T)))) ZP {
+    T z, p;
+};
+
 template <typename T>
 __global__ __launch_bounds__(kCGThreads) void cg_init(int n, const T *__restrict__ b,
                                                       const T *__restrict__ dinv, T *x, T *r,
-                                                      T *z, T *p, double *part) {
+                                                      ZP<T> *w, double *part) {
     __shared__ double lds[16];
     double rz = 0.0, rr = 0.0;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
@@ -308,8 +317,7 @@ __global__ __launch_bounds__(kCGThreads) void cg_init(int n, const T *__restrict
         const T zj = dinv[j] * bj;
         x[j] = (T)0;
         r[j] = bj;
-        z[j] = zj;
-        p[j] = (T)0;  // the first direction is z itself (beta = 0)
+        w[j] = ZP<T>{zj, (T)0};  // the first direction is z itself (beta = 0)
         rz = fma((double)bj, (double)zj, rz);
         rr = fma((double)bj, (double)bj, rr);
     }
@@ -337,22 +345,70 @@ __global__ __launch_bounds__(64) void cg_init_finish(int nb, const double *part,
     }
 }
 
+// Entries e, e + G, ..., e + (kSpmvU - 1) G of a row ending at e1 (those past
+// the end get column -1): columns and values, then the gathered (z, p) pairs.
+constexpr int kSpmvU = 8;
+template <int G, bool NT, typename T>
+__device__ __forceinline__ void load_chunk(int e, int e1, const int32_t *__restrict__ col,
+                                           const T *__restrict__ val,
+                                           const ZP<T> *__restrict__ wold, int (&c)[kSpmvU],
+                                           T (&v)[kSpmvU], ZP<T> (&w)[kSpmvU]) {
+#pragma unroll
+    for (int k = 0; k < kSpmvU; ++k) {
+        const int ek = e + k * G;
+        if (ek < e1) {
+            c[k] = NT ? __builtin_nontemporal_load(col + ek) : col[ek];
+            v[k] = NT ? __builtin_nontemporal_load(val + ek) : val[ek];
+        } else {
+            c[k] = -1;
+            v[k] = (T)0;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kSpmvU; ++k) w[k] = c[k] >= 0 ? wold[c[k]] : ZP<T>{(T)0, (T)0};
+}
+
 // One CG iteration's first half.  From the previous update's partials:
 // rho = r.z and r.r (convergence test); beta = rho / rho_prev (0 on the first
 // iteration); the new direction p_new = z + beta p_old is formed where the
-// SpMV gathers it, q = S p_new, and the rows' p_new . q go to partial.  rho is
-// double-buffered by parity: every workgroup reads rho[par ^ 1] (the previous
-// one) and workgroup 0 writes rho[par].  G lanes per row.
-template <int G, typename T>
+// SpMV gathers it (from the pairs wold = (z, p_old)), q = S p_new, p_new goes
+// to wnew[r].p and the rows' p_new . q to partial.  rho is double-buffered by
+// parity: every workgroup reads rho[par ^ 1] (the previous one) and workgroup
+// 0 writes rho[par].
+//
+// G lanes per row; each lane takes its entries e, e + G, ... kSpmvU at a
+// time, all their loads in flight together (the summation order is that of
+// one entry at a time).  Nothing loaded depends on beta, so the first chunk
+// is requested before the partials are summed, and each row's first chunk and
+// the next row's pointers before the previous row's lane reduction.  NT: the
+// matrix streams past the caches (nontemporal loads), for matrices too large
+// to stay cache-resident between iterations, so that the gathered pairs stay.
+template <int G, bool NT, typename T>
 __global__ __launch_bounds__(256) void spmv_dir(int n, const int32_t *__restrict__ rowptr,
                                                 const int32_t *__restrict__ col,
                                                 const T *__restrict__ val,
-                                                const T *__restrict__ z,
-                                                const T *__restrict__ pold, T *__restrict__ pnew,
-                                                T *__restrict__ q, int nb2, const double *part2,
-                                                double *partial, CGScal *sc, int *done, int first,
-                                                int par) {
+                                                const ZP<T> *__restrict__ wold,
+                                                ZP<T> *__restrict__ wnew, T *__restrict__ q,
+                                                int nb2, const double *part2, double *partial,
+                                                CGScal *sc, int *done, int first, int par) {
     __shared__ double lds[16];
+    const int groups = 256 / G;
+    const int g = threadIdx.x / G, l = threadIdx.x % G;
+    const int stride = gridDim.x * groups;
+    int r = blockIdx.x * groups + g;
+    int e = 0, e1 = 0, en = 0, en1 = 0;
+    if (r < n) {
+        e = rowptr[r] + l;
+        e1 = rowptr[r + 1];
+    }
+    if (r + stride < n) {
+        en = rowptr[r + stride] + l;
+        en1 = rowptr[r + stride + 1];
+    }
+    int c[kSpmvU];
+    T v[kSpmvU];
+    ZP<T> w[kSpmvU];
+    load_chunk<G, NT>(e, e1, col, val, wold, c, v, w);
     if (*done) return;
     const double rz = sum_partials(part2, nb2, lds);
     const double rr = sum_partials(part2 + kCGBlocks, nb2, lds);
@@ -364,34 +420,34 @@ __global__ __launch_bounds__(256) void spmv_dir(int n, const int32_t *__restrict
         return;
     }
     const T beta = first ? (T)0 : (T)(rz / sc->rho[par ^ 1]);
-    const int groups = 256 / G;
-    const int g = threadIdx.x / G, l = threadIdx.x % G;
     double dot = 0.0;
-    for (int r = blockIdx.x * groups + g; r < n; r += gridDim.x * groups) {
+    while (r < n) {
         T acc = (T)0;
-        const int e1 = rowptr[r + 1];
-        int e = rowptr[r] + l;
-        // four strides at a time: the column loads, then the gathers, are all
-        // in flight before the products (same summation order as one by one)
-        for (; e + 3 * G < e1; e += 4 * G) {
-            const int c0 = col[e], c1 = col[e + G], c2 = col[e + 2 * G], c3 = col[e + 3 * G];
-            const T v0 = val[e], v1 = val[e + G], v2 = val[e + 2 * G], v3 = val[e + 3 * G];
-            const T g0 = fma(beta, pold[c0], z[c0]), g1 = fma(beta, pold[c1], z[c1]);
-            const T g2 = fma(beta, pold[c2], z[c2]), g3 = fma(beta, pold[c3], z[c3]);
-            acc = fma(v0, g0, acc);
-            acc = fma(v1, g1, acc);
-            acc = fma(v2, g2, acc);
-            acc = fma(v3, g3, acc);
+        for (;;) {
+#pragma unroll
+            for (int k = 0; k < kSpmvU; ++k)
+                if (c[k] >= 0) acc = fma(v[k], fma(beta, w[k].p, w[k].z), acc);
+            e += kSpmvU * G;
+            if (e >= e1) break;
+            load_chunk<G, NT>(e, e1, col, val, wold, c, v, w);
         }
-        for (; e < e1; e += G) {
-            const int c = col[e];
-            acc = fma(val[e], fma(beta, pold[c], z[c]), acc);
+        const int rc = r;
+        const ZP<T> wr = wold[rc];
+        r += stride;
+        e = en;
+        e1 = en1;
+        if (r < n) {
+            load_chunk<G, NT>(e, e1, col, val, wold, c, v, w);
+            if (r + stride < n) {
+                en = rowptr[r + stride] + l;
+                en1 = rowptr[r + stride + 1];
+            }
         }
         for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
         if (l == 0) {
-            const T pr = fma(beta, pold[r], z[r]);
-            pnew[r] = pr;
-            q[r] = acc;
+            const T pr = fma(beta, wr.p, wr.z);
+            wnew[rc].p = pr;
+            q[rc] = acc;
             dot = fma((double)pr, (double)acc, dot);
         }
     }
@@ -403,15 +459,25 @@ __global__ __launch_bounds__(256) void spmv_dir(int n, const int32_t *__restrict
     }
 }
 
-// alpha = rho / (p.q); x += alpha p; r -= alpha q; z = D^-1 r; partial r.z, r.r
+// alpha = rho / (p.q); x += alpha p; r -= alpha q; z = D^-1 r into w[j].z;
+// partials r.z, r.r
 template <typename T>
 __global__ __launch_bounds__(kCGThreads) void cg_update(int n, int nb1, const double *part1,
-                                                        const T *__restrict__ p,
-                                                        const T *__restrict__ q,
+                                                        ZP<T> *w, const T *__restrict__ q,
                                                         const T *__restrict__ dinv, T *x, T *r,
-                                                        T *z, double *part2, CGScal *sc,
-                                                        int *done, int par) {
+                                                        double *part2, CGScal *sc, int *done,
+                                                        int par) {
     __shared__ double lds[16];
+    // the first element's operands are requested before the partials are summed
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    T pj = (T)0, qj = (T)0, rj = (T)0, xj = (T)0, dj = (T)0;
+    if (j < n) {
+        pj = w[j].p;
+        qj = q[j];
+        rj = r[j];
+        xj = x[j];
+        dj = dinv[j];
+    }
     if (*done) return;
     const double pq = sum_partials(part1, nb1, lds);
     if (!(pq > 0.0)) {  // breakdown (S is positive semidefinite)
@@ -420,12 +486,19 @@ __global__ __launch_bounds__(kCGThreads) void cg_update(int n, int nb1, const do
     }
     const T alpha = (T)(sc->rho[par] / pq);
     double rz = 0.0, rr = 0.0;
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
-        x[j] = fma(alpha, p[j], x[j]);
-        const T rj = fma(-alpha, q[j], r[j]);
+    for (bool head = true; j < n; j += gridDim.x * blockDim.x, head = false) {
+        if (!head) {
+            pj = w[j].p;
+            qj = q[j];
+            rj = r[j];
+            xj = x[j];
+            dj = dinv[j];
+        }
+        x[j] = fma(alpha, pj, xj);
+        rj = fma(-alpha, qj, rj);
         r[j] = rj;
-        const T zj = dinv[j] * rj;
-        z[j] = zj;
+        const T zj = dj * rj;
+        w[j].z = zj;
         rz = fma((double)rj, (double)zj, rz);
         rr = fma((double)rj, (double)rj, rr);
     }
@@ -451,12 +524,17 @@ __global__ __launch_bounds__(64) void cg_check(int nb2, const double *part2, CGS
     }
 }
 
+// lanes per row: at least four nonzeros per lane on average, 8 to 64 lanes
+static int lanes_per_row(const SchurCSR &S) {
+    const double avg = (double)S.nnz / std::max(1, S.n);
+    return avg >= 256.0 ? 64 : avg >= 128.0 ? 32 : avg >= 64.0 ? 16 : 8;
+}
+
 template <typename T>
 static void launch_spmv(hipStream_t st, const SchurCSR &S, const T *val, const T *x, T *y,
                         double *partial, const int *done, unsigned &nb_out) {
     const int n = S.n;
-    const double avg = (double)S.nnz / std::max(1, n);
-    const int G = avg >= 48 ? 64 : 16;
+    const int G = lanes_per_row(S) >= 64 ? 64 : 16;
     const unsigned nb = std::min<unsigned>(kSpmvMaxBlocks, grid_for(n, 256 / G));
     nb_out = nb;
     if (G == 64)
@@ -469,22 +547,94 @@ static void launch_spmv(hipStream_t st, const SchurCSR &S, const T *val, const T
 
 // e0, e1: events recorded at the dispatch's own start and end (may be null)
 template <typename T>
-static void launch_spmv_dir(hipStream_t st, const SchurCSR &S, const T *val, const T *z,
-                            const T *pold, T *pnew, T *q, int nb2, const double *part2,
-                            double *partial, CGScal *sc, int *done, int first, int par,
-                            unsigned &nb_out, hipEvent_t e0, hipEvent_t e1) {
+static void launch_spmv_dir(hipStream_t st, const SchurCSR &S, const T *val, const ZP<T> *wold,
+                            ZP<T> *wnew, T *q, int nb2, const double *part2, double *partial,
+                            CGScal *sc, int *done, int first, int par, unsigned &nb_out,
+                            hipEvent_t e0, hipEvent_t e1) {
     const int n = S.n;
-    const double avg = (double)S.nnz / std::max(1, n);
-    const int G = avg >= 48 ? 64 : 16;
-    const unsigned nb = std::min<unsigned>(kSpmvMaxBlocks, grid_for(n, 256 / G));
+    const int G = lanes_per_row(S);
+    // about as many workgroups as stay resident at once (three per compute
+    // unit at this kernel's register use): each lane group then walks several
+    // rows with the next row's loads in flight
+    const unsigned nb = std::min<unsigned>(kSpmvDirBlocks, grid_for(n, 256 / G));
     nb_out = nb;
     const int32_t *rp = S.rowptr.get(), *cl = S.col.get();
-    if (G == 64)
-        hipExtLaunchKernelGGL(spmv_dir<64, T>, dim3(nb), dim3(256), 0, st, e0, e1, 0, n, rp, cl,
-                              val, z, pold, pnew, q, nb2, part2, partial, sc, done, first, par);
-    else
-        hipExtLaunchKernelGGL(spmv_dir<16, T>, dim3(nb), dim3(256), 0, st, e0, e1, 0, n, rp, cl,
-                              val, z, pold, pnew, q, nb2, part2, partial, sc, done, first, par);
+    // matrices beyond this size do not stay cache-resident between iterations
+    const bool nt = ((double)sizeof(T) + 4.0) * (double)S.nnz > 96.0 * (1 << 20);
+#define OTIP_SPMV_DIR(GG, NT)                                                                  \
+    hipExtLaunchKernelGGL(spmv_dir<GG, NT, T>, dim3(nb), dim3(256), 0, st, e0, e1, 0, n, rp,   \
+                          cl, val, wold, wnew, q, nb2, part2, partial, sc, done, first, par)
+    if (nt) {
+        switch (G) {
+            case 64: OTIP_SPMV_DIR(64, true); break;
+            case 32: OTIP_SPMV_DIR(32, true); break;
+            case 16: OTIP_SPMV_DIR(16, true); break;
+            default: OTIP_SPMV_DIR(8, true); break;
+        }
+    } else {
+        switch (G) {
+            case 64: OTIP_SPMV_DIR(64, false); break;
+            case 32: OTIP_SPMV_DIR(32, false); break;
+            case 16: OTIP_SPMV_DIR(16, false); break;
+            default: OTIP_SPMV_DIR(8, false); break;
+        }
+    }
+#undef OTIP_SPMV_DIR
+}
+
+// Jacobi inverse diagonal of a caller's CSR matrix, by the rule of schur_diag
+// (0 where the diagonal is absent or not positive), and a flag for column
+// indices outside [0, n).  The row pointers were checked on the host.
+__global__ void csr_jacobi(int n, const int32_t *__restrict__ rowptr,
+                           const int32_t *__restrict__ col, const double *__restrict__ val,
+                           double *__restrict__ dinv, int *bad) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    double d = 0.0;
+    int flag = 0;
+    for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+        const int c = col[e];
+        if (c < 0 || c >= n)
+            flag = 1;
+        else if (c == r)
+            d += val[e];
+    }
+    dinv[r] = d > 0.0 ? 1.0 / d : 0.0;
+    if (flag) atomicOr(bad, 1);
+}
+
+void SchurSolver::load_csr(hipStream_t st, int n, int64_t nnz, const int32_t *rowptr,
+                           const int32_t *col, const double *val) {
+    std::vector<int32_t> rp((size_t)n + 1);
+    OTIP_HIP(hipMemcpyAsync(rp.data(), rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost,
+                            st));
+    OTIP_HIP(hipStreamSynchronize(st));
+    OTIP_CHECK(rp[0] == 0 && (int64_t)rp[n] == nnz, 1, "CSR: rowptr[0] != 0 or rowptr[n] != nnz");
+    for (int r = 0; r < n; ++r)
+        OTIP_CHECK(rp[r + 1] >= rp[r], 1, "CSR: row pointers decrease at row " + std::to_string(r));
+    S.n = n;
+    S.nnz = nnz;
+    S.rowptr.need((size_t)n + 1);
+    S.col.need((size_t)std::max<int64_t>(nnz, 1));
+    S.val.need((size_t)std::max<int64_t>(nnz, 1));
+    S.dinv.need((size_t)n);
+    OTIP_HIP(hipMemcpyAsync(S.rowptr.get(), rowptr, sizeof(int32_t) * (n + 1),
+                            hipMemcpyDeviceToDevice, st));
+    if (nnz > 0) {
+        OTIP_HIP(hipMemcpyAsync(S.col.get(), col, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice,
+                                st));
+        OTIP_HIP(hipMemcpyAsync(S.val.get(), val, sizeof(double) * nnz, hipMemcpyDeviceToDevice,
+                                st));
+    }
+    flag_.need(1);
+    OTIP_HIP(hipMemsetAsync(flag_.get(), 0, sizeof(int), st));
+    hipLaunchKernelGGL(csr_jacobi, dim3(grid_for(n, 256)), dim3(256), 0, st, n, S.rowptr.get(),
+                       S.col.get(), S.val.get(), S.dinv.get(), flag_.get());
+    OTIP_HIP(hipGetLastError());
+    int bad = 0;
+    OTIP_HIP(hipMemcpyAsync(&bad, flag_.get(), sizeof(int), hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipStreamSynchronize(st));
+    OTIP_CHECK(!bad, 1, "CSR: column index outside [0, n)");
 }
 
 void SchurSolver::spmv(hipStream_t st, const double *x, double *y) {
@@ -496,13 +646,12 @@ void SchurSolver::spmv(hipStream_t st, const double *x, double *y) {
 // Jacobi-preconditioned CG in storage type T on S x = b.
 template <typename T>
 CGStats SchurSolver::pcg_impl(hipStream_t st, const T *val, const T *dinv, const T *b, T *x,
-                              double rtol, double atol, int maxit, DBuf<T> &r_, DBuf<T> &z_,
-                              DBuf<T> &p_, DBuf<T> &q_) {
+                              double rtol, double atol, int maxit, DBuf<T> &r_, DBuf<T> &p_,
+                              DBuf<T> &q_) {
     const int n = S.n;
     CGStats out;
     r_.need(n);
-    z_.need(n);
-    p_.need(2 * (size_t)n);  // two directions, alternating by iteration parity
+    p_.need(4 * (size_t)n);  // two (z, p) pair arrays, alternating by iteration parity
     q_.need(n);
     part_.need(kSpmvMaxBlocks + 2 * kCGBlocks);
     scal_.need(sizeof(CGScal) / sizeof(double));
@@ -511,10 +660,10 @@ CGStats SchurSolver::pcg_impl(hipStream_t st, const T *val, const T *dinv, const
     double *part2 = part_.get() + kSpmvMaxBlocks;
     CGScal *sc = (CGScal *)scal_.get();
     int *done = flag_.get();
-    T *P[2] = {p_.get(), p_.get() + n};
+    ZP<T> *W[2] = {(ZP<T> *)p_.get(), (ZP<T> *)(p_.get() + 2 * (size_t)n)};
     const unsigned nbv = std::min<unsigned>(kCGBlocks, grid_for(n, kCGThreads));
     hipLaunchKernelGGL((cg_init<T>), dim3(nbv), dim3(kCGThreads), 0, st, n, b, dinv, x, r_.get(),
-                       z_.get(), P[1], part2);
+                       W[1], part2);
     hipLaunchKernelGGL(cg_init_finish, dim3(1), dim3(64), 0, st, (int)nbv, part2, rtol, atol, sc,
                        done);
     OTIP_HIP(hipGetLastError());
@@ -522,6 +671,7 @@ CGStats SchurSolver::pcg_impl(hipStream_t st, const T *val, const T *dinv, const
     int launched = 0;
     CGScal hs{};
     int hdone = 0;
+    double its_prev = 0.0, rr_prev = -1.0;  // at the previous check
     // algorithmic bytes of one fused launch: values and columns, row pointers,
     // the two gathered vectors read once, the new direction and q written
     const double bytes = ((double)sizeof(T) + 4.0) * (double)S.nnz +
@@ -532,11 +682,10 @@ CGStats SchurSolver::pcg_impl(hipStream_t st, const T *val, const T *dinv, const
             unsigned nbs;
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (timer) timer->arm(bytes, &e0, &e1);
-            launch_spmv_dir<T>(st, S, val, z_.get(), P[par ^ 1], P[par], q_.get(), (int)nbv,
-                               part2, part1, sc, done, launched == 0 ? 1 : 0, par, nbs, e0, e1);
+            launch_spmv_dir<T>(st, S, val, W[par ^ 1], W[par], q_.get(), (int)nbv, part2, part1,
+                               sc, done, launched == 0 ? 1 : 0, par, nbs, e0, e1);
             hipLaunchKernelGGL((cg_update<T>), dim3(nbv), dim3(kCGThreads), 0, st, n, (int)nbs,
-                               part1, P[par], q_.get(), dinv, x, r_.get(), z_.get(), part2, sc,
-                               done, par);
+                               part1, W[par], q_.get(), dinv, x, r_.get(), part2, sc, done, par);
             ++launched;
         }
         hipLaunchKernelGGL(cg_check, dim3(1), dim3(64), 0, st, (int)nbv, part2, sc, done);
@@ -544,9 +693,23 @@ CGStats SchurSolver::pcg_impl(hipStream_t st, const T *val, const T *dinv, const
         OTIP_HIP(hipMemcpyAsync(&hs, sc, sizeof(CGScal), hipMemcpyDeviceToHost, st));
         OTIP_HIP(hipMemcpyAsync(&hdone, done, sizeof(int), hipMemcpyDeviceToHost, st));
         OTIP_HIP(hipStreamSynchronize(st));
-        if (timer) timer->collect();
+        // launches past the last executed iteration found the work done
+        if (timer) timer->collect((size_t)std::max(0.0, hs.its - its_prev));
         if (hdone || launched >= maxit) break;
-        chunk = std::min(std::min(chunk * 2, 64), maxit - launched);
+        // next chunk: the iterations still needed at the rate the residual
+        // fell over the last chunk (plus a tenth), else twice the last chunk;
+        // launches past convergence return at once but still cost a dispatch
+        int next = std::min(chunk * 2, 64);
+        const double ran = hs.its - its_prev;
+        if (rr_prev > 0.0 && hs.rr > 0.0 && hs.rr < rr_prev && ran > 0.0) {
+            const double rate = std::log(hs.rr / rr_prev) / ran;
+            const double need = std::log(hs.target * hs.target / hs.rr) / rate;
+            if (std::isfinite(need))
+                next = (int)std::min(64.0, std::max(4.0, std::ceil(1.1 * need) + 1.0));
+        }
+        rr_prev = hs.rr;
+        its_prev = hs.its;
+        chunk = std::min(next, maxit - launched);
         if (chunk <= 0) break;
     }
     out.iterations = (int)hs.its;
@@ -557,7 +720,7 @@ CGStats SchurSolver::pcg_impl(hipStream_t st, const T *val, const T *dinv, const
 
 CGStats SchurSolver::pcg(hipStream_t st, const double *b, double *x, double rtol, double atol,
                          int maxit) {
-    return pcg_impl<double>(st, S.val.get(), S.dinv.get(), b, x, rtol, atol, maxit, r_, z_, p_, q_);
+    return pcg_impl<double>(st, S.val.get(), S.dinv.get(), b, x, rtol, atol, maxit, r_, p_, q_);
 }
 
 __global__ void to_f32(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
@@ -621,7 +784,7 @@ CGStats SchurSolver::pcg_mixed(hipStream_t st, const double *b, double *x, doubl
         if (out.iterations >= maxit) break;
         const double inner = std::max(1e-4, 0.5 * target / rn);
         CGStats cs = pcg_impl<float>(st, val32_.get(), dinv32_.get(), r32, d32, inner, 1e300,
-                                     maxit - out.iterations, rf2_, zf_, pf_, qf_);
+                                     maxit - out.iterations, rf2_, pf_, qf_);
         out.iterations += std::max(cs.iterations, 1);
         hipLaunchKernelGGL(add_f32, dim3(nbv), dim3(256), 0, st, n, d32, x);
     }
