@@ -82,6 +82,65 @@ __device__ __forceinline__ bool in_support(const uint32_t *__restrict__ bm, uint
 constexpr int kScanBlock = 256;
 constexpr int kHistBins = 4096;
 
+// Compaction output of one wave, staged in LDS: the output space is reserved
+// with one global atomic per kStage candidates instead of one per ballot.  The
+// most negative reduced costs cluster in few waves, whose many atomics on the
+// one counter would otherwise serialise.  W words per candidate: (key, idx) or
+// idx alone.  Every lane of the wave calls push and flush.
+constexpr int kStage = 256;
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+template <int W>
+struct WaveStage {
+    uint64_t *buf;  // this wave's kStage * W words of LDS
+    int cnt;        // staged candidates (the same in every lane)
+    unsigned long long *count;
+    uint64_t *out_key, *out_idx;
+    uint64_t cap;
+
+    __device__ void flush() {
+        if (cnt == 0) return;
+        const int lane = threadIdx.x & 63;
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(count, (unsigned long long)cnt);
+        base = __shfl(base, 0, 64);
+        wave_sync();
+        for (int k = lane; k < cnt; k += 64) {
+            const uint64_t pos = base + (uint64_t)k;
+            if (pos < cap) {
+                if (W == 2) {
+                    out_key[pos] = buf[2 * k];
+                    out_idx[pos] = buf[2 * k + 1];
+                } else {
+                    out_idx[pos] = buf[k];
+                }
+            }
+        }
+        wave_sync();
+        cnt = 0;
+    }
+    __device__ void push(bool take, uint64_t key, uint64_t idx) {
+        const uint64_t mask = __ballot(take);
+        if (mask == 0ull) return;
+        const int nw = __popcll(mask);
+        if (cnt + nw > kStage) flush();
+        if (take) {
+            const int lane = threadIdx.x & 63;
+            const int pos = cnt + __popcll(mask & ((1ull << lane) - 1ull));
+            if (W == 2) {
+                buf[2 * pos] = key;
+                buf[2 * pos + 1] = idx;
+            } else {
+                buf[pos] = idx;
+            }
+        }
+        cnt += nw;
+    }
+};
+
 struct PriceArgs {
     int m, n, tj;
     const int32_t *xs;
@@ -106,7 +165,7 @@ struct PriceArgs {
 // the per-variable part of a pricing pass (all lanes of the wave call it)
 template <int MODE>
 __device__ __forceinline__ void price_one(const PriceArgs &a, int i, int j, double r,
-                                          unsigned int *lh) {
+                                          unsigned int *lh, WaveStage<2> &stg) {
     {
         const int pshift = a.shift + 12;
         const bool neg = r < 0.0 && r <= a.rcut;
@@ -118,22 +177,7 @@ __device__ __forceinline__ void price_one(const PriceArgs &a, int i, int j, doub
             if (take && (pshift >= 64 || (key >> pshift) == a.prefix))
                 atomicAdd(&lh[(key >> a.shift) & 4095u], 1u);
         } else {
-            take = take && key <= a.key_max;
-            const uint64_t mask = __ballot(take);
-            if (mask) {
-                const int lane = threadIdx.x & 63;
-                const int leader = __ffsll((long long)mask) - 1;
-                unsigned long long base = 0;
-                if (lane == leader) base = atomicAdd(a.count, (unsigned long long)__popcll(mask));
-                base = __shfl(base, leader, 64);
-                if (take) {
-                    const uint64_t pos = base + __popcll(mask & ((1ull << lane) - 1ull));
-                    if (pos < a.cap) {
-                        a.out_key[pos] = key;
-                        a.out_idx[pos] = idx;
-                    }
-                }
-            }
+            stg.push(take && key <= a.key_max, key, idx);
         }
     }
 }
@@ -144,6 +188,9 @@ __device__ __forceinline__ void price_one(const PriceArgs &a, int i, int j, doub
 template <int MODE>
 __global__ __launch_bounds__(kScanBlock) void price_pass(PriceArgs a) {
     __shared__ unsigned int lh[MODE == 0 ? kHistBins : 1];
+    __shared__ uint64_t sbuf[MODE == 1 ? (kScanBlock / 64) * kStage * 2 : 1];
+    WaveStage<2> stg{sbuf + (MODE == 1 ? (threadIdx.x >> 6) * kStage * 2 : 0), 0, a.count,
+                     a.out_key, a.out_idx, a.cap};
     const int i = blockIdx.x * kScanBlock + threadIdx.x;
     const int j0 = blockIdx.y * a.tj;
     const int j1 = min(a.n, j0 + a.tj);
@@ -165,16 +212,17 @@ __global__ __launch_bounds__(kScanBlock) void price_pass(PriceArgs a) {
         const double r3 = (cost_of(rd, t3) - rd.y) - t3.z;
         const double lo = fmin(fmin(r0, r1), fmin(r2, r3));
         if (__ballot(lo < 0.0 && lo <= a.rcut) == 0ull) continue;
-        price_one<MODE>(a, i, j, r0, lh);
-        price_one<MODE>(a, i, j + 1, r1, lh);
-        price_one<MODE>(a, i, j + 2, r2, lh);
-        price_one<MODE>(a, i, j + 3, r3, lh);
+        price_one<MODE>(a, i, j, r0, lh, stg);
+        price_one<MODE>(a, i, j + 1, r1, lh, stg);
+        price_one<MODE>(a, i, j + 2, r2, lh, stg);
+        price_one<MODE>(a, i, j + 3, r3, lh, stg);
     }
     for (; j < j1; ++j) {
         const JEntry t = ldj(jt, j);
         const double r = (cost_of(rd, t) - rd.y) - t.z;
-        price_one<MODE>(a, i, j, r, lh);
+        price_one<MODE>(a, i, j, r, lh, stg);
     }
+    if (MODE == 1) stg.flush();
     if (MODE == 0) {
         __syncthreads();
         for (int t = threadIdx.x; t < kHistBins; t += kScanBlock)
@@ -639,43 +687,67 @@ int64_t Scanner::initial_support(hipStream_t st, int m, int n, const int32_t *xs
 namespace otip {
 
 // ------------------------------------------------------------ mixed precision
-// FP32 pricing with an FP64 re-check.  Costs are exact in FP32 when every
-// intermediate of |x_i|^2 + |x_j|^2 - 2 x_i.x_j stays below 2^24.  With
-// y32 = fl32(y), z32 = fl32(z) and two FP32 subtractions, the FP32 reduced cost
-// differs from the exact one by at most 3 u32 (C + Y + Z) (u32 = 2^-24, C, Y, Z
-// bounds on |C_ij|, |y|, |z|), and the FP64 one by at most 2 u64 (C + Y + Z);
-// margin = 8 u32 (C + Y + Z) covers twice their sum.  Hence
+// FP32 pricing with an FP64 re-check.  The FP32 pass need not round like the
+// FP64 one, only stay within a proven distance of the exact reduced cost, so
+// it uses the separable form r = (|x_i|^2 - y_i) + (|x_j|^2 - z_j)
+// - 2 x_i.x_j: u_i = fl32(fl64(|x_i|^2 - y_i)) per source, v_j likewise per
+// target, then r32 = fl(b_i (-2 b_j) + fl(a_i (-2 a_j) + fl(u_i + v_j))) with
+// two fused multiply-adds (coordinates and their doubles are exact in FP32):
+// three operations per reduced cost against five in the exact FP64 form.
+// With K = 2 (X + X')^2 + Y + Z (X, X' the largest source and target
+// coordinate magnitudes, Y, Z the largest |y|, |z|), every intermediate is at
+// most K in magnitude and each of the five roundings (two in u and v, three in
+// the sum and the two fused operations) errs by at most u32 K (u32 = 2^-24),
+// up to second-order terms: |r32 - r| <= 4 (u32 + u64) K, while the FP64 scan's
+// value errs by at most 2 u64 K.  margin = 9 u32 K exceeds twice their sum.
+// Hence
 //   r32 < -margin  =>  r64 < 0 (certainly negative);
 //   an entry of the FP64 top-k has r32 <= tau32 + 2 margin, tau32 the k-th
 //   smallest FP32 value among r32 < margin.
 // Every candidate with r32 <= min(margin, tau32 + 2 margin), and every entry of
 // the band -margin <= r32 < margin (for the exact negative count), is
 // re-evaluated in FP64 exactly as the FP64 scan does; the selection is then
-// identical to the FP64 one.
+// identical to the FP64 one.  (The FP32 form is used only while 2 (X + X')^2
+// < 2^24, which keeps the band narrow for duals on the scale of the costs.)
 struct __align__(16) JEntry32 {
-    float B, a2, b2, z;
+    float v, a2, b2, pad;
 };
 
 __device__ __forceinline__ JEntry32 ldj32(const JEntry32 *p, int j) {
     const cfptr q = (cfptr)(p + j);
     JEntry32 e;
-    e.B = q[0];
+    e.v = q[0];
     e.a2 = q[1];
     e.b2 = q[2];
-    e.z = q[3];
+    e.pad = 0.f;
     return e;
+}
+
+// four consecutive entries (j a multiple of 4; the table is 256-byte aligned)
+// with one 64-byte scalar load
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef const __attribute__((address_space(4))) f32x16 *cf16ptr;
+__device__ __forceinline__ void ldj32x4(const JEntry32 *p, int j, JEntry32 (&t)[4]) {
+    const f32x16 q = *(cf16ptr)(p + j);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        t[k].v = q[4 * k];
+        t[k].a2 = q[4 * k + 1];
+        t[k].b2 = q[4 * k + 2];
+        t[k].pad = 0.f;
+    }
 }
 
 __global__ void build_jtab32(int n, const int32_t *__restrict__ xt, const double *__restrict__ z,
                              JEntry32 *__restrict__ jt) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    float a = (float)xt[2 * j], b = (float)xt[2 * j + 1];
+    const double a = (double)xt[2 * j], b = (double)xt[2 * j + 1];
     JEntry32 e;
-    e.B = a * a + b * b;
-    e.a2 = -2.0f * a;
-    e.b2 = -2.0f * b;
-    e.z = (float)z[j];
+    e.v = (float)((a * a + b * b) - z[j]);
+    e.a2 = (float)(-2.0 * a);
+    e.b2 = (float)(-2.0 * b);
+    e.pad = 0.f;
     jt[j] = e;
 }
 
@@ -695,15 +767,52 @@ struct Price32Args {
     uint32_t prefix;    // bits above shift + 12 (no filter when shift + 12 >= 32)
     unsigned long long *hist, *certain, *band;
     float t32;          // compaction: r32 <= t32, or -margin <= r32 < margin
+    float rcut;         // no value of interest lies above rcut (+inf: no bound)
     unsigned long long *count;
     uint64_t *out_idx;
     uint64_t cap;
 };
 
+// the per-variable part of an FP32 pass (all lanes of the wave call it)
+template <int MODE>
+__device__ __forceinline__ void price32_one(const Price32Args &a, int i, int j, float r,
+                                            unsigned int *lh, unsigned int &ncert,
+                                            unsigned int &nband, WaveStage<1> &stg) {
+    const float mg = a.margin;
+    const bool lo = MODE == 0 ? (r < mg && r <= a.rcut) : (r < mg && (r <= a.t32 || r >= -mg));
+    if (__ballot(lo) == 0ull) return;
+    const uint64_t idx = (uint64_t)i + (uint64_t)j * (uint64_t)a.m;
+    bool take = lo && !in_support(a.bitmap, idx);
+    if (MODE == 0) {
+        if (take) {
+            const int pshift = a.shift + 12;
+            if (pshift >= 32) {  // first level: the certain and uncertain counts
+                if (r < -mg)
+                    ++ncert;
+                else
+                    ++nband;
+            }
+            const uint32_t key = fkey(r);
+            if (pshift >= 32 || (key >> pshift) == a.prefix)
+                atomicAdd(&lh[(key >> a.shift) & 4095u], 1u);
+        }
+    } else {
+        stg.push(take, 0ull, idx);
+    }
+}
+
+// FP32 pass.  MODE 0: histogram of one 12-bit digit of the FP32 key of every
+// r32 < margin outside the support (and, on the first level, the counts of
+// the certain negatives r32 < -margin and of the band); MODE 1: append the
+// variable index of every candidate.  Four targets at a time: a group with no
+// value of interest costs one ballot.
 template <int MODE>
 __global__ __launch_bounds__(kScanBlock) void price32_pass(Price32Args a) {
     __shared__ unsigned int lh[MODE == 0 ? kHistBins : 1];
     __shared__ unsigned int lc[2];
+    __shared__ uint64_t sbuf[MODE == 1 ? (kScanBlock / 64) * kStage : 1];
+    WaveStage<1> stg{sbuf + (MODE == 1 ? (threadIdx.x >> 6) * kStage : 0), 0, a.count, nullptr,
+                     a.out_idx, a.cap};
     const int i = blockIdx.x * kScanBlock + threadIdx.x;
     const int j0 = blockIdx.y * a.tj, j1 = min(a.n, j0 + a.tj);
     if (MODE == 0) {
@@ -711,50 +820,44 @@ __global__ __launch_bounds__(kScanBlock) void price32_pass(Price32Args a) {
         if (threadIdx.x < 2) lc[threadIdx.x] = 0u;
         __syncthreads();
     }
-    float A = 0.f, al = 0.f, be = 0.f, yv = -INFINITY;
+    // rows past m get u = +inf: every value they produce is +inf
+    float al = 0.f, be = 0.f, u = INFINITY;
     if (i < a.m) {
-        al = (float)a.xs[2 * i];
-        be = (float)a.xs[2 * i + 1];
-        A = al * al + be * be;
-        yv = (float)a.y[i];
+        const double ad = (double)a.xs[2 * i], bd = (double)a.xs[2 * i + 1];
+        al = (float)ad;
+        be = (float)bd;
+        u = (float)((ad * ad + bd * bd) - a.y[i]);
     }
-    const float mg = a.margin;
-    const int pshift = a.shift + 12;
+    const float lim = fminf(a.margin, a.rcut);
     unsigned int ncert = 0, nband = 0;
-    for (int j = j0; j < j1; ++j) {
-        const JEntry32 t = ldj32(a.jt, j);
-        const float c = fmaf(be, t.b2, fmaf(al, t.a2, A + t.B));
-        const float r = (c - yv) - t.z;
-        const bool lo = r < mg;
-        if (__ballot(lo) == 0ull) continue;
-        const uint64_t idx = (uint64_t)i + (uint64_t)j * (uint64_t)a.m;
-        bool take = lo && !in_support(a.bitmap, idx);
+    int j = j0;
+    for (; j + 4 <= j1; j += 4) {
+        JEntry32 t[4];
+        ldj32x4(a.jt, j, t);
+        const float r0 = fmaf(be, t[0].b2, fmaf(al, t[0].a2, u + t[0].v));
+        const float r1 = fmaf(be, t[1].b2, fmaf(al, t[1].a2, u + t[1].v));
+        const float r2 = fmaf(be, t[2].b2, fmaf(al, t[2].a2, u + t[2].v));
+        const float r3 = fmaf(be, t[3].b2, fmaf(al, t[3].a2, u + t[3].v));
+        const float lo = fminf(fminf(r0, r1), fminf(r2, r3));
+        bool any;
         if (MODE == 0) {
-            if (take) {
-                if (r < -mg)
-                    ++ncert;
-                else
-                    ++nband;
-                const uint32_t key = fkey(r);
-                if (pshift >= 32 || (key >> pshift) == a.prefix)
-                    atomicAdd(&lh[(key >> a.shift) & 4095u], 1u);
-            }
-        } else {
-            take = take && (r <= a.t32 || r >= -mg);
-            const uint64_t mask = __ballot(take);
-            if (mask) {
-                const int lane = threadIdx.x & 63;
-                const int leader = __ffsll((long long)mask) - 1;
-                unsigned long long base = 0;
-                if (lane == leader) base = atomicAdd(a.count, (unsigned long long)__popcll(mask));
-                base = __shfl(base, leader, 64);
-                if (take) {
-                    const uint64_t pos = base + __popcll(mask & ((1ull << lane) - 1ull));
-                    if (pos < a.cap) a.out_idx[pos] = idx;
-                }
-            }
+            any = lo < a.margin && lo <= lim;
+        } else {  // candidates r32 <= t32 (< margin), or the band |r32| < margin
+            const float la = fminf(fminf(fabsf(r0), fabsf(r1)), fminf(fabsf(r2), fabsf(r3)));
+            any = lo <= a.t32 || la < a.margin;
         }
+        if (__ballot(any) == 0ull) continue;
+        price32_one<MODE>(a, i, j, r0, lh, ncert, nband, stg);
+        price32_one<MODE>(a, i, j + 1, r1, lh, ncert, nband, stg);
+        price32_one<MODE>(a, i, j + 2, r2, lh, ncert, nband, stg);
+        price32_one<MODE>(a, i, j + 3, r3, lh, ncert, nband, stg);
     }
+    for (; j < j1; ++j) {
+        const JEntry32 t = ldj32(a.jt, j);
+        const float r = fmaf(be, t.b2, fmaf(al, t.a2, u + t.v));
+        price32_one<MODE>(a, i, j, r, lh, ncert, nband, stg);
+    }
+    if (MODE == 1) stg.flush();
     if (MODE == 0) {
         if (ncert) atomicAdd(&lc[0], ncert);
         if (nband) atomicAdd(&lc[1], nband);
@@ -785,20 +888,25 @@ __global__ void recheck64(int64_t k, int m, const uint64_t *__restrict__ idx,
     const double r = (c - y[i]) - z[j];
     key[t] = r < 0.0 ? dkey(r) : ~0ull;
     // the same FP32 value as the scan, to recognise the band
-    const float af = (float)al, bf = (float)be, ajf = (float)aj, bjf = (float)bj;
-    const float c32 = fmaf(bf, -2.0f * bjf, fmaf(af, -2.0f * ajf, (af * af + bf * bf) + (ajf * ajf + bjf * bjf)));
-    const float r32 = (c32 - (float)y[i]) - (float)z[j];
+    const float u = (float)((al * al + be * be) - y[i]);
+    const float w = (float)((aj * aj + bj * bj) - z[j]);
+    const float r32 = fmaf((float)be, (float)(-2.0 * bj), fmaf((float)al, (float)(-2.0 * aj), u + w));
     if (r32 >= -margin && r32 < margin && r < 0.0) atomicAdd(band_neg, 1ull);
 }
 
+// out[0..3] = max |xs|, max |xt|, max |y|, max |z| over a grid of blocks; out
+// is zeroed first.  The maxima are non-negative, so their IEEE bit patterns
+// order like the values and an integer atomic maximum combines the blocks.
 __global__ void maxabs4(int m, int n, const int32_t *xs, const int32_t *xt, const double *y,
-                        const double *z, double *out) {
+                        const double *z, unsigned long long *out) {
     __shared__ double sm[4][16];
     double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int t = threadIdx.x; t < 2 * m; t += blockDim.x) v[0] = fmax(v[0], fabs((double)xs[t]));
-    for (int t = threadIdx.x; t < 2 * n; t += blockDim.x) v[1] = fmax(v[1], fabs((double)xt[t]));
-    for (int t = threadIdx.x; t < m; t += blockDim.x) v[2] = fmax(v[2], fabs(y[t]));
-    for (int t = threadIdx.x; t < n; t += blockDim.x) v[3] = fmax(v[3], fabs(z[t]));
+    const int stride = gridDim.x * blockDim.x;
+    const int t0 = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int t = t0; t < 2 * m; t += stride) v[0] = fmax(v[0], fabs((double)xs[t]));
+    for (int t = t0; t < 2 * n; t += stride) v[1] = fmax(v[1], fabs((double)xt[t]));
+    for (int t = t0; t < m; t += stride) v[2] = fmax(v[2], fabs(y[t]));
+    for (int t = t0; t < n; t += stride) v[3] = fmax(v[3], fabs(z[t]));
     for (int q = 0; q < 4; ++q) {
         double w = v[q];
         for (int o = 32; o > 0; o >>= 1) w = fmax(w, __shfl_xor(w, o, 64));
@@ -808,8 +916,16 @@ __global__ void maxabs4(int m, int n, const int32_t *xs, const int32_t *xt, cons
     if (threadIdx.x < 4) {
         double w = 0.0;
         for (int k = 0; k < (int)(blockDim.x >> 6); ++k) w = fmax(w, sm[threadIdx.x][k]);
-        out[threadIdx.x] = w;
+        atomicMax(&out[threadIdx.x], (unsigned long long)__double_as_longlong(w));
     }
+}
+
+// the float with ordered FP32 key k (host side), or +inf where k is no number's key
+static float rcut32_of_key(uint32_t k) {
+    const uint32_t u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+    float f;
+    std::memcpy(&f, &u, sizeof f);
+    return std::isnan(f) ? INFINITY : f;
 }
 
 PriceResult Scanner::price_mixed(hipStream_t st, int m, int n, const int32_t *xs,
@@ -821,16 +937,19 @@ PriceResult Scanner::price_mixed(hipStream_t st, int m, int n, const int32_t *xs
     // bounds for the margin and the exactness of FP32 costs
     DBuf<double> &mx = bmin_;
     mx.need(4);
-    hipLaunchKernelGGL(maxabs4, dim3(1), dim3(1024), 0, st, m, n, xs, xt, y, z, mx.get());
+    OTIP_HIP(hipMemsetAsync(mx.get(), 0, 4 * sizeof(double), st));
+    const unsigned nbm = std::min<unsigned>(256, grid_for(2 * (int64_t)std::max(m, n), 256));
+    hipLaunchKernelGGL(maxabs4, dim3(nbm), dim3(256), 0, st, m, n, xs, xt, y, z,
+                       (unsigned long long *)mx.get());
     double h4[4];
     OTIP_HIP(hipMemcpyAsync(h4, mx.get(), sizeof(h4), hipMemcpyDeviceToHost, st));
     OTIP_HIP(hipStreamSynchronize(st));
     const double X = h4[0], Xt = h4[1];
     const double Cbound = 2.0 * (X + Xt) * (X + Xt);
     const double inter = 2.0 * X * X + 2.0 * Xt * Xt + 4.0 * X * Xt;
-    if (!(inter < 16777216.0))  // FP32 costs would not be exact: FP64 scan (same result)
+    if (!(inter < 16777216.0))  // a wide band: the FP64 scan (same result)
         return price(st, m, n, xs, xt, y, z, bitmap, kmax, oi, oj, orr, oidx);
-    const double margin = 8.0 * std::ldexp(1.0, -24) * (Cbound + h4[2] + h4[3]);
+    const double margin = 9.0 * std::ldexp(1.0, -24) * (Cbound + h4[2] + h4[3]);
     const float mg = (float)margin;
 
     jt_.need((size_t)n * sizeof(JEntry32));
@@ -857,6 +976,7 @@ PriceResult Scanner::price_mixed(hipStream_t st, int m, int n, const int32_t *xs
         OTIP_HIP(hipMemsetAsync(hist_.get(), 0, (kHistBins + 2) * sizeof(unsigned long long), st));
         a.shift = shift;
         a.prefix = prefix;
+        a.rcut = (shift + 12 >= 32) ? INFINITY : rcut32_of_key(((prefix + 1u) << (shift + 12)) - 1u);
         hipEvent_t e0_, e1_;
         if (timer) timer->arm((double)m * (double)n, &e0_, &e1_);
         else e0_ = e1_ = nullptr;
@@ -910,6 +1030,7 @@ PriceResult Scanner::price_mixed(hipStream_t st, int m, int n, const int32_t *xs
         ci_.need(cap);
         OTIP_HIP(hipMemsetAsync(cnt_.get(), 0, sizeof(unsigned long long), st));
         a.t32 = t32;
+        a.rcut = INFINITY;
         a.count = cnt_.get();
         a.out_idx = ci_.get();
         a.cap = cap;
