@@ -292,6 +292,31 @@ int otip_pcg(otip_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr, const
              const double *vals, const double *b, double *x, double rtol, int32_t maxit,
              int32_t precision, int32_t *iterations, double *res_norm, double *spmv_stats);
 
+/*
+ * Checkpoint and resume (the paper has none; these serve long solves and the
+ * replay of an iteration).  Every otip_solve records, in host memory, the
+ * state at which it stopped iterating, before its certificate and
+ * purification: the support, the iterate (p, s, y, z), the iteration count
+ * and the loop's own state (solver mode, support-size history, the last CG
+ * work, the stop tolerance in force).
+ *   otip_state_save: writes that record of the context's latest otip_solve to
+ *     buf (HOST, cap bytes) and its length to *size (HOST); with buf NULL only
+ *     the length.  OTIP_EINVAL before any solve or when cap is too small.
+ *   otip_state_load: reads a record (HOST bytes) and makes the context's next
+ *     otip_solve continue from it instead of building an initial support;
+ *     that solve must be of the same problem (m, n and the bytes of a, b, xs,
+ *     xt, compared through a 64-bit hash), else it fails with OTIP_EINVAL.
+ *     The record is checked (sizes, increasing support indices below m*n, an
+ *     interior iterate) before it reaches the device.  y0/z0 are ignored by a
+ *     resumed solve.
+ * A solve stopped by max_iter and resumed with a larger max_iter and
+ * otherwise equal parameters takes the same steps as one solve with the larger
+ * max_iter.  The layout is the library's own (host byte order), versioned.
+ * otip_solve_batch neither records nor resumes.
+ */
+int otip_state_save(otip_ctx *ctx, void *buf, int64_t cap, int64_t *size);
+int otip_state_load(otip_ctx *ctx, const void *buf, int64_t size);
+
 /* ------------------------------------------------------------------------
  * Learned warm start.  A small convolutional network maps the two marginals of
  * a side x side grid problem (pixel i at coordinates (i / side, i % side)) to

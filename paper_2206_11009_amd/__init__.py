@@ -22,7 +22,8 @@ from ._abi import (OTIP_OK, OTIP_EINVAL, OTIP_ENOMEM, OTIP_EHIP, OTIP_ENUMERIC, 
 
 __all__ = ["otip_version", "otip_params_default", "Context", "OtipError", "SolveResult",
            "otip_solve", "otip_solve_batch", "otip_price", "otip_rmin", "otip_kron_apply",
-           "otip_kron_apply_t", "otip_schur", "otip_pcg", "PCGResult", "params", "otip_ws_param_count", "otip_ws_forward",
+           "otip_kron_apply_t", "otip_schur", "otip_pcg", "PCGResult", "otip_state_save",
+           "otip_state_load", "params", "otip_ws_param_count", "otip_ws_forward",
            "otip_ws_grad", "otip_ws_adam", "otip_ws_predict", "load_ws_weights"]
 
 
@@ -256,6 +257,22 @@ def otip_schur(ctx: Context, m: int, n: int, idx, theta):
                                   ctypes.byref(nnz), _ptr(rp), _ptr(ci), _ptr(va), _ptr(M),
                                   _ptr(N)))
     return rp, ci[:nnz.value], va[:nnz.value], M, N
+
+
+def otip_state_save(ctx: Context) -> bytes:
+    """The record of where the context's latest otip_solve stopped iterating."""
+    size = ctypes.c_int64()
+    ctx.check(ctx._lib.otip_state_save(ctx.handle, None, 0, ctypes.byref(size)))
+    buf = ctypes.create_string_buffer(size.value)
+    ctx.check(ctx._lib.otip_state_save(ctx.handle, buf, size.value, ctypes.byref(size)))
+    return buf.raw[:size.value]
+
+
+def otip_state_load(ctx: Context, data: bytes) -> None:
+    """Make the context's next otip_solve (of the same problem) continue from
+    a record written by otip_state_save."""
+    data = bytes(data)
+    ctx.check(ctx._lib.otip_state_load(ctx.handle, ctypes.c_char_p(data), len(data)))
 
 
 class PCGResult:

@@ -62,6 +62,107 @@ int guarded(otip_ctx *ctx, F &&f) {
     }
 }
 
+// Checkpoint byte layout (host byte order): "OTIPCKP1", u32 version, i32 m,
+// n, u64 fingerprint, i32 it, mode, cg_its_last, solves_last, cg_failed,
+// warm_used, direct_its, i64 psi, psi_max, cg_total, f64 tol_int, max_fill,
+// i64 hist_len, then i64 psi_hist[hist_len], u64 idx[psi], f64 p[psi],
+// s[psi], y[m], z[n].
+constexpr char kCkMagic[8] = {'O', 'T', 'I', 'P', 'C', 'K', 'P', '1'};
+constexpr uint32_t kCkVersion = 1;
+
+template <class T>
+void put(std::vector<unsigned char> &o, const T *v, size_t count) {
+    const unsigned char *c = (const unsigned char *)v;
+    o.insert(o.end(), c, c + sizeof(T) * count);
+}
+template <class T>
+void put1(std::vector<unsigned char> &o, T v) {
+    put(o, &v, 1);
+}
+
+std::vector<unsigned char> serialize(const otip::Checkpoint &c) {
+    std::vector<unsigned char> o;
+    put(o, kCkMagic, 8);
+    put1(o, kCkVersion);
+    put1(o, c.m);
+    put1(o, c.n);
+    put1(o, c.fingerprint);
+    for (int32_t v : {c.it, c.mode, c.cg_its_last, c.solves_last, c.cg_failed, c.warm_used,
+                      c.direct_its})
+        put1(o, v);
+    put1(o, c.psi);
+    put1(o, c.psi_max);
+    put1(o, c.cg_total);
+    put1(o, c.tol_int);
+    put1(o, c.max_fill);
+    put1(o, (int64_t)c.psi_hist.size());
+    put(o, c.psi_hist.data(), c.psi_hist.size());
+    put(o, c.idx.data(), c.idx.size());
+    put(o, c.p.data(), c.p.size());
+    put(o, c.s.data(), c.s.size());
+    put(o, c.y.data(), c.y.size());
+    put(o, c.z.data(), c.z.size());
+    return o;
+}
+
+struct ByteReader {
+    const unsigned char *p;
+    size_t left;
+    template <class T>
+    void get(T *v, size_t count) {
+        const size_t len = sizeof(T) * count;
+        OTIP_CHECK(len <= left, OTIP_EINVAL, "checkpoint: truncated");
+        std::memcpy(v, p, len);
+        p += len;
+        left -= len;
+    }
+    template <class T>
+    T get1() {
+        T v;
+        get(&v, 1);
+        return v;
+    }
+};
+
+std::unique_ptr<otip::Checkpoint> deserialize(const void *buf, size_t size) {
+    ByteReader r{(const unsigned char *)buf, size};
+    char magic[8];
+    r.get(magic, 8);
+    OTIP_CHECK(std::memcmp(magic, kCkMagic, 8) == 0 && r.get1<uint32_t>() == kCkVersion,
+               OTIP_EINVAL, "not a checkpoint of this library version");
+    auto c = std::make_unique<otip::Checkpoint>();
+    c->m = r.get1<int32_t>();
+    c->n = r.get1<int32_t>();
+    c->fingerprint = r.get1<uint64_t>();
+    for (int32_t *v : {&c->it, &c->mode, &c->cg_its_last, &c->solves_last, &c->cg_failed,
+                       &c->warm_used, &c->direct_its})
+        *v = r.get1<int32_t>();
+    c->psi = r.get1<int64_t>();
+    c->psi_max = r.get1<int64_t>();
+    c->cg_total = r.get1<int64_t>();
+    c->tol_int = r.get1<double>();
+    c->max_fill = r.get1<double>();
+    const int64_t nh = r.get1<int64_t>();
+    OTIP_CHECK(c->m >= 1 && c->n >= 1 && c->psi >= 1 && nh >= 0, OTIP_EINVAL,
+               "checkpoint: bad sizes");
+    // every array must fit in what is left (no allocation beyond the input)
+    const double need = 8.0 * ((double)nh + 3.0 * (double)c->psi + (double)c->m + (double)c->n);
+    OTIP_CHECK(need == (double)r.left, OTIP_EINVAL, "checkpoint: size does not match its header");
+    c->psi_hist.resize(nh);
+    c->idx.resize(c->psi);
+    c->p.resize(c->psi);
+    c->s.resize(c->psi);
+    c->y.resize(c->m);
+    c->z.resize(c->n);
+    r.get(c->psi_hist.data(), nh);
+    r.get(c->idx.data(), c->psi);
+    r.get(c->p.data(), c->psi);
+    r.get(c->s.data(), c->psi);
+    r.get(c->y.data(), c->m);
+    r.get(c->z.data(), c->n);
+    return c;
+}
+
 }  // namespace
 
 extern "C" {
@@ -363,6 +464,29 @@ int otip_pcg(otip_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr, const
     if (rc != OTIP_OK) return rc;
     if (cs.converged) return OTIP_OK;
     return cs.iterations >= maxit ? OTIP_EMAXITER : OTIP_ENUMERIC;
+}
+
+int otip_state_save(otip_ctx *ctx, void *buf, int64_t cap, int64_t *size) {
+    return guarded(ctx, [&] {
+        OTIP_CHECK(size, OTIP_EINVAL, "otip_state_save: null size");
+        const otip::Checkpoint *c = ctx->solver ? ctx->solver->last_state() : nullptr;
+        OTIP_CHECK(c, OTIP_EINVAL, "otip_state_save: no solve on this context yet");
+        const std::vector<unsigned char> bytes = serialize(*c);
+        *size = (int64_t)bytes.size();
+        if (buf) {
+            OTIP_CHECK(cap >= (int64_t)bytes.size(), OTIP_EINVAL, "otip_state_save: buffer too small");
+            std::memcpy(buf, bytes.data(), bytes.size());
+        }
+    });
+}
+
+int otip_state_load(otip_ctx *ctx, const void *buf, int64_t size) {
+    return guarded(ctx, [&] {
+        OTIP_CHECK(buf && size > 0, OTIP_EINVAL, "otip_state_load: bad arguments");
+        std::unique_ptr<otip::Checkpoint> c = deserialize(buf, (size_t)size);
+        if (!ctx->solver) ctx->solver = std::make_unique<otip::Solver>(ctx->stream);
+        ctx->solver->set_resume(std::move(c));
+    });
 }
 
 int64_t otip_ws_param_count(void) { return otip::WarmNet::param_count(); }

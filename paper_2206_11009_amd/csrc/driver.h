@@ -2,6 +2,7 @@
 #pragma once
 
 #include <cstdarg>
+#include <memory>
 
 #include "../../include/otip.h"
 #include "internal.h"
@@ -23,6 +24,21 @@ void purify_plan(int m, int n, const std::vector<int32_t> &rows, const std::vect
 
 enum class Mode { PCG, Direct };
 
+// Where a solve stopped iterating (before its certificate and purification):
+// the iterate and the loop's own state, enough to continue the iteration
+// exactly as if it had not stopped.  Host memory.
+struct Checkpoint {
+    int32_t m = 0, n = 0;
+    uint64_t fingerprint = 0;  // of m, n and the bytes of a, b, xs, xt
+    int32_t it = 0, mode = 0, cg_its_last = 0, solves_last = 2, cg_failed = 0, warm_used = 0;
+    int32_t direct_its = 0;
+    int64_t psi = 0, psi_max = 0, cg_total = 0;
+    double tol_int = 0.0, max_fill = 0.0;
+    std::vector<int64_t> psi_hist;
+    std::vector<uint64_t> idx;
+    std::vector<double> p, s, y, z;
+};
+
 struct Dir {
     DBuf<double> dp, ds, dy, dz;
 };
@@ -35,6 +51,10 @@ class Solver {
     int64_t schur_export(int m, int n, int64_t psi, const uint64_t *idx, const double *theta,
                          int32_t *rowptr, int32_t *colidx, double *vals, double *Mout,
                          double *Nout);
+    // the state at which the latest run stopped iterating (null before any)
+    const Checkpoint *last_state() const { return have_last_ ? &last_ : nullptr; }
+    // a state for the next run to continue from (it must be the same problem)
+    void set_resume(std::unique_ptr<Checkpoint> c) { pending_ = std::move(c); }
 
   private:
     void rebuild_views();
@@ -53,6 +73,8 @@ class Solver {
     void starting_point();
     void finalize(Result &res);
     void reset_state();
+    void snapshot(int it, double tol_int, const std::vector<int64_t> &hist);
+    void resume_from(const Checkpoint &c);
     int run_without_zeros(const otip_problem &pr, const otip_params &prm, Result &res);
     static double now();
     void log(const char *fmt, ...);
@@ -93,6 +115,10 @@ class Solver {
     DBuf<int32_t> zcoord_;
     bool warm_used = false;
     bool schur_valid = false;
+    uint64_t fp_ = 0;
+    Checkpoint last_;
+    bool have_last_ = false;
+    std::unique_ptr<Checkpoint> pending_;
 
     Mode mode = Mode::PCG;
     bool cg_failed = false;

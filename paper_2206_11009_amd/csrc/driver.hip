@@ -698,6 +698,85 @@ int Solver::run_without_zeros(const otip_problem &pr, const otip_params &prm, Re
     return status;
 }
 
+void Solver::snapshot(int it, double tol_int, const std::vector<int64_t> &hist) {
+    Checkpoint &c = last_;
+    c.m = m;
+    c.n = n;
+    c.fingerprint = fp_;
+    c.it = it;
+    c.mode = mode == Mode::Direct ? 1 : 0;
+    c.cg_its_last = cg_its_last;
+    c.solves_last = solves_last;
+    c.cg_failed = cg_failed ? 1 : 0;
+    c.warm_used = warm_used ? 1 : 0;
+    c.direct_its = direct_its;
+    c.psi = psi_;
+    c.psi_max = psi_max;
+    c.cg_total = cg_total;
+    c.tol_int = tol_int;
+    c.max_fill = max_fill;
+    // one entry per iteration started before `it` (a break inside iteration
+    // `it` has already recorded it)
+    c.psi_hist.assign(hist.begin(), hist.begin() + std::min<size_t>(hist.size(), (size_t)it));
+    c.idx.resize(psi_);
+    c.p.resize(psi_);
+    c.s.resize(psi_);
+    c.y.resize(m);
+    c.z.resize(n);
+    OTIP_HIP(hipMemcpyAsync(c.idx.data(), idx.get(), sizeof(uint64_t) * psi_, hipMemcpyDeviceToHost,
+                            st));
+    OTIP_HIP(hipMemcpyAsync(c.p.data(), p.get(), sizeof(double) * psi_, hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipMemcpyAsync(c.s.data(), s.get(), sizeof(double) * psi_, hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipMemcpyAsync(c.y.data(), y.get(), sizeof(double) * m, hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipMemcpyAsync(c.z.data(), z.get(), sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipStreamSynchronize(st));
+    have_last_ = true;
+}
+
+// The support, iterate and loop state of a checkpoint of this same problem,
+// checked on the host before anything reaches the device.
+void Solver::resume_from(const Checkpoint &c) {
+    OTIP_CHECK(c.m == m && c.n == n && c.fingerprint == fp_, OTIP_EINVAL,
+               "checkpoint belongs to another problem");
+    const uint64_t mn = (uint64_t)m * (uint64_t)n;
+    OTIP_CHECK(c.psi >= 1 && (uint64_t)c.psi <= mn && (int64_t)c.idx.size() == c.psi &&
+                   (int64_t)c.p.size() == c.psi && (int64_t)c.s.size() == c.psi &&
+                   (int64_t)c.y.size() == m && (int64_t)c.z.size() == n,
+               OTIP_EINVAL, "checkpoint: inconsistent sizes");
+    for (int64_t k = 0; k < c.psi; ++k) {
+        OTIP_CHECK(c.idx[k] < mn && (k == 0 || c.idx[k] > c.idx[k - 1]), OTIP_EINVAL,
+                   "checkpoint: support indices out of range or not increasing");
+        OTIP_CHECK(std::isfinite(c.p[k]) && std::isfinite(c.s[k]) && c.p[k] > 0.0 && c.s[k] > 0.0,
+                   OTIP_EINVAL, "checkpoint: iterate not interior");
+    }
+    for (double v : c.y) OTIP_CHECK(std::isfinite(v), OTIP_EINVAL, "checkpoint: non-finite y");
+    for (double v : c.z) OTIP_CHECK(std::isfinite(v), OTIP_EINVAL, "checkpoint: non-finite z");
+    OTIP_CHECK(c.mode == 0 || (c.mode == 1 && n <= P.dense_max_n), OTIP_EINVAL,
+               "checkpoint: solver mode not available");
+    OTIP_CHECK(c.it >= 0 && c.tol_int > 0.0 && c.psi_max >= c.psi, OTIP_EINVAL,
+               "checkpoint: bad loop state");
+    alloc_support(std::max<int64_t>(c.psi * 2, c.psi + 4 * (int64_t)std::max(m, n)));
+    OTIP_HIP(hipMemcpyAsync(idx.get(), c.idx.data(), sizeof(uint64_t) * c.psi,
+                            hipMemcpyHostToDevice, st));
+    OTIP_HIP(hipMemcpyAsync(p.get(), c.p.data(), sizeof(double) * c.psi, hipMemcpyHostToDevice, st));
+    OTIP_HIP(hipMemcpyAsync(s.get(), c.s.data(), sizeof(double) * c.psi, hipMemcpyHostToDevice, st));
+    OTIP_HIP(hipMemcpyAsync(y.get(), c.y.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
+    OTIP_HIP(hipMemcpyAsync(z.get(), c.z.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+    psi_ = c.psi;
+    psi_max = c.psi_max;
+    rebuild_views();
+    foreach(st, psi_, FBits{idx.get(), bitmap.get(), true});
+    mode = c.mode == 1 ? Mode::Direct : Mode::PCG;
+    cg_its_last = c.cg_its_last;
+    solves_last = c.solves_last;
+    warm_used = c.warm_used != 0;
+    direct_its = c.direct_its;
+    cg_total = c.cg_total;
+    max_fill = c.max_fill;
+    OTIP_HIP(hipStreamSynchronize(st));
+    log("otip: m=%d n=%d resumed at iteration %d with psi=%lld\n", m, n, c.it, (long long)c.psi);
+}
+
 // Per-solve scalars back to their initial values; device buffers are kept so
 // that a solver reused for a stream of problems allocates (and frees) nothing
 // once it has seen the largest one.
@@ -767,9 +846,24 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
     {
         // coordinate range -> largest cost (for scaling and the initial support)
         std::vector<int32_t> hx((size_t)2 * m), ht((size_t)2 * n);
+        std::vector<double> ha(m), hb(n);
         OTIP_HIP(hipMemcpyAsync(hx.data(), xs, sizeof(int32_t) * 2 * m, hipMemcpyDeviceToHost, st));
         OTIP_HIP(hipMemcpyAsync(ht.data(), xt, sizeof(int32_t) * 2 * n, hipMemcpyDeviceToHost, st));
+        OTIP_HIP(hipMemcpyAsync(ha.data(), pr.a, sizeof(double) * m, hipMemcpyDeviceToHost, st));
+        OTIP_HIP(hipMemcpyAsync(hb.data(), pr.b, sizeof(double) * n, hipMemcpyDeviceToHost, st));
         OTIP_HIP(hipStreamSynchronize(st));
+        // identity of the problem, for checkpoints (FNV-1a over its bytes)
+        fp_ = 14695981039346656037ull;
+        auto mix = [&](const void *q, size_t len) {
+            const unsigned char *c = (const unsigned char *)q;
+            for (size_t k = 0; k < len; ++k) fp_ = (fp_ ^ c[k]) * 1099511628211ull;
+        };
+        mix(&m, sizeof m);
+        mix(&n, sizeof n);
+        mix(ha.data(), sizeof(double) * m);
+        mix(hb.data(), sizeof(double) * n);
+        mix(hx.data(), sizeof(int32_t) * 2 * m);
+        mix(ht.data(), sizeof(int32_t) * 2 * n);
         int64_t lo[2] = {INT64_MAX, INT64_MAX}, hi[2] = {INT64_MIN, INT64_MIN};
         for (int q = 0; q < m; ++q)
             for (int d = 0; d < 2; ++d) {
@@ -827,34 +921,41 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
     bitmap.need(words);
     OTIP_HIP(hipMemsetAsync(bitmap.get(), 0, words * sizeof(uint32_t), st));
 
-    // ---- initial support (Section 3.2, end)
+    // ---- initial support (Section 3.2, end), or a checkpoint's state
     double ts = now();
     int64_t T = 0;
     DBuf<uint64_t> &init = init_;
     OTIP_CHECK((pr.y0 == nullptr) == (pr.z0 == nullptr), OTIP_EINVAL,
                "warm start needs both y0 and z0");
-    int64_t psi0 = -1;
-    if (pr.y0) {
-        psi0 = scan.warm_support(st, m, n, xs, xt, pr.y0, pr.z0,
-                                 P.ws_kappa > 0 ? P.ws_kappa : P.kappa, init, yws_, zws_);
-        warm_used = psi0 >= 0;
+    const std::unique_ptr<Checkpoint> resume = std::move(pending_);
+    if (resume) {
+        resume_from(*resume);
+    } else {
+        int64_t psi0 = -1;
+        if (pr.y0) {
+            psi0 = scan.warm_support(st, m, n, xs, xt, pr.y0, pr.z0,
+                                     P.ws_kappa > 0 ? P.ws_kappa : P.kappa, init, yws_, zws_);
+            warm_used = psi0 >= 0;
+        }
+        if (psi0 < 0) psi0 = scan.initial_support(st, m, n, xs, xt, P.kappa, cmax, init, &T);
+        alloc_support(std::max<int64_t>(psi0 * 2, psi0 + 4 * (int64_t)std::max(m, n)));
+        OTIP_HIP(hipMemcpyAsync(idx.get(), init.get(), sizeof(uint64_t) * psi0,
+                                hipMemcpyDeviceToDevice, st));
+        psi_ = psi0;
+        psi_max = psi0;
+        rebuild_views();
+        foreach(st, psi_, FBits{idx.get(), bitmap.get(), true});
+        log("otip: m=%d n=%d psi0=%lld T=%lld omega=%g zeta=%g\n", m, n, (long long)psi0,
+            (long long)T, omega, zeta);
+        starting_point();
+        mode = (P.linear_solver == OTIP_LS_DIRECT) ? Mode::Direct : Mode::PCG;
     }
-    if (psi0 < 0) psi0 = scan.initial_support(st, m, n, xs, xt, P.kappa, cmax, init, &T);
-    alloc_support(std::max<int64_t>(psi0 * 2, psi0 + 4 * (int64_t)std::max(m, n)));
-    OTIP_HIP(hipMemcpyAsync(idx.get(), init.get(), sizeof(uint64_t) * psi0, hipMemcpyDeviceToDevice, st));
-    psi_ = psi0;
-    psi_max = psi0;
-    rebuild_views();
-    foreach(st, psi_, FBits{idx.get(), bitmap.get(), true});
-    log("otip: m=%d n=%d psi0=%lld T=%lld omega=%g zeta=%g\n", m, n, (long long)psi0,
-        (long long)T, omega, zeta);
-    starting_point();
     t_setup += now() - ts;
 
-    mode = (P.linear_solver == OTIP_LS_DIRECT) ? Mode::Direct : Mode::PCG;
     if (mode == Mode::Direct)
         OTIP_CHECK(n <= P.dense_max_n, OTIP_EUNSUPPORTED, "direct solver: n exceeds dense_max_n");
     std::vector<int64_t> psi_hist;
+    if (resume) psi_hist = resume->psi_hist;
     const int64_t kcap = P.enter_cap > 0 ? P.enter_cap : m;
     DBuf<uint64_t> &sel_idx = sel_idx_;
     DBuf<double> &sel_r = sel_r_;
@@ -862,9 +963,9 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
     sel_r.need(kcap);
     DBuf<uint8_t> &removed = removed_;
     int status = OTIP_EMAXITER;
-    int it = 0;
-    cg_failed = false;
-    double tol_int = P.tol;
+    int it = resume ? resume->it : 0;
+    cg_failed = resume ? resume->cg_failed != 0 : false;
+    double tol_int = resume ? resume->tol_int : P.tol;
     for (int round = 0;; ++round) {
     status = OTIP_EMAXITER;
     for (; it < P.max_iter; ++it) {
@@ -1069,6 +1170,7 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
             it, (long long)psi_hist.back(), rel1, rel2, relmu, ap, ad, sigma, ncorr, cg_its_iter,
             mode == Mode::Direct ? "dir" : "pcg", (long long)k, (long long)nrem);
     }
+    snapshot(it, tol_int, psi_hist);
     if (status == OTIP_OK) ++it;
     double tf = now();
     finalize(res);
