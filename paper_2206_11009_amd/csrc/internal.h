@@ -141,7 +141,10 @@ class SchurSolver {
     template <typename T>
     CGStats pcg_impl(hipStream_t st, const T *val, const T *dinv, const T *b, T *x, double rtol,
                      double atol, int maxit, DBuf<T> &r, DBuf<T> &p, DBuf<T> &q);
-    DBuf<int32_t> cnt_;
+    DBuf<int32_t> cnt_, rk_;
+    DBuf<double> rth_;
+    int64_t psi_ = 0;  // support size of the last symbolic()
+    int32_t span_ = 0;  // largest kmax - kmin + 1 over the rows of S
     DBuf<char> tmp_;
     DBuf<int64_t> off64_, cnt64_;
     DBuf<double> r_, p_, q_, part_, scal_, rd_, sx_, rpart_;

@@ -13,15 +13,48 @@
 namespace otip {
 
 // ---------------------------------------------------------------- symbolic
+// Row-ordered copies of the support's targets and weights: rk[t] =
+// sj[csr_pos[t]] and rth[t] = theta[csr_pos[t]], so that the targets of a
+// source (sorted) are read contiguously, without the permutation.
+__global__ void pack_rows(int64_t psi, const int32_t *__restrict__ csr_pos,
+                          const int32_t *__restrict__ sj, const double *__restrict__ theta,
+                          int32_t *__restrict__ rk, double *__restrict__ rth) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < psi;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int q = csr_pos[t];
+        if (rk) rk[t] = sj[q];
+        if (rth) rth[t] = theta[q];
+    }
+}
+
+__device__ __forceinline__ int wave_min_i(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double rdlane_d(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ void lds_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // One wave per S row j.  The union of the targets of all sources adjacent to j
 // is marked in a per-wave LDS bitmap over [kmin, kmax]; the marked bits, read in
-// order, are the sorted column indices of row j.
+// order, are the sorted column indices of row j.  The sources of column j are
+// read one per lane; their target lists four at a time, all loads in flight.
 template <bool FILL>
 __global__ __launch_bounds__(64) void schur_pattern(int n, const int32_t *__restrict__ col_ptr,
                                                     const int32_t *__restrict__ si,
                                                     const int32_t *__restrict__ row_ptr,
-                                                    const int32_t *__restrict__ csr_pos,
-                                                    const int32_t *__restrict__ sj,
+                                                    const int32_t *__restrict__ rk,
                                                     int32_t *__restrict__ cnt,
                                                     const int32_t *__restrict__ rowptr,
                                                     int32_t *__restrict__ col,
@@ -32,21 +65,43 @@ __global__ __launch_bounds__(64) void schur_pattern(int n, const int32_t *__rest
     const int lane = threadIdx.x;
     const int c0 = col_ptr[j], c1 = col_ptr[j + 1];
     int kmin = n, kmax = -1;
-    for (int e = c0; e < c1; ++e) {
+    for (int e = c0 + lane; e < c1; e += 64) {
         const int i = si[e];
         const int r0 = row_ptr[i], r1 = row_ptr[i + 1];
-        kmin = min(kmin, sj[csr_pos[r0]]);
-        kmax = max(kmax, sj[csr_pos[r1 - 1]]);
+        kmin = min(kmin, rk[r0]);
+        kmax = max(kmax, rk[r1 - 1]);
     }
+    kmin = wave_min_i(kmin);
+    kmax = wave_max_i(kmax);
     const int w0 = kmin >> 5, w1 = kmax >> 5;
     for (int w = w0 + lane; w <= w1; w += 64) bits[w - w0] = 0u;
     __syncthreads();
-    for (int e = c0; e < c1; ++e) {
-        const int i = si[e];
-        const int r0 = row_ptr[i], r1 = row_ptr[i + 1];
-        for (int r = r0 + lane; r < r1; r += 64) {
-            const int k = sj[csr_pos[r]];
-            atomicOr(&bits[(k >> 5) - w0], 1u << (k & 31));
+    for (int e0 = c0; e0 < c1; e0 += 64) {
+        int r0l = 0, r1l = 0;
+        if (e0 + lane < c1) {
+            const int i = si[e0 + lane];
+            r0l = row_ptr[i];
+            r1l = row_ptr[i + 1];
+        }
+        const int ns = min(64, c1 - e0);
+        for (int s0 = 0; s0 < ns; s0 += 4) {
+            int k[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int sl = min(s0 + u, ns - 1);
+                const int r = __builtin_amdgcn_readlane(r0l, sl) + lane;
+                k[u] = (s0 + u < ns && r < __builtin_amdgcn_readlane(r1l, sl)) ? rk[r] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (k[u] >= 0) atomicOr(&bits[(k[u] >> 5) - w0], 1u << (k[u] & 31));
+                if (s0 + u < ns) {  // sources with more than 64 targets
+                    const int r1 = __builtin_amdgcn_readlane(r1l, s0 + u);
+                    for (int r = __builtin_amdgcn_readlane(r0l, s0 + u) + 64 + lane; r < r1;
+                         r += 64)
+                        atomicOr(&bits[(rk[r] >> 5) - w0], 1u << (rk[r] & 31));
+                }
+            }
         }
     }
     __syncthreads();
@@ -54,7 +109,10 @@ __global__ __launch_bounds__(64) void schur_pattern(int n, const int32_t *__rest
         int c = 0;
         for (int w = w0 + lane; w <= w1; w += 64) c += __popc(bits[w - w0]);
         c = wave_sum_i(c);
-        if (lane == 0) cnt[j] = c;
+        if (lane == 0) {
+            cnt[j] = c;
+            atomicMax(&cnt[n], kmax - kmin + 1);  // the widest row's column span
+        }
         return;
     }
     int base = rowptr[j];
@@ -98,9 +156,13 @@ void SchurSolver::symbolic(hipStream_t st, int m, int n, int64_t psi, const int3
     const int words = (n + 31) / 32 + 1;
     OTIP_CHECK(words * 4 <= 64 * 1024, 6, "Schur pattern: n too large for the LDS bitmap");
     S.n = n;
-    cnt_.need((size_t)n);
+    cnt_.need((size_t)n + 1);
+    OTIP_HIP(hipMemsetAsync(cnt_.get() + n, 0, sizeof(int32_t), st));
+    rk_.need((size_t)std::max<int64_t>(psi, 1));
+    hipLaunchKernelGGL(pack_rows, dim3(std::min<unsigned>(4096, grid_for(psi, 256))), dim3(256), 0,
+                       st, psi, csr_pos, sj, nullptr, rk_.get(), nullptr);
     hipLaunchKernelGGL(schur_pattern<false>, dim3(n), dim3(64), words * 4, st, n, col_ptr, si,
-                       row_ptr, csr_pos, sj, cnt_.get(), nullptr, nullptr, nullptr, nullptr);
+                       row_ptr, rk_.get(), cnt_.get(), nullptr, nullptr, nullptr, nullptr);
     OTIP_HIP(hipGetLastError());
     cnt64_.need((size_t)n);
     off64_.need((size_t)n);
@@ -112,7 +174,9 @@ void SchurSolver::symbolic(hipStream_t st, int m, int n, int64_t psi, const int3
                        cnt_.get(), S.rowptr.get());
     int32_t nnz = 0;
     OTIP_HIP(hipMemcpyAsync(&nnz, S.rowptr.get() + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipMemcpyAsync(&span_, cnt_.get() + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     OTIP_HIP(hipStreamSynchronize(st));
+    OTIP_CHECK(span_ >= 1 && span_ <= n, 5, "Schur pattern: bad column span");
     OTIP_CHECK(nnz >= n, 5, "Schur pattern: missing diagonal");
     S.nnz = nnz;
     S.col.need((size_t)nnz);
@@ -121,8 +185,9 @@ void SchurSolver::symbolic(hipStream_t st, int m, int n, int64_t psi, const int3
     S.val.need((size_t)nnz);
     S.dinv.need((size_t)n);
     hipLaunchKernelGGL(schur_pattern<true>, dim3(n), dim3(64), words * 4, st, n, col_ptr, si,
-                       row_ptr, csr_pos, sj, nullptr, S.rowptr.get(), S.col.get(), S.row.get(),
+                       row_ptr, rk_.get(), nullptr, S.rowptr.get(), S.col.get(), S.row.get(),
                        S.diag.get());
+    psi_ = psi;
     OTIP_HIP(hipGetLastError());
 }
 
@@ -161,38 +226,72 @@ __global__ void schur_offdiag(int64_t nnz, const int32_t *__restrict__ srow,
 }
 
 // Off-diagonal values by rows, for n <= kRowAccMax: one wavefront per row j of
-// S accumulates sum_i theta_ij theta_ik / M_i into a dense LDS row over the
+// S accumulates sum_i theta_ij theta_ik / M_i into a dense LDS row (over the
+// widest column span of any row, so that many rows fit a compute unit) over the
 // sources i of column j in increasing i (each source's targets k are distinct,
 // and successive sources are ordered by the wave's program order), then
 // gathers the row's pattern.  Same products and summation order as
 // schur_offdiag, so the values are identical; the work is
-// sum_j sum_{i in col j} deg(i) instead of a merge per nonzero.
+// sum_j sum_{i in col j} deg(i) instead of a merge per nonzero.  The sources'
+// data are read one per lane and their row-ordered targets and weights (rk,
+// rth) four sources at a time, before the four are accumulated in order.
 constexpr int kRowAccMax = 8192;
 
 __global__ __launch_bounds__(64) void schur_offdiag_rows(
     int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ scol,
     const int32_t *__restrict__ col_ptr, const int32_t *__restrict__ si,
-    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ csr_pos,
-    const int32_t *__restrict__ sj, const double *__restrict__ theta,
+    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ rk,
+    const double *__restrict__ rth, const double *__restrict__ theta,
     const double *__restrict__ invM, double *__restrict__ val) {
     extern __shared__ double acc[];
     const int j = blockIdx.x, l = threadIdx.x;
     const int e0 = rowptr[j], e1 = rowptr[j + 1];
-    for (int e = e0 + l; e < e1; e += 64) acc[scol[e]] = 0.0;
+    // the row's columns are sorted and span at most the LDS row: k at k - kb
+    const int kb = scol[e0];
+    for (int e = e0 + l; e < e1; e += 64) acc[scol[e] - kb] = 0.0;
     __syncthreads();
-    for (int a = col_ptr[j]; a < col_ptr[j + 1]; ++a) {
-        const int i = si[a];
-        const double ta = theta[a], im = invM[i];
-        for (int t = row_ptr[i] + l; t < row_ptr[i + 1]; t += 64) {
-            const int q = csr_pos[t];
-            const int k = sj[q];
-            acc[k] = fma(ta * theta[q], im, acc[k]);
+    const int c0 = col_ptr[j], c1 = col_ptr[j + 1];
+    for (int a0 = c0; a0 < c1; a0 += 64) {
+        int r0l = 0, r1l = 0;
+        double tml = 0.0, iml = 0.0;
+        if (a0 + l < c1) {
+            const int i = si[a0 + l];
+            r0l = row_ptr[i];
+            r1l = row_ptr[i + 1];
+            tml = theta[a0 + l];
+            iml = invM[i];
         }
-        __syncthreads();
+        const int ns = min(64, c1 - a0);
+        for (int s0 = 0; s0 < ns; s0 += 4) {
+            int k[4];
+            double th[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int sl = min(s0 + u, ns - 1);
+                const int r = __builtin_amdgcn_readlane(r0l, sl) + l;
+                const bool ok = s0 + u < ns && r < __builtin_amdgcn_readlane(r1l, sl);
+                k[u] = ok ? rk[r] : -1;
+                th[u] = ok ? rth[r] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (s0 + u >= ns) break;
+                const int sl = s0 + u;
+                const double ta = rdlane_d(tml, sl), im = rdlane_d(iml, sl);
+                if (k[u] >= 0) acc[k[u] - kb] = fma(ta * th[u], im, acc[k[u] - kb]);
+                // sources with more than 64 targets: the rest, still before the
+                // next source
+                const int r1 = __builtin_amdgcn_readlane(r1l, sl);
+                for (int r = __builtin_amdgcn_readlane(r0l, sl) + 64 + l; r < r1; r += 64)
+                    acc[rk[r] - kb] = fma(ta * rth[r], im, acc[rk[r] - kb]);
+                lds_wave_sync();
+            }
+        }
     }
+    __syncthreads();
     for (int e = e0 + l; e < e1; e += 64) {
         const int k = scol[e];
-        val[e] = (k == j) ? 0.0 : -acc[k];
+        val[e] = (k == j) ? 0.0 : -acc[k - kb];
     }
 }
 
@@ -218,11 +317,15 @@ __global__ __launch_bounds__(256) void schur_diag(int n, const int32_t *__restri
 void SchurSolver::numeric(hipStream_t st, int m, int n, const int32_t *col_ptr,
                           const int32_t *si, const int32_t *row_ptr, const int32_t *csr_pos,
                           const int32_t *sj, const double *theta, const double *invM) {
-    if (n <= kRowAccMax)
-        hipLaunchKernelGGL(schur_offdiag_rows, dim3(n), dim3(64), sizeof(double) * n, st, n,
-                           S.rowptr.get(), S.col.get(), col_ptr, si, row_ptr, csr_pos, sj, theta,
-                           invM, S.val.get());
-    else
+    if (n <= kRowAccMax) {
+        // the targets rk of this support were packed by symbolic()
+        rth_.need((size_t)std::max<int64_t>(psi_, 1));
+        hipLaunchKernelGGL(pack_rows, dim3(std::min<unsigned>(4096, grid_for(psi_, 256))),
+                           dim3(256), 0, st, psi_, csr_pos, sj, theta, nullptr, rth_.get());
+        hipLaunchKernelGGL(schur_offdiag_rows, dim3(n), dim3(64), sizeof(double) * span_, st, n,
+                           S.rowptr.get(), S.col.get(), col_ptr, si, row_ptr, rk_.get(),
+                           rth_.get(), theta, invM, S.val.get());
+    } else
         hipLaunchKernelGGL(schur_offdiag, dim3(grid_for(S.nnz, 256)), dim3(256), 0, st, S.nnz,
                            S.row.get(), S.col.get(), col_ptr, si, theta, invM, S.val.get());
     hipLaunchKernelGGL(schur_diag, dim3(grid_for(n, 4)), dim3(256), 0, st, n, S.rowptr.get(),
