@@ -111,8 +111,9 @@ __global__ __launch_bounds__(64) void ldl_diag(int n, int kb, int nb, double *A,
 }
 
 // Rows below the diagonal block: W21 = A21 L11^-T (so W21 = L21 D1) and
-// L21 = W21 D1^-1.  A 64-row tile of A21 and Linv are staged in LDS; each
-// thread forms 16 entries of W as dot products with rows of Linv.
+// L21 = W21 D1^-1.  A 64-row tile of A21 and Linv are staged in LDS and
+// W = A21 Linv^T is formed on the FP64 matrix cores (Linv is zero above its
+// diagonal); each wave forms a 32 x 32 quarter as 2 x 2 blocks of 16 x 16.
 __global__ __launch_bounds__(256) void ldl_panel(int n, int kb, int nb, double *A,
                                                  const double *d, double *W,
                                                  const double *Linv) {
@@ -126,22 +127,41 @@ __global__ __launch_bounds__(256) void ldl_panel(int n, int kb, int nb, double *
         Li[a][k] = Linv[(size_t)a + (size_t)k * NB];  // Linv(a, k)
     }
     __syncthreads();
-    const int a = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const int i = r0 + a;
-    // W(i, k) = sum_t A(i, t) * Linv(k, t), t <= k
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+    d4 acc[2][2];
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
-        const int k = 16 * q + c;
-        double v = 0.0;
-        for (int tt = 0; tt <= k && tt < nb; ++tt) v = fma(As[a][tt], Li[k][tt], v);
-        if (i < n && k < nb) {
-            const double dd = d[kb + k];
-            const bool inf = isinf(dd);
-            const double wk = inf ? 0.0 : v;
-            W[(size_t)(i - kb - nb) + (size_t)k * rows] = wk;
-            A[(size_t)i + (size_t)(kb + k) * n] = inf ? 0.0 : wk / dd;
-        }
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) acc[u][v] = d4{0.0, 0.0, 0.0, 0.0};
+    // W(a, k) = sum_t A(a, t) Linv(k, t)
+#pragma unroll 4
+    for (int t = 0; t < NB; t += 4) {
+        const double a0 = As[wr + li][t + lk], a1 = As[wr + 16 + li][t + lk];
+        const double b0 = Li[wc + li][t + lk], b1 = Li[wc + 16 + li][t + lk];
+        acc[0][0] = mfma4(a0, b0, acc[0][0]);
+        acc[0][1] = mfma4(a0, b1, acc[0][1]);
+        acc[1][0] = mfma4(a1, b0, acc[1][0]);
+        acc[1][1] = mfma4(a1, b1, acc[1][1]);
     }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int a = wr + 16 * u + mfma_row(lane, q);
+                const int k = wc + 16 * v + li;
+                const int i = r0 + a;
+                if (i < n && k < nb) {
+                    const double dd = d[kb + k];
+                    const bool inf = isinf(dd);
+                    const double wk = inf ? 0.0 : acc[u][v][q];
+                    W[(size_t)(i - kb - nb) + (size_t)k * rows] = wk;
+                    A[(size_t)i + (size_t)(kb + k) * n] = inf ? 0.0 : wk / dd;
+                }
+            }
 }
 
 // A22 -= L21 W21^T on lower-triangular 64x64 tiles; each wave forms a 32x32
