@@ -164,40 +164,47 @@ __global__ __launch_bounds__(256) void ldl_panel(int n, int kb, int nb, double *
             }
 }
 
-// A22 -= L21 W21^T on lower-triangular 64x64 tiles; each wave forms a 32x32
-// quarter of the tile as 2x2 blocks of 16x16 matrix-core products
+// A22 -= L21 W21^T on lower-triangular 64x64 tiles, one workgroup per tile of
+// the lower triangle (1D grid, tile (ti, tj) with tj <= ti from the block
+// index); each wave forms a 32x32 quarter of the tile as 2x2 blocks of 16x16
+// matrix-core products, with its operands loaded straight from global memory
+// into the registers of the matrix-core layout (no LDS, no barrier).
 __global__ __launch_bounds__(256) void ldl_update(int n, int kb, int nb, double *A,
                                                   const double *W) {
     const int r0 = kb + nb;
     const int rows = n - r0;
-    const int ti = blockIdx.x, tj = blockIdx.y;
-    if (tj > ti) return;
-    __shared__ double Ls[NB][NB + 1];
-    __shared__ double Ws[NB][NB + 1];
+    const int blk = blockIdx.x;
+    int ti = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= blk) ++ti;
+    while (ti * (ti + 1) / 2 > blk) --ti;
+    const int tj = blk - ti * (ti + 1) / 2;
     const int i0 = ti * NB, j0 = tj * NB;
-    for (int t = threadIdx.x; t < NB * NB; t += blockDim.x) {
-        const int a = t % NB, k = t / NB;
-        const int ii = i0 + a, jj = j0 + a;
-        Ls[a][k] = (ii < rows && k < nb) ? A[(size_t)(r0 + ii) + (size_t)(kb + k) * n] : 0.0;
-        Ws[a][k] = (jj < rows && k < nb) ? W[(size_t)jj + (size_t)k * rows] : 0.0;
-    }
-    __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
+    // operands: L(i0 + wr + 16u + li, k) and W(j0 + wc + 16v + li, k), k = 4t + lk
+    double av[2][16], bv[2][16];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int ii = i0 + wr + 16 * u + li, jj = j0 + wc + 16 * u + li;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int k = 4 * t + lk;
+            av[u][t] = (ii < rows && k < nb) ? A[(size_t)(r0 + ii) + (size_t)(kb + k) * n] : 0.0;
+            bv[u][t] = (jj < rows && k < nb) ? W[(size_t)jj + (size_t)k * rows] : 0.0;
+        }
+    }
     d4 acc[2][2];
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
         for (int v = 0; v < 2; ++v) acc[u][v] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-    for (int k = 0; k < NB; k += 4) {
-        const double a0 = Ls[wr + li][k + lk], a1 = Ls[wr + 16 + li][k + lk];
-        const double b0 = Ws[wc + li][k + lk], b1 = Ws[wc + 16 + li][k + lk];
-        acc[0][0] = mfma4(a0, b0, acc[0][0]);
-        acc[0][1] = mfma4(a0, b1, acc[0][1]);
-        acc[1][0] = mfma4(a1, b0, acc[1][0]);
-        acc[1][1] = mfma4(a1, b1, acc[1][1]);
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        acc[0][0] = mfma4(av[0][t], bv[0][t], acc[0][0]);
+        acc[0][1] = mfma4(av[0][t], bv[1][t], acc[0][1]);
+        acc[1][0] = mfma4(av[1][t], bv[0][t], acc[1][0]);
+        acc[1][1] = mfma4(av[1][t], bv[1][t], acc[1][1]);
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u)
@@ -252,8 +259,13 @@ __global__ __launch_bounds__(256) void inv_mul(int n, int b, int mode, const dou
     for (int u = 0; u < 2; ++u)
 #pragma unroll
         for (int v = 0; v < 2; ++v) acc[u][v] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int kt = kt0; kt < kt1; ++kt) {
-        for (int t = threadIdx.x; t < NB * NB; t += 256) {
+    // each thread moves elements t = threadIdx.x + 256 e of the two tiles; the
+    // next k-tile is fetched into registers while the current one is multiplied
+    double pa[NB * NB / 256], pb[NB * NB / 256];
+    auto fetch = [&](int kt) {
+#pragma unroll
+        for (int e = 0; e < NB * NB / 256; ++e) {
+            const int t = threadIdx.x + 256 * e;
             const int q = t % NB, k = t / NB;  // element (q, k) of the A and B tiles
             const int ar = ti * NB + q, ak = kt * NB + k;
             const int bk = kt * NB + q, bc = tj * NB + k;
@@ -265,10 +277,20 @@ __global__ __launch_bounds__(256) void inv_mul(int n, int b, int mode, const dou
                 if (ar < rows2 && ak < rows2) av = X[(size_t)(r2 + ar) + (size_t)(r2 + ak) * n];
                 if (bk < rows2) bv = Tp[(size_t)bk + (size_t)bc * b];
             }
-            As[q][k] = av;
-            Bs[q][k] = bv;
+            pa[e] = av;
+            pb[e] = bv;
+        }
+    };
+    if (kt0 < kt1) fetch(kt0);
+    for (int kt = kt0; kt < kt1; ++kt) {
+#pragma unroll
+        for (int e = 0; e < NB * NB / 256; ++e) {
+            const int t = threadIdx.x + 256 * e;
+            As[t % NB][t / NB] = pa[e];
+            Bs[t % NB][t / NB] = pb[e];
         }
         __syncthreads();
+        if (kt + 1 < kt1) fetch(kt + 1);
 #pragma unroll 4
         for (int k = 0; k < NB; k += 4) {
             const double a0 = As[wr + li][k + lk], a1 = As[wr + 16 + li][k + lk];
@@ -454,8 +476,8 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
             hipLaunchKernelGGL(ldl_panel, dim3(grid_for(rows, NB)), dim3(256), 0, st, n, kb, nb,
                                A, d_.get(), W_.get(), Li);
             const unsigned tiles = grid_for(rows, NB);
-            hipLaunchKernelGGL(ldl_update, dim3(tiles, tiles), dim3(256), 0, st, n, kb, nb, A,
-                               W_.get());
+            hipLaunchKernelGGL(ldl_update, dim3(tiles * (tiles + 1) / 2), dim3(256), 0, st, n, kb,
+                               nb, A, W_.get());
         }
     }
     // X = L^-1 (unit lower; the strict lower part of A holds L)
