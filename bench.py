@@ -32,11 +32,13 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 # HBM traffic of the fused Schur SpMV measured by rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE (separate runs) on `bench.py --steps 1 --warmup 0 --no-cpu-baseline
-# --no-forms`, scaled by what the counters read for a 1 GiB device copy; valid
-# only for the kernel source it was measured on (the SHA-256 of spmv_dir's text).
+# --no-forms`, scaled by what the counters read for a 1 GiB device copy, mean
+# over the launches that did work; valid only for the kernel source it was
+# measured on (the SHA-256 of the text of load_chunk and spmv_dir).
 SPMV_TRAFFIC = {"source": "paper_2206_11009_amd/csrc/schur.hip",
-                "sha256": "43d84d2e35c30395e1c72a321017adcc6068042e438eb6afad49501af23448c3",
-                "bytes_per_launch": 11667382.0}
+                "functions": ["load_chunk", "spmv_dir"],
+                "sha256": "b7d3d64dbbdb6f1b70dc204ca01743bbd6207ed3a1ff743a2bc37396851125fb",
+                "bytes_per_launch": 14233052.0}
 FP64_VECTOR_PEAK_TF = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 PRICE_FLOPS_PER_COST = 7.0     # C_ij: one add + two FMAs (5 flops); r: two subtractions
 WORKLOADS = {
@@ -166,17 +168,20 @@ def summary(sec, infos):
                              for i in infos)}
 
 
-def kernel_source_sha256(path, name):
-    """SHA-256 of one kernel's source text: from its signature to the first
-    line that closes a top-level block."""
+def kernel_source_sha256(path, names):
+    """SHA-256 of the source text of the named functions (each from its
+    signature to the first line that closes a top-level block), in order."""
     import hashlib
     with open(os.path.join(ROOT, path)) as f:
         src = f.read()
-    start = src.find(f"void {name}(")
-    if start < 0:
-        return None
-    end = src.find("\n}\n", start)
-    return hashlib.sha256(src[start:end + 3].encode()).hexdigest()
+    h = hashlib.sha256()
+    for name in names:
+        start = src.find(f"void {name}(")
+        if start < 0:
+            return None
+        end = src.find("\n}\n", start)
+        h.update(src[start:end + 3].encode())
+    return h.hexdigest()
 
 
 def measured_traffic():
@@ -184,7 +189,8 @@ def measured_traffic():
     source differs from the one the counters were taken on."""
     if SPMV_TRAFFIC["sha256"] is None:
         return None
-    if kernel_source_sha256(SPMV_TRAFFIC["source"], "spmv_dir") != SPMV_TRAFFIC["sha256"]:
+    if kernel_source_sha256(SPMV_TRAFFIC["source"], SPMV_TRAFFIC["functions"]) != \
+            SPMV_TRAFFIC["sha256"]:
         return None
     return SPMV_TRAFFIC["bytes_per_launch"]
 
