@@ -71,25 +71,27 @@ __global__ __launch_bounds__(64) void ldl_diag(int n, int kb, int nb, double *A,
     for (int c = 0; c < NB; ++c)
         t[c] = (i < nb && c < nb && c <= i) ? A[(size_t)(kb + i) + (size_t)(kb + c) * n] : 0.0;
     int ninf_local = 0;
+    double dmine = 0.0;
+    // branch-free steps: an infinite or absent pivot gives multipliers 0,
+    // which leave the row unchanged (and its column of L zero), so the whole
+    // recurrence is one basic block and the compiler can overlap a step's
+    // pivot with the previous step's updates
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
-        if (k < nb) {
-            double piv = rdlane(t[k], k);
-            if (!(piv > pivtol * rdlane(oi, k)) || !(piv > 0.0)) piv = INFINITY;
-            const bool fin = !isinf(piv);
-            ninf_local += fin ? 0 : 1;
-            if (i == k) d[kb + k] = piv;
-            if (fin) {
-                const double l = (i > k && i < nb) ? t[k] / piv : 0.0;
-                const double ld = l * piv;
+        const bool act = k < nb;
+        double piv = rdlane(t[k], k);
+        const bool bad = !(piv > pivtol * rdlane(oi, k)) || !(piv > 0.0);
+        piv = bad ? INFINITY : piv;
+        const bool fin = act && !bad;
+        ninf_local += (act && bad) ? 1 : 0;
+        dmine = (i == k) ? piv : dmine;
+        const double l = (fin && i > k && i < nb) ? t[k] / piv : 0.0;
+        const double ld = fin ? l * piv : 0.0;
 #pragma unroll
-                for (int j = k + 1; j < NB; ++j) t[j] = fma(-ld, rdlane(l, j), t[j]);
-                if (i > k) t[k] = l;
-            } else if (i > k) {
-                t[k] = 0.0;  // infinite pivot: the column of L is zero
-            }
-        }
+        for (int j = k + 1; j < NB; ++j) t[j] = fma(-ld, rdlane(l, j), t[j]);
+        t[k] = (act && i > k) ? l : t[k];
     }
+    if (i < nb) d[kb + i] = dmine;
     if (i == 0 && ninf_local) atomicAdd(ninf, ninf_local);
 #pragma unroll
     for (int c = 0; c < NB; ++c)
