@@ -21,7 +21,7 @@ to something other than itself (closed forms, brute force, library LP solvers,
 the paper's identities); see ``tests/test_oracle_pins.py``.
 """
 from . import _cscan  # noqa: F401
-from .ipm import (OracleParams, OracleResult, solve, initial_support, sq_costs,  # noqa: F401
+from .ipm import (OracleParams, OracleResult, solve, initial_support, sq_costs, costs,  # noqa: F401
                   A_apply, AT_apply, normal_blocks, schur_complement)
 from .purify import purify_to_forest, is_forest  # noqa: F401
 

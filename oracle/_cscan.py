@@ -39,15 +39,16 @@ def lib():
         build()
         L = ctypes.CDLL(_LIB)
         L.orc_price.restype = _i64
-        L.orc_price.argtypes = [_i64, _i64, _p, _p, _p, _p, _p, _i64, _i64, _p, _p, _p]
+        _ci = ctypes.c_int
+        L.orc_price.argtypes = [_i64, _i64, _p, _p, _p, _p, _p, _i64, _i64, _p, _p, _p, _ci]
         L.orc_rmin.restype = ctypes.c_double
-        L.orc_rmin.argtypes = [_i64, _i64, _p, _p, _p, _p, _p]
+        L.orc_rmin.argtypes = [_i64, _i64, _p, _p, _p, _p, _p, _ci]
         L.orc_cost_hist.restype = None
-        L.orc_cost_hist.argtypes = [_i64, _i64, _p, _p, _i64, _p]
+        L.orc_cost_hist.argtypes = [_i64, _i64, _p, _p, _i64, _p, _ci]
         L.orc_collect_le.restype = _i64
-        L.orc_collect_le.argtypes = [_i64, _i64, _p, _p, _i64, _p, _i64]
+        L.orc_collect_le.argtypes = [_i64, _i64, _p, _p, _i64, _p, _i64, _ci]
         L.orc_row_col_argmin.restype = None
-        L.orc_row_col_argmin.argtypes = [_i64, _i64, _p, _p, _p, _p]
+        L.orc_row_col_argmin.argtypes = [_i64, _i64, _p, _p, _p, _p, _ci]
         _i32 = ctypes.c_int32
         L.orc_ldl_symbolic.restype = None
         L.orc_ldl_symbolic.argtypes = [_i32, _p, _p, _p, _p, _p, _p]
@@ -68,8 +69,9 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def price(xs, xt, y, z, support_idx, kmax):
-    """(idx, r, n_negative): the <= kmax most negative reduced costs outside the support."""
+def price(xs, xt, y, z, support_idx, kmax, kind=0):
+    """(idx, r, n_negative): the <= kmax most negative reduced costs outside the support
+    (cost kind as in scan.c)."""
     xs = _c(xs, np.int32); xt = _c(xt, np.int32)
     y = _c(y, np.float64); z = _c(z, np.float64)
     sup = _c(support_idx, np.int64)
@@ -79,41 +81,43 @@ def price(xs, xt, y, z, support_idx, kmax):
     out_r = np.empty(max(kmax, 1), np.float64)
     nneg = np.zeros(1, np.int64)
     k = lib().orc_price(m, n, _ptr(xs), _ptr(xt), _ptr(y), _ptr(z), _ptr(sup), sup.shape[0],
-                        kmax, _ptr(out_idx), _ptr(out_r), _ptr(nneg))
+                        kmax, _ptr(out_idx), _ptr(out_r), _ptr(nneg), int(kind))
     if k < 0:
         raise MemoryError("orc_price")
     return out_idx[:k].copy(), out_r[:k].copy(), int(nneg[0])
 
 
-def rmin(xs, xt, y, z):
+def rmin(xs, xt, y, z, kind=0):
     xs = _c(xs, np.int32); xt = _c(xt, np.int32)
     y = _c(y, np.float64); z = _c(z, np.float64)
     arg = np.zeros(1, np.int64)
-    v = lib().orc_rmin(xs.shape[0], xt.shape[0], _ptr(xs), _ptr(xt), _ptr(y), _ptr(z), _ptr(arg))
+    v = lib().orc_rmin(xs.shape[0], xt.shape[0], _ptr(xs), _ptr(xt), _ptr(y), _ptr(z), _ptr(arg),
+                       int(kind))
     return float(v), int(arg[0])
 
 
-def cost_hist(xs, xt, cmax):
+def cost_hist(xs, xt, cmax, kind=0):
     xs = _c(xs, np.int32); xt = _c(xt, np.int32)
     h = np.zeros(int(cmax) + 1, np.int64)
-    lib().orc_cost_hist(xs.shape[0], xt.shape[0], _ptr(xs), _ptr(xt), int(cmax), _ptr(h))
+    lib().orc_cost_hist(xs.shape[0], xt.shape[0], _ptr(xs), _ptr(xt), int(cmax), _ptr(h), int(kind))
     return h
 
 
-def collect_le(xs, xt, T, cap):
+def collect_le(xs, xt, T, cap, kind=0):
     xs = _c(xs, np.int32); xt = _c(xt, np.int32)
     out = np.empty(max(int(cap), 1), np.int64)
-    k = lib().orc_collect_le(xs.shape[0], xt.shape[0], _ptr(xs), _ptr(xt), int(T), _ptr(out), int(cap))
+    k = lib().orc_collect_le(xs.shape[0], xt.shape[0], _ptr(xs), _ptr(xt), int(T), _ptr(out), int(cap),
+                             int(kind))
     if k > cap:
         raise RuntimeError("collect_le: capacity too small")
     return out[:k].copy()
 
 
-def row_col_argmin(xs, xt):
+def row_col_argmin(xs, xt, kind=0):
     xs = _c(xs, np.int32); xt = _c(xt, np.int32)
     ra = np.empty(xs.shape[0], np.int64)
     ca = np.empty(xt.shape[0], np.int64)
-    lib().orc_row_col_argmin(xs.shape[0], xt.shape[0], _ptr(xs), _ptr(xt), _ptr(ra), _ptr(ca))
+    lib().orc_row_col_argmin(xs.shape[0], xt.shape[0], _ptr(xs), _ptr(xt), _ptr(ra), _ptr(ca), int(kind))
     return ra, ca
 
 

@@ -114,6 +114,10 @@ class OracleParams:
     # cap on the number of entering columns per iteration; <= 0 means m
     # (Section 3.2: at most m variables enter or leave per iteration)
     enter_cap: int = 0
+    # cost between pixels (Section 5.1): 0 squared 2-norm (this project's
+    # default workload), 1 the 1-norm, 2 the 2-norm, 3 the inf-norm of the
+    # integer offset (see ``costs``)
+    cost_kind: int = 0
 
 
 @dataclass
@@ -145,6 +149,36 @@ def sq_costs(xs, xt, rows, cols):
     """Integer squared Euclidean cost of the variables (rows[k], cols[k])."""
     d = xs[rows].astype(np.int64) - xt[cols].astype(np.int64)
     return (d * d).sum(axis=1)
+
+
+def costs(xs, xt, rows, cols, kind=0):
+    """C_ij of the variables (rows[k], cols[k]) for a cost kind of Section 5.1,
+    from the integer offset d = x_i - x'_j: 0 |d|_2^2, 1 |d|_1, 2 |d|_2 (the
+    correctly rounded square root of the exact integer |d|_2^2), 3 |d|_inf.
+    Returned as doubles (exact for kinds 0, 1, 3)."""
+    d = xs[rows].astype(np.int64) - xt[cols].astype(np.int64)
+    if kind == 0:
+        return (d * d).sum(axis=1).astype(np.float64)
+    if kind == 1:
+        return np.abs(d).sum(axis=1).astype(np.float64)
+    if kind == 2:
+        return np.sqrt((d * d).sum(axis=1).astype(np.float64))
+    if kind == 3:
+        return np.abs(d).max(axis=1).astype(np.float64)
+    raise ValueError("cost kind must be 0, 1, 2 or 3")
+
+
+def cost_span(xs, xt, kind=0):
+    """Largest integer cost key over all pairs' bounding box: the cost itself
+    for kinds 0, 1, 3 and the squared norm for kind 2 (its square root is
+    increasing, so thresholds on it select the same sets)."""
+    span = np.maximum(xs.max(0).astype(np.int64), xt.max(0).astype(np.int64)) - \
+        np.minimum(xs.min(0).astype(np.int64), xt.min(0).astype(np.int64))
+    if kind == 1:
+        return int(span.sum())
+    if kind == 3:
+        return int(span.max())
+    return int((span * span).sum())
 
 
 def A_apply(vals, rows, cols, m, n):
@@ -302,21 +336,20 @@ def pcg(S, b, tol, maxit, prec, atol=math.inf):
 # The method
 # ---------------------------------------------------------------------------
 
-def initial_support(xs, xt, kappa):
+def initial_support(xs, xt, kappa, kind=0):
     """Section 3.2 (end): the variables of small cost, about kappa*(m+n-1) of
     them -- all (i, j) with c_ij <= T for the smallest integer T reaching that
     count -- plus the cheapest target of every source and the cheapest source of
-    every target so that every row and column of the plan is covered."""
+    every target so that every row and column of the plan is covered.  For the
+    2-norm the threshold is on the squared norm (the same sets)."""
     m, n = xs.shape[0], xt.shape[0]
     target = int(math.ceil(kappa * (m + n - 1)))
-    span = np.maximum(xs.max(0).astype(np.int64), xt.max(0).astype(np.int64)) - \
-        np.minimum(xs.min(0).astype(np.int64), xt.min(0).astype(np.int64))
-    cmax = int((span * span).sum())
-    hist = _cscan.cost_hist(xs, xt, cmax)
+    cmax = cost_span(xs, xt, kind)
+    hist = _cscan.cost_hist(xs, xt, cmax, kind)
     cum = np.cumsum(hist)
     T = int(np.searchsorted(cum, min(target, m * n)))
-    base = _cscan.collect_le(xs, xt, T, int(cum[T]))
-    ra, ca = _cscan.row_col_argmin(xs, xt)
+    base = _cscan.collect_le(xs, xt, T, int(cum[T]), kind)
+    ra, ca = _cscan.row_col_argmin(xs, xt, kind)
     extra = np.concatenate([np.arange(m) + ra * m, ca + np.arange(n) * m])
     return np.unique(np.concatenate([base, extra])), T
 
@@ -329,7 +362,7 @@ def _max_step(x, dx):
 
 
 class _State:
-    pass
+    kind = 0  # cost kind (squared Euclidean unless the solve sets another)
 
 
 def _components(rows, cols, m, n):
@@ -422,7 +455,7 @@ def _set_support(st, idx, p, s):
     st.s = s[order]
     st.rows = st.idx % st.m
     st.cols = st.idx // st.m
-    st.c = sq_costs(st.xs, st.xt, st.rows, st.cols).astype(np.float64) * st.zeta
+    st.c = costs(st.xs, st.xt, st.rows, st.cols, st.kind) * st.zeta
     st.psi = st.idx.shape[0]
 
 
@@ -449,11 +482,15 @@ def _polish(st, params):
 
 
 def solve(a, b, xs, xt, params: OracleParams | None = None, log=None) -> OracleResult:
-    """Solve the Kantorovich LP with squared-Euclidean cost between integer
-    coordinates xs (m x 2) and xt (n x 2), marginals a and b (sum a = sum b)."""
+    """Solve the Kantorovich LP with the cost of ``params.cost_kind`` (default
+    squared Euclidean) between integer coordinates xs (m x 2) and xt (n x 2),
+    marginals a and b (sum a = sum b)."""
     P = params or OracleParams()
     t0 = time.perf_counter()
     st = _State()
+    st.kind = int(P.cost_kind)
+    if st.kind not in (0, 1, 2, 3):
+        raise ValueError("cost kind must be 0, 1, 2 or 3")
     st.a = np.asarray(a, np.float64)
     st.b = np.asarray(b, np.float64)
     st.xs = np.ascontiguousarray(xs, np.int32)
@@ -468,9 +505,9 @@ def solve(a, b, xs, xt, params: OracleParams | None = None, log=None) -> OracleR
     # exact power-of-two scaling: p_s = omega p, c_s = zeta c, duals y_s = zeta y
     st.omega, st.zeta = 1.0, 1.0
     if P.scale:
-        span = np.maximum(st.xs.max(0).astype(np.int64), st.xt.max(0).astype(np.int64)) - \
-            np.minimum(st.xs.min(0).astype(np.int64), st.xt.min(0).astype(np.int64))
-        cmax = max(1, int((span * span).sum()))
+        cmax = max(1.0, float(cost_span(st.xs, st.xt, st.kind)))
+        if st.kind == 2:
+            cmax = max(1.0, math.sqrt(cmax))
         st.omega = 2.0 ** round(math.log2(m / st.a.sum()))
         st.zeta = 2.0 ** -math.ceil(math.log2(cmax))
         st.a = st.a * st.omega
@@ -478,7 +515,7 @@ def solve(a, b, xs, xt, params: OracleParams | None = None, log=None) -> OracleR
     f_norm = math.sqrt(float(st.a @ st.a + st.b @ st.b))
     kcap = m if P.enter_cap <= 0 else P.enter_cap
 
-    idx0, _T = initial_support(st.xs, st.xt, P.kappa)
+    idx0, _T = initial_support(st.xs, st.xt, P.kappa, st.kind)
     _set_support(st, idx0, np.ones(idx0.shape[0]), np.ones(idx0.shape[0]))
     _starting_point(st, P)
 
@@ -528,7 +565,7 @@ def _iterate(st, P, tol_int, it, mode, psi_hist, hist, cg_total, direct_its, max
         # 2. stop test, then the a-posteriori pricing check
         if max(rel1, rel2, relmu) < tol_int:
             sel, rsel, _ = _cscan.price(st.xs, st.xt, st.y / st.zeta, st.z / st.zeta,
-                                        st.idx, kcap)
+                                        st.idx, kcap, st.kind)
             big = np.abs(rsel * st.zeta) * st.a.sum() > P.cert_rel * max(1.0, abs(prim))
             if not big.any():
                 return "optimal", it + 1, cg_failed, mode, cg_total, direct_its, max_fill
@@ -609,7 +646,7 @@ def _iterate(st, P, tol_int, it, mode, psi_hist, hist, cg_total, direct_its, max
         mu_new = float(st.p @ st.s) / st.psi
         # 5. pricing and support update
         sel, rsel, nneg = _cscan.price(st.xs, st.xt, st.y / st.zeta, st.z / st.zeta,
-                                       st.idx, kcap)
+                                       st.idx, kcap, st.kind)
         keep = np.ones(st.psi, dtype=bool)
         if max(rel1, rel2) <= P.remove_gate:
             thr = P.remove_rel * np.minimum(st.a[st.rows], st.b[st.cols])
@@ -659,8 +696,8 @@ def _finalize(st, P, status, it, cg_total, direct_its, max_fill, hist, t0):
         if predrop:
             keep &= pu >= P.drop_rel * np.minimum(a[st.rows], b[st.cols])
         rows, cols, flows = purify_to_forest(st.rows[keep], st.cols[keep], pu[keep],
-                                             sq_costs(st.xs, st.xt, st.rows[keep],
-                                                      st.cols[keep]), m, n)
+                                             costs(st.xs, st.xt, st.rows[keep],
+                                                   st.cols[keep], st.kind), m, n)
         # the forest's flows as the marginals determine them, kept only if
         # they stay nonnegative
         big = flows >= P.drop_rel * np.minimum(a[rows], b[cols])
@@ -670,12 +707,12 @@ def _finalize(st, P, status, it, cg_total, direct_its, max_fill, hist, t0):
             break
     order = np.argsort(rows + cols * m, kind="stable")
     rows, cols, flows = rows[order], cols[order], flows[order]
-    costs = sq_costs(st.xs, st.xt, rows, cols).astype(np.float64)
-    objective = math.fsum((costs * flows).tolist())
+    cvals = costs(st.xs, st.xt, rows, cols, st.kind)
+    objective = math.fsum((cvals * flows).tolist())
     suma = a.sum()
 
     def bound(yv, zv):
-        rm, _ = _cscan.rmin(st.xs, st.xt, yv, zv)
+        rm, _ = _cscan.rmin(st.xs, st.xt, yv, zv, st.kind)
         return math.fsum((a * yv).tolist()) + math.fsum((b * zv).tolist()) + suma * min(0.0, rm), rm
 
     # gauge: z_{n-1} = 0 (adding t to y and -t to z leaves c - A^T y unchanged)
@@ -686,7 +723,7 @@ def _finalize(st, P, status, it, cg_total, direct_its, max_fill, hist, t0):
     # dual recovery after termination (Section 3.3): duals of the basic plan,
     # y_i + z_j = C_ij on its forest edges, each tree anchored at the
     # interior-point dual of its smallest node; kept if their bound is stronger
-    yb, zb = basis_duals(rows, cols, costs, y, z, m, n)
+    yb, zb = basis_duals(rows, cols, cvals, y, z, m, n)
     dual_b, r_min_b = bound(yb, zb)
     if dual_b > dual:
         y, z, dual, r_min = yb, zb, dual_b, r_min_b

@@ -21,7 +21,7 @@ The steps are written plainly:
    back to row node i.  Along the cycle "e, path" the signs alternate: raising
    the flow on e by t lowers the 1st, 3rd, ... path edges and raises the 2nd,
    4th, ... ones by t.  The cost changes by t * (c_e + sum c_plus - sum c_minus),
-   an exact integer for integer costs.
+   an exact integer for integer costs (a correctly rounded sum otherwise).
 3. If that change is <= 0 push t > 0 ("+" direction, also on a tie), else push
    in the "-" direction; t is the smallest flow among the edges that decrease
    (ties: lowest variable index).  That bottleneck edge is set to exactly 0 and
@@ -29,6 +29,7 @@ The steps are written plainly:
 """
 from __future__ import annotations
 
+import math
 from collections import deque
 
 import numpy as np
@@ -90,12 +91,13 @@ def purify_to_forest(rows, cols, flows, costs, m, n):
     """Cancel every cycle of the plan's support; returns (rows, cols, flows).
 
     rows, cols: int arrays (0-based source / target of each edge), flows >= 0,
-    costs: the integer cost of each edge.  Edges with zero flow are dropped.
+    costs: the cost of each edge (doubles, exact for integer costs).  Edges with
+    zero flow are dropped.
     """
     rows = np.asarray(rows, np.int64)
     cols = np.asarray(cols, np.int64)
     flows = np.asarray(flows, np.float64).copy()
-    costs = np.asarray(costs, np.int64)
+    costs = np.asarray(costs, np.float64)
     keep = flows > 0.0
     rows, cols, flows, costs = rows[keep], cols[keep], flows[keep], costs[keep]
     E = flows.shape[0]
@@ -122,7 +124,7 @@ def purify_to_forest(rows, cols, flows, costs, m, n):
         path = _forest_path(adj, v, u)
         minus = path[0::2]
         plus = path[1::2]
-        dcost = cs[e] + sum(cs[k] for k in plus) - sum(cs[k] for k in minus)
+        dcost = math.fsum([cs[e]] + [cs[k] for k in plus] + [-cs[k] for k in minus])
         if dcost <= 0:
             dec, inc = minus, [e] + plus
         else:

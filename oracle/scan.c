@@ -8,25 +8,46 @@
  *
  * Everything here is a direct, unblocked loop over the variables in the
  * paper's vec order (variable index idx = i + j*m, i the source, j the target;
- * Section 2.1 and the index map of Section 3.4, read 0-based).  Costs are the
- * integer squared Euclidean distance between integer pixel coordinates
- * (Section 5.1 uses pixel offsets; the squared 2-norm is this project's
- * workload), computed exactly in 64-bit integers and converted to double.
+ * Section 2.1 and the index map of Section 3.4, read 0-based).  Costs are
+ * norms of the integer offset (d0, d1) between pixel coordinates (Section 5.1
+ * uses the 1-, 2- and inf-norm; the squared 2-norm is this project's default
+ * workload), by `kind`:
+ *   0  d0^2 + d1^2            (exact in 64-bit integers, then double)
+ *   1  |d0| + |d1|            (exact)
+ *   2  sqrt(d0^2 + d1^2)      (IEEE square root, correctly rounded, of the
+ *                              exact integer)
+ *   3  max(|d0|, |d1|)        (exact)
  *
  * The reduced cost of variable (i, j) is evaluated as ((double)c_ij - y_i) - z_j,
  * i.e. c - A^T y with the two dual blocks subtracted in that order
  * (Section 3.4).  Build with -O2 -ffp-contract=off and no fast-math so that
  * this is exactly two IEEE-754 double subtractions.
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
-static inline int64_t sq_cost(const int32_t *xs, const int32_t *xt, int64_t i, int64_t j)
+static inline int64_t iabs64(int64_t v) { return v < 0 ? -v : v; }
+
+/* The integer that orders the costs of a kind: the cost itself for kinds 0,
+ * 1 and 3, the squared norm for kind 2 (the square root is increasing).  The
+ * initial support's thresholds and cheapest entries are taken on it. */
+static inline int64_t cost_key(const int32_t *xs, const int32_t *xt, int64_t i, int64_t j,
+                               int kind)
 {
     int64_t d0 = (int64_t)xs[2 * i] - (int64_t)xt[2 * j];
     int64_t d1 = (int64_t)xs[2 * i + 1] - (int64_t)xt[2 * j + 1];
+    if (kind == 1) return iabs64(d0) + iabs64(d1);
+    if (kind == 3) return iabs64(d0) > iabs64(d1) ? iabs64(d0) : iabs64(d1);
     return d0 * d0 + d1 * d1;
+}
+
+/* The cost C_ij as a double. */
+static inline double cost_d(const int32_t *xs, const int32_t *xt, int64_t i, int64_t j, int kind)
+{
+    int64_t q = cost_key(xs, xt, i, j, kind);
+    return kind == 2 ? sqrt((double)q) : (double)q;
 }
 
 /* ---- bounded max-heap keyed by (r, idx), keeps the kmax smallest keys ---- */
@@ -79,7 +100,7 @@ static int cmp_key(const void *a, const void *b)
  */
 int64_t orc_price(int64_t m, int64_t n, const int32_t *xs, const int32_t *xt,
                   const double *y, const double *z, const int64_t *sup, int64_t psi,
-                  int64_t kmax, int64_t *out_idx, double *out_r, int64_t *n_neg)
+                  int64_t kmax, int64_t *out_idx, double *out_r, int64_t *n_neg, int kind)
 {
     key_t_ *h = NULL;
     int64_t hn = 0, neg = 0, sp = 0;
@@ -92,7 +113,7 @@ int64_t orc_price(int64_t m, int64_t n, const int32_t *xs, const int32_t *xt,
             int64_t idx = i + j * m;
             while (sp < psi && sup[sp] < idx) ++sp;
             if (sp < psi && sup[sp] == idx) continue;
-            double c = (double)sq_cost(xs, xt, i, j);
+            double c = cost_d(xs, xt, i, j, kind);
             double r = (c - y[i]) - z[j];
             if (!(r < 0.0)) continue;
             ++neg;
@@ -121,39 +142,39 @@ int64_t orc_price(int64_t m, int64_t n, const int32_t *xs, const int32_t *xt,
  * s_hat = c - A^T y_hat (Section 3.3).
  */
 double orc_rmin(int64_t m, int64_t n, const int32_t *xs, const int32_t *xt,
-                const double *y, const double *z, int64_t *argmin)
+                const double *y, const double *z, int64_t *argmin, int kind)
 {
     double best = 0.0;
     int64_t arg = -1;
     for (int64_t j = 0; j < n; ++j)
         for (int64_t i = 0; i < m; ++i) {
-            double r = ((double)sq_cost(xs, xt, i, j) - y[i]) - z[j];
+            double r = (cost_d(xs, xt, i, j, kind) - y[i]) - z[j];
             if (arg < 0 || r < best) { best = r; arg = i + j * m; }
         }
     if (argmin) *argmin = arg;
     return best;
 }
 
-/* Histogram of the integer costs c_ij <= cmax over all variables. */
+/* Histogram of the integer cost keys <= cmax over all variables. */
 void orc_cost_hist(int64_t m, int64_t n, const int32_t *xs, const int32_t *xt,
-                   int64_t cmax, int64_t *hist)
+                   int64_t cmax, int64_t *hist, int kind)
 {
     memset(hist, 0, sizeof(int64_t) * (size_t)(cmax + 1));
     for (int64_t j = 0; j < n; ++j)
         for (int64_t i = 0; i < m; ++i) {
-            int64_t c = sq_cost(xs, xt, i, j);
+            int64_t c = cost_key(xs, xt, i, j, kind);
             if (c <= cmax) hist[c]++;
         }
 }
 
-/* All variable indices with c_ij <= T, ascending; returns the count (capped). */
+/* All variable indices with cost key <= T, ascending; returns the count (capped). */
 int64_t orc_collect_le(int64_t m, int64_t n, const int32_t *xs, const int32_t *xt,
-                       int64_t T, int64_t *out_idx, int64_t cap)
+                       int64_t T, int64_t *out_idx, int64_t cap, int kind)
 {
     int64_t k = 0;
     for (int64_t j = 0; j < n; ++j)
         for (int64_t i = 0; i < m; ++i)
-            if (sq_cost(xs, xt, i, j) <= T) {
+            if (cost_key(xs, xt, i, j, kind) <= T) {
                 if (k < cap) out_idx[k] = i + j * m;
                 ++k;
             }
@@ -163,12 +184,12 @@ int64_t orc_collect_le(int64_t m, int64_t n, const int32_t *xs, const int32_t *x
 /* For every source i the target of least cost (ties: smallest j), and for
  * every target j the source of least cost (ties: smallest i). */
 void orc_row_col_argmin(int64_t m, int64_t n, const int32_t *xs, const int32_t *xt,
-                        int64_t *row_arg, int64_t *col_arg)
+                        int64_t *row_arg, int64_t *col_arg, int kind)
 {
     for (int64_t i = 0; i < m; ++i) {
         int64_t best = -1, arg = -1;
         for (int64_t j = 0; j < n; ++j) {
-            int64_t c = sq_cost(xs, xt, i, j);
+            int64_t c = cost_key(xs, xt, i, j, kind);
             if (arg < 0 || c < best) { best = c; arg = j; }
         }
         row_arg[i] = arg;
@@ -176,7 +197,7 @@ void orc_row_col_argmin(int64_t m, int64_t n, const int32_t *xs, const int32_t *
     for (int64_t j = 0; j < n; ++j) {
         int64_t best = -1, arg = -1;
         for (int64_t i = 0; i < m; ++i) {
-            int64_t c = sq_cost(xs, xt, i, j);
+            int64_t c = cost_key(xs, xt, i, j, kind);
             if (arg < 0 || c < best) { best = c; arg = i; }
         }
         col_arg[j] = arg;
