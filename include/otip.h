@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define OTIP_ABI_VERSION 2
+#define OTIP_ABI_VERSION 3
 
 enum otip_status {
     OTIP_OK = 0,
@@ -50,6 +50,17 @@ enum otip_status {
 
 enum otip_linear_solver { OTIP_LS_AUTO = 0, OTIP_LS_PCG = 1, OTIP_LS_DIRECT = 2 };
 enum otip_precision { OTIP_FP64 = 0, OTIP_MIXED = 1 };
+
+/* Cost C_ij between integer pixel coordinates, from the offset d = x_i - x'_j
+ * (Section 5.1 compares the 1-, 2- and inf-norms; the squared 2-norm is the
+ * default).  Every cost is evaluated exactly, except the 2-norm, which is the
+ * correctly rounded square root of the exact integer d0^2 + d1^2. */
+enum otip_cost {
+    OTIP_COST_SQEUCLID = 0, /* d0^2 + d1^2 */
+    OTIP_COST_L1 = 1,       /* |d0| + |d1| */
+    OTIP_COST_L2 = 2,       /* sqrt(d0^2 + d1^2) */
+    OTIP_COST_LINF = 3      /* max(|d0|, |d1|) */
+};
 
 /*
  * Solver parameters.  Defaults (otip_params_default) are the paper's values
@@ -111,7 +122,8 @@ typedef struct otip_params {
  *   y0, z0: optional predicted duals (m and n doubles, cost units) or both NULL.
  *        When given, the initial support is built from them instead of from
  *        the costs alone (a warm start); the method and its certificate are
- *        unchanged.  Non-finite values fall back to the plain initial support. */
+ *        unchanged.  Non-finite values fall back to the plain initial support.
+ *   cost_kind: otip_cost (0, the squared 2-norm, in a zero-initialised struct). */
 typedef struct otip_problem {
     int32_t m;
     int32_t n;
@@ -121,6 +133,7 @@ typedef struct otip_problem {
     const int32_t *xt;
     const double *y0;
     const double *z0;
+    int32_t cost_kind; /* otip_cost; any other value is OTIP_EINVAL */
 } otip_problem;
 
 /* Summary of a solve (Section 5.3 reports iterations, time, CG iterations,
@@ -215,27 +228,30 @@ void otip_result_free(otip_result *r);
 
 /*
  * Pricing scan (Sections 3.2 and 3.4): over all variables NOT in the support,
- * the reduced costs r_ij = ((double)C_ij - y_i) - z_j (two IEEE double
- * subtractions in this order); the at most kmax strictly negative ones, ordered
- * by (r, i + j*m) ascending, are returned.
+ * the reduced costs r_ij = (C_ij - y_i) - z_j (two IEEE double subtractions in
+ * this order, C_ij the double of otip_cost cost_kind); the at most kmax
+ * strictly negative ones, ordered by (r, i + j*m) ascending, are returned.
  *   xs, xt, y (m), z (n): DEVICE.  support_bitmap: DEVICE, ceil(m*n/32) words,
  *   bit (idx & 31) of word idx >> 5 set for variables in the support; NULL for
  *   an empty support.  out_i, out_j (int32), out_r (double): DEVICE, kmax
  *   entries.  out_count (selected) and out_nneg (all negative reduced costs
  *   outside the support): HOST.
  *   precision: OTIP_FP64, or OTIP_MIXED (FP32 scan with an FP64 re-check of
- *   every candidate within a proven margin; same result).
+ *   every candidate within a proven margin; same result).  The FP32 scan is
+ *   written for the squared cost: the other kinds take the FP64 scan.
  *   tile: targets per workgroup (as otip_params.price_tile; 0 = by size).
  */
 int otip_price(otip_ctx *ctx, int32_t m, int32_t n, const int32_t *xs, const int32_t *xt,
                const double *y, const double *z, const uint32_t *support_bitmap, int64_t kmax,
-               int32_t precision, int32_t tile, int32_t *out_i, int32_t *out_j, double *out_r,
-               int64_t *out_count, int64_t *out_nneg);
+               int32_t precision, int32_t tile, int32_t cost_kind, int32_t *out_i,
+               int32_t *out_j, double *out_r, int64_t *out_count, int64_t *out_nneg);
 
-/* min over ALL (i, j) of ((double)C_ij - y_i) - z_j and the first variable index
- * attaining it (Section 3.3: s_hat = c - A^T y_hat).  Outputs are HOST. */
+/* min over ALL (i, j) of (C_ij - y_i) - z_j (C_ij of otip_cost cost_kind) and
+ * the first variable index attaining it (Section 3.3: s_hat = c - A^T y_hat).
+ * Outputs are HOST. */
 int otip_rmin(otip_ctx *ctx, int32_t m, int32_t n, const int32_t *xs, const int32_t *xt,
-              const double *y, const double *z, double *out_rmin, int64_t *out_arg);
+              const double *y, const double *z, int32_t cost_kind, double *out_rmin,
+              int64_t *out_arg);
 
 /*
  * Matrix-free Kronecker products of Section 2.1 on a dense m x n array X

@@ -18,7 +18,8 @@ import numpy as np
 from . import _abi
 from ._abi import (OTIP_OK, OTIP_EINVAL, OTIP_ENOMEM, OTIP_EHIP, OTIP_ENUMERIC, OTIP_EUNSUPPORTED,  # noqa: F401
                    OTIP_EMAXITER, OTIP_FP64, OTIP_MIXED, OTIP_LS_AUTO, OTIP_LS_PCG,  # noqa: F401
-                   OTIP_LS_DIRECT, otip_params, otip_problem, otip_info)
+                   OTIP_LS_DIRECT, OTIP_COST_SQEUCLID, OTIP_COST_L1, OTIP_COST_L2,  # noqa: F401
+                   OTIP_COST_LINF, otip_params, otip_problem, otip_info)
 
 __all__ = ["otip_version", "otip_params_default", "Context", "OtipError", "SolveResult",
            "otip_solve", "otip_solve_batch", "otip_price", "otip_rmin", "otip_kron_apply",
@@ -120,7 +121,7 @@ class SolveResult:
         raise AttributeError(k)
 
 
-def _problem(ctx, a, b, xs, xt, y0=None, z0=None):
+def _problem(ctx, a, b, xs, xt, y0=None, z0=None, cost_kind=0):
     torch = _torch()
     A = _dev(a, torch.float64, ctx.device)
     B = _dev(b, torch.float64, ctx.device)
@@ -131,7 +132,7 @@ def _problem(ctx, a, b, xs, xt, y0=None, z0=None):
     pr = otip_problem(int(A.shape[0]), int(B.shape[0]), A.data_ptr(), B.data_ptr(),
                       XS.data_ptr(), XT.data_ptr(),
                       Y0.data_ptr() if Y0 is not None else None,
-                      Z0.data_ptr() if Z0 is not None else None)
+                      Z0.data_ptr() if Z0 is not None else None, int(cost_kind))
     return pr, (A, B, XS, XT, Y0, Z0)
 
 
@@ -148,10 +149,10 @@ def _collect(ctx, res_handle, rc):
 
 
 def otip_solve(ctx: Context, a, b, xs, xt, prm: otip_params | None = None, y0=None,
-               z0=None) -> SolveResult:
+               z0=None, cost_kind: int = OTIP_COST_SQEUCLID) -> SolveResult:
     """Solve one problem; a, b, xs, xt (and the optional warm-start duals y0,
-    z0) may be numpy arrays or torch tensors."""
-    pr, keep = _problem(ctx, a, b, xs, xt, y0, z0)
+    z0) may be numpy arrays or torch tensors; cost_kind is an OTIP_COST_*."""
+    pr, keep = _problem(ctx, a, b, xs, xt, y0, z0, cost_kind)
     h = ctypes.c_void_p()
     rc = ctx._lib.otip_solve(ctx.handle, ctypes.byref(pr),
                              ctypes.byref(prm) if prm is not None else None, ctypes.byref(h))
@@ -168,13 +169,15 @@ def otip_solve(ctx: Context, a, b, xs, xt, prm: otip_params | None = None, y0=No
     return SolveResult(rc, d, rows, cols, vals, y, z)
 
 
-def otip_solve_batch(ctx: Context, problems, prm: otip_params | None = None):
-    """Solve a list of (a, b, xs, xt) or (a, b, xs, xt, y0, z0) problems;
-    returns a list of SolveResult in the same order."""
+def otip_solve_batch(ctx: Context, problems, prm: otip_params | None = None,
+                     cost_kind: int = OTIP_COST_SQEUCLID):
+    """Solve a list of (a, b, xs, xt) or (a, b, xs, xt, y0, z0) problems, all
+    with the cost cost_kind; returns a list of SolveResult in the same order."""
     prs = (otip_problem * len(problems))()
     keep = []
     for k, prob in enumerate(problems):
-        pr, kk = _problem(ctx, *prob)
+        prob = tuple(prob) + (None,) * (6 - len(prob))
+        pr, kk = _problem(ctx, *prob, cost_kind=cost_kind)
         prs[k] = pr
         keep.append(kk)
     outs = (ctypes.c_void_p * len(problems))()
@@ -195,7 +198,7 @@ def otip_solve_batch(ctx: Context, problems, prm: otip_params | None = None):
 
 
 def otip_price(ctx: Context, xs, xt, y, z, bitmap, kmax: int, precision: int = OTIP_FP64,
-               tile: int = 0):
+               tile: int = 0, cost_kind: int = OTIP_COST_SQEUCLID):
     """Pricing scan; returns (i, j, r) device tensors of the selected columns and
     the count of negative reduced costs outside the support."""
     torch = _torch()
@@ -210,19 +213,21 @@ def otip_price(ctx: Context, xs, xt, y, z, bitmap, kmax: int, precision: int = O
     cnt, nneg = ctypes.c_int64(), ctypes.c_int64()
     ctx.check(ctx._lib.otip_price(ctx.handle, m, n, _ptr(XS), _ptr(XT), _ptr(Y), _ptr(Z),
                                   _ptr(BM) if BM is not None else None, int(kmax), precision,
-                                  int(tile), _ptr(oi), _ptr(oj), _ptr(orr), ctypes.byref(cnt),
+                                  int(tile), int(cost_kind), _ptr(oi), _ptr(oj), _ptr(orr),
+                                  ctypes.byref(cnt),
                                   ctypes.byref(nneg)))
     c = int(cnt.value)
     return oi[:c], oj[:c], orr[:c], int(nneg.value)
 
 
-def otip_rmin(ctx: Context, xs, xt, y, z):
+def otip_rmin(ctx: Context, xs, xt, y, z, cost_kind: int = OTIP_COST_SQEUCLID):
     torch = _torch()
     XS, XT = _dev(xs, torch.int32, ctx.device), _dev(xt, torch.int32, ctx.device)
     Y, Z = _dev(y, torch.float64, ctx.device), _dev(z, torch.float64, ctx.device)
     v, arg = ctypes.c_double(), ctypes.c_int64()
     ctx.check(ctx._lib.otip_rmin(ctx.handle, int(XS.shape[0]), int(XT.shape[0]), _ptr(XS),
-                                 _ptr(XT), _ptr(Y), _ptr(Z), ctypes.byref(v), ctypes.byref(arg)))
+                                 _ptr(XT), _ptr(Y), _ptr(Z), int(cost_kind), ctypes.byref(v),
+                                 ctypes.byref(arg)))
     return float(v.value), int(arg.value)
 
 

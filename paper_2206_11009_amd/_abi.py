@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libotip.so")
 OTIP_OK, OTIP_EINVAL, OTIP_ENOMEM, OTIP_EHIP, OTIP_EMAXITER, OTIP_ENUMERIC, OTIP_EUNSUPPORTED = range(7)
 OTIP_LS_AUTO, OTIP_LS_PCG, OTIP_LS_DIRECT = 0, 1, 2
 OTIP_FP64, OTIP_MIXED = 0, 1
+OTIP_COST_SQEUCLID, OTIP_COST_L1, OTIP_COST_L2, OTIP_COST_LINF = 0, 1, 2, 3
 
 _c_i32, _c_i64, _c_f64, _p = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
 
@@ -39,7 +40,7 @@ class otip_params(ctypes.Structure):
 
 class otip_problem(ctypes.Structure):
     _fields_ = [("m", _c_i32), ("n", _c_i32), ("a", _p), ("b", _p), ("xs", _p), ("xt", _p),
-                ("y0", _p), ("z0", _p)]
+                ("y0", _p), ("z0", _p), ("cost_kind", _c_i32)]
 
 
 class otip_info(ctypes.Structure):
@@ -74,8 +75,9 @@ SIGNATURES = {
     "otip_result_copy": (ctypes.c_int, [_p, _p, _p, _p, _p, _p]),
     "otip_result_free": (None, [_p]),
     "otip_price": (ctypes.c_int, [_p, _c_i32, _c_i32, _p, _p, _p, _p, _p, _c_i64, _c_i32, _c_i32,
-                                  _p, _p, _p, ctypes.POINTER(_c_i64), ctypes.POINTER(_c_i64)]),
-    "otip_rmin": (ctypes.c_int, [_p, _c_i32, _c_i32, _p, _p, _p, _p,
+                                  _c_i32, _p, _p, _p, ctypes.POINTER(_c_i64),
+                                  ctypes.POINTER(_c_i64)]),
+    "otip_rmin": (ctypes.c_int, [_p, _c_i32, _c_i32, _p, _p, _p, _p, _c_i32,
                                  ctypes.POINTER(_c_f64), ctypes.POINTER(_c_i64)]),
     "otip_kron_apply": (ctypes.c_int, [_p, _c_i32, _c_i32, _p, _p, _p]),
     "otip_kron_apply_t": (ctypes.c_int, [_p, _c_i32, _c_i32, _p, _p, _p]),

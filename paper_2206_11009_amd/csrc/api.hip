@@ -372,12 +372,15 @@ void otip_result_free(otip_result *r) { delete r; }
 
 int otip_price(otip_ctx *ctx, int32_t m, int32_t n, const int32_t *xs, const int32_t *xt,
                const double *y, const double *z, const uint32_t *support_bitmap, int64_t kmax,
-               int32_t precision, int32_t tile, int32_t *out_i, int32_t *out_j, double *out_r,
-               int64_t *out_count, int64_t *out_nneg) {
+               int32_t precision, int32_t tile, int32_t cost_kind, int32_t *out_i,
+               int32_t *out_j, double *out_r, int64_t *out_count, int64_t *out_nneg) {
     return guarded(ctx, [&] {
         ctx->scan.tile = tile;
         OTIP_CHECK(m >= 1 && n >= 1 && xs && xt && y && z && kmax >= 0, OTIP_EINVAL,
                    "otip_price: bad arguments");
+        OTIP_CHECK(cost_kind >= OTIP_COST_SQEUCLID && cost_kind <= OTIP_COST_LINF, OTIP_EINVAL,
+                   "otip_price: unknown cost kind");
+        ctx->scan.kind = cost_kind;
         OTIP_CHECK(kmax == 0 || (out_i && out_j && out_r), OTIP_EINVAL,
                    "otip_price: null outputs");
         otip::PriceResult pr;
@@ -394,10 +397,14 @@ int otip_price(otip_ctx *ctx, int32_t m, int32_t n, const int32_t *xs, const int
 }
 
 int otip_rmin(otip_ctx *ctx, int32_t m, int32_t n, const int32_t *xs, const int32_t *xt,
-              const double *y, const double *z, double *out_rmin, int64_t *out_arg) {
+              const double *y, const double *z, int32_t cost_kind, double *out_rmin,
+              int64_t *out_arg) {
     return guarded(ctx, [&] {
         OTIP_CHECK(m >= 1 && n >= 1 && xs && xt && y && z && out_rmin, OTIP_EINVAL,
                    "otip_rmin: bad arguments");
+        OTIP_CHECK(cost_kind >= OTIP_COST_SQEUCLID && cost_kind <= OTIP_COST_LINF, OTIP_EINVAL,
+                   "otip_rmin: unknown cost kind");
+        ctx->scan.kind = cost_kind;
         ctx->scan.rmin(ctx->stream, m, n, xs, xt, y, z, out_rmin, out_arg);
     });
 }

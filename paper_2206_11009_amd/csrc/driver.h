@@ -17,7 +17,7 @@ struct Result {
 
 // Host-side purification of a plan to an acyclic support (purify.cpp).
 void purify_plan(int m, int n, const std::vector<int32_t> &rows, const std::vector<int32_t> &cols,
-                 const std::vector<double> &flows, const std::vector<int64_t> &costs,
+                 const std::vector<double> &flows, const std::vector<double> &costs,
                  const std::vector<double> &a, const std::vector<double> &b, double drop_rel,
                  std::vector<int32_t> &orows, std::vector<int32_t> &ocols,
                  std::vector<double> &oflows);
@@ -90,7 +90,8 @@ class Solver {
 
     int m = 0, n = 0;
     const int32_t *xs = nullptr, *xt = nullptr;
-    int64_t cmax = 0;
+    int kind = 0;      // otip_cost
+    int64_t cmax = 0;  // largest cost key (the squared norm for the 2-norm)
     double omega = 1.0, zeta = 1.0, fnorm = 0.0;
     const double *a_in = nullptr, *b_in = nullptr;
 

@@ -114,21 +114,33 @@ static void foreach(hipStream_t st, int64_t N, F f) {
 }
 
 // =============================================================== support views
+// C_ij of a cost kind (Section 5.1) from the integer offset d = x_i - x_j
+// (|d| <= 2^15: every integer here is an exact double; the 2-norm is the
+// correctly rounded square root of the exact d0^2 + d1^2)
+__host__ __device__ inline double pair_cost(const int32_t *xs, const int32_t *xt, int i, int j,
+                                            int kind) {
+    const int64_t d0 = (int64_t)xs[2 * i] - xt[2 * j], d1 = (int64_t)xs[2 * i + 1] - xt[2 * j + 1];
+    const int64_t a0 = d0 < 0 ? -d0 : d0, a1 = d1 < 0 ? -d1 : d1;
+    if (kind == OTIP_COST_L1) return (double)(a0 + a1);
+    if (kind == OTIP_COST_LINF) return (double)(a0 > a1 ? a0 : a1);
+    const double q = (double)(d0 * d0 + d1 * d1);
+    return kind == OTIP_COST_L2 ? std::sqrt(q) : q;
+}
+
 // idx sorted ascending -> (i, j), scaled costs
 struct FDerive {
     const uint64_t *idx;
     int32_t *si, *sj;
     double *c;
     const int32_t *xs, *xt;
-    int m;
+    int m, kind;
     double zeta;
     __device__ void operator()(int64_t k) const {
         const uint64_t v = idx[k];
         const int i = (int)(v % (uint64_t)m), j = (int)(v / (uint64_t)m);
         si[k] = i;
         sj[k] = j;
-        const int64_t d0 = (int64_t)xs[2 * i] - xt[2 * j], d1 = (int64_t)xs[2 * i + 1] - xt[2 * j + 1];
-        c[k] = (double)(d0 * d0 + d1 * d1) * zeta;
+        c[k] = pair_cost(xs, xt, i, j, kind) * zeta;
     }
 };
 
@@ -171,7 +183,7 @@ struct FBits {
 
 void Solver::rebuild_views() {
     const int64_t psi = psi_;
-    foreach(st, psi, FDerive{idx.get(), si.get(), sj.get(), c.get(), xs, xt, m, zeta});
+    foreach(st, psi, FDerive{idx.get(), si.get(), sj.get(), c.get(), xs, xt, m, kind, zeta});
     col_ptr.need((size_t)n + 1);
     foreach(st, (int64_t)n + 1, FLowerBound{sj.get(), psi, col_ptr.get()});
     // compressed-row view: stable sort of positions by source
@@ -635,7 +647,7 @@ int Solver::run_without_zeros(const otip_problem &pr, const otip_params &prm, Re
     OTIP_HIP(hipMemcpyAsync(dy, cy.data(), sizeof(double) * cy.size(), hipMemcpyHostToDevice, st));
     OTIP_HIP(hipMemcpyAsync(dx, cx.data(), sizeof(int32_t) * cx.size(), hipMemcpyHostToDevice, st));
     otip_problem sub{mk, nk, dm, dm + mk, dx, dx + 2 * (size_t)mk,
-                     hy0.empty() ? nullptr : dy, hz0.empty() ? nullptr : dy + mk};
+                     hy0.empty() ? nullptr : dy, hz0.empty() ? nullptr : dy + mk, pr.cost_kind};
     Result r;
     const int status = run(sub, prm, r);  // no zero masses left: no further recursion
     res.info = r.info;
@@ -815,6 +827,10 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
     b_in = pr.b;
     OTIP_CHECK(m >= 1 && n >= 1, OTIP_EINVAL, "m and n must be >= 1");
     OTIP_CHECK(pr.a && pr.b && pr.xs && pr.xt, OTIP_EINVAL, "null problem array");
+    OTIP_CHECK(pr.cost_kind >= OTIP_COST_SQEUCLID && pr.cost_kind <= OTIP_COST_LINF, OTIP_EINVAL,
+               "unknown cost kind");
+    kind = pr.cost_kind;
+    scan.kind = kind;
     // ---- validation on the device data (masses > 0, balanced)
     double sa, sb, mina, minb, bad, zeros;
     {
@@ -860,6 +876,7 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
         };
         mix(&m, sizeof m);
         mix(&n, sizeof n);
+        mix(&kind, sizeof kind);
         mix(ha.data(), sizeof(double) * m);
         mix(hb.data(), sizeof(double) * n);
         mix(hx.data(), sizeof(int32_t) * 2 * m);
@@ -878,13 +895,19 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
         for (int d = 0; d < 2; ++d)
             OTIP_CHECK(lo[d] >= -(1 << 14) && hi[d] <= (1 << 14), OTIP_EINVAL,
                        "coordinates must lie in [-2^14, 2^14]");
-        cmax = (hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]);
+        const int64_t w0 = hi[0] - lo[0], w1 = hi[1] - lo[1];
+        cmax = kind == OTIP_COST_L1     ? w0 + w1
+               : kind == OTIP_COST_LINF ? std::max(w0, w1)
+                                        : w0 * w0 + w1 * w1;
     }
     omega = 1.0;
     zeta = 1.0;
     if (P.scale) {
+        // the largest cost bounds the scale: for the 2-norm the root of its key
+        double cm = (double)std::max<int64_t>(1, cmax);
+        if (kind == OTIP_COST_L2) cm = std::sqrt(cm);
         omega = std::ldexp(1.0, (int)std::lround(std::log2((double)m / sa)));
-        zeta = std::ldexp(1.0, -(int)std::ceil(std::log2((double)std::max<int64_t>(1, cmax))));
+        zeta = std::ldexp(1.0, -(int)std::ceil(std::log2(cm)));
     }
     a.need(m);
     b.need(n);
@@ -1354,11 +1377,8 @@ void Solver::finalize(Result &res) {
     OTIP_HIP(hipMemcpyAsync(p.get(), pkeep, sizeof(double) * psi_, hipMemcpyDeviceToDevice, st));
     std::vector<int32_t> rows(psi), cols(psi);
     std::vector<double> flows(psi);
-    std::vector<int64_t> costs(psi);
-    auto icost = [&](int i, int j) {
-        const int64_t d0 = (int64_t)hxs[2 * i] - hxt[2 * j], d1 = (int64_t)hxs[2 * i + 1] - hxt[2 * j + 1];
-        return d0 * d0 + d1 * d1;
-    };
+    std::vector<double> costs(psi);
+    auto icost = [&](int i, int j) { return pair_cost(hxs.data(), hxt.data(), i, j, kind); };
     for (int64_t k = 0; k < psi; ++k) {
         rows[k] = (int32_t)(hidx[k] % (uint64_t)m);
         cols[k] = (int32_t)(hidx[k] / (uint64_t)m);
@@ -1385,7 +1405,7 @@ void Solver::finalize(Result &res) {
     std::vector<double> terms;
     terms.reserve(res.vals.size());
     for (size_t k = 0; k < res.vals.size(); ++k)
-        terms.push_back((double)icost(res.rows[k], res.cols[k]) * res.vals[k]);
+        terms.push_back(icost(res.rows[k], res.cols[k]) * res.vals[k]);
     const double obj = ksum(terms);
     const double suma = ksum(ha);
     double *yu = yun.need(m), *zu = zun.need(n);
@@ -1427,7 +1447,7 @@ void Solver::finalize(Result &res) {
                 for (auto [v, k] : adj[u])
                     if (!seen[v]) {
                         seen[v] = 1;
-                        pot[v] = (double)icost(res.rows[k], res.cols[k]) - pot[u];
+                        pot[v] = icost(res.rows[k], res.cols[k]) - pot[u];
                         stack.push_back(v);
                     }
             }

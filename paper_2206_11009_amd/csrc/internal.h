@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "../../include/otip.h"
 #include "common.h"
 
 namespace otip {
@@ -40,6 +41,7 @@ class Scanner {
     LaunchTimer *timer = nullptr;  // pricing-pass launches (optional)
     int64_t scans = 0;             // full m*n passes so far
     int tile = 0;                  // targets per scan block (0: chosen from m, n)
+    int kind = 0;                  // otip_cost of every scan
     // <= kmax most negative reduced costs outside the support, ordered by
     // (r, idx); outputs may be null.
     PriceResult price(hipStream_t st, int m, int n, const int32_t *xs, const int32_t *xt,

@@ -69,19 +69,42 @@ struct Forest {
     }
 };
 
+// The sign of an exact sum of doubles, so that the direction taken around a
+// cycle does not depend on rounding (costs such as square roots are not
+// integers).  The terms are accumulated into a nonoverlapping expansion with
+// error-free additions (Knuth's two-sum), the grow-expansion of Shewchuk's
+// adaptive-precision arithmetic with zero components dropped; the largest
+// component of such an expansion has the sign of the sum.
+struct ExactSum {
+    std::vector<double> e;  // increasing magnitude, nonoverlapping
+    void add(double b) {
+        size_t k = 0;
+        for (size_t q = 0; q < e.size(); ++q) {
+            const double s = b + e[q];
+            const double bv = s - b;
+            const double err = (b - (s - bv)) + (e[q] - bv);
+            if (err != 0.0) e[k++] = err;
+            b = s;
+        }
+        e.resize(k);
+        if (b != 0.0) e.push_back(b);
+    }
+    int sign() const { return e.empty() ? 0 : (e.back() > 0.0 ? 1 : -1); }
+};
+
 }  // namespace
 
 // One purification attempt; returns true when the forest flows recomputed from
 // the marginals are nonnegative (an exactly feasible basic plan).
 static bool purify_attempt(int m, int n, const std::vector<int32_t> &rows_in,
                            const std::vector<int32_t> &cols_in, const std::vector<double> &flows_in,
-                           const std::vector<int64_t> &costs_in, const std::vector<double> &a,
+                           const std::vector<double> &costs_in, const std::vector<double> &a,
                            const std::vector<double> &b, double drop_rel, bool predrop,
                            std::vector<int32_t> &orows, std::vector<int32_t> &ocols,
                            std::vector<double> &oflows) {
     std::vector<int32_t> R, C;
     std::vector<double> F;
-    std::vector<int64_t> W;
+    std::vector<double> W;
     // with predrop, numerically-zero flows leave before any cycle is cancelled
     for (size_t k = 0; k < flows_in.size(); ++k)
         if (flows_in[k] > 0.0 &&
@@ -152,10 +175,11 @@ static bool purify_attempt(int m, int n, const std::vector<int32_t> &rows_in,
         std::vector<int> path(up_v.begin(), up_v.end());
         path.insert(path.end(), up_u.rbegin(), up_u.rend());
         // alternate: 1st, 3rd, ... path edges decrease when e increases
-        int64_t dcost = W[e];
-        for (size_t t = 0; t < path.size(); ++t) dcost += (t % 2 == 0) ? -W[path[t]] : W[path[t]];
+        ExactSum dcost;
+        dcost.add(W[e]);
+        for (size_t t = 0; t < path.size(); ++t) dcost.add((t % 2 == 0) ? -W[path[t]] : W[path[t]]);
         std::vector<int> dec, inc;
-        if (dcost <= 0) {
+        if (dcost.sign() <= 0) {
             inc.push_back(e);
             for (size_t t = 0; t < path.size(); ++t) (t % 2 == 0 ? dec : inc).push_back(path[t]);
         } else {
@@ -250,7 +274,7 @@ static bool purify_attempt(int m, int n, const std::vector<int32_t> &rows_in,
 
 void purify_plan(int m, int n, const std::vector<int32_t> &rows_in,
                  const std::vector<int32_t> &cols_in, const std::vector<double> &flows_in,
-                 const std::vector<int64_t> &costs_in, const std::vector<double> &a,
+                 const std::vector<double> &costs_in, const std::vector<double> &a,
                  const std::vector<double> &b, double drop_rel, std::vector<int32_t> &orows,
                  std::vector<int32_t> &ocols, std::vector<double> &oflows) {
     if (purify_attempt(m, n, rows_in, cols_in, flows_in, costs_in, a, b, drop_rel, true, orows,

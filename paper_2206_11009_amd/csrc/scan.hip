@@ -15,7 +15,9 @@
 
 namespace otip {
 
-// Per-target table: B_j = |x_j|^2, -2 x_j0, -2 x_j1 and z_j, all exact doubles.
+// Per-target table, all exact doubles.  Squared cost: B_j = |x_j|^2, a2 =
+// -2 x_j0, b2 = -2 x_j1; the norm costs: B_j = x_j0, a2 = x_j1 (b2 unused).
+// Then z_j.
 struct __align__(32) JEntry {
     double B, a2, b2, z;
 };
@@ -35,15 +37,21 @@ __device__ __forceinline__ JEntry ldj(const JEntry *p, int j) {
     return e;
 }
 
-__global__ void build_jtab(int n, const int32_t *__restrict__ xt, const double *__restrict__ z,
-                           JEntry *__restrict__ jt) {
+__global__ void build_jtab(int n, int kind, const int32_t *__restrict__ xt,
+                           const double *__restrict__ z, JEntry *__restrict__ jt) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     double a = (double)xt[2 * j], b = (double)xt[2 * j + 1];
     JEntry e;
-    e.B = a * a + b * b;
-    e.a2 = -2.0 * a;
-    e.b2 = -2.0 * b;
+    if (kind == OTIP_COST_SQEUCLID) {
+        e.B = a * a + b * b;
+        e.a2 = -2.0 * a;
+        e.b2 = -2.0 * b;
+    } else {
+        e.B = a;
+        e.a2 = b;
+        e.b2 = 0.0;
+    }
     e.z = z ? z[j] : 0.0;
     jt[j] = e;
 }
@@ -69,10 +77,18 @@ __device__ __forceinline__ RowData load_row(int i, int m, const int32_t *__restr
     return d;
 }
 
-// C_ij exactly: |x_i|^2 + |x_j|^2 - 2 x_i.x_j; every intermediate is an integer
-// below 2^53, so the two fused multiply-adds are exact.
+// C_ij of a cost kind (Section 5.1).  Squared: |x_i|^2 + |x_j|^2 - 2 x_i.x_j;
+// every intermediate is an integer below 2^53, so the two fused multiply-adds
+// are exact.  Norms of the offset d = x_i - x_j (|d| <= 2^15): the 1- and
+// inf-norms are exact; for the 2-norm d0^2 + d1^2 <= 2^31 is formed exactly
+// by the fused multiply-add and its IEEE square root is correctly rounded.
+template <int K>
 __device__ __forceinline__ double cost_of(const RowData &r, const JEntry &t) {
-    return fma(r.be, t.b2, fma(r.al, t.a2, r.A + t.B));
+    if (K == OTIP_COST_SQEUCLID) return fma(r.be, t.b2, fma(r.al, t.a2, r.A + t.B));
+    const double d0 = r.al - t.B, d1 = r.be - t.a2;
+    if (K == OTIP_COST_L1) return fabs(d0) + fabs(d1);
+    if (K == OTIP_COST_L2) return __builtin_sqrt(fma(d0, d0, d1 * d1));
+    return fmax(fabs(d0), fabs(d1));
 }
 
 __device__ __forceinline__ bool in_support(const uint32_t *__restrict__ bm, uint64_t idx) {
@@ -185,7 +201,7 @@ __device__ __forceinline__ void price_one(const PriceArgs &a, int i, int j, doub
 // Pricing pass.  MODE 0: histogram of one 12-bit digit of the ordered key of
 // every strictly negative reduced cost outside the support.  MODE 1: append
 // (key, idx) of those with key <= key_max.
-template <int MODE>
+template <int MODE, int K>
 __global__ __launch_bounds__(kScanBlock) void price_pass(PriceArgs a) {
     __shared__ unsigned int lh[MODE == 0 ? kHistBins : 1];
     __shared__ uint64_t sbuf[MODE == 1 ? (kScanBlock / 64) * kStage * 2 : 1];
@@ -206,10 +222,10 @@ __global__ __launch_bounds__(kScanBlock) void price_pass(PriceArgs a) {
     for (; j + 4 <= j1; j += 4) {
         const JEntry t0 = ldj(jt, j), t1 = ldj(jt, j + 1), t2 = ldj(jt, j + 2),
                      t3 = ldj(jt, j + 3);
-        const double r0 = (cost_of(rd, t0) - rd.y) - t0.z;
-        const double r1 = (cost_of(rd, t1) - rd.y) - t1.z;
-        const double r2 = (cost_of(rd, t2) - rd.y) - t2.z;
-        const double r3 = (cost_of(rd, t3) - rd.y) - t3.z;
+        const double r0 = (cost_of<K>(rd, t0) - rd.y) - t0.z;
+        const double r1 = (cost_of<K>(rd, t1) - rd.y) - t1.z;
+        const double r2 = (cost_of<K>(rd, t2) - rd.y) - t2.z;
+        const double r3 = (cost_of<K>(rd, t3) - rd.y) - t3.z;
         const double lo = fmin(fmin(r0, r1), fmin(r2, r3));
         if (__ballot(lo < 0.0 && lo <= a.rcut) == 0ull) continue;
         price_one<MODE>(a, i, j, r0, lh, stg);
@@ -219,7 +235,7 @@ __global__ __launch_bounds__(kScanBlock) void price_pass(PriceArgs a) {
     }
     for (; j < j1; ++j) {
         const JEntry t = ldj(jt, j);
-        const double r = (cost_of(rd, t) - rd.y) - t.z;
+        const double r = (cost_of<K>(rd, t) - rd.y) - t.z;
         price_one<MODE>(a, i, j, r, lh, stg);
     }
     if (MODE == 1) stg.flush();
@@ -253,6 +269,12 @@ static double rcut_of_key(uint64_t k) {
     return std::isnan(d) ? INFINITY : d;
 }
 
+// the instance of a kernel templated on the cost kind
+template <typename Fn>
+static Fn by_kind(int kind, Fn k0, Fn k1, Fn k2, Fn k3) {
+    return kind == OTIP_COST_L1 ? k1 : kind == OTIP_COST_L2 ? k2 : kind == OTIP_COST_LINF ? k3 : k0;
+}
+
 int pick_tj(int m, int n, int tile) {
     if (tile >= 16 && tile <= 256 && (tile & (tile - 1)) == 0) return tile;
     const int64_t rb = (m + 255) / 256;
@@ -263,7 +285,7 @@ int pick_tj(int m, int n, int tile) {
 
 void Scanner::prepare(hipStream_t st, int m, int n, const int32_t *xt, const double *z) {
     jt_.need((size_t)n * sizeof(JEntry));
-    hipLaunchKernelGGL(build_jtab, dim3(grid_for(n, 256)), dim3(256), 0, st, n, xt, z,
+    hipLaunchKernelGGL(build_jtab, dim3(grid_for(n, 256)), dim3(256), 0, st, n, kind, xt, z,
                        (JEntry *)jt_.get());
     OTIP_HIP(hipGetLastError());
 }
@@ -299,7 +321,9 @@ PriceResult Scanner::price(hipStream_t st, int m, int n, const int32_t *xs, cons
         hipEvent_t e0_, e1_;
         if (timer) timer->arm((double)m * (double)n, &e0_, &e1_);
         else e0_ = e1_ = nullptr;
-        hipExtLaunchKernelGGL(price_pass<0>, grid, dim3(kScanBlock), 0, st, e0_, e1_, 0, a);
+        hipExtLaunchKernelGGL(by_kind(kind, price_pass<0, 0>, price_pass<0, 1>, price_pass<0, 2>,
+                                      price_pass<0, 3>),
+                              grid, dim3(kScanBlock), 0, st, e0_, e1_, 0, a);
         OTIP_HIP(hipGetLastError());
         OTIP_HIP(hipMemcpyAsync(h.data(), hist_.get(), kHistBins * sizeof(unsigned long long),
                                 hipMemcpyDeviceToHost, st));
@@ -367,7 +391,9 @@ PriceResult Scanner::price(hipStream_t st, int m, int n, const int32_t *xs, cons
     hipEvent_t e0_, e1_;
     if (timer) timer->arm((double)m * (double)n, &e0_, &e1_);
     else e0_ = e1_ = nullptr;
-    hipExtLaunchKernelGGL(price_pass<1>, grid, dim3(kScanBlock), 0, st, e0_, e1_, 0, a);
+    hipExtLaunchKernelGGL(by_kind(kind, price_pass<1, 0>, price_pass<1, 1>, price_pass<1, 2>,
+                                  price_pass<1, 3>),
+                          grid, dim3(kScanBlock), 0, st, e0_, e1_, 0, a);
     OTIP_HIP(hipGetLastError());
     unsigned long long emitted = 0;
     OTIP_HIP(hipMemcpyAsync(&emitted, cnt_.get(), sizeof(emitted), hipMemcpyDeviceToHost, st));
@@ -401,6 +427,7 @@ struct MinArgs {
     uint64_t *barg;
 };
 
+template <int K>
 __global__ __launch_bounds__(kScanBlock) void rmin_pass(MinArgs a) {
     __shared__ double sv[kScanBlock / 64];
     __shared__ uint64_t si[kScanBlock / 64];
@@ -411,7 +438,7 @@ __global__ __launch_bounds__(kScanBlock) void rmin_pass(MinArgs a) {
     uint64_t arg = ~0ull;
     for (int j = j0; j < j1; ++j) {
         const JEntry t = ldj(a.jt, j);
-        const double r = (cost_of(rd, t) - rd.y) - t.z;
+        const double r = (cost_of<K>(rd, t) - rd.y) - t.z;
         if (r < best) {  // first j attaining the minimum for this row
             best = r;
             arg = (uint64_t)i + (uint64_t)j * (uint64_t)a.m;
@@ -453,7 +480,8 @@ void Scanner::rmin(hipStream_t st, int m, int n, const int32_t *xs, const int32_
     bmin_.need(nb);
     barg_.need(nb);
     MinArgs a{m, n, tj, xs, y, (const JEntry *)jt_.get(), bmin_.get(), barg_.get()};
-    hipLaunchKernelGGL(rmin_pass, grid, dim3(kScanBlock), 0, st, a);
+    hipLaunchKernelGGL(by_kind(kind, rmin_pass<0>, rmin_pass<1>, rmin_pass<2>, rmin_pass<3>),
+                       grid, dim3(kScanBlock), 0, st, a);
     OTIP_HIP(hipGetLastError());
     scans++;
     std::vector<double> v(nb);
@@ -474,14 +502,20 @@ void Scanner::rmin(hipStream_t st, int m, int n, const int32_t *xs, const int32_
 }
 
 // ------------------------------------------------------- initial support scans
-__device__ __forceinline__ int64_t int_cost(const int32_t *xs, const int32_t *xt, int i, int j) {
+// The integer that orders the costs of a kind: the cost itself for the
+// squared, 1- and inf-norm costs, the squared norm for the 2-norm (its square
+// root is increasing, so thresholds and argmins on it select the same sets).
+__device__ __forceinline__ int64_t int_cost(const int32_t *xs, const int32_t *xt, int i, int j,
+                                            int kind) {
     int64_t d0 = (int64_t)xs[2 * i] - xt[2 * j];
     int64_t d1 = (int64_t)xs[2 * i + 1] - xt[2 * j + 1];
+    if (kind == OTIP_COST_L1) return (d0 < 0 ? -d0 : d0) + (d1 < 0 ? -d1 : d1);
+    if (kind == OTIP_COST_LINF) return max(d0 < 0 ? -d0 : d0, d1 < 0 ? -d1 : d1);
     return d0 * d0 + d1 * d1;
 }
 
 // histogram of (c - lo) >> shift for lo <= c <= hi; count of c < lo
-__global__ __launch_bounds__(kScanBlock) void cost_hist(int m, int n, int tj, const int32_t *xs,
+__global__ __launch_bounds__(kScanBlock) void cost_hist(int m, int n, int tj, int kind, const int32_t *xs,
                                                         const int32_t *xt, int64_t lo, int64_t hi,
                                                         int shift, unsigned long long *hist,
                                                         unsigned long long *below) {
@@ -495,7 +529,7 @@ __global__ __launch_bounds__(kScanBlock) void cost_hist(int m, int n, int tj, co
     if (i < m) {
         unsigned int nb = 0;
         for (int j = j0; j < j1; ++j) {
-            int64_t c = int_cost(xs, xt, i, j);
+            int64_t c = int_cost(xs, xt, i, j, kind);
             if (c < lo)
                 ++nb;
             else if (c <= hi)
@@ -510,19 +544,19 @@ __global__ __launch_bounds__(kScanBlock) void cost_hist(int m, int n, int tj, co
 }
 
 // number of c_ij <= T in each column j (one block per column)
-__global__ __launch_bounds__(kScanBlock) void count_le_col(int m, int n, const int32_t *xs,
+__global__ __launch_bounds__(kScanBlock) void count_le_col(int m, int n, int kind, const int32_t *xs,
                                                            const int32_t *xt, int64_t T,
                                                            int64_t *cnt) {
     __shared__ double lds[16];
     const int j = blockIdx.x;
     int c = 0;
-    for (int i = threadIdx.x; i < m; i += kScanBlock) c += int_cost(xs, xt, i, j) <= T;
+    for (int i = threadIdx.x; i < m; i += kScanBlock) c += int_cost(xs, xt, i, j, kind) <= T;
     double t = block_sum((double)c, lds);
     if (threadIdx.x == 0) cnt[j] = (int64_t)t;
 }
 
 // write the variable indices with c_ij <= T of column j in increasing i
-__global__ __launch_bounds__(kScanBlock) void collect_le_col(int m, int n, const int32_t *xs,
+__global__ __launch_bounds__(kScanBlock) void collect_le_col(int m, int n, int kind, const int32_t *xs,
                                                              const int32_t *xt, int64_t T,
                                                              const int64_t *off,
                                                              uint64_t *out) {
@@ -532,7 +566,7 @@ __global__ __launch_bounds__(kScanBlock) void collect_le_col(int m, int n, const
     int64_t base = off[j];
     for (int i0 = 0; i0 < m; i0 += kScanBlock) {
         const int i = i0 + threadIdx.x;
-        const bool take = i < m && int_cost(xs, xt, i, j) <= T;
+        const bool take = i < m && int_cost(xs, xt, i, j, kind) <= T;
         const uint64_t mask = __ballot(take);
         if (lane == 0) wcount[w] = __popcll(mask);
         __syncthreads();
@@ -550,7 +584,7 @@ __global__ __launch_bounds__(kScanBlock) void collect_le_col(int m, int n, const
 }
 
 // cheapest target of each source (ties: smallest j) -> variable index
-__global__ __launch_bounds__(kScanBlock) void row_argmin(int m, int n, const int32_t *xs,
+__global__ __launch_bounds__(kScanBlock) void row_argmin(int m, int n, int kind, const int32_t *xs,
                                                          const int32_t *xt, uint64_t *out) {
     __shared__ int64_t sc[kScanBlock];
     __shared__ int sj[kScanBlock];
@@ -558,7 +592,7 @@ __global__ __launch_bounds__(kScanBlock) void row_argmin(int m, int n, const int
     int64_t best = INT64_MAX;
     int arg = n;
     for (int j = threadIdx.x; j < n; j += kScanBlock) {
-        int64_t c = int_cost(xs, xt, i, j);
+        int64_t c = int_cost(xs, xt, i, j, kind);
         if (c < best) {
             best = c;
             arg = j;
@@ -578,7 +612,7 @@ __global__ __launch_bounds__(kScanBlock) void row_argmin(int m, int n, const int
 }
 
 // cheapest source of each target (ties: smallest i) -> variable index
-__global__ __launch_bounds__(kScanBlock) void col_argmin(int m, int n, const int32_t *xs,
+__global__ __launch_bounds__(kScanBlock) void col_argmin(int m, int n, int kind, const int32_t *xs,
                                                          const int32_t *xt, uint64_t *out) {
     __shared__ int64_t sc[kScanBlock];
     __shared__ int si[kScanBlock];
@@ -586,7 +620,7 @@ __global__ __launch_bounds__(kScanBlock) void col_argmin(int m, int n, const int
     int64_t best = INT64_MAX;
     int arg = m;
     for (int i = threadIdx.x; i < m; i += kScanBlock) {
-        int64_t c = int_cost(xs, xt, i, j);
+        int64_t c = int_cost(xs, xt, i, j, kind);
         if (c < best) {
             best = c;
             arg = i;
@@ -621,7 +655,7 @@ int64_t Scanner::initial_support(hipStream_t st, int m, int n, const int32_t *xs
         while (((hi - lo) >> shift) >= kHistBins) ++shift;
         OTIP_HIP(hipMemsetAsync(hist_.get(), 0, kHistBins * sizeof(unsigned long long), st));
         OTIP_HIP(hipMemsetAsync(cnt_.get(), 0, sizeof(unsigned long long), st));
-        hipLaunchKernelGGL(cost_hist, grid, dim3(kScanBlock), 0, st, m, n, tj, xs, xt, lo, hi,
+        hipLaunchKernelGGL(cost_hist, grid, dim3(kScanBlock), 0, st, m, n, tj, kind, xs, xt, lo, hi,
                            shift, hist_.get(), cnt_.get());
         OTIP_HIP(hipGetLastError());
         unsigned long long below = 0;
@@ -655,7 +689,7 @@ int64_t Scanner::initial_support(hipStream_t st, int m, int n, const int32_t *xs
     DBuf<int64_t> &off = i64b_;
     cnt.need((size_t)n);
     off.need((size_t)n + 1);
-    hipLaunchKernelGGL(count_le_col, dim3(n), dim3(kScanBlock), 0, st, m, n, xs, xt, T, cnt.get());
+    hipLaunchKernelGGL(count_le_col, dim3(n), dim3(kScanBlock), 0, st, m, n, kind, xs, xt, T, cnt.get());
     OTIP_HIP(hipGetLastError());
     exclusive_scan_i64(st, cnt.get(), off.get(), n, tmp_);
     int64_t last_off = 0, last_cnt = 0;
@@ -666,11 +700,11 @@ int64_t Scanner::initial_support(hipStream_t st, int m, int n, const int32_t *xs
     const int64_t tot = nle + m + n;
     DBuf<uint64_t> &tmpk = u64a_;
     tmpk.need((size_t)tot);
-    hipLaunchKernelGGL(collect_le_col, dim3(n), dim3(kScanBlock), 0, st, m, n, xs, xt, T, off.get(),
+    hipLaunchKernelGGL(collect_le_col, dim3(n), dim3(kScanBlock), 0, st, m, n, kind, xs, xt, T, off.get(),
                        tmpk.get());
-    hipLaunchKernelGGL(row_argmin, dim3(m), dim3(kScanBlock), 0, st, m, n, xs, xt,
+    hipLaunchKernelGGL(row_argmin, dim3(m), dim3(kScanBlock), 0, st, m, n, kind, xs, xt,
                        tmpk.get() + nle);
-    hipLaunchKernelGGL(col_argmin, dim3(n), dim3(kScanBlock), 0, st, m, n, xs, xt,
+    hipLaunchKernelGGL(col_argmin, dim3(n), dim3(kScanBlock), 0, st, m, n, kind, xs, xt,
                        tmpk.get() + nle + m);
     OTIP_HIP(hipGetLastError());
     // union: sort and drop duplicates
@@ -934,6 +968,10 @@ PriceResult Scanner::price_mixed(hipStream_t st, int m, int n, const int32_t *xs
                                  double *orr, uint64_t *oidx) {
     PriceResult res{0, 0, 0};
     if (m <= 0 || n <= 0) return res;
+    // the FP32 scan is written for the squared cost; the norm costs take the
+    // FP64 scan (same result)
+    if (kind != OTIP_COST_SQEUCLID)
+        return price(st, m, n, xs, xt, y, z, bitmap, kmax, oi, oj, orr, oidx);
     // bounds for the margin and the exactness of FP32 costs
     DBuf<double> &mx = bmin_;
     mx.need(4);

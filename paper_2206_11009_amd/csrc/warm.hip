@@ -17,22 +17,28 @@ namespace {
 constexpr int kWB = 256;
 constexpr int kWBins = 4096;
 
+// C_ij of a cost kind (Section 5.1) from the integer offset d = x_i - x_j:
+// |d| <= 2^15, so d0^2 + d1^2 <= 2^31 and every integer here is an exact
+// double; the 2-norm is its correctly rounded square root.
 __device__ __forceinline__ double wcost(const int32_t *__restrict__ xs,
-                                        const int32_t *__restrict__ xt, int i, int j) {
+                                        const int32_t *__restrict__ xt, int i, int j, int kind) {
     const int64_t d0 = (int64_t)xs[2 * i] - xt[2 * j];
     const int64_t d1 = (int64_t)xs[2 * i + 1] - xt[2 * j + 1];
-    // |d| <= 2^15, so d0^2 + d1^2 <= 2^31 and the double is exact
-    return (double)(d0 * d0 + d1 * d1);
+    const int64_t a0 = d0 < 0 ? -d0 : d0, a1 = d1 < 0 ? -d1 : d1;
+    if (kind == OTIP_COST_L1) return (double)(a0 + a1);
+    if (kind == OTIP_COST_LINF) return (double)max(a0, a1);
+    const double q = (double)(d0 * d0 + d1 * d1);
+    return kind == OTIP_COST_L2 ? __builtin_sqrt(q) : q;
 }
 
 // one block per column: z_j = min_i (C_ij - y_i)
-__global__ __launch_bounds__(kWB) void ctrans_col(int m, int n, const int32_t *xs,
+__global__ __launch_bounds__(kWB) void ctrans_col(int m, int n, int kind, const int32_t *xs,
                                                   const int32_t *xt, const double *y,
                                                   double *z) {
     __shared__ double lds[kWB / 64];
     const int j = blockIdx.x;
     double best = INFINITY;
-    for (int i = threadIdx.x; i < m; i += kWB) best = fmin(best, wcost(xs, xt, i, j) - y[i]);
+    for (int i = threadIdx.x; i < m; i += kWB) best = fmin(best, wcost(xs, xt, i, j, kind) - y[i]);
     best = wave_min(best);
     if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = best;
     __syncthreads();
@@ -43,7 +49,7 @@ __global__ __launch_bounds__(kWB) void ctrans_col(int m, int n, const int32_t *x
 }
 
 // one block per row: y_i = min_j (C_ij - z_j) and its argmin (smallest j on ties)
-__global__ __launch_bounds__(kWB) void ctrans_row(int m, int n, const int32_t *xs,
+__global__ __launch_bounds__(kWB) void ctrans_row(int m, int n, int kind, const int32_t *xs,
                                                   const int32_t *xt, const double *z, double *y,
                                                   uint64_t *cover) {
     __shared__ double sv[kWB];
@@ -52,7 +58,7 @@ __global__ __launch_bounds__(kWB) void ctrans_row(int m, int n, const int32_t *x
     double best = INFINITY;
     int arg = n;
     for (int j = threadIdx.x; j < n; j += kWB) {
-        const double v = wcost(xs, xt, i, j) - z[j];
+        const double v = wcost(xs, xt, i, j, kind) - z[j];
         if (v < best) {
             best = v;
             arg = j;
@@ -79,7 +85,7 @@ __global__ __launch_bounds__(kWB) void ctrans_row(int m, int n, const int32_t *x
 }
 
 // one block per column: argmin_i r_ij (smallest i on ties)
-__global__ __launch_bounds__(kWB) void rc_col_argmin(int m, int n, const int32_t *xs,
+__global__ __launch_bounds__(kWB) void rc_col_argmin(int m, int n, int kind, const int32_t *xs,
                                                      const int32_t *xt, const double *y,
                                                      const double *z, uint64_t *cover) {
     __shared__ double sv[kWB];
@@ -89,7 +95,7 @@ __global__ __launch_bounds__(kWB) void rc_col_argmin(int m, int n, const int32_t
     double best = INFINITY;
     int arg = m;
     for (int i = threadIdx.x; i < m; i += kWB) {
-        const double v = (wcost(xs, xt, i, j) - y[i]) - zj;
+        const double v = (wcost(xs, xt, i, j, kind) - y[i]) - zj;
         if (v < best) {
             best = v;
             arg = i;
@@ -114,7 +120,7 @@ __global__ __launch_bounds__(kWB) void rc_col_argmin(int m, int n, const int32_t
 
 // histogram of 12-bit digit (key >> shift) of r's ordered key over the keys
 // whose bits above shift+12 equal prefix; grid (row blocks, column tiles)
-__global__ __launch_bounds__(kWB) void rc_hist(int m, int n, int tj, const int32_t *xs,
+__global__ __launch_bounds__(kWB) void rc_hist(int m, int n, int kind, int tj, const int32_t *xs,
                                                const int32_t *xt, const double *y,
                                                const double *z, int shift, uint64_t prefix,
                                                unsigned long long *hist) {
@@ -127,7 +133,7 @@ __global__ __launch_bounds__(kWB) void rc_hist(int m, int n, int tj, const int32
     if (i < m) {
         const double yi = y[i];
         for (int j = j0; j < j1; ++j) {
-            const uint64_t key = dkey((wcost(xs, xt, i, j) - yi) - z[j]);
+            const uint64_t key = dkey((wcost(xs, xt, i, j, kind) - yi) - z[j]);
             if (pshift >= 64 || (key >> pshift) == prefix)
                 atomicAdd(&lh[(key >> shift) & 4095u], 1u);
         }
@@ -138,7 +144,7 @@ __global__ __launch_bounds__(kWB) void rc_hist(int m, int n, int tj, const int32
 }
 
 // per column: number of keys <= key_max
-__global__ __launch_bounds__(kWB) void rc_count_col(int m, int n, const int32_t *xs,
+__global__ __launch_bounds__(kWB) void rc_count_col(int m, int n, int kind, const int32_t *xs,
                                                     const int32_t *xt, const double *y,
                                                     const double *z, uint64_t key_max,
                                                     int64_t *cnt) {
@@ -147,13 +153,13 @@ __global__ __launch_bounds__(kWB) void rc_count_col(int m, int n, const int32_t 
     const double zj = z[j];
     int c = 0;
     for (int i = threadIdx.x; i < m; i += kWB)
-        c += dkey((wcost(xs, xt, i, j) - y[i]) - zj) <= key_max;
+        c += dkey((wcost(xs, xt, i, j, kind) - y[i]) - zj) <= key_max;
     const double t = block_sum((double)c, lds);
     if (threadIdx.x == 0) cnt[j] = (int64_t)t;
 }
 
 // per column: the variable indices with key <= key_max, increasing i
-__global__ __launch_bounds__(kWB) void rc_collect_col(int m, int n, const int32_t *xs,
+__global__ __launch_bounds__(kWB) void rc_collect_col(int m, int n, int kind, const int32_t *xs,
                                                       const int32_t *xt, const double *y,
                                                       const double *z, uint64_t key_max,
                                                       const int64_t *off, uint64_t *out) {
@@ -164,7 +170,7 @@ __global__ __launch_bounds__(kWB) void rc_collect_col(int m, int n, const int32_
     int64_t base = off[j];
     for (int i0 = 0; i0 < m; i0 += kWB) {
         const int i = i0 + threadIdx.x;
-        const bool take = i < m && dkey((wcost(xs, xt, i, j) - y[i]) - zj) <= key_max;
+        const bool take = i < m && dkey((wcost(xs, xt, i, j, kind) - y[i]) - zj) <= key_max;
         const uint64_t mask = __ballot(take);
         if (lane == 0) wcount[w] = __popcll(mask);
         __syncthreads();
@@ -191,14 +197,14 @@ __global__ void nonfinite_flag(int64_t len, const double *v, int *flag) {
 
 void Scanner::ctransform_rows(hipStream_t st, int m, int n, const int32_t *xs, const int32_t *xt,
                               const double *z, double *y) {
-    hipLaunchKernelGGL(ctrans_row, dim3(m), dim3(kWB), 0, st, m, n, xs, xt, z, y,
+    hipLaunchKernelGGL(ctrans_row, dim3(m), dim3(kWB), 0, st, m, n, kind, xs, xt, z, y,
                        (uint64_t *)nullptr);
     OTIP_HIP(hipGetLastError());
 }
 
 void Scanner::ctransform_cols(hipStream_t st, int m, int n, const int32_t *xs, const int32_t *xt,
                               const double *y, double *z) {
-    hipLaunchKernelGGL(ctrans_col, dim3(n), dim3(kWB), 0, st, m, n, xs, xt, y, z);
+    hipLaunchKernelGGL(ctrans_col, dim3(n), dim3(kWB), 0, st, m, n, kind, xs, xt, y, z);
     OTIP_HIP(hipGetLastError());
 }
 
@@ -220,9 +226,9 @@ int64_t Scanner::warm_support(hipStream_t st, int m, int n, const int32_t *xs, c
     double *y = yw.need(m), *z = zw.need(n);
     DBuf<uint64_t> &cover = u64b_;
     cover.need((size_t)m + n);
-    hipLaunchKernelGGL(ctrans_col, dim3(n), dim3(kWB), 0, st, m, n, xs, xt, y0, z);
-    hipLaunchKernelGGL(ctrans_row, dim3(m), dim3(kWB), 0, st, m, n, xs, xt, z, y, cover.get());
-    hipLaunchKernelGGL(rc_col_argmin, dim3(n), dim3(kWB), 0, st, m, n, xs, xt, y, z,
+    hipLaunchKernelGGL(ctrans_col, dim3(n), dim3(kWB), 0, st, m, n, kind, xs, xt, y0, z);
+    hipLaunchKernelGGL(ctrans_row, dim3(m), dim3(kWB), 0, st, m, n, kind, xs, xt, z, y, cover.get());
+    hipLaunchKernelGGL(rc_col_argmin, dim3(n), dim3(kWB), 0, st, m, n, kind, xs, xt, y, z,
                        cover.get() + m);
     OTIP_HIP(hipGetLastError());
 
@@ -238,7 +244,7 @@ int64_t Scanner::warm_support(hipStream_t st, int m, int n, const int32_t *xs, c
     for (int level = 0; level < 2; ++level) {
         const int shift = level == 0 ? 52 : 40;
         OTIP_HIP(hipMemsetAsync(hist_.get(), 0, kWBins * sizeof(unsigned long long), st));
-        hipLaunchKernelGGL(rc_hist, grid, dim3(kWB), 0, st, m, n, tj, xs, xt, y, z, shift, prefix,
+        hipLaunchKernelGGL(rc_hist, grid, dim3(kWB), 0, st, m, n, kind, tj, xs, xt, y, z, shift, prefix,
                            hist_.get());
         OTIP_HIP(hipGetLastError());
         OTIP_HIP(hipMemcpyAsync(h.data(), hist_.get(), kWBins * sizeof(unsigned long long),
@@ -258,7 +264,7 @@ int64_t Scanner::warm_support(hipStream_t st, int m, int n, const int32_t *xs, c
     DBuf<int64_t> &off = i64b_;
     cnt.need((size_t)n);
     off.need((size_t)n + 1);
-    hipLaunchKernelGGL(rc_count_col, dim3(n), dim3(kWB), 0, st, m, n, xs, xt, y, z, key_max,
+    hipLaunchKernelGGL(rc_count_col, dim3(n), dim3(kWB), 0, st, m, n, kind, xs, xt, y, z, key_max,
                        cnt.get());
     OTIP_HIP(hipGetLastError());
     exclusive_scan_i64(st, cnt.get(), off.get(), n, tmp_);
@@ -274,7 +280,7 @@ int64_t Scanner::warm_support(hipStream_t st, int m, int n, const int32_t *xs, c
     const int64_t tot = nle + m + n;
     DBuf<uint64_t> &tmpk = u64a_;
     tmpk.need((size_t)tot);
-    hipLaunchKernelGGL(rc_collect_col, dim3(n), dim3(kWB), 0, st, m, n, xs, xt, y, z, key_max,
+    hipLaunchKernelGGL(rc_collect_col, dim3(n), dim3(kWB), 0, st, m, n, kind, xs, xt, y, z, key_max,
                        off.get(), tmpk.get());
     OTIP_HIP(hipGetLastError());
     OTIP_HIP(hipMemcpyAsync(tmpk.get() + nle, cover.get(), sizeof(uint64_t) * (m + n),

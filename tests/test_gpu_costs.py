@@ -1,0 +1,267 @@
+"""The norm costs of Section 5.1 (1-, 2- and inf-norm of the pixel offset)
+through the C-ABI against the CPU oracle: pricing selections and the
+reduced-cost minimum bit for bit (ragged sizes, ties, the full coordinate
+range, the 64x64 workload), whole solves to the oracle's optimum with a
+certificate on the kind's costs (both linear solvers, mixed precision, batches,
+zero masses, warm starts), checkpoints bound to the kind, and rejected kinds."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import _cscan
+from synthetic import batch_instances, config_instance
+
+pytestmark = pytest.mark.gpu
+
+KINDS = [1, 2, 3]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2206_11009_amd as otip
+    c = otip.Context(0)
+    yield c
+    c.close()
+
+
+def bitmap_of(support, m, n):
+    words = np.zeros((m * n + 31) // 32, np.uint32)
+    s = np.asarray(support, np.int64)
+    np.bitwise_or.at(words, s >> 5, (np.uint32(1) << (s & 31).astype(np.uint32)))
+    return words.view(np.int32)
+
+
+def price_check(ctx, xs, xt, y, z, support, kmax, kind, precision=0):
+    import paper_2206_11009_amd as otip
+    m, n = len(xs), len(xt)
+    bm = bitmap_of(support, m, n) if len(support) else None
+    oi, oj, orr, nneg = otip.otip_price(ctx, xs, xt, y, z, bm, kmax, precision, cost_kind=kind)
+    g_idx = oi.cpu().numpy().astype(np.int64) + oj.cpu().numpy().astype(np.int64) * m
+    o_idx, o_r, o_neg = _cscan.price(xs, xt, y, z, np.sort(np.asarray(support, np.int64)), kmax,
+                                     kind)
+    assert nneg == o_neg
+    np.testing.assert_array_equal(g_idx, o_idx)
+    np.testing.assert_array_equal(orr.cpu().numpy(), o_r)
+    return nneg
+
+
+def all_costs(xs, xt, kind):
+    m, n = len(xs), len(xt)
+    ii, jj = np.meshgrid(np.arange(m), np.arange(n), indexing="ij")
+    return oracle.costs(xs, xt, ii.ravel(), jj.ravel(), kind).reshape(m, n)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("m,n,kmax,seed", [(13, 11, 7, 0), (300, 257, 300, 1), (1000, 700, 50, 2),
+                                           (257, 129, 0, 3)])
+def test_pricing_bit_exact(ctx, kind, m, n, kmax, seed):
+    rng = np.random.default_rng(seed)
+    xs = rng.integers(0, 60, (m, 2)).astype(np.int32)
+    xt = rng.integers(0, 60, (n, 2)).astype(np.int32)
+    y = rng.uniform(0, 40, m)
+    z = rng.uniform(0, 40, n)
+    support = rng.choice(m * n, size=min(m * n // 3, 5000), replace=False)
+    nneg = price_check(ctx, xs, xt, y, z, support, kmax, kind)
+    assert 0 < nneg < m * n - len(support)         # both signs occur
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_pricing_ties_and_mixed_request(ctx, kind):
+    """Integer duals make many reduced costs equal (all of them integers for
+    the 1- and inf-norms); the cut follows the variable index.  A mixed
+    precision request gives the same selection (the FP64 scan)."""
+    rng = np.random.default_rng(9)
+    m, n = 400, 300
+    xs = rng.integers(0, 20, (m, 2)).astype(np.int32)
+    xt = rng.integers(0, 20, (n, 2)).astype(np.int32)
+    y = rng.integers(0, 12, m).astype(float)
+    z = rng.integers(0, 12, n).astype(float)
+    for kmax in (1, 17, 999, 5000):
+        price_check(ctx, xs, xt, y, z, [], kmax, kind)
+    price_check(ctx, xs, xt, y, z, [], 999, kind, precision=1)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_pricing_full_coordinate_range(ctx, kind):
+    """Coordinates over all of [-2^14, 2^14]: offsets up to 2^15, squared norms
+    up to 2^31 (the exact integer under the 2-norm's root)."""
+    rng = np.random.default_rng(11)
+    m, n = 700, 900
+    lim = 1 << 14
+    xs = rng.integers(-lim, lim + 1, (m, 2)).astype(np.int32)
+    xt = rng.integers(-lim, lim + 1, (n, 2)).astype(np.int32)
+    xs[0] = (-lim, -lim)
+    xt[0] = (lim, lim)
+    scale = {1: 65536.0, 2: 46341.0, 3: 32768.0}[kind]
+    y = rng.uniform(0, scale / 2, m)
+    z = rng.uniform(0, scale / 2, n)
+    price_check(ctx, xs, xt, y, z, [], 20000, kind)
+    import paper_2206_11009_amd as otip
+    v, arg = otip.otip_rmin(ctx, xs, xt, y, z, cost_kind=kind)
+    assert (v, arg) == _cscan.rmin(xs, xt, y, z, kind)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_pricing_and_rmin_64x64(ctx, kind):
+    """The 64x64 workload (16.8M variables) with duals near the optimum's scale."""
+    import paper_2206_11009_amd as otip
+    inst = config_instance("c2", 0)
+    m = inst.m
+    rng = np.random.default_rng(3)
+    c0 = oracle.costs(inst.xs, inst.xt, np.arange(m), np.arange(m), kind)
+    y = rng.uniform(0, 3, m) + c0
+    z = rng.uniform(0, 3, m)
+    support = rng.choice(m * m, 50000, replace=False)
+    price_check(ctx, inst.xs, inst.xt, y, z, support, m, kind)
+    v, arg = otip.otip_rmin(ctx, inst.xs, inst.xt, y, z, cost_kind=kind)
+    assert (v, arg) == _cscan.rmin(inst.xs, inst.xt, y, z, kind)
+
+
+def check_result(res, a, b, xs, xt, kind):
+    m, n = len(a), len(b)
+    assert res.status == 0, res.info
+    assert res.marginal_residual <= 1e-8
+    assert res.rel_gap <= 1e-6
+    assert len(res.flows) <= m + n - 1
+    assert oracle.is_forest(res.rows, res.cols, m, n)
+    c = oracle.costs(xs, xt, res.rows, res.cols, kind)
+    assert abs(float(c @ res.flows) - res.objective) <= 1e-12 * max(1, abs(res.objective))
+    rmin, _ = _cscan.rmin(xs, xt, res.y, res.z, kind)
+    assert rmin == pytest.approx(res.r_min, rel=1e-12, abs=1e-12)
+    bound = a @ res.y + b @ res.z + a.sum() * min(0.0, rmin)
+    assert (res.objective - bound) / max(1.0, abs(res.objective)) <= 1e-6
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("k", [0, 4])
+def test_solve_16x16_matches_oracle(ctx, kind, k):
+    import paper_2206_11009_amd as otip
+    inst = config_instance("c1", k)
+    res = otip.otip_solve(ctx, inst.a, inst.b, inst.xs, inst.xt, cost_kind=kind)
+    check_result(res, inst.a, inst.b, inst.xs, inst.xt, kind)
+    ref = oracle.solve(inst.a, inst.b, inst.xs, inst.xt, oracle.OracleParams(cost_kind=kind))
+    assert abs(res.objective - ref.objective) <= 1e-6 * abs(ref.objective)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("variant", ["direct_only", "mixed"])
+def test_solver_variants(ctx, kind, variant):
+    import paper_2206_11009_amd as otip
+    inst = config_instance("c1", 2)
+    if variant == "direct_only":
+        prm = otip.params(linear_solver=otip.OTIP_LS_DIRECT)
+    else:
+        prm = otip.params(precision=otip.OTIP_MIXED, switch_cost=0)
+    res = otip.otip_solve(ctx, inst.a, inst.b, inst.xs, inst.xt, prm, cost_kind=kind)
+    check_result(res, inst.a, inst.b, inst.xs, inst.xt, kind)
+    ref = oracle.solve(inst.a, inst.b, inst.xs, inst.xt, oracle.OracleParams(cost_kind=kind))
+    assert abs(res.objective - ref.objective) <= 1e-6 * abs(ref.objective)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_rectangular_and_zero_masses(ctx, kind):
+    """Ragged point clouds with zero-mass rows and columns (dropped, then given
+    c-transform duals under the kind's costs)."""
+    import paper_2206_11009_amd as otip
+    rng = np.random.default_rng(30 + kind)
+    m, n = 61, 44
+    xs = rng.integers(-40, 40, (m, 2)).astype(np.int32)
+    xt = rng.integers(-40, 40, (n, 2)).astype(np.int32)
+    a = rng.uniform(0.1, 1.0, m)
+    b = rng.uniform(0.1, 1.0, n)
+    zr = rng.choice(m, 6, replace=False)
+    zc = np.append(rng.choice(n - 1, 4, replace=False), n - 1)
+    a[zr] = 0.0
+    b[zc] = 0.0
+    a /= a.sum()
+    b /= b.sum()
+    res = otip.otip_solve(ctx, a, b, xs, xt, cost_kind=kind)
+    check_result(res, a, b, xs, xt, kind)
+    assert not np.isin(res.rows, zr).any() and not np.isin(res.cols, zc).any()
+    ki, kj = np.flatnonzero(a > 0), np.flatnonzero(b > 0)
+    ref = oracle.solve(a[ki], b[kj], xs[ki], xt[kj], oracle.OracleParams(cost_kind=kind))
+    assert abs(res.objective - ref.objective) <= 1e-6 * abs(ref.objective)
+    C = all_costs(xs, xt, kind)
+    r = C - res.y[:, None] - res.z[None, :]
+    tol = 1e-9 * C.max()
+    assert r[zr].min() >= -tol and r[:, zc].min() >= -tol
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_warm_start_from_optimal_duals(ctx, kind):
+    """Duals of the oracle's optimum as the prediction: the warm initial support
+    is built from the kind's reduced costs and the solve certifies the same
+    optimum."""
+    import paper_2206_11009_amd as otip
+    inst = config_instance("c1", 7)
+    ref = oracle.solve(inst.a, inst.b, inst.xs, inst.xt, oracle.OracleParams(cost_kind=kind))
+    res = otip.otip_solve(ctx, inst.a, inst.b, inst.xs, inst.xt, y0=ref.y, z0=ref.z,
+                          cost_kind=kind)
+    check_result(res, inst.a, inst.b, inst.xs, inst.xt, kind)
+    assert abs(res.objective - ref.objective) <= 1e-6 * abs(ref.objective)
+
+
+def test_batch_with_a_norm_cost(ctx):
+    import paper_2206_11009_amd as otip
+    insts = batch_instances(6)
+    res = otip.otip_solve_batch(ctx, [(i.a, i.b, i.xs, i.xt) for i in insts],
+                                otip.params(batch_workers=3), cost_kind=otip.OTIP_COST_LINF)
+    for inst, r in zip(insts, res):
+        check_result(r, inst.a, inst.b, inst.xs, inst.xt, 3)
+        one = otip.otip_solve(ctx, inst.a, inst.b, inst.xs, inst.xt, cost_kind=3)
+        assert r.objective == one.objective
+        np.testing.assert_array_equal(r.flows, one.flows)
+
+
+def load_golden():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "oracle_c2_costs.json")
+    with open(path) as f:
+        return {r["cost_kind"]: r for r in json.load(f)["results"]}
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_solve_64x64_matches_stored_oracle(ctx, kind):
+    import paper_2206_11009_amd as otip
+    inst = config_instance("c2", 0)
+    res = otip.otip_solve(ctx, inst.a, inst.b, inst.xs, inst.xt, cost_kind=kind)
+    check_result(res, inst.a, inst.b, inst.xs, inst.xt, kind)
+    ref = load_golden()[kind]["objective"]
+    assert abs(res.objective - ref) <= 1e-6 * abs(ref)
+
+
+def test_checkpoint_is_bound_to_the_cost_kind(ctx):
+    import paper_2206_11009_amd as otip
+    inst = config_instance("c1", 1)
+    full = otip.otip_solve(ctx, inst.a, inst.b, inst.xs, inst.xt, cost_kind=1)
+    part = otip.otip_solve(ctx, inst.a, inst.b, inst.xs, inst.xt, otip.params(max_iter=6),
+                           cost_kind=1)
+    assert part.status == otip.OTIP_EMAXITER
+    rec = otip.otip_state_save(ctx)
+    otip.otip_state_load(ctx, rec)
+    with pytest.raises(otip.OtipError) as e:
+        otip.otip_solve(ctx, inst.a, inst.b, inst.xs, inst.xt, cost_kind=0)
+    assert e.value.code == otip.OTIP_EINVAL
+    otip.otip_state_load(ctx, rec)
+    resumed = otip.otip_solve(ctx, inst.a, inst.b, inst.xs, inst.xt, cost_kind=1)
+    assert resumed.objective == full.objective and resumed.iterations == full.iterations
+    np.testing.assert_array_equal(resumed.flows, full.flows)
+
+
+@pytest.mark.parametrize("kind", [-1, 4])
+def test_unknown_cost_kind_is_rejected(ctx, kind):
+    import paper_2206_11009_amd as otip
+    inst = config_instance("c1", 0)
+    with pytest.raises(otip.OtipError) as e:
+        otip.otip_solve(ctx, inst.a, inst.b, inst.xs, inst.xt, cost_kind=kind)
+    assert e.value.code == otip.OTIP_EINVAL
+    y, z = np.zeros(inst.m), np.zeros(inst.n)
+    with pytest.raises(otip.OtipError) as e:
+        otip.otip_price(ctx, inst.xs, inst.xt, y, z, None, 10, cost_kind=kind)
+    assert e.value.code == otip.OTIP_EINVAL
+    with pytest.raises(otip.OtipError) as e:
+        otip.otip_rmin(ctx, inst.xs, inst.xt, y, z, cost_kind=kind)
+    assert e.value.code == otip.OTIP_EINVAL
+    assert otip.otip_solve(ctx, inst.a, inst.b, inst.xs, inst.xt).status == 0
