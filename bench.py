@@ -11,8 +11,10 @@ fly, FP64); step k solves seed k mod 5.  Inputs are uploaded to HBM before the
 timed region.
 
 Prints one JSON line: seconds per LP (lower is better) of the plain FP64
-method, the live roofline of the dominant kernel (HIP events around each of its
-launches on its stream), pricing throughput, the same instances solved by the
+method, the live roofline of the dominant kernel (HIP events recorded by each of
+its dispatches; the timed kernels are the Schur SpMV, the pricing pass and the
+dense factor's diagonal-block and trailing-update kernels, and the one with the
+largest total time is reported, the others beside it), pricing throughput, the same instances solved by the
 mixed-precision and learned-warm-start forms ("forms"; the network's prediction
 is inside the timed region), and the CPU oracle timed on a bounded sample of the
 same workload.  --config c4 times whole batches of 512 uneven instances
@@ -30,16 +32,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-# HBM traffic of the fused Schur SpMV measured by rocprofv3 --pmc FETCH_SIZE and
-# WRITE_SIZE (separate runs) on `bench.py --steps 1 --warmup 0 --no-cpu-baseline
+# HBM traffic per launch measured by rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
+# (separate runs) on `bench.py --steps 1 --warmup 0 --no-cpu-baseline
 # --no-forms`, scaled by what the counters read for a 1 GiB device copy, mean
 # over the launches that did work; valid only for the kernel source it was
-# measured on (the SHA-256 of the text of load_chunk and spmv_dir).
-SPMV_TRAFFIC = {"source": "paper_2206_11009_amd/csrc/schur.hip",
-                "functions": ["load_chunk", "spmv_dir"],
-                "sha256": "b7d3d64dbbdb6f1b70dc204ca01743bbd6207ed3a1ff743a2bc37396851125fb",
-                "bytes_per_launch": 14233052.0}
+# measured on (the SHA-256 of the text of the listed functions).
+KERNEL_TRAFFIC = {
+    "spmv_dir": {"source": "paper_2206_11009_amd/csrc/schur.hip",
+                 "functions": ["load_chunk", "spmv_dir"],
+                 "sha256": "b7d3d64dbbdb6f1b70dc204ca01743bbd6207ed3a1ff743a2bc37396851125fb",
+                 "bytes_per_launch": 2868914.0},
+    "ldl_diag": {"source": "paper_2206_11009_amd/csrc/dense.hip",
+                 "functions": ["ldl_diag"],
+                 "sha256": "d84efdddbf5d1c34bece123a49c8a5f24749e21aea1737be96a77ca12544ae64",
+                 "bytes_per_launch": 364920.0},
+}
 FP64_VECTOR_PEAK_TF = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+FP64_MATRIX_PEAK_TF = 78.6     # dense FP64 matrix-core peak
 PRICE_FLOPS_PER_COST = 7.0     # C_ij: one add + two FMAs (5 flops); r: two subtractions
 WORKLOADS = {
     "c1": "16x16 Gaussian-mixture grid pair (m=n=256, 65,536 variables), 3 bumps, FP64",
@@ -184,15 +193,15 @@ def kernel_source_sha256(path, names):
     return h.hexdigest()
 
 
-def measured_traffic():
-    """Counter-measured SpMV bytes per launch, or None once the kernel's
-    source differs from the one the counters were taken on."""
-    if SPMV_TRAFFIC["sha256"] is None:
+def measured_traffic(kernel):
+    """Counter-measured bytes per launch of a kernel, or None when none were
+    taken or once its source differs from the one the counters were taken on."""
+    t = KERNEL_TRAFFIC.get(kernel)
+    if t is None or t["sha256"] is None:
         return None
-    if kernel_source_sha256(SPMV_TRAFFIC["source"], SPMV_TRAFFIC["functions"]) != \
-            SPMV_TRAFFIC["sha256"]:
+    if kernel_source_sha256(t["source"], t["functions"]) != t["sha256"]:
         return None
-    return SPMV_TRAFFIC["bytes_per_launch"]
+    return t["bytes_per_launch"]
 
 
 def rooflines(infos):
@@ -205,17 +214,36 @@ def rooflines(infos):
     spmv = {"bound": "hbm", "kernel": "spmv_dir (Schur SpMV fused with the CG direction update)",
             "achieved": spmv_b / max(spmv_ms, 1e-12) / 1e6, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "avg_launch_us": 1e3 * spmv_ms / max(spmv_n, 1), "launches": spmv_n,
-            "total_ms": spmv_ms, "traffic": measured_traffic(),
+            "total_ms": spmv_ms, "traffic": measured_traffic("spmv_dir"),
             "algorithmic_bytes_per_launch": spmv_b / max(spmv_n, 1)}
     price = {"bound": "alu", "kernel": "price_pass (pricing scan)",
              "achieved": PRICE_FLOPS_PER_COST * pr_e / max(pr_ms, 1e-12) / 1e9,
              "peak": FP64_VECTOR_PEAK_TF, "unit": "TFLOP/s",
              "avg_launch_us": 1e3 * pr_ms / max(pr_n, 1), "launches": pr_n, "total_ms": pr_ms,
              "traffic": None}
-    for r in (spmv, price):
+    dg_ms = sum(i["diag_ms"] for i in infos)
+    dg_n = sum(i["diag_launches"] for i in infos)
+    dg_f = sum(i["diag_flops"] for i in infos)
+    up_ms = sum(i["update_ms"] for i in infos)
+    up_n = sum(i["update_launches"] for i in infos)
+    up_f = sum(i["update_flops"] for i in infos)
+    diag = {"bound": "alu", "kernel": "ldl_diag (64x64 diagonal-block LDL^T and inverse of its "
+            "unit lower factor, one wavefront)",
+            "achieved": dg_f / max(dg_ms, 1e-12) / 1e9, "peak": FP64_VECTOR_PEAK_TF,
+            "unit": "TFLOP/s", "avg_launch_us": 1e3 * dg_ms / max(dg_n, 1), "launches": dg_n,
+            "total_ms": dg_ms, "traffic": measured_traffic("ldl_diag"),
+            "algorithmic_flops_per_launch": dg_f / max(dg_n, 1)}
+    update = {"bound": "mfma", "kernel": "ldl_update (trailing update of the dense LDL^T)",
+              "achieved": up_f / max(up_ms, 1e-12) / 1e9, "peak": FP64_MATRIX_PEAK_TF,
+              "unit": "TFLOP/s", "avg_launch_us": 1e3 * up_ms / max(up_n, 1), "launches": up_n,
+              "total_ms": up_ms, "traffic": None,
+              "algorithmic_flops_per_launch": up_f / max(up_n, 1)}
+    named = {"spmv_dir": spmv, "price_pass": price, "ldl_diag": diag, "ldl_update": update}
+    for r in named.values():
         r["frac"] = r["achieved"] / r["peak"]
-    dominant, other = (spmv, price) if spmv_ms >= pr_ms else (price, spmv)
-    return dominant, other, pr_e / max(pr_ms, 1e-12) / 1e6
+    top = max(named, key=lambda k: named[k]["total_ms"])
+    other = {k: v for k, v in named.items() if k != top and v["launches"] > 0}
+    return named[top], other, pr_e / max(pr_ms, 1e-12) / 1e6
 
 
 def main():

@@ -159,7 +159,7 @@ typedef struct otip_info {
     double seconds_setup;      /* initial support, starting point */
     double seconds_final;      /* polish, purification, certificate */
     int64_t pricing_scans;     /* full m*n passes of the pricing and certificate scans */
-    /* with params.profile: event-timed launches of the two hot kernels */
+    /* with params.profile: event-timed launches of the hot kernels */
     int64_t spmv_launches;     /* Schur SpMV launches inside CG (fused with the direction
                                   update p = z + beta p) */
     double spmv_ms;            /* their summed durations */
@@ -168,6 +168,16 @@ typedef struct otip_info {
     int64_t price_launches;    /* pricing-pass launches */
     double price_ms;
     double price_elems;        /* reduced costs evaluated: m*n per launch */
+    int64_t diag_launches;     /* diagonal-block factor launches of the dense LDL^T (those of
+                                  the first of every 8 factorisations: events at every dispatch
+                                  of the dependent chain would slow it) */
+    double diag_ms;
+    double diag_flops;         /* 2 b^3 / 3 per launch of a b x b block (factor and inverse of
+                                  its unit lower factor, b^3 / 3 each) */
+    int64_t update_launches;   /* trailing-update launches of the dense LDL^T (same sample) */
+    double update_ms;
+    double update_flops;       /* r^2 b per launch: the lower triangle of an r x r trailing
+                                  matrix less a rank-b product */
 } otip_info;
 
 typedef struct otip_ctx otip_ctx;

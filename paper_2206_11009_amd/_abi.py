@@ -53,7 +53,9 @@ class otip_info(ctypes.Structure):
         ("seconds_direct", _c_f64), ("seconds_update", _c_f64), ("seconds_setup", _c_f64),
         ("seconds_final", _c_f64), ("pricing_scans", _c_i64), ("spmv_launches", _c_i64),
         ("spmv_ms", _c_f64), ("spmv_bytes", _c_f64), ("price_launches", _c_i64),
-        ("price_ms", _c_f64), ("price_elems", _c_f64),
+        ("price_ms", _c_f64), ("price_elems", _c_f64), ("diag_launches", _c_i64),
+        ("diag_ms", _c_f64), ("diag_flops", _c_f64), ("update_launches", _c_i64),
+        ("update_ms", _c_f64), ("update_flops", _c_f64),
     ]
 
     def as_dict(self):

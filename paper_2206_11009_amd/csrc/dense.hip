@@ -468,18 +468,24 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
     hipLaunchKernelGGL(dense_fill, dim3(n), dim3(64), 0, st, n, S.rowptr.get(), S.col.get(),
                        S.val.get(), A, orig_.get());
     OTIP_HIP(hipMemsetAsync(ninf_.get(), 0, sizeof(int), st));
+    const bool timed = factorisations_++ % std::max(1, timer_stride) == 0;
+    LaunchTimer *tdiag = timed ? diag_timer : nullptr, *tupd = timed ? update_timer : nullptr;
     for (int kb = 0; kb < n; kb += NB) {
         const int nb = std::min(NB, n - kb);
         double *Li = linv + (size_t)(kb / NB) * NB * NB;
-        hipLaunchKernelGGL(ldl_diag, dim3(1), dim3(64), 0, st, n, kb, nb, A, orig_.get(),
-                           d_.get(), pivtol, ninf_.get(), Li);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (tdiag) tdiag->arm(2.0 * nb * nb * nb / 3.0, &e0, &e1);
+        hipExtLaunchKernelGGL(ldl_diag, dim3(1), dim3(64), 0, st, e0, e1, 0, n, kb, nb, A,
+                              (const double *)orig_.get(), d_.get(), pivtol, ninf_.get(), Li);
         const int rows = n - kb - nb;
         if (rows > 0) {
             hipLaunchKernelGGL(ldl_panel, dim3(grid_for(rows, NB)), dim3(256), 0, st, n, kb, nb,
                                A, d_.get(), W_.get(), Li);
             const unsigned tiles = grid_for(rows, NB);
-            hipLaunchKernelGGL(ldl_update, dim3(tiles * (tiles + 1) / 2), dim3(256), 0, st, n, kb,
-                               nb, A, W_.get());
+            e0 = e1 = nullptr;
+            if (tupd) tupd->arm((double)rows * rows * nb, &e0, &e1);
+            hipExtLaunchKernelGGL(ldl_update, dim3(tiles * (tiles + 1) / 2), dim3(256), 0, st, e0,
+                                  e1, 0, n, kb, nb, A, (const double *)W_.get());
         }
     }
     // X = L^-1 (unit lower; the strict lower part of A holds L)
@@ -518,6 +524,8 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
     OTIP_HIP(hipMemcpyAsync(&hc, c.get(), sizeof(hc), hipMemcpyDeviceToHost, st));
     OTIP_HIP(hipMemcpyAsync(&hbad, bad_.get(), sizeof(int), hipMemcpyDeviceToHost, st));
     OTIP_HIP(hipStreamSynchronize(st));
+    if (tdiag) tdiag->collect();
+    if (tupd) tupd->collect();
     nnzL_ = (int64_t)hc + n;
     inverse_ok_ = hbad == 0;
     if (!inverse_ok_)  // U = L^T for the backward substitution

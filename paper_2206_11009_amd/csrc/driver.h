@@ -86,7 +86,7 @@ class Solver {
     SchurSolver schur;
     DenseLDL ldl;
     DBuf<char> tmp;
-    LaunchTimer t_spmv, t_price;
+    LaunchTimer t_spmv, t_price, t_diag, t_upd;
 
     int m = 0, n = 0;
     const int32_t *xs = nullptr, *xt = nullptr;

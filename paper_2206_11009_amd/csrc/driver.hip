@@ -807,6 +807,9 @@ void Solver::reset_state() {
     t_pricing = t_newton = t_direct = t_update = t_setup = t_final = 0.0;
     t_spmv.reset();
     t_price.reset();
+    t_diag.reset();
+    t_upd.reset();
+    ldl.restart_sampling();
     scan.scans = 0;
     warm_used = false;
 }
@@ -815,9 +818,11 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
     const double T0 = now();
     reset_state();
     P = prm;
-    t_spmv.on = t_price.on = P.profile != 0;
+    t_spmv.on = t_price.on = t_diag.on = t_upd.on = P.profile != 0;
     schur.timer = &t_spmv;
     scan.timer = &t_price;
+    ldl.diag_timer = &t_diag;
+    ldl.update_timer = &t_upd;
     scan.tile = P.price_tile;
     m = pr.m;
     n = pr.n;
@@ -1233,6 +1238,12 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
     res.info.price_launches = t_price.launches;
     res.info.price_ms = t_price.ms;
     res.info.price_elems = t_price.work;
+    res.info.diag_launches = t_diag.launches;
+    res.info.diag_ms = t_diag.ms;
+    res.info.diag_flops = t_diag.work;
+    res.info.update_launches = t_upd.launches;
+    res.info.update_ms = t_upd.ms;
+    res.info.update_flops = t_upd.work;
     return status;
 }
 

@@ -162,12 +162,19 @@ class DenseLDL {
     void solve(hipStream_t st, const double *b, double *x);
     int64_t nnz_L() const { return nnzL_; }
     int n = 0;
+    // optional timers of the diagonal-factor and trailing-update launches;
+    // they time the first of every timer_stride factorisations (events at
+    // every dispatch of a dependent chain slow it down)
+    LaunchTimer *diag_timer = nullptr, *update_timer = nullptr;
+    int timer_stride = 8;
+    void restart_sampling() { factorisations_ = 0; }
 
   private:
     DBuf<double> A_, X_, XT_, T_, d_, orig_, W_, v_, linv_;
     DBuf<int> ninf_, bad_;
     DBuf<unsigned long long> cnt_;
     int64_t nnzL_ = 0;
+    int64_t factorisations_ = 0;
     bool inverse_ok_ = true;
 };
 
