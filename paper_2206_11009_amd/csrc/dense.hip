@@ -113,39 +113,43 @@ __global__ __launch_bounds__(64) void ldl_diag(int n, int kb, int nb, double *A,
 }
 
 // Rows below the diagonal block: W21 = A21 L11^-T (so W21 = L21 D1) and
-// L21 = W21 D1^-1.  A 64-row tile of A21 and Linv are staged in LDS and
-// W = A21 Linv^T is formed on the FP64 matrix cores (Linv is zero above its
-// diagonal); each wave forms a 32 x 32 quarter as 2 x 2 blocks of 16 x 16.
+// L21 = W21 D1^-1.  One workgroup per 64-row tile forms W = A21 Linv^T on the
+// FP64 matrix cores (Linv is zero above its diagonal); each wave forms a
+// 32 x 32 quarter as 2 x 2 blocks of 16 x 16, with its operands loaded straight
+// from global memory into the registers of the matrix-core layout (no LDS, no
+// barrier).
 __global__ __launch_bounds__(256) void ldl_panel(int n, int kb, int nb, double *A,
                                                  const double *d, double *W,
                                                  const double *Linv) {
-    __shared__ double As[NB][NB + 1];
-    __shared__ double Li[NB][NB + 1];
     const int r0 = kb + nb + blockIdx.x * NB;
     const int rows = n - kb - nb;
-    for (int t = threadIdx.x; t < NB * NB; t += 256) {
-        const int a = t % NB, k = t / NB;
-        As[a][k] = (r0 + a < n && k < nb) ? A[(size_t)(r0 + a) + (size_t)(kb + k) * n] : 0.0;
-        Li[a][k] = Linv[(size_t)a + (size_t)k * NB];  // Linv(a, k)
-    }
-    __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
+    // operands: A(r0 + wr + 16u + li, kb + c) and Linv(wc + 16u + li, c), c = 4t + lk
+    double av[2][16], bv[2][16];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int ii = r0 + wr + 16 * u + li, kk = wc + 16 * u + li;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int c = 4 * t + lk;
+            av[u][t] = (ii < n && c < nb) ? A[(size_t)ii + (size_t)(kb + c) * n] : 0.0;
+            bv[u][t] = Linv[(size_t)kk + (size_t)c * NB];
+        }
+    }
     d4 acc[2][2];
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
         for (int v = 0; v < 2; ++v) acc[u][v] = d4{0.0, 0.0, 0.0, 0.0};
-    // W(a, k) = sum_t A(a, t) Linv(k, t)
-#pragma unroll 4
-    for (int t = 0; t < NB; t += 4) {
-        const double a0 = As[wr + li][t + lk], a1 = As[wr + 16 + li][t + lk];
-        const double b0 = Li[wc + li][t + lk], b1 = Li[wc + 16 + li][t + lk];
-        acc[0][0] = mfma4(a0, b0, acc[0][0]);
-        acc[0][1] = mfma4(a0, b1, acc[0][1]);
-        acc[1][0] = mfma4(a1, b0, acc[1][0]);
-        acc[1][1] = mfma4(a1, b1, acc[1][1]);
+    // W(a, k) = sum_c A(a, c) Linv(k, c)
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        acc[0][0] = mfma4(av[0][t], bv[0][t], acc[0][0]);
+        acc[0][1] = mfma4(av[0][t], bv[1][t], acc[0][1]);
+        acc[1][0] = mfma4(av[1][t], bv[0][t], acc[1][0]);
+        acc[1][1] = mfma4(av[1][t], bv[1][t], acc[1][1]);
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u)
@@ -153,9 +157,8 @@ __global__ __launch_bounds__(256) void ldl_panel(int n, int kb, int nb, double *
         for (int v = 0; v < 2; ++v)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int a = wr + 16 * u + mfma_row(lane, q);
+                const int i = r0 + wr + 16 * u + mfma_row(lane, q);
                 const int k = wc + 16 * v + li;
-                const int i = r0 + a;
                 if (i < n && k < nb) {
                     const double dd = d[kb + k];
                     const bool inf = isinf(dd);
