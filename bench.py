@@ -16,8 +16,9 @@ its dispatches; the timed kernels are the Schur SpMV, the pricing pass and the
 dense factor's diagonal-block and trailing-update kernels, and the one with the
 largest total time is reported, the others beside it), pricing throughput, the same instances solved by the
 mixed-precision and learned-warm-start forms ("forms"; the network's prediction
-is inside the timed region), and the CPU oracle timed on a bounded sample of the
-same workload.  --config c4 times whole batches of 512 uneven instances
+is inside the timed region), the same instances under the 1-, 2- and inf-norm
+costs of the paper's experiments ("norm_costs"), and the CPU oracle timed on a
+bounded sample of the same workload.  --config c4 times whole batches of 512 uneven instances
 (otip_solve_batch) and reports seconds per LP of the batch.
 """
 from __future__ import annotations
@@ -119,7 +120,7 @@ def side_of(inst):
     return side if side * side == inst.m == inst.n else None
 
 
-def run_single(ctx, dev, insts, prm, weights, steps, warmup):
+def run_single(ctx, dev, insts, prm, weights, steps, warmup, cost_kind=0):
     """Seconds per LP over `steps` solves (after `warmup`), with the learned
     prediction (inside the timed region) when weights are given."""
     import torch
@@ -128,9 +129,9 @@ def run_single(ctx, dev, insts, prm, weights, steps, warmup):
     def one(k):
         a, b, xs, xt = dev[k]
         if weights is None:
-            return otip.otip_solve(ctx, a, b, xs, xt, prm)
+            return otip.otip_solve(ctx, a, b, xs, xt, prm, cost_kind=cost_kind)
         y0, z0 = otip.otip_ws_predict(ctx, weights, side_of(insts[k]), a, b)
-        return otip.otip_solve(ctx, a, b, xs, xt, prm, y0=y0, z0=z0)
+        return otip.otip_solve(ctx, a, b, xs, xt, prm, y0=y0, z0=z0, cost_kind=cost_kind)
 
     for k in range(warmup):
         one(k)
@@ -298,6 +299,14 @@ def main():
                            args.warmup)
             forms[name] = summary(s2, inf2)
             forms[name]["speedup_vs_plain"] = sec / s2
+    # the same problems under the costs of Section 5.1 (1-, 2- and inf-norm of
+    # the pixel offset), plain FP64 method
+    norm_costs = {}
+    if not args.no_forms and not batched:
+        for name, kind in (("l1", 1), ("l2", 2), ("linf", 3)):
+            s3, inf3 = run_single(ctx, dev, insts, otip.params(precision=prec, **tune), None,
+                                  args.steps, args.warmup, cost_kind=kind)
+            norm_costs[name] = summary(s3, inf3)
 
     out = {
         "metric": baseline_metric(),
@@ -324,6 +333,7 @@ def main():
         "cg_iterations_mean": forms[f"{args.precision}_plain"]["cg_iterations_mean"],
         "rel_gap_max": forms[f"{args.precision}_plain"]["rel_gap_max"],
         "forms": forms,
+        "norm_costs": norm_costs,
     }
     if not args.no_cpu_baseline and not batched:
         out["cpu_baseline"] = cpu_baseline(args.config, fallback_its=out["iterations_mean"])

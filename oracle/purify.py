@@ -22,10 +22,12 @@ The steps are written plainly:
    the flow on e by t lowers the 1st, 3rd, ... path edges and raises the 2nd,
    4th, ... ones by t.  The cost changes by t * (c_e + sum c_plus - sum c_minus),
    an exact integer for integer costs (a correctly rounded sum otherwise).
-3. If that change is <= 0 push t > 0 ("+" direction, also on a tie), else push
-   in the "-" direction; t is the smallest flow among the edges that decrease
-   (ties: lowest variable index).  That bottleneck edge is set to exactly 0 and
-   leaves; if it was a forest edge, e takes its place in F.
+3. If that change is < 0 push t > 0 ("+" direction), else, on a tie too, push
+   in the "-" direction (e decreases: on a tie either direction keeps the cost,
+   and e, the smallest flow on its cycle of the maximum-flow forest, then
+   usually leaves, so the forest stays); t is the smallest flow among the edges
+   that decrease (ties: lowest variable index).  That bottleneck edge is set to
+   exactly 0 and leaves; if it was a forest edge, e takes its place in F.
 """
 from __future__ import annotations
 
@@ -125,7 +127,7 @@ def purify_to_forest(rows, cols, flows, costs, m, n):
         minus = path[0::2]
         plus = path[1::2]
         dcost = math.fsum([cs[e]] + [cs[k] for k in plus] + [-cs[k] for k in minus])
-        if dcost <= 0:
+        if dcost < 0:
             dec, inc = minus, [e] + plus
         else:
             dec, inc = [e] + plus, minus

@@ -48,6 +48,18 @@ struct Forest {
 
     Forest(int v, int E) : V(v), adj(v), in_forest(E, 0), parent(v, -1), pedge(v, -1), depth(v, 0) {}
 
+    // remove edge e from the adjacency of node u (the lists hold forest edges
+    // only, so that re-hanging a subtree walks the tree and nothing else)
+    void unlink(int u, int e) {
+        auto &L = adj[u];
+        for (size_t q = 0; q < L.size(); ++q)
+            if (L[q].second == e) {
+                L[q] = L.back();
+                L.pop_back();
+                return;
+            }
+    }
+
     void hang(int root, int par, int pe, int d0) {
         // BFS over forest edges from root, parent pointers away from `par`
         std::queue<int> q;
@@ -178,8 +190,11 @@ static bool purify_attempt(int m, int n, const std::vector<int32_t> &rows_in,
         ExactSum dcost;
         dcost.add(W[e]);
         for (size_t t = 0; t < path.size(); ++t) dcost.add((t % 2 == 0) ? -W[path[t]] : W[path[t]]);
+        // e increases only where that lowers the cost; on a tie it decreases,
+        // and as the smallest flow on its cycle of the maximum-flow forest it
+        // then usually leaves, so the forest is not re-hung
         std::vector<int> dec, inc;
-        if (dcost.sign() <= 0) {
+        if (dcost.sign() < 0) {
             inc.push_back(e);
             for (size_t t = 0; t < path.size(); ++t) (t % 2 == 0 ? dec : inc).push_back(path[t]);
         } else {
@@ -200,6 +215,8 @@ static bool purify_attempt(int m, int n, const std::vector<int32_t> &rows_in,
             const int child = (fo.parent[bu] == bv && fo.pedge[bu] == bott) ? bu : bv;
             fo.in_forest[bott] = 0;
             fo.in_forest[e] = 1;
+            fo.unlink(bu, bott);
+            fo.unlink(bv, bott);
             fo.adj[u].push_back({v, e});
             fo.adj[v].push_back({u, e});
             // which endpoint of e lies in the detached subtree of `child`?
