@@ -6,9 +6,11 @@
 // n x n array, block width 64:
 //   1. the 64 x 64 diagonal block is factorised by one wavefront, which also
 //      inverts its unit lower factor;
-//   2. every row below solves w_i L11^T = a_i (w = L21 D1) and l_i = w_i D1^-1;
+//   2. the rows below form W21 = A21 L11^-T (= L21 D1) and L21 = W21 D1^-1;
 //   3. the trailing lower triangle is updated, A22 -= L21 W21^T, in 64 x 64
-//      tiles staged through LDS.
+//      tiles.
+// Steps 2 and 3 run on the FP64 matrix cores with operands loaded straight
+// into registers.
 // A pivot d_k <= pivtol * S_kk (original diagonal) or d_k <= 0 becomes +inf:
 // its column of L is zero and the solve returns 0 for that unknown.
 // After the factorisation X = L^-1 is formed (recursive doubling with tiled
@@ -199,6 +201,21 @@ __global__ __launch_bounds__(256) void ldl_update(int n, int kb, int nb, double 
             bv[u][t] = (jj < rows && k < nb) ? W[(size_t)jj + (size_t)k * rows] : 0.0;
         }
     }
+    // the tile's current values, requested with the operands so that their
+    // latency is hidden behind the products
+    double cur[2][2][4];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int ii = i0 + wr + 16 * u + mfma_row(lane, q);
+                const int jj = j0 + wc + 16 * v + li;
+                cur[u][v][q] = (ii < rows && jj < rows && ii >= jj)
+                                   ? A[(size_t)(r0 + ii) + (size_t)(r0 + jj) * n]
+                                   : 0.0;
+            }
     d4 acc[2][2];
 #pragma unroll
     for (int u = 0; u < 2; ++u)
@@ -219,10 +236,8 @@ __global__ __launch_bounds__(256) void ldl_update(int n, int kb, int nb, double 
             for (int q = 0; q < 4; ++q) {
                 const int ii = i0 + wr + 16 * u + mfma_row(lane, q);
                 const int jj = j0 + wc + 16 * v + li;
-                if (ii < rows && jj < rows && ii >= jj) {
-                    double *p = &A[(size_t)(r0 + ii) + (size_t)(r0 + jj) * n];
-                    *p -= acc[u][v][q];
-                }
+                if (ii < rows && jj < rows && ii >= jj)
+                    A[(size_t)(r0 + ii) + (size_t)(r0 + jj) * n] = cur[u][v][q] - acc[u][v][q];
             }
 }
 
