@@ -177,7 +177,9 @@ typedef struct otip_info {
     int64_t update_launches;   /* trailing-update launches of the dense LDL^T (same sample) */
     double update_ms;
     double update_flops;       /* r^2 b per launch: the lower triangle of an r x r trailing
-                                  matrix less a rank-b product */
+                                  matrix less a rank-b product (b = 64 or, two block columns
+                                  at once, 128); 2b (c(r-c) + c(c+1)/2) for a launch that
+                                  updates only the next c-wide block column */
 } otip_info;
 
 typedef struct otip_ctx otip_ctx;

@@ -171,36 +171,43 @@ __global__ __launch_bounds__(256) void ldl_panel(int n, int kb, int nb, double *
             }
 }
 
-// A22 -= L21 W21^T on lower-triangular 64x64 tiles, one workgroup per tile of
+// A22 -= sum over panels of L21 W21^T on lower-triangular 64x64 tiles of the
+// trailing matrix that starts at row and column r0, one workgroup per tile of
 // the lower triangle (1D grid, tile (ti, tj) with tj <= ti from the block
 // index); each wave forms a 32x32 quarter of the tile as 2x2 blocks of 16x16
 // matrix-core products, with its operands loaded straight from global memory
-// into the registers of the matrix-core layout (no LDS, no barrier).
-__global__ __launch_bounds__(256) void ldl_update(int n, int kb, int nb, double *A,
-                                                  const double *W) {
-    const int r0 = kb + nb;
+// into the registers of the matrix-core layout (no LDS, no barrier).  Panel p
+// holds the columns [kcol, kcol + nb) of L (in A) and its W with row r0 + j at
+// wrow0 + j (leading dimension wld).  Two panels per launch halve the passes
+// over the trailing matrix; first_col restricts the launch to the first tile
+// column (the next diagonal block and the rows below it).
+struct UpdPanel {
+    const double *W;
+    int kcol, nb, wrow0, wld;
+};
+struct UpdArgs {
+    int n, r0, first_col;
+    UpdPanel p[2];
+};
+template <int NP>
+__global__ __launch_bounds__(256) void ldl_update(double *A, UpdArgs a) {
+    const int n = a.n, r0 = a.r0;
     const int rows = n - r0;
     const int blk = blockIdx.x;
-    int ti = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);
-    while ((ti + 1) * (ti + 2) / 2 <= blk) ++ti;
-    while (ti * (ti + 1) / 2 > blk) --ti;
-    const int tj = blk - ti * (ti + 1) / 2;
+    int ti, tj;
+    if (a.first_col) {
+        ti = blk;
+        tj = 0;
+    } else {
+        ti = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);
+        while ((ti + 1) * (ti + 2) / 2 <= blk) ++ti;
+        while (ti * (ti + 1) / 2 > blk) --ti;
+        tj = blk - ti * (ti + 1) / 2;
+    }
     const int i0 = ti * NB, j0 = tj * NB;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
-    // operands: L(i0 + wr + 16u + li, k) and W(j0 + wc + 16v + li, k), k = 4t + lk
-    double av[2][16], bv[2][16];
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        const int ii = i0 + wr + 16 * u + li, jj = j0 + wc + 16 * u + li;
-#pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            const int k = 4 * t + lk;
-            av[u][t] = (ii < rows && k < nb) ? A[(size_t)(r0 + ii) + (size_t)(kb + k) * n] : 0.0;
-            bv[u][t] = (jj < rows && k < nb) ? W[(size_t)jj + (size_t)k * rows] : 0.0;
-        }
-    }
     // the tile's current values, requested with the operands so that their
     // latency is hidden behind the products
     double cur[2][2][4];
@@ -222,11 +229,32 @@ __global__ __launch_bounds__(256) void ldl_update(int n, int kb, int nb, double 
 #pragma unroll
         for (int v = 0; v < 2; ++v) acc[u][v] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        acc[0][0] = mfma4(av[0][t], bv[0][t], acc[0][0]);
-        acc[0][1] = mfma4(av[0][t], bv[1][t], acc[0][1]);
-        acc[1][0] = mfma4(av[1][t], bv[0][t], acc[1][0]);
-        acc[1][1] = mfma4(av[1][t], bv[1][t], acc[1][1]);
+    for (int pi = 0; pi < NP; ++pi) {
+        const UpdPanel P = a.p[pi];
+        // operands: L(r0 + i0 + wr + 16u + li, kcol + k) and W(j0 + wc + 16u + li, k),
+        // k = 4t + lk
+        double av[2][16], bv[2][16];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int ii = i0 + wr + 16 * u + li, jj = j0 + wc + 16 * u + li;
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const int k = 4 * t + lk;
+                av[u][t] = (ii < rows && k < P.nb)
+                               ? A[(size_t)(r0 + ii) + (size_t)(P.kcol + k) * n]
+                               : 0.0;
+                bv[u][t] = (jj < rows && k < P.nb)
+                               ? P.W[(size_t)(P.wrow0 + jj) + (size_t)k * P.wld]
+                               : 0.0;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            acc[0][0] = mfma4(av[0][t], bv[0][t], acc[0][0]);
+            acc[0][1] = mfma4(av[0][t], bv[1][t], acc[0][1]);
+            acc[1][0] = mfma4(av[1][t], bv[0][t], acc[1][0]);
+            acc[1][1] = mfma4(av[1][t], bv[1][t], acc[1][1]);
+        }
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u)
@@ -479,7 +507,7 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
     double *A = A_.need(total);
     d_.need(n);
     orig_.need(n);
-    W_.need((size_t)n * NB);
+    W_.need((size_t)2 * n * NB);
     double *linv = linv_.need((size_t)nblk * NB * NB);
     ninf_.need(1);
     hipLaunchKernelGGL(dense_zero, dim3(2048), dim3(256), 0, st, total, A);
@@ -488,22 +516,55 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
     OTIP_HIP(hipMemsetAsync(ninf_.get(), 0, sizeof(int), st));
     const bool timed = factorisations_++ % std::max(1, timer_stride) == 0;
     LaunchTimer *tdiag = timed ? diag_timer : nullptr, *tupd = timed ? update_timer : nullptr;
-    for (int kb = 0; kb < n; kb += NB) {
-        const int nb = std::min(NB, n - kb);
-        double *Li = linv + (size_t)(kb / NB) * NB * NB;
+    double *Wa = W_.get(), *Wb = W_.get() + (size_t)n * NB;
+    auto diag = [&](int kb, int nb) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (tdiag) tdiag->arm(2.0 * nb * nb * nb / 3.0, &e0, &e1);
         hipExtLaunchKernelGGL(ldl_diag, dim3(1), dim3(64), 0, st, e0, e1, 0, n, kb, nb, A,
-                              (const double *)orig_.get(), d_.get(), pivtol, ninf_.get(), Li);
+                              (const double *)orig_.get(), d_.get(), pivtol, ninf_.get(),
+                              linv + (size_t)(kb / NB) * NB * NB);
+    };
+    auto panel = [&](int kb, int nb, double *W) {
+        hipLaunchKernelGGL(ldl_panel, dim3(grid_for(n - kb - nb, NB)), dim3(256), 0, st, n, kb,
+                           nb, A, d_.get(), W, (const double *)(linv + (size_t)(kb / NB) * NB * NB));
+    };
+    auto update = [&](int np, const UpdArgs &u, unsigned blocks, double flops) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (tupd) tupd->arm(flops, &e0, &e1);
+        if (np == 2)
+            hipExtLaunchKernelGGL(ldl_update<2>, dim3(blocks), dim3(256), 0, st, e0, e1, 0, A, u);
+        else
+            hipExtLaunchKernelGGL(ldl_update<1>, dim3(blocks), dim3(256), 0, st, e0, e1, 0, A, u);
+    };
+    // Block steps, two at a time where a pair leaves rows below it: after
+    // the first block's panel only the second block's column is updated, the
+    // second block is factorised, and the rest of the trailing matrix takes
+    // both panels in one pass.
+    for (int kb = 0; kb < n;) {
+        const int nb = std::min(NB, n - kb);
+        diag(kb, nb);
         const int rows = n - kb - nb;
-        if (rows > 0) {
-            hipLaunchKernelGGL(ldl_panel, dim3(grid_for(rows, NB)), dim3(256), 0, st, n, kb, nb,
-                               A, d_.get(), W_.get(), Li);
-            const unsigned tiles = grid_for(rows, NB);
-            e0 = e1 = nullptr;
-            if (tupd) tupd->arm((double)rows * rows * nb, &e0, &e1);
-            hipExtLaunchKernelGGL(ldl_update, dim3(tiles * (tiles + 1) / 2), dim3(256), 0, st, e0,
-                                  e1, 0, n, kb, nb, A, (const double *)W_.get());
+        if (rows == 0) break;
+        panel(kb, nb, Wa);
+        const UpdPanel pa{Wa, kb, nb, 0, rows};
+        const int kb2 = kb + nb, nb2 = std::min(NB, n - kb2), rows2 = n - kb2 - nb2;
+        if (rows2 > 0) {
+            UpdArgs u1{n, kb2, 1, {pa, pa}};
+            update(1, u1, grid_for(rows, NB),
+                   2.0 * nb * ((double)nb2 * (rows - nb2) + nb2 * (nb2 + 1) / 2.0));
+            diag(kb2, nb2);
+            panel(kb2, nb2, Wb);
+            const UpdPanel pa2{Wa, kb, nb, nb2, rows};
+            const UpdPanel pb{Wb, kb2, nb2, 0, rows2};
+            UpdArgs u2{n, kb2 + nb2, 0, {pa2, pb}};
+            const unsigned t2 = grid_for(rows2, NB);
+            update(2, u2, t2 * (t2 + 1) / 2, (double)rows2 * rows2 * (nb + nb2));
+            kb = kb2 + nb2;
+        } else {
+            UpdArgs u1{n, kb2, 0, {pa, pa}};
+            const unsigned t1 = grid_for(rows, NB);
+            update(1, u1, t1 * (t1 + 1) / 2, (double)rows * rows * nb);
+            kb = kb2;
         }
     }
     // X = L^-1 (unit lower; the strict lower part of A holds L)
