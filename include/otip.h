@@ -332,8 +332,9 @@ int otip_pcg(otip_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr, const
  *     the length.  OTIP_EINVAL before any solve or when cap is too small.
  *   otip_state_load: reads a record (HOST bytes) and makes the context's next
  *     otip_solve continue from it instead of building an initial support;
- *     that solve must be of the same problem (m, n and the bytes of a, b, xs,
- *     xt, compared through a 64-bit hash), else it fails with OTIP_EINVAL.
+ *     that solve must be of the same problem (m, n, the cost kind and the
+ *     bytes of a, b, xs, xt, compared through a 64-bit hash), else it fails
+ *     with OTIP_EINVAL.
  *     The record is checked (sizes, increasing support indices below m*n, an
  *     interior iterate) before it reaches the device.  y0/z0 are ignored by a
  *     resumed solve.

@@ -29,7 +29,7 @@ enum class Mode { PCG, Direct };
 // exactly as if it had not stopped.  Host memory.
 struct Checkpoint {
     int32_t m = 0, n = 0;
-    uint64_t fingerprint = 0;  // of m, n and the bytes of a, b, xs, xt
+    uint64_t fingerprint = 0;  // of m, n, the cost kind and the bytes of a, b, xs, xt
     int32_t it = 0, mode = 0, cg_its_last = 0, solves_last = 2, cg_failed = 0, warm_used = 0;
     int32_t direct_its = 0;
     int64_t psi = 0, psi_max = 0, cg_total = 0;
