@@ -122,7 +122,9 @@ __global__ __launch_bounds__(64) void ldl_diag(int n, int kb, int nb, double *A,
 // barrier).
 __global__ __launch_bounds__(256) void ldl_panel(int n, int kb, int nb, double *A,
                                                  const double *d, double *W,
-                                                 const double *Linv) {
+                                                 const double *Linv,
+                                                 unsigned long long *nnz) {
+    int nz = 0;  // nonzeros of L21 written here (the fill statistic)
     const int r0 = kb + nb + blockIdx.x * NB;
     const int rows = n - kb - nb;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -165,10 +167,14 @@ __global__ __launch_bounds__(256) void ldl_panel(int n, int kb, int nb, double *
                     const double dd = d[kb + k];
                     const bool inf = isinf(dd);
                     const double wk = inf ? 0.0 : acc[u][v][q];
+                    const double lv = inf ? 0.0 : wk / dd;
                     W[(size_t)(i - kb - nb) + (size_t)k * rows] = wk;
-                    A[(size_t)i + (size_t)(kb + k) * n] = inf ? 0.0 : wk / dd;
+                    A[(size_t)i + (size_t)(kb + k) * n] = lv;
+                    nz += lv != 0.0;
                 }
             }
+    nz = wave_sum_i(nz);
+    if ((threadIdx.x & 63) == 0 && nz) atomicAdd(nnz, (unsigned long long)nz);
 }
 
 // A22 -= sum over panels of L21 W21^T on lower-triangular 64x64 tiles of the
@@ -464,40 +470,42 @@ __global__ void scale_by_pivots(int n, const double *__restrict__ d, double *y) 
 }
 
 // U = L^T (64 x 64 tiles through LDS), unit diagonal implied
+// Nonzeros of the strict lower part of every 64 x 64 diagonal block of L (one
+// workgroup per block), for the fill statistic; the panels count the rest.
+__global__ __launch_bounds__(256) void count_diag_blocks(int n, const double *__restrict__ A,
+                                                         unsigned long long *nnz) {
+    const int kb = blockIdx.x * NB, nb = min(NB, n - kb);
+    int c = 0;
+    for (int t = threadIdx.x; t < NB * NB; t += 256) {
+        const int r = t % NB, q = t / NB;
+        c += (r < nb && q < r) && A[(size_t)(kb + r) + (size_t)(kb + q) * n] != 0.0;
+    }
+    c = wave_sum_i(c);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(nnz, (unsigned long long)c);
+}
+
+// (and, with a flag, sets it when an entry of the strict lower part is not
+// finite)
 __global__ __launch_bounds__(256) void transpose_lower(int n, const double *__restrict__ L,
-                                                       double *__restrict__ U) {
+                                                       double *__restrict__ U, int *flag) {
     __shared__ double tile[64][65];
     const int bi = blockIdx.x * 64, bj = blockIdx.y * 64;  // tile of L: rows bi.., cols bj..
     if (blockIdx.y > blockIdx.x) return;
+    bool bad = false;
     for (int t = threadIdx.x; t < 64 * 64; t += 256) {
         const int r = t % 64, c = t / 64;
         const int i = bi + r, j = bj + c;
-        tile[r][c] = (i < n && j < n && i > j) ? L[(size_t)i + (size_t)j * n] : 0.0;
+        const double v = (i < n && j < n && i > j) ? L[(size_t)i + (size_t)j * n] : 0.0;
+        bad |= !isfinite(v);
+        tile[r][c] = v;
     }
+    if (flag && __ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
     __syncthreads();
     for (int t = threadIdx.x; t < 64 * 64; t += 256) {
         const int r = t % 64, c = t / 64;  // U(bj + r, bi + c) = L(bi + c, bj + r)
         const int i = bj + r, j = bi + c;
         if (i < n && j < n) U[(size_t)i + (size_t)j * n] = tile[c][r];
     }
-}
-
-__global__ void any_nonfinite(size_t total, const double *__restrict__ X, int *flag) {
-    bool bad = false;
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-         t += (size_t)gridDim.x * blockDim.x)
-        bad |= !isfinite(X[t]);
-    if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
-}
-
-__global__ void count_nonzero_lower(int n, const double *A, unsigned long long *cnt) {
-    unsigned long long c = 0;
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < (size_t)n * n;
-         t += (size_t)gridDim.x * blockDim.x) {
-        const size_t i = t % n, j = t / n;
-        if (i > j && A[t] != 0.0) ++c;
-    }
-    if (c) atomicAdd(cnt, c);
 }
 
 int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
@@ -514,6 +522,8 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
     hipLaunchKernelGGL(dense_fill, dim3(n), dim3(64), 0, st, n, S.rowptr.get(), S.col.get(),
                        S.val.get(), A, orig_.get());
     OTIP_HIP(hipMemsetAsync(ninf_.get(), 0, sizeof(int), st));
+    unsigned long long *nzL = cnt_.need(1);  // nonzeros of L, counted where they are written
+    OTIP_HIP(hipMemsetAsync(nzL, 0, sizeof(unsigned long long), st));
     const bool timed = factorisations_++ % std::max(1, timer_stride) == 0;
     LaunchTimer *tdiag = timed ? diag_timer : nullptr, *tupd = timed ? update_timer : nullptr;
     double *Wa = W_.get(), *Wb = W_.get() + (size_t)n * NB;
@@ -526,7 +536,8 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
     };
     auto panel = [&](int kb, int nb, double *W) {
         hipLaunchKernelGGL(ldl_panel, dim3(grid_for(n - kb - nb, NB)), dim3(256), 0, st, n, kb,
-                           nb, A, d_.get(), W, (const double *)(linv + (size_t)(kb / NB) * NB * NB));
+                           nb, A, d_.get(), W, (const double *)(linv + (size_t)(kb / NB) * NB * NB),
+                           nzL);
     };
     auto update = [&](int np, const UpdArgs &u, unsigned blocks, double flops) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -588,19 +599,18 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
     OTIP_HIP(hipGetLastError());
     XT_.need(total);
     const unsigned tl = grid_for(n, 64);
-    hipLaunchKernelGGL(transpose_lower, dim3(tl, tl), dim3(256), 0, st, n, X, XT_.get());
-    DBuf<unsigned long long> &c = cnt_;
-    c.need(1);
-    OTIP_HIP(hipMemsetAsync(c.get(), 0, sizeof(unsigned long long), st));
-    hipLaunchKernelGGL(count_nonzero_lower, dim3(1024), dim3(256), 0, st, n, A, c.get());
     // an explicit inverse can overflow where the factor itself is finite
-    // (products of large multipliers): then solve by substitution
+    // (products of large multipliers): then solve by substitution.  The
+    // transpose reads all of X's strict lower part (its diagonal is 1, its
+    // upper part 0) and flags a non-finite entry.
+    hipLaunchKernelGGL(count_diag_blocks, dim3(nblk), dim3(256), 0, st, n, (const double *)A, nzL);
     OTIP_HIP(hipMemsetAsync(bad_.need(1), 0, sizeof(int), st));
-    hipLaunchKernelGGL(any_nonfinite, dim3(1024), dim3(256), 0, st, total, X, bad_.get());
+    hipLaunchKernelGGL(transpose_lower, dim3(tl, tl), dim3(256), 0, st, n, X, XT_.get(),
+                       bad_.get());
     int hn = 0, hbad = 0;
     unsigned long long hc = 0;
     OTIP_HIP(hipMemcpyAsync(&hn, ninf_.get(), sizeof(int), hipMemcpyDeviceToHost, st));
-    OTIP_HIP(hipMemcpyAsync(&hc, c.get(), sizeof(hc), hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipMemcpyAsync(&hc, nzL, sizeof(hc), hipMemcpyDeviceToHost, st));
     OTIP_HIP(hipMemcpyAsync(&hbad, bad_.get(), sizeof(int), hipMemcpyDeviceToHost, st));
     OTIP_HIP(hipStreamSynchronize(st));
     if (tdiag) tdiag->collect();
@@ -608,7 +618,8 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
     nnzL_ = (int64_t)hc + n;
     inverse_ok_ = hbad == 0;
     if (!inverse_ok_)  // U = L^T for the backward substitution
-        hipLaunchKernelGGL(transpose_lower, dim3(tl, tl), dim3(256), 0, st, n, A, XT_.get());
+        hipLaunchKernelGGL(transpose_lower, dim3(tl, tl), dim3(256), 0, st, n, A, XT_.get(),
+                           (int *)nullptr);
     return hn;
 }
 
