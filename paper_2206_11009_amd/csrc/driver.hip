@@ -535,6 +535,48 @@ void Solver::update_support(const uint64_t *add_idx, int64_t nadd, double pin,
 
 // removal (Section 3.2): small p leave once near convergence; the largest p of
 // every row and column stays so that no row or column is left uncovered.
+// G lanes per segment (a row of the compressed-row view, through its
+// positions, or a column of the compressed-column view): marks the entry of
+// largest p, ties to the smaller variable index.  That order is total, so the
+// marked entry does not depend on how the lanes split the segment.
+template <int G, bool ROWS>
+__global__ __launch_bounds__(256) void protect_max_k(int64_t segs, const int32_t *__restrict__ ptr,
+                                                     const int32_t *__restrict__ pos,
+                                                     const double *__restrict__ p,
+                                                     const uint64_t *__restrict__ id,
+                                                     uint8_t *__restrict__ prot) {
+    constexpr int groups = 256 / G;
+    const int g = threadIdx.x / G, l = threadIdx.x % G;
+    for (int64_t sg = (int64_t)blockIdx.x * groups + g; sg < segs;
+         sg += (int64_t)gridDim.x * groups) {
+        const int b = ptr[sg], e = ptr[sg + 1];
+        int best = -1;
+        double bp = 0.0;
+        unsigned long long bi = 0ull;
+        for (int q = b + l; q < e; q += G) {
+            const int k = ROWS ? pos[q] : q;
+            const double pk = p[k];
+            const unsigned long long ik = id[k];
+            if (best < 0 || pk > bp || (pk == bp && ik < bi)) {
+                best = k;
+                bp = pk;
+                bi = ik;
+            }
+        }
+        for (int o = G / 2; o > 0; o >>= 1) {
+            const int ob = __shfl_xor(best, o, G);
+            const double op = __shfl_xor(bp, o, G);
+            const unsigned long long oi = __shfl_xor(bi, o, G);
+            if (ob >= 0 && (best < 0 || op > bp || (op == bp && oi < bi))) {
+                best = ob;
+                bp = op;
+                bi = oi;
+            }
+        }
+        if (l == 0 && best >= 0) prot[best] = 1;
+    }
+}
+
 int64_t Solver::select_removals(uint8_t *removed) {
     const int64_t psi = psi_;
     uint8_t *pr = prot.get();
@@ -543,20 +585,13 @@ int64_t Solver::select_removals(uint8_t *removed) {
     const double *pp = p.get();
     const uint64_t *id = idx.get();
     const int32_t *rp = row_ptr.get(), *cp = csr_pos.get(), *cptr = col_ptr.get();
-    foreach(st, m, [=] __device__(int64_t i) {
-        int best = -1;
-        for (int e = rp[i]; e < rp[i + 1]; ++e) {
-            const int k = cp[e];
-            if (best < 0 || pp[k] > pp[best] || (pp[k] == pp[best] && id[k] < id[best])) best = k;
-        }
-        if (best >= 0) pr[best] = 1;
-    });
-    foreach(st, n, [=] __device__(int64_t j) {
-        int best = -1;
-        for (int k = cptr[j]; k < cptr[j + 1]; ++k)
-            if (best < 0 || pp[k] > pp[best] || (pp[k] == pp[best] && id[k] < id[best])) best = k;
-        if (best >= 0) pr[best] = 1;
-    });
+    // the largest entry of every row and every column stays (no row or
+    // column of the plan may lose its last entry)
+    hipLaunchKernelGGL((protect_max_k<16, true>), dim3(std::min<int64_t>(4096, (m + 15) / 16)),
+                       dim3(256), 0, st, (int64_t)m, rp, cp, pp, id, pr);
+    hipLaunchKernelGGL((protect_max_k<16, false>), dim3(std::min<int64_t>(4096, (n + 15) / 16)),
+                       dim3(256), 0, st, (int64_t)n, cptr, (const int32_t *)nullptr, pp, id, pr);
+    OTIP_HIP(hipGetLastError());
     const double *aa = a.get(), *bb = b.get();
     const int32_t *ii = si.get(), *jj = sj.get();
     const double rel = P.remove_rel;
