@@ -236,11 +236,16 @@ __global__ __launch_bounds__(256) void segsum_k(int64_t rows, F f) {
         if (l == 0) f.finish(r, acc);
     }
 }
+// lanes per segment: the segments are short (tens of entries) and their
+// entries are reached through dependent gathers, so more lanes per segment
+// put more of them in flight at once
+constexpr int kSegLanes = 32;
 template <class F>
 static void segsum(hipStream_t st, int64_t rows, F f) {
     if (rows <= 0) return;
-    const unsigned g = (unsigned)std::min<int64_t>(4096, (rows + 15) / 16);
-    hipLaunchKernelGGL((segsum_k<16, F>), dim3(g), dim3(256), 0, st, rows, f);
+    constexpr int per_block = 256 / kSegLanes;
+    const unsigned g = (unsigned)std::min<int64_t>(4096, (rows + per_block - 1) / per_block);
+    hipLaunchKernelGGL((segsum_k<kSegLanes, F>), dim3(g), dim3(256), 0, st, rows, f);
     OTIP_HIP(hipGetLastError());
 }
 
