@@ -49,7 +49,11 @@ __device__ __forceinline__ void lds_wave_sync() {
 // One wave per S row j.  The union of the targets of all sources adjacent to j
 // is marked in a per-wave LDS bitmap over [kmin, kmax]; the marked bits, read in
 // order, are the sorted column indices of row j.  The sources of column j are
-// read one per lane; their target lists four at a time, all loads in flight.
+// read one per lane; their target lists kSrcGroup at a time, all loads in flight.
+// sources whose target lists are requested together before any is applied
+// (their loads overlap; the order of application is unchanged)
+constexpr int kSrcGroup = 16;
+
 template <bool FILL>
 __global__ __launch_bounds__(64) void schur_pattern(int n, const int32_t *__restrict__ col_ptr,
                                                     const int32_t *__restrict__ si,
@@ -84,16 +88,16 @@ __global__ __launch_bounds__(64) void schur_pattern(int n, const int32_t *__rest
             r1l = row_ptr[i + 1];
         }
         const int ns = min(64, c1 - e0);
-        for (int s0 = 0; s0 < ns; s0 += 4) {
-            int k[4];
+        for (int s0 = 0; s0 < ns; s0 += kSrcGroup) {
+            int k[kSrcGroup];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < kSrcGroup; ++u) {
                 const int sl = min(s0 + u, ns - 1);
                 const int r = __builtin_amdgcn_readlane(r0l, sl) + lane;
                 k[u] = (s0 + u < ns && r < __builtin_amdgcn_readlane(r1l, sl)) ? rk[r] : -1;
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < kSrcGroup; ++u) {
                 if (k[u] >= 0) atomicOr(&bits[(k[u] >> 5) - w0], 1u << (k[u] & 31));
                 if (s0 + u < ns) {  // sources with more than 64 targets
                     const int r1 = __builtin_amdgcn_readlane(r1l, s0 + u);
@@ -234,7 +238,7 @@ __global__ void schur_offdiag(int64_t nnz, const int32_t *__restrict__ srow,
 // schur_offdiag, so the values are identical; the work is
 // sum_j sum_{i in col j} deg(i) instead of a merge per nonzero.  The sources'
 // data are read one per lane and their row-ordered targets and weights (rk,
-// rth) four sources at a time, before the four are accumulated in order.
+// rth) kSrcGroup sources at a time, before they are accumulated in order.
 constexpr int kRowAccMax = 8192;
 
 __global__ __launch_bounds__(64) void schur_offdiag_rows(
@@ -262,11 +266,11 @@ __global__ __launch_bounds__(64) void schur_offdiag_rows(
             iml = invM[i];
         }
         const int ns = min(64, c1 - a0);
-        for (int s0 = 0; s0 < ns; s0 += 4) {
-            int k[4];
-            double th[4];
+        for (int s0 = 0; s0 < ns; s0 += kSrcGroup) {
+            int k[kSrcGroup];
+            double th[kSrcGroup];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < kSrcGroup; ++u) {
                 const int sl = min(s0 + u, ns - 1);
                 const int r = __builtin_amdgcn_readlane(r0l, sl) + l;
                 const bool ok = s0 + u < ns && r < __builtin_amdgcn_readlane(r1l, sl);
@@ -274,7 +278,7 @@ __global__ __launch_bounds__(64) void schur_offdiag_rows(
                 th[u] = ok ? rth[r] : 0.0;
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < kSrcGroup; ++u) {
                 if (s0 + u >= ns) break;
                 const int sl = s0 + u;
                 const double ta = rdlane_d(tml, sl), im = rdlane_d(iml, sl);
