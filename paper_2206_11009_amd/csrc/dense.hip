@@ -120,45 +120,50 @@ __global__ __launch_bounds__(64) void ldl_diag(int n, int kb, int nb, double *A,
 // 32 x 32 quarter as 2 x 2 blocks of 16 x 16, with its operands loaded straight
 // from global memory into the registers of the matrix-core layout (no LDS, no
 // barrier).
+template <int TR>
 __global__ __launch_bounds__(256) void ldl_panel(int n, int kb, int nb, double *A,
                                                  const double *d, double *W,
                                                  const double *Linv,
                                                  unsigned long long *nnz) {
+    // the four waves split the TR x 64 tile into WC column groups of 64 / WC
+    // columns and 4 / WC row groups: UR 16-row and VC 16-column blocks each
+    constexpr int WC = TR >= 32 ? 2 : 4;
+    constexpr int UR = TR / (4 / WC) / 16, VC = 64 / WC / 16;
     int nz = 0;  // nonzeros of L21 written here (the fill statistic)
-    const int r0 = kb + nb + blockIdx.x * NB;
+    const int r0 = kb + nb + blockIdx.x * TR;
     const int rows = n - kb - nb;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    const int wr = (wave / WC) * (16 * UR), wc = (wave % WC) * (16 * VC);
     const int li = lane & 15, lk = lane >> 4;
-    // operands: A(r0 + wr + 16u + li, kb + c) and Linv(wc + 16u + li, c), c = 4t + lk
-    double av[2][16], bv[2][16];
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        const int ii = r0 + wr + 16 * u + li, kk = wc + 16 * u + li;
-#pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            const int c = 4 * t + lk;
-            av[u][t] = (ii < n && c < nb) ? A[(size_t)ii + (size_t)(kb + c) * n] : 0.0;
-            bv[u][t] = Linv[(size_t)kk + (size_t)c * NB];
-        }
-    }
-    d4 acc[2][2];
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-        for (int v = 0; v < 2; ++v) acc[u][v] = d4{0.0, 0.0, 0.0, 0.0};
-    // W(a, k) = sum_c A(a, c) Linv(k, c)
+    // operands: A(r0 + wr + 16u + li, kb + c) and Linv(wc + 16v + li, c), c = 4t + lk
+    double av[UR][16], bv[VC][16];
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
-        acc[0][0] = mfma4(av[0][t], bv[0][t], acc[0][0]);
-        acc[0][1] = mfma4(av[0][t], bv[1][t], acc[0][1]);
-        acc[1][0] = mfma4(av[1][t], bv[0][t], acc[1][0]);
-        acc[1][1] = mfma4(av[1][t], bv[1][t], acc[1][1]);
+        const int c = 4 * t + lk;
+#pragma unroll
+        for (int u = 0; u < UR; ++u) {
+            const int ii = r0 + wr + 16 * u + li;
+            av[u][t] = (ii < n && c < nb) ? A[(size_t)ii + (size_t)(kb + c) * n] : 0.0;
+        }
+#pragma unroll
+        for (int v = 0; v < VC; ++v) bv[v][t] = Linv[(size_t)(wc + 16 * v + li) + (size_t)c * NB];
     }
+    d4 acc[UR][VC];
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
+    for (int u = 0; u < UR; ++u)
 #pragma unroll
-        for (int v = 0; v < 2; ++v)
+        for (int v = 0; v < VC; ++v) acc[u][v] = d4{0.0, 0.0, 0.0, 0.0};
+    // W(a, k) = sum_c A(a, c) Linv(k, c)
+#pragma unroll
+    for (int t = 0; t < 16; ++t)
+#pragma unroll
+        for (int u = 0; u < UR; ++u)
+#pragma unroll
+            for (int v = 0; v < VC; ++v) acc[u][v] = mfma4(av[u][t], bv[v][t], acc[u][v]);
+#pragma unroll
+    for (int u = 0; u < UR; ++u)
+#pragma unroll
+        for (int v = 0; v < VC; ++v)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int i = r0 + wr + 16 * u + mfma_row(lane, q);
@@ -176,6 +181,9 @@ __global__ __launch_bounds__(256) void ldl_panel(int n, int kb, int nb, double *
     nz = wave_sum_i(nz);
     if ((threadIdx.x & 63) == 0 && nz) atomicAdd(nnz, (unsigned long long)nz);
 }
+
+// rows per panel workgroup
+constexpr int kPanelRows = 16;
 
 // A22 -= sum over panels of L21 W21^T on lower-triangular 64x64 tiles of the
 // trailing matrix that starts at row and column r0, one workgroup per tile of
@@ -535,7 +543,7 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
                               linv + (size_t)(kb / NB) * NB * NB);
     };
     auto panel = [&](int kb, int nb, double *W) {
-        hipLaunchKernelGGL(ldl_panel, dim3(grid_for(n - kb - nb, NB)), dim3(256), 0, st, n, kb,
+        hipLaunchKernelGGL(ldl_panel<kPanelRows>, dim3(grid_for(n - kb - nb, kPanelRows)), dim3(256), 0, st, n, kb,
                            nb, A, d_.get(), W, (const double *)(linv + (size_t)(kb / NB) * NB * NB),
                            nzL);
     };
