@@ -203,32 +203,39 @@ struct UpdArgs {
     int n, r0, first_col;
     UpdPanel p[2];
 };
-template <int NP>
+// TR: rows per workgroup tile.  The triangle of tiles uses 64 x 64 tiles;
+// a first-column launch may use TR = 16 (one workgroup per 16 rows of the
+// 64-wide block column, four waves of 16 x 16 across its columns), which
+// fills the chip in the early block steps and shortens each wave's chain.
+template <int NP, int TR>
 __global__ __launch_bounds__(256) void ldl_update(double *A, UpdArgs a) {
+    constexpr int WC = TR >= 32 ? 2 : 4;
+    constexpr int UR = TR / (4 / WC) / 16, VC = 64 / WC / 16;
     const int n = a.n, r0 = a.r0;
     const int rows = n - r0;
     const int blk = blockIdx.x;
-    int ti, tj;
+    int i0, j0;
     if (a.first_col) {
-        ti = blk;
-        tj = 0;
+        i0 = blk * TR;
+        j0 = 0;
     } else {
-        ti = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);
+        int ti = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);
         while ((ti + 1) * (ti + 2) / 2 <= blk) ++ti;
         while (ti * (ti + 1) / 2 > blk) --ti;
-        tj = blk - ti * (ti + 1) / 2;
+        const int tj = blk - ti * (ti + 1) / 2;
+        i0 = ti * NB;
+        j0 = tj * NB;
     }
-    const int i0 = ti * NB, j0 = tj * NB;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    const int wr = (wave / WC) * (16 * UR), wc = (wave % WC) * (16 * VC);
     const int li = lane & 15, lk = lane >> 4;
     // the tile's current values, requested with the operands so that their
     // latency is hidden behind the products
-    double cur[2][2][4];
+    double cur[UR][VC][4];
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
+    for (int u = 0; u < UR; ++u)
 #pragma unroll
-        for (int v = 0; v < 2; ++v)
+        for (int v = 0; v < VC; ++v)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int ii = i0 + wr + 16 * u + mfma_row(lane, q);
@@ -237,43 +244,46 @@ __global__ __launch_bounds__(256) void ldl_update(double *A, UpdArgs a) {
                                    ? A[(size_t)(r0 + ii) + (size_t)(r0 + jj) * n]
                                    : 0.0;
             }
-    d4 acc[2][2];
+    d4 acc[UR][VC];
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
+    for (int u = 0; u < UR; ++u)
 #pragma unroll
-        for (int v = 0; v < 2; ++v) acc[u][v] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int v = 0; v < VC; ++v) acc[u][v] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int pi = 0; pi < NP; ++pi) {
         const UpdPanel P = a.p[pi];
-        // operands: L(r0 + i0 + wr + 16u + li, kcol + k) and W(j0 + wc + 16u + li, k),
+        // operands: L(r0 + i0 + wr + 16u + li, kcol + k) and W(j0 + wc + 16v + li, k),
         // k = 4t + lk
-        double av[2][16], bv[2][16];
+        double av[UR][16], bv[VC][16];
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int ii = i0 + wr + 16 * u + li, jj = j0 + wc + 16 * u + li;
+        for (int t = 0; t < 16; ++t) {
+            const int k = 4 * t + lk;
 #pragma unroll
-            for (int t = 0; t < 16; ++t) {
-                const int k = 4 * t + lk;
+            for (int u = 0; u < UR; ++u) {
+                const int ii = i0 + wr + 16 * u + li;
                 av[u][t] = (ii < rows && k < P.nb)
                                ? A[(size_t)(r0 + ii) + (size_t)(P.kcol + k) * n]
                                : 0.0;
-                bv[u][t] = (jj < rows && k < P.nb)
+            }
+#pragma unroll
+            for (int v = 0; v < VC; ++v) {
+                const int jj = j0 + wc + 16 * v + li;
+                bv[v][t] = (jj < rows && k < P.nb)
                                ? P.W[(size_t)(P.wrow0 + jj) + (size_t)k * P.wld]
                                : 0.0;
             }
         }
 #pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            acc[0][0] = mfma4(av[0][t], bv[0][t], acc[0][0]);
-            acc[0][1] = mfma4(av[0][t], bv[1][t], acc[0][1]);
-            acc[1][0] = mfma4(av[1][t], bv[0][t], acc[1][0]);
-            acc[1][1] = mfma4(av[1][t], bv[1][t], acc[1][1]);
-        }
+        for (int t = 0; t < 16; ++t)
+#pragma unroll
+            for (int u = 0; u < UR; ++u)
+#pragma unroll
+                for (int v = 0; v < VC; ++v) acc[u][v] = mfma4(av[u][t], bv[v][t], acc[u][v]);
     }
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
+    for (int u = 0; u < UR; ++u)
 #pragma unroll
-        for (int v = 0; v < 2; ++v)
+        for (int v = 0; v < VC; ++v)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int ii = i0 + wr + 16 * u + mfma_row(lane, q);
@@ -282,6 +292,9 @@ __global__ __launch_bounds__(256) void ldl_update(double *A, UpdArgs a) {
                     A[(size_t)(r0 + ii) + (size_t)(r0 + jj) * n] = cur[u][v][q] - acc[u][v][q];
             }
 }
+
+// rows per workgroup of a first-column update
+constexpr int kFirstColRows = 16;
 
 // X = L^-1 by recursive doubling.  The 64 x 64 diagonal blocks of X are the
 // block inverses from ldl_diag.  At level b (b = 64, 128, ...) every pair of
@@ -551,9 +564,14 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (tupd) tupd->arm(flops, &e0, &e1);
         if (np == 2)
-            hipExtLaunchKernelGGL(ldl_update<2>, dim3(blocks), dim3(256), 0, st, e0, e1, 0, A, u);
+            hipExtLaunchKernelGGL((ldl_update<2, 64>), dim3(blocks), dim3(256), 0, st, e0, e1, 0,
+                                  A, u);
+        else if (u.first_col)
+            hipExtLaunchKernelGGL((ldl_update<1, kFirstColRows>), dim3(blocks), dim3(256), 0, st,
+                                  e0, e1, 0, A, u);
         else
-            hipExtLaunchKernelGGL(ldl_update<1>, dim3(blocks), dim3(256), 0, st, e0, e1, 0, A, u);
+            hipExtLaunchKernelGGL((ldl_update<1, 64>), dim3(blocks), dim3(256), 0, st, e0, e1, 0,
+                                  A, u);
     };
     // Block steps, two at a time where a pair leaves rows below it: after
     // the first block's panel only the second block's column is updated, the
@@ -569,7 +587,7 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
         const int kb2 = kb + nb, nb2 = std::min(NB, n - kb2), rows2 = n - kb2 - nb2;
         if (rows2 > 0) {
             UpdArgs u1{n, kb2, 1, {pa, pa}};
-            update(1, u1, grid_for(rows, NB),
+            update(1, u1, grid_for(rows, kFirstColRows),
                    2.0 * nb * ((double)nb2 * (rows - nb2) + nb2 * (nb2 + 1) / 2.0));
             diag(kb2, nb2);
             panel(kb2, nb2, Wb);
