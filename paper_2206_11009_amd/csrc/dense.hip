@@ -8,7 +8,7 @@
 //      inverts its unit lower factor;
 //   2. the rows below form W21 = A21 L11^-T (= L21 D1) and L21 = W21 D1^-1;
 //   3. the trailing lower triangle is updated, A22 -= L21 W21^T, in 64 x 64
-//      tiles.
+//      tiles (16-row tiles where only the next block column is updated).
 // Steps 2 and 3 run on the FP64 matrix cores with operands loaded straight
 // into registers.
 // A pivot d_k <= pivtol * S_kk (original diagonal) or d_k <= 0 becomes +inf:
@@ -115,11 +115,12 @@ __global__ __launch_bounds__(64) void ldl_diag(int n, int kb, int nb, double *A,
 }
 
 // Rows below the diagonal block: W21 = A21 L11^-T (so W21 = L21 D1) and
-// L21 = W21 D1^-1.  One workgroup per 64-row tile forms W = A21 Linv^T on the
-// FP64 matrix cores (Linv is zero above its diagonal); each wave forms a
-// 32 x 32 quarter as 2 x 2 blocks of 16 x 16, with its operands loaded straight
+// L21 = W21 D1^-1.  One workgroup per TR-row tile forms W = A21 Linv^T on the
+// FP64 matrix cores (Linv is zero above its diagonal); its four waves split
+// the TR x 64 tile into blocks of 16 x 16, with their operands loaded straight
 // from global memory into the registers of the matrix-core layout (no LDS, no
-// barrier).
+// barrier).  Small tiles (TR = 16) give the early block steps enough
+// workgroups and each wave a short chain of products.
 template <int TR>
 __global__ __launch_bounds__(256) void ldl_panel(int n, int kb, int nb, double *A,
                                                  const double *d, double *W,
