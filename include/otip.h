@@ -159,13 +159,16 @@ typedef struct otip_info {
     double seconds_setup;      /* initial support, starting point */
     double seconds_final;      /* polish, purification, certificate */
     int64_t pricing_scans;     /* full m*n passes of the pricing and certificate scans */
-    /* with params.profile: event-timed launches of the hot kernels */
+    /* with params.profile: event-timed launches of the hot kernels, sampled so
+       that the events do not slow the solve */
     int64_t spmv_launches;     /* Schur SpMV launches inside CG (fused with the direction
-                                  update p = z + beta p) */
+                                  update p = z + beta p), those of the first of every 8 CG
+                                  solves */
     double spmv_ms;            /* their summed durations */
     double spmv_bytes;         /* their algorithmic bytes: 12 nnz + 36 n per launch (FP64;
                                   8 nnz + 20 n for the FP32 inner solves) */
-    int64_t price_launches;    /* pricing-pass launches */
+    int64_t price_launches;    /* pricing-pass launches of the first of every 8 pricing
+                                  calls */
     double price_ms;
     double price_elems;        /* reduced costs evaluated: m*n per launch */
     int64_t diag_launches;     /* diagonal-block factor launches of the dense LDL^T (those of

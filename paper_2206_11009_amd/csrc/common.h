@@ -4,6 +4,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstdio>
 #include <stdexcept>
@@ -64,9 +65,15 @@ struct DBuf {
     T *get() const { return ptr; }
 };
 
-// Event timing of individual kernel launches on their stream (opt-in).
+// Event timing of individual kernel launches on their stream (opt-in).  A
+// caller that makes many calls (CG solves, pricing calls) may sample them: it
+// opens each call with begin_call(), and only the first of every `stride`
+// calls since the last reset() records events.
 struct LaunchTimer {
     bool on = false;
+    bool active = true;
+    int stride = 1;
+    int64_t calls = 0;
     int64_t launches = 0;
     double ms = 0.0, work = 0.0;
     std::vector<hipEvent_t> ev;
@@ -75,9 +82,10 @@ struct LaunchTimer {
     ~LaunchTimer() {
         for (auto e : ev) (void)hipEventDestroy(e);
     }
+    void begin_call() { active = calls++ % std::max(1, stride) == 0; }
     // record the start event of a launch carrying `w` units of work
     void start(hipStream_t st, double w) {
-        if (!on) return;
+        if (!on || !active) return;
         if (used + 2 > ev.size()) {
             for (int k = 0; k < 64; ++k) {
                 hipEvent_t e;
@@ -89,7 +97,7 @@ struct LaunchTimer {
         pending_work.push_back(w);
     }
     void stop(hipStream_t st) {
-        if (!on) return;
+        if (!on || !active) return;
         (void)hipEventRecord(ev[used + 1], st);
         used += 2;
     }
@@ -97,7 +105,7 @@ struct LaunchTimer {
     // records them at the dispatch's own start and end; null when timing is off
     void arm(double w, hipEvent_t *a, hipEvent_t *b) {
         *a = *b = nullptr;
-        if (!on) return;
+        if (!on || !active) return;
         if (used + 2 > ev.size()) {
             for (int k = 0; k < 64; ++k) {
                 hipEvent_t e;
@@ -111,6 +119,8 @@ struct LaunchTimer {
         pending_work.push_back(w);
     }
     void reset() {
+        active = true;
+        calls = 0;
         launches = 0;
         ms = work = 0.0;
         used = 0;
