@@ -296,6 +296,8 @@ __global__ __launch_bounds__(256) void ldl_update(double *A, UpdArgs a) {
 
 // rows per workgroup of a first-column update
 constexpr int kFirstColRows = 16;
+// from this order on, the top doubling level of the inverse is not formed
+constexpr int kSplitMinN = 2048;
 
 // X = L^-1 by recursive doubling.  The 64 x 64 diagonal blocks of X are the
 // block inverses from ldl_diag.  At level b (b = 64, 128, ...) every pair of
@@ -395,35 +397,50 @@ __global__ __launch_bounds__(256) void inv_mul(int n, int b, int mode, const dou
 }
 
 // Solve L D L^T x = b with X = L^-1 (unit lower, column-major) and XT, the
-// strict upper part of X^T: two products, one wavefront per entry.
-// forward: y_i = (b_i + sum_{j<i} X(i, j) b_j) / d_i   (infinite pivot: 0)
-__global__ __launch_bounds__(256) void inv_fwd(int n, const double *__restrict__ XT,
-                                               const double *__restrict__ d,
-                                               const double *__restrict__ b,
-                                               double *__restrict__ y) {
-    const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (i >= n) return;
+// strict upper part of X^T, by products with one wavefront per entry.  Without
+// a split: forward y_i = (b_i + sum_{j<i} X(i, j) b_j) / d_i (infinite pivot:
+// 0), backward x_j = y_j + sum_{i>j} X(i, j) y_i.  With a split at h (the top
+// doubling level not formed, X holding only the diagonal inverses X11 and
+// X22), the factor's own block L21 sits between them:
+//   z1 = X11 b1,  z2 = X22 (b2 - L21 z1),  y = D^-1 z,
+//   x2 = X22^T y2,  x1 = X11^T (y1 - L21^T x2).
+// Rows: out_i = base_i + sgn sum_{j0 <= j < min(i, j1)} M(i, j) v_j for i in
+// [i0, i1), with M(i, j) read as MT(j, i) (column i of MT is row i of M), and
+// y_i = out_i / d_i when y is given.
+__global__ __launch_bounds__(256) void x_rows(int n, int i0, int i1, int j0, int j1,
+                                              const double *__restrict__ MT,
+                                              const double *__restrict__ v,
+                                              const double *__restrict__ base, double sgn,
+                                              const double *__restrict__ d,
+                                              double *__restrict__ out, double *__restrict__ y) {
+    const int i = i0 + blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (i >= i1) return;
     double acc = 0.0;
-    const double *col = XT + (size_t)i * n;  // column i of X^T = row i of X
-    for (int j = lane; j < i; j += 64) acc = fma(col[j], b[j], acc);
+    const double *col = MT + (size_t)i * n;
+    const int je = min(i, j1);
+    for (int j = j0 + lane; j < je; j += 64) acc = fma(col[j], v[j], acc);
     acc = wave_sum(acc);
     if (lane == 0) {
-        const double v = b[i] + acc;
-        y[i] = isinf(d[i]) ? 0.0 : v / d[i];
+        const double val = base[i] + sgn * acc;
+        if (out) out[i] = val;
+        if (y) y[i] = isinf(d[i]) ? 0.0 : val / d[i];
     }
 }
 
-// backward: x_j = y_j + sum_{i>j} X(i, j) y_i
-__global__ __launch_bounds__(256) void inv_bwd(int n, const double *__restrict__ X,
-                                               const double *__restrict__ y,
-                                               double *__restrict__ x) {
-    const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (j >= n) return;
+// Columns: out_j = base_j + sgn sum_{max(j+1, i0) <= i < i1} M(i, j) v_i for j
+// in [j0, j1) (column j of M is contiguous).
+__global__ __launch_bounds__(256) void x_cols(int n, int j0, int j1, int i0, int i1,
+                                              const double *__restrict__ M,
+                                              const double *__restrict__ v,
+                                              const double *__restrict__ base, double sgn,
+                                              double *__restrict__ out) {
+    const int j = j0 + blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (j >= j1) return;
     double acc = 0.0;
-    const double *col = X + (size_t)j * n;
-    for (int i = j + 1 + lane; i < n; i += 64) acc = fma(col[i], y[i], acc);
+    const double *col = M + (size_t)j * n;
+    for (int i = max(j + 1, i0) + lane; i < i1; i += 64) acc = fma(col[i], v[i], acc);
     acc = wave_sum(acc);
-    if (lane == 0) x[j] = y[j] + acc;
+    if (lane == 0) out[j] = base[j] + sgn * acc;
 }
 
 // Substitution solves, one launch per 64-wide block column (used for a
@@ -507,12 +524,14 @@ __global__ __launch_bounds__(256) void count_diag_blocks(int n, const double *__
 }
 
 // (and, with a flag, sets it when an entry of the strict lower part is not
-// finite)
-__global__ __launch_bounds__(256) void transpose_lower(int n, const double *__restrict__ L,
-                                                       double *__restrict__ U, int *flag) {
+// finite).  With L2, the block of rows >= h and columns < h comes from L2.
+__global__ __launch_bounds__(256) void transpose_lower(int n, const double *__restrict__ L1,
+                                                       double *__restrict__ U, int *flag,
+                                                       const double *__restrict__ L2, int h) {
     __shared__ double tile[64][65];
     const int bi = blockIdx.x * 64, bj = blockIdx.y * 64;  // tile of L: rows bi.., cols bj..
     if (blockIdx.y > blockIdx.x) return;
+    const double *L = (L2 && bi >= h && bj < h) ? L2 : L1;
     bool bad = false;
     for (int t = threadIdx.x; t < 64 * 64; t += 256) {
         const int r = t % 64, c = t / 64;
@@ -609,14 +628,22 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
     double *X = X_.need(total);
     hipLaunchKernelGGL(dense_zero, dim3(2048), dim3(256), 0, st, total, X);
     hipLaunchKernelGGL(inv_init, dim3(nblk), dim3(256), 0, st, n, linv, X);
+    // From kSplitMinN on, the top level (one pair, [0, h) and [h, n), three
+    // quarters of the doubling's flops) is not formed: the solves apply
+    // between the two diagonal inverses instead, a bandwidth-bound product
+    // much cheaper than the two matrix products it replaces.
+    int top = NB;
+    while (2 * top < n) top *= 2;
+    split_ = (n > NB && n >= kSplitMinN) ? top : n;
+    const int bend = split_ < n ? split_ : n;
     if (n > NB) {
         size_t tmax = 0;
-        for (int b = NB; b < n; b *= 2) {
+        for (int b = NB; b < bend; b *= 2) {
             const int pairs = (n - b + 2 * b - 1) / (2 * b);
             tmax = std::max(tmax, (size_t)pairs * b * b);
         }
-        double *T = T_.need(tmax);
-        for (int b = NB; b < n; b *= 2) {
+        double *T = tmax ? T_.need(tmax) : nullptr;
+        for (int b = NB; b < bend; b *= 2) {
             const int pairs = (n - b + 2 * b - 1) / (2 * b);
             dim3 grid(b / NB, b / NB, pairs);
             hipLaunchKernelGGL(inv_mul, grid, dim3(256), 0, st, n, b, 0, A, X, T);
@@ -633,7 +660,7 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
     hipLaunchKernelGGL(count_diag_blocks, dim3(nblk), dim3(256), 0, st, n, (const double *)A, nzL);
     OTIP_HIP(hipMemsetAsync(bad_.need(1), 0, sizeof(int), st));
     hipLaunchKernelGGL(transpose_lower, dim3(tl, tl), dim3(256), 0, st, n, X, XT_.get(),
-                       bad_.get());
+                       bad_.get(), split_ < n ? (const double *)A : nullptr, split_);
     int hn = 0, hbad = 0;
     unsigned long long hc = 0;
     OTIP_HIP(hipMemcpyAsync(&hn, ninf_.get(), sizeof(int), hipMemcpyDeviceToHost, st));
@@ -646,16 +673,38 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
     inverse_ok_ = hbad == 0;
     if (!inverse_ok_)  // U = L^T for the backward substitution
         hipLaunchKernelGGL(transpose_lower, dim3(tl, tl), dim3(256), 0, st, n, A, XT_.get(),
-                           (int *)nullptr);
+                           (int *)nullptr, (const double *)nullptr, n);
     return hn;
 }
 
 void DenseLDL::solve(hipStream_t st, const double *b, double *x) {
     double *y = v_.need(n);
     if (inverse_ok_) {
-        const unsigned g = grid_for(n, 4);
-        hipLaunchKernelGGL(inv_fwd, dim3(g), dim3(256), 0, st, n, XT_.get(), d_.get(), b, y);
-        hipLaunchKernelGGL(inv_bwd, dim3(g), dim3(256), 0, st, n, X_.get(), y, x);
+        const double *X = X_.get(), *XT = XT_.get(), *d = d_.get();
+        const int h = split_;
+        if (h >= n) {
+            const unsigned g = grid_for(n, 4);
+            hipLaunchKernelGGL(x_rows, dim3(g), dim3(256), 0, st, n, 0, n, 0, n, XT, b, b, 1.0, d,
+                               (double *)nullptr, y);
+            hipLaunchKernelGGL(x_cols, dim3(g), dim3(256), 0, st, n, 0, n, 0, n, X, y, y, 1.0, x);
+        } else {
+            // z (rows < h) and w = b2 - L21 z1 (rows >= h) in separate halves of t
+            double *t = t_.need(2 * (size_t)n), *z = t, *w = t + n;
+            const unsigned g1 = grid_for(h, 4), g2 = grid_for(n - h, 4);
+            hipLaunchKernelGGL(x_rows, dim3(g1), dim3(256), 0, st, n, 0, h, 0, h, XT, b, b, 1.0, d,
+                               z, y);
+            hipLaunchKernelGGL(x_rows, dim3(g2), dim3(256), 0, st, n, h, n, 0, h, XT,
+                               (const double *)z, b, -1.0, d, w, (double *)nullptr);
+            hipLaunchKernelGGL(x_rows, dim3(g2), dim3(256), 0, st, n, h, n, h, n, XT,
+                               (const double *)w, (const double *)w, 1.0, d, (double *)nullptr, y);
+            // x2 = X22^T y2; z1 = y1 - L21^T x2 (L21 from the factor); x1 = X11^T z1
+            hipLaunchKernelGGL(x_cols, dim3(g2), dim3(256), 0, st, n, h, n, 0, n, X, y, y, 1.0, x);
+            hipLaunchKernelGGL(x_cols, dim3(g1), dim3(256), 0, st, n, 0, h, h, n,
+                               (const double *)A_.get(), (const double *)x, (const double *)y,
+                               -1.0, z);
+            hipLaunchKernelGGL(x_cols, dim3(g1), dim3(256), 0, st, n, 0, h, 0, h, X,
+                               (const double *)z, (const double *)z, 1.0, x);
+        }
         OTIP_HIP(hipGetLastError());
         return;
     }

@@ -170,12 +170,13 @@ class DenseLDL {
     void restart_sampling() { factorisations_ = 0; }
 
   private:
-    DBuf<double> A_, X_, XT_, T_, d_, orig_, W_, v_, linv_;
+    DBuf<double> A_, X_, XT_, T_, d_, orig_, W_, v_, linv_, t_;
     DBuf<int> ninf_, bad_;
     DBuf<unsigned long long> cnt_;
     int64_t nnzL_ = 0;
     int64_t factorisations_ = 0;
     bool inverse_ok_ = true;
+    int split_ = 0;  // X holds the diagonal inverses of [0, split_) and [split_, n)
 };
 
 // Warm-start network (cnn.hip): 4 dilated 3x3 convolution layers, 32 channels,
