@@ -296,8 +296,6 @@ __global__ __launch_bounds__(256) void ldl_update(double *A, UpdArgs a) {
 
 // rows per workgroup of a first-column update
 constexpr int kFirstColRows = 16;
-// from this order on, the top doubling level of the inverse is not formed
-constexpr int kSplitMinN = 2048;
 
 // X = L^-1 by recursive doubling.  The 64 x 64 diagonal blocks of X are the
 // block inverses from ldl_diag.  At level b (b = 64, 128, ...) every pair of
@@ -628,13 +626,13 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
     double *X = X_.need(total);
     hipLaunchKernelGGL(dense_zero, dim3(2048), dim3(256), 0, st, total, X);
     hipLaunchKernelGGL(inv_init, dim3(nblk), dim3(256), 0, st, n, linv, X);
-    // From kSplitMinN on, the top level (one pair, [0, h) and [h, n), three
+    // From kDenseSplitMinN on, the top level (one pair, [0, h) and [h, n), three
     // quarters of the doubling's flops) is not formed: the solves apply
     // between the two diagonal inverses instead, a bandwidth-bound product
     // much cheaper than the two matrix products it replaces.
     int top = NB;
     while (2 * top < n) top *= 2;
-    split_ = (n > NB && n >= kSplitMinN) ? top : n;
+    split_ = (n > NB && n >= kDenseSplitMinN) ? top : n;
     const int bend = split_ < n ? split_ : n;
     if (n > NB) {
         size_t tmax = 0;

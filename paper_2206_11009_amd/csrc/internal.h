@@ -154,6 +154,10 @@ class SchurSolver {
     DBuf<int> flag_;
 };
 
+// From this order on, the dense inverse X = L^-1 omits its top doubling level
+// and the solves apply the factor's off-diagonal block between the two halves.
+constexpr int kDenseSplitMinN = 2048;
+
 // Dense LDL^T (FP64) of a Schur complement with the infinite-pivot rule.
 class DenseLDL {
   public:
