@@ -402,6 +402,23 @@ __global__ __launch_bounds__(256) void inv_mul(int n, int b, int mode, const dou
 // X22), the factor's own block L21 sits between them:
 //   z1 = X11 b1,  z2 = X22 (b2 - L21 z1),  y = D^-1 z,
 //   x2 = X22^T y2,  x1 = X11^T (y1 - L21^T x2).
+// One lane's share of a wavefront's dot product: sum of a[k] v[k] for k = k0,
+// k0 + 64, ... below k1, in four independent chains so that four loads of
+// each operand are in flight.
+__device__ __forceinline__ double dot4(const double *__restrict__ a,
+                                       const double *__restrict__ v, int k0, int k1) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int k = k0;
+    for (; k + 192 < k1; k += 256) {
+        s0 = fma(a[k], v[k], s0);
+        s1 = fma(a[k + 64], v[k + 64], s1);
+        s2 = fma(a[k + 128], v[k + 128], s2);
+        s3 = fma(a[k + 192], v[k + 192], s3);
+    }
+    for (; k < k1; k += 64) s0 = fma(a[k], v[k], s0);
+    return (s0 + s1) + (s2 + s3);
+}
+
 // Rows: out_i = base_i + sgn sum_{j0 <= j < min(i, j1)} M(i, j) v_j for i in
 // [i0, i1), with M(i, j) read as MT(j, i) (column i of MT is row i of M), and
 // y_i = out_i / d_i when y is given.
@@ -413,11 +430,8 @@ __global__ __launch_bounds__(256) void x_rows(int n, int i0, int i1, int j0, int
                                               double *__restrict__ out, double *__restrict__ y) {
     const int i = i0 + blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (i >= i1) return;
-    double acc = 0.0;
     const double *col = MT + (size_t)i * n;
-    const int je = min(i, j1);
-    for (int j = j0 + lane; j < je; j += 64) acc = fma(col[j], v[j], acc);
-    acc = wave_sum(acc);
+    const double acc = wave_sum(dot4(col, v, j0 + lane, min(i, j1)));
     if (lane == 0) {
         const double val = base[i] + sgn * acc;
         if (out) out[i] = val;
@@ -434,10 +448,8 @@ __global__ __launch_bounds__(256) void x_cols(int n, int j0, int j1, int i0, int
                                               double *__restrict__ out) {
     const int j = j0 + blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (j >= j1) return;
-    double acc = 0.0;
     const double *col = M + (size_t)j * n;
-    for (int i = max(j + 1, i0) + lane; i < i1; i += 64) acc = fma(col[i], v[i], acc);
-    acc = wave_sum(acc);
+    const double acc = wave_sum(dot4(col, v, max(j + 1, i0) + lane, i1));
     if (lane == 0) out[j] = base[j] + sgn * acc;
 }
 
