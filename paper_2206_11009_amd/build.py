@@ -16,6 +16,10 @@ ARCH = os.environ.get("OTIP_ARCH", "gfx950")
 HIPFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wno-unused-result", "-I", os.path.join(HERE, "..", "include")]
+# per-source additions: the diagonal-block factor's fully unrolled pivot loop
+# (two wavefronts, 64 steps) is above the default size limit for a pragma
+# unroll; left rolled in the early passes, its register arrays go to scratch
+FILE_FLAGS = {"dense.hip": ["-mllvm", "-pragma-unroll-threshold=65536"]}
 
 
 def sources():
@@ -29,7 +33,7 @@ def _compile(src):
     deps.append(os.path.join(HERE, "..", "include", "otip.h"))
     if os.path.exists(obj) and all(os.path.getmtime(obj) >= os.path.getmtime(d) for d in deps):
         return obj, ""
-    cmd = ["hipcc"] + HIPFLAGS + ["-c", src, "-o", obj]
+    cmd = ["hipcc"] + HIPFLAGS + FILE_FLAGS.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
     if src.endswith(".cpp"):
         cmd = ["hipcc", "-O3", "-std=c++17", "-fPIC", "-c", src, "-o", obj]
     p = subprocess.run(cmd, capture_output=True, text=True)

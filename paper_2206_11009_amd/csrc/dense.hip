@@ -47,71 +47,88 @@ __global__ void dense_zero(size_t total, double *A) {
         A[t] = 0.0;
 }
 
-// Factor the diagonal block [kb, kb+nb) in one wavefront.  Lane i keeps row i
-// of the block in registers.  Every value one lane needs from another (the
-// pivot, column k of L, an entry of L11 for the inverse) is read with
-// v_readlane at a compile-time lane index into a scalar register, so the
-// recurrence runs without LDS round trips.  Right-looking: at pivot k each
-// lane applies the rank-one update to its row (entries right of its diagonal
-// receive values that are never read).  Then lane c solves L11 x = e_c for
-// column c of L11^-1 (right-looking, dependent chains 64 long), which goes to
-// Linv (64 x 64 column-major, identity-padded) through LDS for a coalesced store.
+// Factor the diagonal block [kb, kb+nb) and invert its unit lower factor, two
+// wavefronts.  In the factor wave, lane i keeps row i of the block in
+// registers; every value one lane needs from another (the pivot, column k of
+// L) is read with v_readlane at a compile-time lane index into a scalar
+// register, so the recurrence runs without LDS round trips.  Right-looking: at
+// pivot k each lane applies the rank-one update to its row (entries right of
+// its diagonal receive values that are never read).  Lane c of the inverse
+// wave solves L11 x = e_c for column c of L11^-1 (right-looking, dependent
+// chains 64 long), which goes to Linv (64 x 64 column-major, identity-padded)
+// through LDS for a coalesced store.  Column s of that recurrence needs only
+// column s of L, final once pivot s is done: the factor wave hands the columns
+// over through LDS after every kDiagStepBlock pivots, so the inverse runs
+// behind the factor instead of after it.
+constexpr int kDiagStepBlock = 8;
+
 __device__ __forceinline__ double rdlane(double v, int lane) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
     const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
     return __hiloint2double(hi, lo);
 }
 
-__global__ __launch_bounds__(64) void ldl_diag(int n, int kb, int nb, double *A,
-                                               const double *orig, double *d, double pivtol,
-                                               int *ninf, double *Linv) {
-    __shared__ double Ls[NB][NB + 1];
-    const int i = threadIdx.x;
-    const double oi = i < nb ? orig[kb + i] : 1.0;
-    double t[NB];
+__global__ __launch_bounds__(128) void ldl_diag(int n, int kb, int nb, double *A,
+                                                const double *orig, double *d, double pivtol,
+                                                int *ninf, double *Linv) {
+    __shared__ double Lc[NB][NB + 1];  // columns of L, factor wave -> inverse wave
+    __shared__ double Ls[NB][NB + 1];  // L11^-1, transposed for the store
+    const int i = threadIdx.x & 63;
+    const bool fw = threadIdx.x < 64;  // the factor wave (wave-uniform)
+    // factor wave: row i of the block; inverse wave: column i of L11^-1
+    double u[NB];
+    const double oi = (fw && i < nb) ? orig[kb + i] : 1.0;
 #pragma unroll
     for (int c = 0; c < NB; ++c)
-        t[c] = (i < nb && c < nb && c <= i) ? A[(size_t)(kb + i) + (size_t)(kb + c) * n] : 0.0;
+        u[c] = fw ? ((i < nb && c < nb && c <= i) ? A[(size_t)(kb + i) + (size_t)(kb + c) * n]
+                                                  : 0.0)
+                  : ((c == i) ? 1.0 : 0.0);
     int ninf_local = 0;
     double dmine = 0.0;
-    // branch-free steps: an infinite or absent pivot gives multipliers 0,
-    // which leave the row unchanged (and its column of L zero), so the whole
-    // recurrence is one basic block and the compiler can overlap a step's
-    // pivot with the previous step's updates
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
-        const bool act = k < nb;
-        double piv = rdlane(t[k], k);
-        const bool bad = !(piv > pivtol * rdlane(oi, k)) || !(piv > 0.0);
-        piv = bad ? INFINITY : piv;
-        const bool fin = act && !bad;
-        ninf_local += (act && bad) ? 1 : 0;
-        dmine = (i == k) ? piv : dmine;
-        const double l = (fin && i > k && i < nb) ? t[k] / piv : 0.0;
-        const double ld = fin ? l * piv : 0.0;
+        if (fw) {
+            const bool act = k < nb;
+            double piv = rdlane(u[k], k);
+            const bool bad = !(piv > pivtol * rdlane(oi, k)) || !(piv > 0.0);
+            piv = bad ? INFINITY : piv;
+            const bool fin = act && !bad;
+            ninf_local += (act && bad) ? 1 : 0;
+            dmine = (i == k) ? piv : dmine;
+            const double l = (fin && i > k && i < nb) ? u[k] / piv : 0.0;
+            const double ld = fin ? l * piv : 0.0;
 #pragma unroll
-        for (int j = k + 1; j < NB; ++j) t[j] = fma(-ld, rdlane(l, j), t[j]);
-        t[k] = (act && i > k) ? l : t[k];
+            for (int j = k + 1; j < NB; ++j) u[j] = fma(-ld, rdlane(l, j), u[j]);
+            u[k] = (act && i > k) ? l : u[k];
+            Lc[i][k] = u[k];
+        }
+        if (k % kDiagStepBlock == kDiagStepBlock - 1) {
+            __syncthreads();
+            if (!fw) {
+#pragma unroll
+                for (int s2 = k + 1 - kDiagStepBlock; s2 <= k; ++s2) {
+                    const double l = Lc[i][s2];
+#pragma unroll
+                    for (int r = s2 + 1; r < NB; ++r) u[r] = fma(-rdlane(l, r), u[s2], u[r]);
+                }
+            }
+        }
     }
-    if (i < nb) d[kb + i] = dmine;
-    if (i == 0 && ninf_local) atomicAdd(ninf, ninf_local);
+    if (fw) {
+        if (i < nb) d[kb + i] = dmine;
+        if (i == 0 && ninf_local) atomicAdd(ninf, ninf_local);
 #pragma unroll
-    for (int c = 0; c < NB; ++c)
-        if (i < nb && c < i && c < nb) A[(size_t)(kb + i) + (size_t)(kb + c) * n] = t[c];
-    // lane i: column i of L11^-1; L(r, s) (s < r) is t[s] of lane r, and it is
-    // zero outside the block (rows and columns >= nb stayed zero above)
-    double x[NB];
+        for (int c = 0; c < NB; ++c)
+            if (i < nb && c < i && c < nb) A[(size_t)(kb + i) + (size_t)(kb + c) * n] = u[c];
+    } else {
 #pragma unroll
-    for (int r = 0; r < NB; ++r) x[r] = (r == i) ? 1.0 : 0.0;
-#pragma unroll
-    for (int s2 = 0; s2 < NB; ++s2)
-#pragma unroll
-        for (int r = s2 + 1; r < NB; ++r) x[r] = fma(-rdlane(t[s2], r), x[s2], x[r]);
-#pragma unroll
-    for (int r = 0; r < NB; ++r) Ls[r][i] = x[r];
+        for (int r = 0; r < NB; ++r) Ls[r][i] = u[r];
+    }
     __syncthreads();
+    if (!fw) {
 #pragma unroll
-    for (int c = 0; c < NB; ++c) Linv[(size_t)i + (size_t)c * NB] = Ls[i][c];
+        for (int c = 0; c < NB; ++c) Linv[(size_t)i + (size_t)c * NB] = Ls[i][c];
+    }
 }
 
 // Rows below the diagonal block: W21 = A21 L11^-T (so W21 = L21 D1) and
@@ -581,7 +598,7 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
     auto diag = [&](int kb, int nb) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (tdiag) tdiag->arm(2.0 * nb * nb * nb / 3.0, &e0, &e1);
-        hipExtLaunchKernelGGL(ldl_diag, dim3(1), dim3(64), 0, st, e0, e1, 0, n, kb, nb, A,
+        hipExtLaunchKernelGGL(ldl_diag, dim3(1), dim3(128), 0, st, e0, e1, 0, n, kb, nb, A,
                               (const double *)orig_.get(), d_.get(), pivtol, ninf_.get(),
                               linv + (size_t)(kb / NB) * NB * NB);
     };
