@@ -60,7 +60,8 @@ __global__ void dense_zero(size_t total, double *A) {
 // column s of L, final once pivot s is done: the factor wave hands the columns
 // over through LDS after every kDiagStepBlock pivots, so the inverse runs
 // behind the factor instead of after it.
-constexpr int kDiagStepBlock = 8;
+constexpr int kDiagStepBlock = 16;
+static_assert(NB % kDiagStepBlock == 0, "the last hand-over must follow pivot NB - 1");
 
 __device__ __forceinline__ double rdlane(double v, int lane) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
