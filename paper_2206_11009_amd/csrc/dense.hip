@@ -4,8 +4,8 @@
 //
 // Right-looking blocked factorisation of the lower triangle of a column-major
 // n x n array, block width 64:
-//   1. the 64 x 64 diagonal block is factorised by one wavefront, which also
-//      inverts its unit lower factor;
+//   1. the 64 x 64 diagonal block is factorised by one wavefront while a
+//      second inverts its unit lower factor, column by column behind it;
 //   2. the rows below form W21 = A21 L11^-T (= L21 D1) and L21 = W21 D1^-1;
 //   3. the trailing lower triangle is updated, A22 -= L21 W21^T, in 64 x 64
 //      tiles (16-row tiles where only the next block column is updated).
@@ -15,7 +15,8 @@
 // its column of L is zero and the solve returns 0 for that unknown.
 // After the factorisation X = L^-1 is formed (recursive doubling with tiled
 // products), so that each solve x = X^T D^-1 X b is two matrix-vector
-// products instead of a chain of dependent triangular steps.
+// products instead of a chain of dependent triangular steps; for large n
+// without its top level, the solves then applying L21 between the halves.
 #include "internal.h"
 
 namespace otip {
