@@ -191,6 +191,11 @@ typedef struct otip_result otip_result;
 /* ABI version of the loaded library (OTIP_ABI_VERSION). */
 int otip_version(void);
 
+/* Identity of the sources the library was built from: a 16-hex-digit hash of
+ * the library's source files and this header, fixed at build time.  Static
+ * string, never NULL; "unknown" for a build that did not set it. */
+const char *otip_source_id(void);
+
 /* Fill *p with the defaults described above. */
 void otip_params_default(otip_params *p);
 

@@ -65,6 +65,7 @@ class otip_info(ctypes.Structure):
 # name -> (restype, argtypes); exactly the declarations of include/otip.h
 SIGNATURES = {
     "otip_version": (ctypes.c_int, []),
+    "otip_source_id": (ctypes.c_char_p, []),
     "otip_params_default": (None, [ctypes.POINTER(otip_params)]),
     "otip_create": (ctypes.c_int, [ctypes.POINTER(_p), ctypes.c_int, _p]),
     "otip_destroy": (None, [_p]),
@@ -114,5 +115,11 @@ def load():
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
+        # a library built from other sources than the ones beside it is refused
+        from .build import source_id
+        built, here = L.otip_source_id().decode(), source_id()
+        if built != here:
+            raise ImportError(f"{LIB_PATH} was built from other sources ({built}, sources "
+                              f"here {here}); rebuild with paper_2206_11009_amd/build.py")
         _lib = L
     return _lib

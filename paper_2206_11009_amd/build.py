@@ -27,13 +27,35 @@ def sources():
                   if f.endswith((".hip", ".cpp")))
 
 
+def source_id() -> str:
+    """Hash of every library source and the ABI header: compiled into the
+    library (otip_source_id) and compared by the binding at load time, so a
+    library built from other sources is refused instead of silently used."""
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(f for f in os.listdir(SRC) if f.endswith((".hip", ".cpp", ".h")))
+    for f in files:
+        h.update(f.encode())
+        with open(os.path.join(SRC, f), "rb") as fh:
+            h.update(fh.read())
+    with open(os.path.join(HERE, "..", "include", "otip.h"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def _compile(src):
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
     deps = [src] + [os.path.join(SRC, h) for h in os.listdir(SRC) if h.endswith(".h")]
     deps.append(os.path.join(HERE, "..", "include", "otip.h"))
+    extra = []
+    if os.path.basename(src) == "api.hip":
+        # carries the source hash: rebuilt whenever any source changes
+        deps += sources()
+        extra = [f'-DOTIP_SOURCE_ID="{source_id()}"']
     if os.path.exists(obj) and all(os.path.getmtime(obj) >= os.path.getmtime(d) for d in deps):
         return obj, ""
-    cmd = ["hipcc"] + HIPFLAGS + FILE_FLAGS.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
+    cmd = (["hipcc"] + HIPFLAGS + FILE_FLAGS.get(os.path.basename(src), []) + extra +
+           ["-c", src, "-o", obj])
     if src.endswith(".cpp"):
         cmd = ["hipcc", "-O3", "-std=c++17", "-fPIC", "-c", src, "-o", obj]
     p = subprocess.run(cmd, capture_output=True, text=True)

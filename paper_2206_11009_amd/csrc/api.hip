@@ -169,6 +169,11 @@ extern "C" {
 
 int otip_version(void) { return OTIP_ABI_VERSION; }
 
+#ifndef OTIP_SOURCE_ID
+#define OTIP_SOURCE_ID "unknown"
+#endif
+const char *otip_source_id(void) { return OTIP_SOURCE_ID; }
+
 void otip_params_default(otip_params *p) {
     if (!p) return;
     std::memset(p, 0, sizeof(*p));

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -32,12 +33,27 @@ struct Error : std::runtime_error {
         if (!(cond)) throw ::otip::Error((code), (msg));     \
     } while (0)
 
+// Debug aid: with OTIP_POISON set in the environment every buffer is filled
+// with 0xFF bytes (NaN doubles, -1 integers) when it is allocated and again at
+// its first use in each solve (a new poison epoch per solve and host thread),
+// so that a read of memory the current problem never wrote gives the same
+// result on every machine and in every schedule.
+inline bool poison_allocations() {
+    static const bool on = std::getenv("OTIP_POISON") != nullptr;
+    return on;
+}
+inline uint64_t &poison_epoch() {
+    static thread_local uint64_t e = 1;
+    return e;
+}
+
 // Growable device allocation owned by a context.  Contents are not preserved
 // across growth.
 template <typename T>
 struct DBuf {
     T *ptr = nullptr;
     size_t cap = 0;
+    uint64_t epoch_ = 0;  // poison epoch of the last fill (debug aid)
     DBuf() = default;
     DBuf(const DBuf &) = delete;
     DBuf &operator=(const DBuf &) = delete;
@@ -59,6 +75,13 @@ struct DBuf {
                                    " bytes failed: " + hipGetErrorString(e));
             }
             cap = c;
+            epoch_ = 0;
+        }
+        if (poison_allocations() && epoch_ != poison_epoch()) {
+            if (hipDeviceSynchronize() != hipSuccess || hipMemset(ptr, 0xFF, cap * sizeof(T)) != hipSuccess ||
+                hipDeviceSynchronize() != hipSuccess)
+                throw Error(3, "poisoning a buffer failed");
+            epoch_ = poison_epoch();
         }
         return ptr;
     }

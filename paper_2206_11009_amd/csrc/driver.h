@@ -78,6 +78,10 @@ class Solver {
     int run_without_zeros(const otip_problem &pr, const otip_params &prm, Result &res);
     static double now();
     void log(const char *fmt, ...);
+    // debug aid (OTIP_TRACE in the environment): FNV-1a hash of a device
+    // buffer, printed with the problem's fingerprint, a tag and the iteration
+    void trace(const char *tag, int it, const void *dev, size_t bytes);
+    void trace_val(const char *tag, int it, double v);
 
     hipStream_t st;
     otip_params P{};

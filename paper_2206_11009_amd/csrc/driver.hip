@@ -410,7 +410,6 @@ void Solver::assemble() {
     rowsum(theta.get(), nullptr, M.get(), 1.0);
     colsum(theta.get(), nullptr, N.get(), 1.0);
     foreach(st, m, FInv{M.get(), invM.get()});
-    auto t0 = std::chrono::steady_clock::now();
     if (!schur_valid) {
         schur.symbolic(st, m, n, psi_, col_ptr.get(), si.get(), row_ptr.get(), csr_pos.get(),
                        sj.get());
@@ -418,13 +417,35 @@ void Solver::assemble() {
     }
     schur.numeric(st, m, n, col_ptr.get(), si.get(), row_ptr.get(), csr_pos.get(), sj.get(),
                   theta.get(), invM.get());
-    (void)t0;
 }
 
 // ============================================================ scaffolding
 double Solver::now() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
         .count();
+}
+
+static bool trace_on() {
+    static const bool on = std::getenv("OTIP_TRACE") != nullptr;
+    return on;
+}
+
+void Solver::trace(const char *tag, int it, const void *dev, size_t bytes) {
+    if (!trace_on()) return;
+    std::vector<unsigned char> h(bytes);
+    if (bytes) {
+        OTIP_HIP(hipMemcpyAsync(h.data(), dev, bytes, hipMemcpyDeviceToHost, st));
+        OTIP_HIP(hipStreamSynchronize(st));
+    }
+    uint64_t f = 14695981039346656037ull;
+    for (unsigned char c : h) f = (f ^ c) * 1099511628211ull;
+    fprintf(stderr, "TRACE %016llx %d %s %016llx %zu\n", (unsigned long long)fp_, it, tag,
+            (unsigned long long)f, bytes);
+}
+
+void Solver::trace_val(const char *tag, int it, double v) {
+    if (!trace_on()) return;
+    fprintf(stderr, "TRACE %016llx %d %s %a\n", (unsigned long long)fp_, it, tag, v);
 }
 
 void Solver::log(const char *fmt, ...) {
@@ -835,6 +856,7 @@ void Solver::resume_from(const Checkpoint &c) {
 // that a solver reused for a stream of problems allocates (and frees) nothing
 // once it has seen the largest one.
 void Solver::reset_state() {
+    if (poison_allocations()) ++poison_epoch();
     psi_ = psi_max = 0;
     schur_valid = false;
     mode = Mode::PCG;
@@ -882,7 +904,7 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
     kind = pr.cost_kind;
     scan.kind = kind;
     // ---- validation on the device data (masses > 0, balanced)
-    double sa, sb, mina, minb, bad, zeros;
+    double sa, sb, bad, zeros;
     {
         const double *A = pr.a, *B = pr.b;
         const int mm = m;
@@ -902,8 +924,6 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
         sb = v[1];
         bad = v[2];
         zeros = v[3];
-        (void)mina;
-        (void)minb;
     }
     OTIP_CHECK(bad == 0.0, OTIP_EINVAL, "masses must be finite and nonnegative");
     OTIP_CHECK(sa > 0.0 && sb > 0.0, OTIP_EINVAL, "total mass must be positive");
@@ -963,7 +983,6 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
     b.need(n);
     foreach(st, m, FScaleIn{pr.a, a.get(), omega});
     foreach(st, n, FScaleIn{pr.b, b.get(), omega});
-    fnorm = std::sqrt((sa * sa) * 0 + 0);  // replaced below with the exact norm
     {
         const double *A = a.get(), *B = b.get();
         const int mm = m;
@@ -1021,6 +1040,10 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
         log("otip: m=%d n=%d psi0=%lld T=%lld omega=%g zeta=%g\n", m, n, (long long)psi0,
             (long long)T, omega, zeta);
         starting_point();
+        trace("p0", -1, p.get(), sizeof(double) * psi_);
+        trace("s0", -1, s.get(), sizeof(double) * psi_);
+        trace("y0", -1, y.get(), sizeof(double) * m);
+        trace("z0", -1, z.get(), sizeof(double) * n);
         mode = (P.linear_solver == OTIP_LS_DIRECT) ? Mode::Direct : Mode::PCG;
     }
     t_setup += now() - ts;
@@ -1045,6 +1068,13 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
         double tn = now();
         double rel1, rel2, mu, primal, r1n;
         residuals(rel1, rel2, mu, primal, r1n);
+        trace("idx", it, idx.get(), sizeof(uint64_t) * psi_);
+        trace("p", it, p.get(), sizeof(double) * psi_);
+        trace("s", it, s.get(), sizeof(double) * psi_);
+        trace("y", it, y.get(), sizeof(double) * m);
+        trace("z", it, z.get(), sizeof(double) * n);
+        trace("r2", it, r2.get(), sizeof(double) * psi_);
+        trace_val("mu", it, mu);
         if (!std::isfinite(rel1) || !std::isfinite(rel2) || !std::isfinite(mu)) {
             log("otip: it %d non-finite iterate\n", it);
             status = OTIP_ENUMERIC;
@@ -1115,9 +1145,14 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
         }
         // ---- Newton direction
         assemble();
+        trace("theta", it, theta.get(), sizeof(double) * psi_);
+        trace("Sval", it, schur.S.val.get(), sizeof(double) * schur.S.nnz);
+        trace("Scol", it, schur.S.col.get(), sizeof(int32_t) * schur.S.nnz);
+        trace_val("mode", it, mode == Mode::Direct ? 1.0 : 0.0);
         double td = now();
         if (mode == Mode::Direct) {
             ldl.factor(st, schur.S, P.pivot_tol);
+            trace("piv", it, ldl.pivots(), sizeof(double) * n);
             max_fill = std::max(max_fill, 100.0 * (double)ldl.nnz_L() / ((double)n * n));
             direct_its++;
         }
@@ -1126,7 +1161,6 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
         max_cg_solve = 0;
         cg_failed = false;
         const double atol = P.cg_eta * std::max(r1n, P.cg_floor * (1.0 + fnorm));
-        const double t_solves0 = now();
         int nsolves = 2;
         // predictor (sigma = 0)
         double *rr3 = r3.get();
@@ -1134,6 +1168,9 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
         foreach(st, psi_, [=] __device__(int64_t k) { rr3[k] = -pp[k] * ss[k]; });
         Dir &Da = D[0];
         newton(r1a.get(), r1b.get(), r2.get(), r3.get(), P.cg_tol_pred, atol, Da);
+        trace("rhs_a", it, rhs.get(), sizeof(double) * n);
+        trace("dz_a", it, Da.dz.get(), sizeof(double) * n);
+        trace("dp_a", it, Da.dp.get(), sizeof(double) * psi_);
         double apa, ada;
         max_steps(Da, apa, ada);
         apa = std::min(1.0, apa);
@@ -1160,6 +1197,7 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
         }
         int cur = 1;
         newton(r1a.get(), r1b.get(), r2.get(), r3.get(), P.cg_tol_pred, atol, D[cur]);
+        trace("dz_c", it, D[cur].dz.get(), sizeof(double) * n);
         double ap, ad;
         max_steps(D[cur], ap, ad);
         ap = std::min(1.0, P.step_scale * ap);
@@ -1207,7 +1245,6 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
         }
         cg_total += cg_its_iter;
         if (mode == Mode::PCG) cg_its_last = cg_its_iter;
-        (void)t_solves0;
         solves_last = nsolves;
         const bool failed_now = cg_failed;
         // ---- update
@@ -1235,6 +1272,12 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
         // ---- pricing and support update
         int64_t nneg = 0;
         const int64_t k = price(kcap, sel_idx.get(), sel_r.get(), &nneg);
+        trace_val("ap", it, ap);
+        trace_val("ad", it, ad);
+        trace_val("ncorr", it, ncorr);
+        trace_val("cg", it, cg_its_iter);
+        trace_val("nneg", it, (double)nneg);
+        trace("sel", it, sel_idx.get(), sizeof(uint64_t) * k);
         double tu = now();
         int64_t nrem = 0;
         removed.need(psi_);
@@ -1379,8 +1422,6 @@ void Solver::starting_point() {
 // the Newton step with r2 = r3 = 0), purification to a basic plan, dual
 // certificate from one full reduced-cost scan (Section 3.3: s_hat = c - A^T y_hat).
 void Solver::finalize(Result &res) {
-    const double fsum1 = 0.0;
-    (void)fsum1;
     // the projection below moves p off the interior; keep the interior
     // iterate for a resumed iteration
     double *pkeep = zpsi.need(psi_);
@@ -1446,6 +1487,15 @@ void Solver::finalize(Result &res) {
         cols[k] = (int32_t)(hidx[k] / (uint64_t)m);
         flows[k] = hp[k] / omega;
         costs[k] = icost(rows[k], cols[k]);
+    }
+    if (trace_on()) {
+        uint64_t f = 14695981039346656037ull;
+        for (double v : hp) {
+            const unsigned char *c = (const unsigned char *)&v;
+            for (int q = 0; q < 8; ++q) f = (f ^ c[q]) * 1099511628211ull;
+        }
+        fprintf(stderr, "TRACE %016llx -1 polished %016llx %lld\n", (unsigned long long)fp_,
+                (unsigned long long)f, (long long)psi);
     }
     purify_plan(m, n, rows, cols, flows, costs, ha, hb, P.drop_rel, res.rows, res.cols, res.vals);
     // gauge z_{n-1} = 0 on the unscaled duals

@@ -165,6 +165,7 @@ class DenseLDL {
     int factor(hipStream_t st, const SchurCSR &S, double pivtol);
     void solve(hipStream_t st, const double *b, double *x);
     int64_t nnz_L() const { return nnzL_; }
+    const double *pivots() const { return d_.get(); }
     int n = 0;
     // optional timers of the diagonal-factor and trailing-update launches;
     // they time the first of every timer_stride factorisations (events at

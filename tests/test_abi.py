@@ -64,3 +64,11 @@ def test_product_path_needs_a_gpu():
         pytest.skip("GPU present")
     with pytest.raises(otip.OtipError):
         otip.Context(0)
+
+
+def test_library_was_built_from_these_sources():
+    """The loaded library carries the hash of the sources beside it (a stale
+    build is refused at load time rather than tested in place of them)."""
+    from paper_2206_11009_amd import _abi
+    from paper_2206_11009_amd.build import source_id
+    assert _abi.load().otip_source_id().decode() == source_id()
