@@ -285,6 +285,22 @@ int otip_kron_apply_t(otip_ctx *ctx, int32_t m, int32_t n, const double *y, cons
                       double *X);
 
 /*
+ * otip_kron_apply without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, kernels and results (bit for bit)
+ * as otip_kron_apply; X, rowsum and colsum are caller-owned DEVICE arrays.
+ * The partial sums live in a static array of 64 MiB per GPU (held from library
+ * load to process end), so m and n are limited to
+ *   ceil(n / 64) m + ceil(m / 1024) n <= 8,388,608   (m n up to about 4.9e8);
+ * larger sizes return OTIP_EINVAL with a message and launch nothing.  Every
+ * call on one GPU shares that GPU's array: calls that overlap in time on one
+ * GPU (several contexts or streams) race and must be serialised by the caller.
+ * Errors: OTIP_EINVAL (bad arguments, too large), OTIP_EHIP.
+ */
+int otip_kron_apply_noalloc(otip_ctx *ctx, int32_t m, int32_t n, const double *X,
+                            double *rowsum, double *colsum);
+
+/*
  * Normal-equation blocks on a support (Sections 3.5 and 4).  idx: DEVICE, psi
  * variable indices sorted ascending, no duplicates, every row and column of
  * the plan covered; theta: DEVICE, psi positive values (theta = p/s).

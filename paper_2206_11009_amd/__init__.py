@@ -23,7 +23,7 @@ from ._abi import (OTIP_OK, OTIP_EINVAL, OTIP_ENOMEM, OTIP_EHIP, OTIP_ENUMERIC, 
 
 __all__ = ["otip_version", "otip_params_default", "Context", "OtipError", "SolveResult",
            "otip_solve", "otip_solve_batch", "otip_price", "otip_rmin", "otip_kron_apply",
-           "otip_kron_apply_t", "otip_schur", "otip_pcg", "PCGResult", "otip_state_save",
+           "otip_kron_apply_t", "otip_kron_apply_noalloc", "otip_schur", "otip_pcg", "PCGResult", "otip_state_save",
            "otip_state_load", "params", "otip_ws_param_count", "otip_ws_forward",
            "otip_ws_grad", "otip_ws_adam", "otip_ws_predict", "load_ws_weights"]
 
@@ -236,6 +236,14 @@ def otip_kron_apply(ctx: Context, X, rowsum, colsum):
     (pass X as an (n, m) row-major tensor, i.e. vec(X) contiguous)."""
     n, m = X.shape
     ctx.check(ctx._lib.otip_kron_apply(ctx.handle, m, n, _ptr(X), _ptr(rowsum), _ptr(colsum)))
+
+
+def otip_kron_apply_noalloc(ctx: Context, X, rowsum, colsum):
+    """otip_kron_apply with its partial sums in the library's static per-GPU
+    scratch (no device allocation); raises OtipError for sizes beyond it."""
+    n, m = X.shape
+    ctx.check(ctx._lib.otip_kron_apply_noalloc(ctx.handle, m, n, _ptr(X), _ptr(rowsum),
+                                               _ptr(colsum)))
 
 
 def otip_kron_apply_t(ctx: Context, y, z, X):

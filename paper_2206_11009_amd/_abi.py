@@ -84,6 +84,7 @@ SIGNATURES = {
                                  ctypes.POINTER(_c_f64), ctypes.POINTER(_c_i64)]),
     "otip_kron_apply": (ctypes.c_int, [_p, _c_i32, _c_i32, _p, _p, _p]),
     "otip_kron_apply_t": (ctypes.c_int, [_p, _c_i32, _c_i32, _p, _p, _p]),
+    "otip_kron_apply_noalloc": (ctypes.c_int, [_p, _c_i32, _c_i32, _p, _p, _p]),
     "otip_schur": (ctypes.c_int, [_p, _c_i32, _c_i32, _c_i64, _p, _p, ctypes.POINTER(_c_i64),
                                   _p, _p, _p, _p, _p]),
     "otip_pcg": (ctypes.c_int, [_p, _c_i32, _c_i64, _p, _p, _p, _p, _p, _c_f64, _c_i32, _c_i32,

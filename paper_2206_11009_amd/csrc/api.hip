@@ -223,6 +223,9 @@ int otip_create(otip_ctx **ctx, int device, void *hip_stream) {
     auto c = std::make_unique<otip_ctx>();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
+    // the device address of this GPU's static scratch (otip_kron_apply_noalloc)
+    const int rc = guarded(c.get(), [&] { otip::kron_scratch_init(device); });
+    if (rc != OTIP_OK) return rc;
     *ctx = c.release();
     return OTIP_OK;
 }
@@ -420,6 +423,16 @@ int otip_kron_apply(otip_ctx *ctx, int32_t m, int32_t n, const double *X, double
         OTIP_CHECK(m >= 1 && n >= 1 && X && rowsum && colsum, OTIP_EINVAL,
                    "otip_kron_apply: bad arguments");
         otip::kron_apply(ctx->stream, m, n, X, rowsum, colsum, ctx->buf_a, ctx->buf_b);
+        OTIP_HIP(hipStreamSynchronize(ctx->stream));
+    });
+}
+
+int otip_kron_apply_noalloc(otip_ctx *ctx, int32_t m, int32_t n, const double *X,
+                            double *rowsum, double *colsum) {
+    return guarded(ctx, [&] {
+        OTIP_CHECK(m >= 1 && n >= 1 && X && rowsum && colsum, OTIP_EINVAL,
+                   "otip_kron_apply_noalloc: bad arguments");
+        otip::kron_apply_noalloc(ctx->stream, ctx->device, m, n, X, rowsum, colsum);
         OTIP_HIP(hipStreamSynchronize(ctx->stream));
     });
 }

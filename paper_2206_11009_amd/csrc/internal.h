@@ -210,5 +210,12 @@ class WarmNet {
 void kron_apply(hipStream_t st, int m, int n, const double *X, double *rowsum, double *colsum,
                 DBuf<double> &prow, DBuf<double> &pcol);
 void kron_apply_t(hipStream_t st, int m, int n, const double *y, const double *z, double *X);
+// the same A x with its partial sums in a static per-GPU array (no allocation):
+// kKronScratchDoubles doubles (64 MiB), enough for m n up to about 4.9e8
+constexpr int64_t kKronScratchDoubles = (int64_t)8 << 20;
+void kron_scratch_init(int device);  // once per device, that device current
+int64_t kron_scratch_need(int m, int n);
+void kron_apply_noalloc(hipStream_t st, int device, int m, int n, const double *X,
+                        double *rowsum, double *colsum);
 
 }  // namespace otip

@@ -10,6 +10,8 @@
 // and reduces each column over the block.
 // Partial sums per tile go to small side arrays that a second, fixed-order
 // pass adds up, so the result is bitwise reproducible.
+#include <mutex>
+
 #include "internal.h"
 
 namespace otip {
@@ -116,6 +118,60 @@ __global__ __launch_bounds__(256) void kron_t_tile(int m, int n, const double *_
                 if (rows[q] < m) col[rows[q]] = yv[q] + zj;
         }
     }
+}
+
+// ------------------------------------------------------- allocation-free variant
+// The partial sums of kron_apply live in one file-scope device array per GPU
+// instead of context buffers.  Host code never passes the array's name to a
+// kernel (on the host it is only a stand-in for the symbol): the device
+// address of each GPU's copy is resolved once per device by
+// kron_scratch_init and used from then on.
+static __device__ __align__(256) double scratch[kKronScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+double *scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+void kron_scratch_init(int device) {
+    OTIP_CHECK(device >= 0 && device < kMaxDevices, OTIP_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> g(scratch_mu);
+    if (scratch_ptr[device]) return;
+    void *p = nullptr;
+    OTIP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    OTIP_CHECK(p != nullptr, OTIP_EHIP, "scratch array has no device address");
+    scratch_ptr[device] = (double *)p;
+}
+
+int64_t kron_scratch_need(int m, int n) {
+    const int64_t rtiles = (m + KR_ROWS - 1) / KR_ROWS, ctiles = (n + KR_COLS - 1) / KR_COLS;
+    return ctiles * (int64_t)m + rtiles * (int64_t)n;
+}
+
+void kron_apply_noalloc(hipStream_t st, int device, int m, int n, const double *X,
+                        double *rowsum, double *colsum) {
+    OTIP_CHECK(device >= 0 && device < kMaxDevices, OTIP_EINVAL, "device index out of range");
+    double *base;
+    {
+        std::lock_guard<std::mutex> g(scratch_mu);
+        base = scratch_ptr[device];
+    }
+    OTIP_CHECK(base != nullptr, OTIP_EHIP, "scratch not set up on this device");
+    const int64_t need = kron_scratch_need(m, n);
+    OTIP_CHECK(need <= kKronScratchDoubles, OTIP_EINVAL,
+               "otip_kron_apply_noalloc: m x n needs " + std::to_string(need) +
+                   " partial sums, more than the " + std::to_string(kKronScratchDoubles) +
+                   " of the static scratch");
+    const int rtiles = (m + KR_ROWS - 1) / KR_ROWS, ctiles = (n + KR_COLS - 1) / KR_COLS;
+    double *prow = base, *pcol = base + (size_t)ctiles * m;
+    // every partial read by kron_finish is written by kron_tile: nothing to clear
+    hipLaunchKernelGGL(kron_tile, dim3(rtiles, ctiles), dim3(256), 0, st, m, n, X, prow, pcol);
+    hipLaunchKernelGGL(kron_finish, dim3(grid_for(m, 256)), dim3(256), 0, st, m, ctiles,
+                       (const double *)prow, rowsum);
+    hipLaunchKernelGGL(kron_finish, dim3(grid_for(n, 256)), dim3(256), 0, st, n, rtiles,
+                       (const double *)pcol, colsum);
+    OTIP_HIP(hipGetLastError());
 }
 
 void kron_apply_t(hipStream_t st, int m, int n, const double *y, const double *z, double *X) {
