@@ -40,7 +40,8 @@ def lib():
         L = ctypes.CDLL(_LIB)
         L.orc_price.restype = _i64
         _ci = ctypes.c_int
-        L.orc_price.argtypes = [_i64, _i64, _p, _p, _p, _p, _p, _i64, _i64, _p, _p, _p, _ci]
+        L.orc_price.argtypes = [_i64, _i64, _p, _p, _p, _p, _p, _i64, _i64, _p, _p, _p, _ci,
+                                _i64]
         L.orc_rmin.restype = ctypes.c_double
         L.orc_rmin.argtypes = [_i64, _i64, _p, _p, _p, _p, _p, _ci]
         L.orc_cost_hist.restype = None
@@ -50,13 +51,18 @@ def lib():
         L.orc_row_col_argmin.restype = None
         L.orc_row_col_argmin.argtypes = [_i64, _i64, _p, _p, _p, _p, _ci]
         _i32 = ctypes.c_int32
-        L.orc_ldl_symbolic.restype = None
-        L.orc_ldl_symbolic.argtypes = [_i32, _p, _p, _p, _p, _p, _p]
-        L.orc_ldl_numeric.restype = _i32
-        L.orc_ldl_numeric.argtypes = [_i32, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p,
-                                      ctypes.c_double]
+        L.orc_ldl_factor.restype = _p
+        L.orc_ldl_factor.argtypes = [_i32, _p, _p, _p, ctypes.c_double]
+        L.orc_ldl_free.restype = None
+        L.orc_ldl_free.argtypes = [_p]
+        L.orc_ldl_nnz.restype = _i64
+        L.orc_ldl_nnz.argtypes = [_p]
+        L.orc_ldl_ninf.restype = _i32
+        L.orc_ldl_ninf.argtypes = [_p]
         L.orc_ldl_solve.restype = None
-        L.orc_ldl_solve.argtypes = [_i32, _p, _p, _p, _p, _p]
+        L.orc_ldl_solve.argtypes = [_p, _p]
+        L.orc_ldl_export.restype = None
+        L.orc_ldl_export.argtypes = [_p, _p, _p, _p, _p]
         _lib = L
     return _lib
 
@@ -69,9 +75,10 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def price(xs, xt, y, z, support_idx, kmax, kind=0):
+def price(xs, xt, y, z, support_idx, kmax, kind=0, key_limit=0):
     """(idx, r, n_negative): the <= kmax most negative reduced costs outside the support
-    (cost kind as in scan.c)."""
+    (cost kind as in scan.c); key_limit > 0 scans only the variables whose cost
+    key is below it (the heuristic subset of Section 3.4)."""
     xs = _c(xs, np.int32); xt = _c(xt, np.int32)
     y = _c(y, np.float64); z = _c(z, np.float64)
     sup = _c(support_idx, np.int64)
@@ -81,7 +88,8 @@ def price(xs, xt, y, z, support_idx, kmax, kind=0):
     out_r = np.empty(max(kmax, 1), np.float64)
     nneg = np.zeros(1, np.int64)
     k = lib().orc_price(m, n, _ptr(xs), _ptr(xt), _ptr(y), _ptr(z), _ptr(sup), sup.shape[0],
-                        kmax, _ptr(out_idx), _ptr(out_r), _ptr(nneg), int(kind))
+                        kmax, _ptr(out_idx), _ptr(out_r), _ptr(nneg), int(kind),
+                        int(key_limit))
     if k < 0:
         raise MemoryError("orc_price")
     return out_idx[:k].copy(), out_r[:k].copy(), int(nneg[0])
@@ -122,8 +130,9 @@ def row_col_argmin(xs, xt, kind=0):
 
 
 class LDL:
-    """L D L^T of a symmetric sparse matrix (upper triangle used) under a given
-    symmetric permutation, with small/negative pivots replaced by +inf."""
+    """L D L^T of a symmetric sparse matrix (lower triangle used) under a given
+    symmetric permutation, with small or negative pivots replaced by +inf
+    (``ldl.c``: column by column from the definition of the factorisation)."""
 
     def __init__(self, S, perm, pivtol):
         import scipy.sparse as sp
@@ -131,32 +140,38 @@ class LDL:
         self.n = n
         self.perm = np.asarray(perm, np.int64)
         Sp = S.tocsr()[self.perm][:, self.perm]
-        U = sp.triu(Sp, format="csc")
-        U.sort_indices()
-        Ap = _c(U.indptr, np.int32)
-        Ai = _c(U.indices, np.int32)
-        Ax = _c(U.data, np.float64)
-        self.Lp = np.zeros(n + 1, np.int32)
-        parent = np.zeros(n, np.int32)
-        lnz = np.zeros(n, np.int32)
-        flag = np.zeros(n, np.int32)
-        L = lib()
-        L.orc_ldl_symbolic(n, _ptr(Ap), _ptr(Ai), _ptr(self.Lp), _ptr(parent), _ptr(lnz), _ptr(flag))
-        nnz = int(self.Lp[n])
-        self.Li = np.zeros(max(nnz, 1), np.int32)
-        self.Lx = np.zeros(max(nnz, 1), np.float64)
-        self.D = np.zeros(n, np.float64)
-        Y = np.zeros(n, np.float64)
-        pattern = np.zeros(n, np.int32)
-        self.n_inf = L.orc_ldl_numeric(n, _ptr(Ap), _ptr(Ai), _ptr(Ax), _ptr(self.Lp), _ptr(parent),
-                                       _ptr(lnz), _ptr(self.Li), _ptr(self.Lx), _ptr(self.D),
-                                       _ptr(Y), _ptr(pattern), _ptr(flag), float(pivtol))
-        self.nnz_L = nnz + n          # strictly lower part plus the unit diagonal
+        Lo = sp.tril(Sp, format="csc")
+        Lo.sort_indices()
+        Ap = _c(Lo.indptr, np.int32)
+        Ai = _c(Lo.indices, np.int32)
+        Ax = _c(Lo.data, np.float64)
+        self._h = lib().orc_ldl_factor(n, _ptr(Ap), _ptr(Ai), _ptr(Ax), float(pivtol))
+        if not self._h:
+            raise MemoryError("orc_ldl_factor")
+        self.n_inf = int(lib().orc_ldl_ninf(self._h))
+        self.nnz_L = int(lib().orc_ldl_nnz(self._h)) + n  # strictly lower part + unit diagonal
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc_ldl_free(h)
+            self._h = None
+
+    def factors(self):
+        """(L as a scipy CSC unit lower triangular matrix, D) in the permuted order."""
+        import scipy.sparse as sp
+        nnz = self.nnz_L - self.n
+        colp = np.empty(self.n + 1, np.int64)
+        row = np.empty(max(nnz, 1), np.int32)
+        val = np.empty(max(nnz, 1), np.float64)
+        d = np.empty(self.n, np.float64)
+        lib().orc_ldl_export(self._h, _ptr(colp), _ptr(row), _ptr(val), _ptr(d))
+        L = sp.csc_matrix((val[:nnz], row[:nnz], colp), shape=(self.n, self.n))
+        return (L + sp.identity(self.n, format="csc")).tocsc(), d
 
     def solve(self, b):
         x = _c(np.asarray(b, np.float64)[self.perm], np.float64)
-        lib().orc_ldl_solve(self.n, _ptr(x), _ptr(self.Lp), _ptr(self.Li), _ptr(self.Lx),
-                            _ptr(self.D))
+        lib().orc_ldl_solve(self._h, _ptr(x))
         out = np.empty_like(x)
         out[self.perm] = x
         return out

@@ -1,103 +1,217 @@
 /*
- * CPU oracle -- sparse LDL^T factorisation with the "infinite pivot" rule.
+ * CPU oracle -- L D L^T of a sparse symmetric matrix with the infinite-pivot
+ * rule.
  *
  * TEST INFRASTRUCTURE ONLY (see oracle/__init__.py); shares no code with the
  * HIP library.
  *
- * Section 4.2: once the method switches to a direct solver, the Schur
- * complement (symmetric, singular, weakly diagonally dominant) is factorised
- * exactly as L D L^T after a fill-reducing ordering.  One pivot is expected to
- * vanish; the paper notes that a modified factorisation replacing small pivots
- * by an infinitely large value handles it.  Here a pivot d_k <= pivtol * a_kk
- * (a_kk the original diagonal entry) is set to +inf: the multipliers in its
- * column become 0 and the solve returns 0 for that unknown, which grounds one
- * node of every (numerically) disconnected component.
+ * Section 4.2: after the switch the Schur complement (symmetric, singular by
+ * one per connected component of the support, weakly diagonally dominant) is
+ * factorised exactly as L D L^T, after a fill-reducing ordering chosen by the
+ * caller.  The paper's remark on the vanishing pivot allows replacing it by an
+ * infinitely large value.  Reading used here: a pivot d_k that is not above
+ * pivtol * a_kk (a_kk the diagonal entry of the input) or not positive becomes
+ * +inf.  Its column of L is then zero (the multipliers divide by +inf), it
+ * contributes nothing to later columns, and the solve returns 0 for that
+ * unknown.
  *
- * Algorithm: the up-looking row-by-row factorisation (elimination tree,
- * nonzero pattern of row k of L from the tree reach of column k of A), as
- * described in T. Davis, "Direct Methods for Sparse Linear Systems", SIAM 2006,
- * chapter 4.  Input: the UPPER triangle of the (already permuted) matrix in
- * compressed-column form (rows i <= k in column k).  0-based int32 indices.
+ * The factor is computed column by column straight from its definition,
+ *     d_k  = a_kk - sum_{j<k} l_kj^2 d_j,
+ *     l_ik = (a_ik - sum_{j<k} l_ij l_kj d_j) / d_k,   i > k,
+ * i.e. column k of the lower triangle of A is gathered into a dense work
+ * vector w, every earlier column j whose entry l_kj is structurally nonzero
+ * subtracts (l_kj d_j) L(k:n, j) from it, then d_k = w_k and L(k+1:n, k) =
+ * w(k+1:n) / d_k.  The earlier columns that reach row k are kept in one list
+ * per row: a finished column waits in the list of the row of its first entry,
+ * and after it has been used for row r it moves to the list of its next row.
+ * The structure of a column is the union of the structures that reach it, so
+ * the entries counted are those of the symbolic factorisation (an infinite
+ * pivot's column keeps its structure, with zero values).
+ *
+ * Input: the LOWER triangle (rows i >= k) of the already permuted matrix in
+ * compressed-column form, 0-based int32 indices; entries above the diagonal
+ * are ignored.
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
 
-/* elimination tree and column counts of L */
-void orc_ldl_symbolic(int32_t n, const int32_t *Ap, const int32_t *Ai,
-                      int32_t *Lp, int32_t *Parent, int32_t *Lnz, int32_t *Flag)
+typedef struct {
+    int32_t n, ninf;
+    int64_t nnz, cap;
+    int64_t *colp;  /* n + 1: start of each column of L (strictly lower part) */
+    int32_t *row;   /* row index of each stored entry, increasing in a column */
+    double *val;    /* its value l_ik */
+    double *d;      /* n pivots (+inf for an infinite pivot) */
+} orc_ldl;
+
+static int cmp_i32(const void *a, const void *b)
 {
-    for (int32_t k = 0; k < n; ++k) {
-        Parent[k] = -1;
-        Flag[k] = k;
-        Lnz[k] = 0;
-        for (int32_t p = Ap[k]; p < Ap[k + 1]; ++p) {
-            int32_t i = Ai[p];
-            if (i >= k) continue;
-            for (; Flag[i] != k; i = Parent[i]) {
-                if (Parent[i] == -1) Parent[i] = k;
-                Lnz[i]++;
-                Flag[i] = k;
-            }
-        }
-    }
-    Lp[0] = 0;
-    for (int32_t k = 0; k < n; ++k) Lp[k + 1] = Lp[k] + Lnz[k];
+    const int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
 }
 
-/* numeric factorisation; returns the number of infinite pivots */
-int32_t orc_ldl_numeric(int32_t n, const int32_t *Ap, const int32_t *Ai, const double *Ax,
-                        const int32_t *Lp, const int32_t *Parent, int32_t *Lnz,
-                        int32_t *Li, double *Lx, double *D, double *Y,
-                        int32_t *Pattern, int32_t *Flag, double pivtol)
+void orc_ldl_free(orc_ldl *F)
 {
-    int32_t ninf = 0;
+    if (!F) return;
+    free(F->colp);
+    free(F->row);
+    free(F->val);
+    free(F->d);
+    free(F);
+}
+
+static int grow(orc_ldl *F, int64_t need)
+{
+    if (need <= F->cap) return 1;
+    int64_t c = F->cap ? F->cap : 1024;
+    while (c < need) c *= 2;
+    int32_t *r = (int32_t *)realloc(F->row, sizeof(int32_t) * (size_t)c);
+    if (!r) return 0;
+    F->row = r;
+    double *v = (double *)realloc(F->val, sizeof(double) * (size_t)c);
+    if (!v) return 0;
+    F->val = v;
+    F->cap = c;
+    return 1;
+}
+
+/* factorise; returns NULL when memory runs out */
+orc_ldl *orc_ldl_factor(int32_t n, const int32_t *Ap, const int32_t *Ai, const double *Ax,
+                        double pivtol)
+{
+    orc_ldl *F = (orc_ldl *)calloc(1, sizeof(orc_ldl));
+    double *w = (double *)calloc((size_t)n + 1, sizeof(double));
+    int32_t *seen = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
+    int32_t *pat = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
+    int32_t *head = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
+    int32_t *link = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
+    int64_t *next_pos = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
+    if (F) {
+        F->n = n;
+        F->colp = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+        F->d = (double *)calloc((size_t)n + 1, sizeof(double));
+    }
+    if (!F || !w || !seen || !pat || !head || !link || !next_pos || !F->colp || !F->d) {
+        orc_ldl_free(F);
+        F = NULL;
+        goto done;
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        seen[i] = -1;
+        head[i] = -1;
+    }
     for (int32_t k = 0; k < n; ++k) {
+        int32_t np = 0;
         double akk = 0.0;
-        Y[k] = 0.0;
-        int32_t top = n;
-        Flag[k] = k;
-        Lnz[k] = 0;
-        for (int32_t p = Ap[k]; p < Ap[k + 1]; ++p) {
-            int32_t i = Ai[p];
-            if (i > k) continue;
-            Y[i] += Ax[p];
-            if (i == k) akk += Ax[p];
-            int32_t len = 0;
-            for (; Flag[i] != k; i = Parent[i]) {
-                Pattern[len++] = i;
-                Flag[i] = k;
+        /* column k of A, rows >= k */
+        seen[k] = k;
+        w[k] = 0.0;
+        for (int32_t q = Ap[k]; q < Ap[k + 1]; ++q) {
+            const int32_t i = Ai[q];
+            if (i < k) continue;
+            if (seen[i] != k) {
+                seen[i] = k;
+                w[i] = 0.0;
+                pat[np++] = i;
             }
-            while (len > 0) Pattern[--top] = Pattern[--len];
+            w[i] += Ax[q];
+            if (i == k) akk += Ax[q];
         }
-        D[k] = Y[k];
-        Y[k] = 0.0;
-        for (; top < n; ++top) {
-            int32_t i = Pattern[top];
-            double yi = Y[i];
-            Y[i] = 0.0;
-            int32_t p2 = Lp[i] + Lnz[i];
-            for (int32_t p = Lp[i]; p < p2; ++p) Y[Li[p]] -= Lx[p] * yi;
-            double lki = isinf(D[i]) ? 0.0 : yi / D[i];
-            D[k] -= lki * yi;
-            Li[p2] = k;
-            Lx[p2] = lki;
-            Lnz[i]++;
+        /* the earlier columns with an entry in row k */
+        int32_t j = head[k];
+        head[k] = -1;
+        while (j >= 0) {
+            const int32_t after = link[j];
+            const int64_t p0 = next_pos[j]; /* F->row[p0] == k */
+            const int finite = isfinite(F->d[j]);
+            const double c = finite ? F->val[p0] * F->d[j] : 0.0;
+            for (int64_t q = p0; q < F->colp[j + 1]; ++q) {
+                const int32_t i = F->row[q];
+                if (seen[i] != k) {
+                    seen[i] = k;
+                    w[i] = 0.0;
+                    pat[np++] = i;
+                }
+                if (finite) w[i] -= F->val[q] * c;
+            }
+            if (p0 + 1 < F->colp[j + 1]) {
+                const int32_t r = F->row[p0 + 1];
+                next_pos[j] = p0 + 1;
+                link[j] = head[r];
+                head[r] = j;
+            }
+            j = after;
         }
-        if (!(D[k] > pivtol * akk) || !(D[k] > 0.0)) {
-            D[k] = INFINITY;
-            ++ninf;
+        /* pivot and column k of L */
+        double dk = w[k];
+        if (!(dk > pivtol * akk) || !(dk > 0.0)) {
+            dk = INFINITY;
+            F->ninf++;
+        }
+        F->d[k] = dk;
+        /* pat holds the rows > k reached (k itself was marked before) */
+        int32_t m = 0;
+        for (int32_t t = 0; t < np; ++t)
+            if (pat[t] > k) pat[m++] = pat[t];
+        qsort(pat, (size_t)m, sizeof(int32_t), cmp_i32);
+        if (!grow(F, F->nnz + m)) {
+            orc_ldl_free(F);
+            F = NULL;
+            goto done;
+        }
+        F->colp[k] = F->nnz;
+        for (int32_t t = 0; t < m; ++t) {
+            F->row[F->nnz] = pat[t];
+            F->val[F->nnz] = isinf(dk) ? 0.0 : w[pat[t]] / dk;
+            F->nnz++;
+        }
+        F->colp[k + 1] = F->nnz;
+        if (m > 0) {
+            const int32_t r = pat[0];
+            next_pos[k] = F->colp[k];
+            link[k] = head[r];
+            head[r] = k;
         }
     }
-    return ninf;
+done:
+    free(w);
+    free(seen);
+    free(pat);
+    free(head);
+    free(link);
+    free(next_pos);
+    return F;
 }
 
-/* solve L D L^T x = b in place */
-void orc_ldl_solve(int32_t n, double *x, const int32_t *Lp, const int32_t *Li,
-                   const double *Lx, const double *D)
+int64_t orc_ldl_nnz(const orc_ldl *F) { return F->nnz; }
+int32_t orc_ldl_ninf(const orc_ldl *F) { return F->ninf; }
+
+/* x <- (L D L^T)^{-1} x: forward with L, scale by D (an infinite pivot gives
+ * 0), backward with L^T */
+void orc_ldl_solve(const orc_ldl *F, double *x)
 {
-    for (int32_t j = 0; j < n; ++j)
-        for (int32_t p = Lp[j]; p < Lp[j + 1]; ++p) x[Li[p]] -= Lx[p] * x[j];
-    for (int32_t j = 0; j < n; ++j) x[j] = isinf(D[j]) ? 0.0 : x[j] / D[j];
-    for (int32_t j = n - 1; j >= 0; --j)
-        for (int32_t p = Lp[j]; p < Lp[j + 1]; ++p) x[j] -= Lx[p] * x[Li[p]];
+    const int32_t n = F->n;
+    for (int32_t j = 0; j < n; ++j) {
+        const double xj = x[j];
+        for (int64_t q = F->colp[j]; q < F->colp[j + 1]; ++q) x[F->row[q]] -= F->val[q] * xj;
+    }
+    for (int32_t j = 0; j < n; ++j) x[j] = isinf(F->d[j]) ? 0.0 : x[j] / F->d[j];
+    for (int32_t j = n - 1; j >= 0; --j) {
+        double s = x[j];
+        for (int64_t q = F->colp[j]; q < F->colp[j + 1]; ++q) s -= F->val[q] * x[F->row[q]];
+        x[j] = s;
+    }
+}
+
+/* copy the factor out: colp (n + 1), row and val (nnz), d (n) */
+void orc_ldl_export(const orc_ldl *F, int64_t *colp, int32_t *row, double *val, double *d)
+{
+    memcpy(colp, F->colp, sizeof(int64_t) * ((size_t)F->n + 1));
+    if (F->nnz) {
+        memcpy(row, F->row, sizeof(int32_t) * (size_t)F->nnz);
+        memcpy(val, F->val, sizeof(double) * (size_t)F->nnz);
+    }
+    memcpy(d, F->d, sizeof(double) * (size_t)F->n);
 }

@@ -458,3 +458,247 @@ def test_schur_pattern_of_forest_support_is_chordal():
         if r_ != c_:
             adj[r_].add(c_)
     assert _is_chordal(adj)
+
+
+# --------------------------------------------------------------- Section 4.2
+def _brute_fill(pattern):
+    """Entries of the strictly lower factor from symbolic elimination on a
+    dense boolean matrix: eliminating k joins every pair of its later
+    neighbours (the elimination graph)."""
+    P = pattern.copy()
+    n = P.shape[0]
+    total = 0
+    for k in range(n):
+        later = np.nonzero(P[k + 1:, k])[0] + k + 1
+        total += later.size
+        for a in later:
+            P[later, a] = True
+            P[a, later] = True
+    return total
+
+
+def _random_spd(rng, n, density):
+    A = sp.random(n, n, density=density, random_state=int(rng.integers(1 << 30)))
+    A = A + A.T
+    return (A + sp.diags(np.asarray(abs(A).sum(1)).ravel() + 1.0)).tocsr()
+
+
+@pytest.mark.parametrize("n,density", [(1, 1.0), (7, 0.3), (60, 0.08), (200, 0.02)])
+def test_ldl_reconstructs_the_matrix_and_counts_the_symbolic_fill(n, density):
+    """L D L^T equals the permuted matrix, and the stored entries of L are
+    exactly those of symbolic elimination (so the fill statistic is the true
+    one)."""
+    rng = np.random.default_rng(n)
+    A = _random_spd(rng, n, density)
+    perm = rng.permutation(n)
+    F = _cscan.LDL(A, perm, 1e-12)
+    assert F.n_inf == 0
+    L, d = F.factors()
+    Ap = A[perm][:, perm].toarray()
+    np.testing.assert_allclose((L @ sp.diags(d) @ L.T).toarray(), Ap, rtol=0, atol=1e-12 * abs(Ap).max())
+    assert np.allclose(np.diag(L.toarray()), 1.0) and sp.triu(L, 1).nnz == 0
+    assert F.nnz_L - n == _brute_fill(Ap != 0.0)
+    b = rng.standard_normal(n)
+    np.testing.assert_allclose(A @ F.solve(b), b, atol=1e-10)
+
+
+def test_ldl_infinite_pivot_grounds_each_component():
+    """A weighted graph Laplacian is singular once per connected component: the
+    factorisation replaces exactly that many pivots by +inf (the paper's
+    modified factorisation) and returns a solution of every consistent
+    system, equal to the minimum-norm one up to a constant per component."""
+    rng = np.random.default_rng(3)
+    blocks = []
+    for size in (9, 14, 6):
+        W = sp.random(size, size, density=0.5, random_state=int(rng.integers(1 << 30)))
+        W = W + W.T + sp.diags(np.ones(size - 1), 1) + sp.diags(np.ones(size - 1), -1)  # connected
+        W = sp.csr_matrix(W - sp.diags(W.diagonal()))
+        blocks.append(sp.diags(np.asarray(W.sum(1)).ravel()) - W)
+    S = sp.block_diag(blocks).tocsr()
+    n = S.shape[0]
+    comp = np.repeat(np.arange(3), [9, 14, 6])
+    F = _cscan.LDL(S, rng.permutation(n), 1e-10)
+    assert F.n_inf == 3
+    b = rng.standard_normal(n)
+    b -= (np.bincount(comp, b) / np.bincount(comp))[comp]  # consistent: zero sum per component
+    x = F.solve(b)
+    np.testing.assert_allclose(S @ x, b, atol=1e-10)
+    x_pinv = np.linalg.pinv(S.toarray()) @ b
+    shift = x - x_pinv
+    for c in range(3):
+        assert np.ptp(shift[comp == c]) < 1e-9
+
+
+def test_ldl_of_forest_schur_complement_has_zero_fill_under_a_perfect_ordering():
+    """Corollary 1 with the factor itself: the Schur complement of an acyclic
+    support, ordered by a perfect elimination ordering (reversed maximum
+    cardinality search), factorises with no entry outside its own pattern."""
+    rng = np.random.default_rng(21)
+    m, n = 18, 14
+    nodes = list(range(m + n))
+    rng.shuffle(nodes)
+    edges = []
+    for k in range(1, m + n):
+        v = nodes[k]
+        cands = [u for u in nodes[:k] if (u < m) != (v < m)]
+        if cands:
+            u = cands[rng.integers(len(cands))]
+            i, j = (u, v - m) if u < m else (v, u - m)
+            edges.append(i + j * m)
+    idx = np.unique(edges)
+    rows, cols = idx % m, idx // m
+    M, N, V = oracle.normal_blocks(rng.uniform(0.5, 2, idx.size), rows, cols, m, n)
+    S = oracle.schur_complement(M, N, V, "M").tocsr()
+    adj = [set(S[r].indices) - {r} for r in range(n)]
+    weight, order, seen = [0] * n, [], [False] * n
+    for _ in range(n):
+        v = max((u for u in range(n) if not seen[u]), key=lambda u: weight[u])
+        seen[v] = True
+        order.append(v)
+        for u in adj[v]:
+            if not seen[u]:
+                weight[u] += 1
+    peo = np.array(order[::-1])
+    F = _cscan.LDL(S, peo, 1e-12)
+    assert F.nnz_L == sp.tril(S).nnz
+
+
+# --------------------------------------------------------------- Section 3.4
+def _norm_dist(xs, xt, kind):
+    """m x n distances in the cost's norm, and the squared 2-norm, by numpy."""
+    d = xs[:, None, :].astype(np.int64) - xt[None, :, :].astype(np.int64)
+    sq = (d * d).sum(-1)
+    if kind == 1:
+        return np.abs(d).sum(-1).astype(float), sq
+    if kind == 3:
+        return np.abs(d).max(-1).astype(float), sq
+    return np.sqrt(sq), sq
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2, 3])
+@pytest.mark.parametrize("radius", [0.05, 0.2, 0.5])
+def test_heuristic_subset_is_the_disk_of_the_largest_distance(kind, radius):
+    """J = {cost key < L} holds exactly the pairs closer than radius * D, with D
+    the largest distance of the points' bounding box in the cost's norm (so J
+    is the same fraction of all pairs at every image side, Section 5.1)."""
+    side = 24
+    xs = grid_coords(side)
+    xt = grid_coords(side)
+    L = I.heuristic_key_limit(xs, xt, radius, kind)
+    dist, sq = _norm_dist(xs, xt, kind)
+    D = {0: math.sqrt(2) * (side - 1), 2: math.sqrt(2) * (side - 1), 1: 2 * (side - 1),
+         3: side - 1}[kind]
+    key = sq if kind in (0, 2) else dist.astype(np.int64)
+    inside = dist < radius * D
+    np.testing.assert_array_equal(key < L, inside)
+
+
+@pytest.mark.parametrize("kind", [0, 2])
+@pytest.mark.parametrize("kmax", [1, 9, 10_000])
+def test_heuristic_pricing_is_pricing_restricted_to_the_subset(kind, kmax):
+    """Pricing over J equals a brute-force sort of the reduced costs of J's
+    variables outside the support; a limit above every key is the full scan."""
+    rng = np.random.default_rng(30 + kmax + kind)
+    m, n = 17, 14
+    xs = rng.integers(0, 12, (m, 2)).astype(np.int32)
+    xt = rng.integers(0, 12, (n, 2)).astype(np.int32)
+    y, z = rng.uniform(0, 60, m), rng.uniform(0, 60, n)
+    support = np.sort(rng.choice(m * n, 25, replace=False))
+    L = 30
+    _, sq = _norm_dist(xs, xt, kind)
+    c = np.sqrt(sq) if kind == 2 else sq.astype(float)
+    r = (c - y[:, None]) - z[None, :]
+    idx_all = np.arange(m * n)
+    rv = r.reshape(-1, order="F")
+    keyv = sq.reshape(-1, order="F")
+    ok = (rv < 0) & (keyv < L) & ~np.isin(idx_all, support)
+    cand = idx_all[ok]
+    cand = cand[np.lexsort((cand, rv[cand]))]
+    idx, rr, nneg = _cscan.price(xs, xt, y, z, support, kmax, kind, key_limit=L)
+    assert nneg == cand.size
+    np.testing.assert_array_equal(idx, cand[:kmax])
+    np.testing.assert_array_equal(rr, rv[cand[:kmax]])
+    full = _cscan.price(xs, xt, y, z, support, kmax, kind)
+    above = _cscan.price(xs, xt, y, z, support, kmax, kind, key_limit=int(sq.max()) + 1)
+    for u, v in zip(full, above):
+        np.testing.assert_array_equal(u, v)
+
+
+@pytest.mark.parametrize("k,kind", [(0, 0), (1, 0), (2, 1)])
+def test_heuristic_pricing_solve_reaches_the_lp_optimum(k, kind):
+    """With heuristic pricing (3 iterations on J, then a full scan) the method
+    still ends at the optimum: the stop test's pricing and the certificate scan
+    every variable."""
+    inst = config_instance("c1", k)
+    P = oracle.OracleParams(heur_radius=0.15, heur_run=3, cost_kind=kind)
+    hist = []
+    res = oracle.solve(inst.a, inst.b, inst.xs, inst.xt, P, log=hist.append)
+    assert any(h.get("heuristic") for h in hist) and not all(h.get("heuristic") for h in hist)
+    if kind == 0:
+        ref = lp_optimum(inst.a, inst.b, inst.xs, inst.xt)
+    else:
+        ref = oracle.solve(inst.a, inst.b, inst.xs, inst.xt,
+                           oracle.OracleParams(cost_kind=kind)).objective
+    assert abs(res.objective - ref) <= 1e-7 * ref
+    assert res.rel_gap <= 1e-6 and res.marginal_residual <= 1e-8
+
+
+# --------------------------------------------------------------- Sections 4.2, 4.3 remarks
+def test_ordering_is_reused_while_the_pattern_stays_inside_it():
+    """The symbolic part (ordering) of the factorisation is kept while the
+    Schur pattern shrinks and recomputed when it grows; the factor it gives is
+    exact either way."""
+    rng = np.random.default_rng(40)
+    n = 80
+    A = _random_spd(rng, n, 0.06)
+    cache = {}
+    F1 = I.direct_factor(A, 1e-12, cache)
+    assert cache.get("reused", 0) == 0
+    # drop some off-diagonal pairs (symmetric): pattern shrinks -> reused
+    C = sp.triu(A, 1).tocoo()
+    keep = rng.random(C.nnz) > 0.3
+    U = sp.coo_matrix((C.data[keep], (C.row[keep], C.col[keep])), shape=A.shape)
+    B = U + U.T
+    B = (B + sp.diags(np.asarray(abs(B).sum(1)).ravel() + 1.0)).tocsr()
+    F2 = I.direct_factor(B, 1e-12, cache)
+    assert cache["reused"] == 1
+    b = rng.standard_normal(n)
+    np.testing.assert_allclose(B @ F2.solve(b), b, atol=1e-10)
+    np.testing.assert_allclose(A @ F1.solve(b), b, atol=1e-10)
+    # a new off-diagonal pair outside the pattern -> a new ordering
+    i, j = np.argwhere((A.toarray() == 0) & ~np.eye(n, dtype=bool))[0]
+    E = sp.coo_matrix(([0.5, 0.5], ([i, j], [j, i])), shape=A.shape)
+    G = (A + E + sp.diags(np.full(n, 1.0))).tocsr()
+    I.direct_factor(G, 1e-12, cache)
+    assert cache["reused"] == 1
+
+
+def test_forced_switch_back_to_cg_still_reaches_the_optimum():
+    """A switch to the direct solver at iteration 4 and a forced return to CG
+    at iteration 8 (remark of Section 4.3): the following iterations run CG and
+    the solve ends at the LP optimum."""
+    inst = config_instance("c1", 1)
+    hist = []
+    P = oracle.OracleParams(force_switch_at=4, force_switch_back_at=8)
+    res = oracle.solve(inst.a, inst.b, inst.xs, inst.xt, P, log=hist.append)
+    assert res.switches_back == 1
+    solvers = [h["solver"] for h in hist]
+    k = next(q for q, h in enumerate(hist) if h.get("switch_back"))
+    assert hist[k]["it"] == 8 and solvers[k - 1] == "direct"
+    ref = lp_optimum(inst.a, inst.b, inst.xs, inst.xt)
+    assert abs(res.objective - ref) <= 1e-7 * ref
+    check_invariants(res, inst.a, inst.b, inst.xs, inst.xt)
+
+
+def test_switch_back_rule_alternating_solvers_reach_the_optimum():
+    """Thresholds that make the support-drop rule fire at every chance and the
+    growth rule at any growth of the support: the solvers alternate while
+    columns enter, and the method still converges."""
+    inst = config_instance("c1", 2)
+    hist = []
+    P = oracle.OracleParams(switch_drop=-10.0, switch_back_grow=1e-9, max_iter=300)
+    res = oracle.solve(inst.a, inst.b, inst.xs, inst.xt, P, log=hist.append)
+    assert res.switches_back >= 3
+    ref = lp_optimum(inst.a, inst.b, inst.xs, inst.xt)
+    assert abs(res.objective - ref) <= 1e-7 * ref
+    check_invariants(res, inst.a, inst.b, inst.xs, inst.xt)
