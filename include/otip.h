@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define OTIP_ABI_VERSION 3
+#define OTIP_ABI_VERSION 4
 
 enum otip_status {
     OTIP_OK = 0,
@@ -110,6 +110,23 @@ typedef struct otip_params {
                                 0: chosen from m and n */
     double ws_kappa;         /* warm start: initial support ~ ws_kappa*(m+n-1) smallest
                                 reduced costs under the given duals (0: use kappa) */
+    double heur_radius;      /* Section 3.4 heuristic pricing: > 0 prices only
+                                J = {(i,j): distance < heur_radius * D} (D the largest
+                                distance of the points' bounding box in the cost's norm;
+                                integer key bound ceil(r^2 Dsq) for the squared and 2-norm
+                                costs, ceil(r D) for the 1- and inf-norm) in heur_run
+                                consecutive iterations out of every heur_run + 1; the
+                                stop test and certificate always scan all m n.  0: off */
+    int32_t heur_run;        /* consecutive heuristic iterations before a full scan (3) */
+    double switch_back_grow; /* Section 4.3 remark: after the switch, return to CG when
+                                psi has grown by this fraction over the switch window
+                                (and the switch was made by the support-drop rule);
+                                0: never */
+    int32_t force_switch_back_at; /* >= 0: return to CG at this iteration if the direct
+                                     solver is in use (host-forced test hook) */
+    int32_t schur_reuse;     /* 1: keep the Schur pattern across support updates that
+                                only remove entries (a superset of the new one; its
+                                extra entries get the value 0) */
 } otip_params;
 
 /* Problem description.  All arrays are DEVICE pointers.
@@ -183,6 +200,9 @@ typedef struct otip_info {
                                   matrix less a rank-b product (b = 64 or, two block columns
                                   at once, 128); 2b (c(r-c) + c(c+1)/2) for a launch that
                                   updates only the next c-wide block column */
+    int64_t heuristic_scans;   /* pricing calls on the heuristic subset (Section 3.4) */
+    int64_t switches_back;     /* returns from the direct solver to CG (Section 4.3) */
+    int64_t patterns_kept;     /* support updates that kept the Schur pattern (schur_reuse) */
 } otip_info;
 
 typedef struct otip_ctx otip_ctx;
@@ -265,6 +285,23 @@ int otip_price(otip_ctx *ctx, int32_t m, int32_t n, const int32_t *xs, const int
                const double *y, const double *z, const uint32_t *support_bitmap, int64_t kmax,
                int32_t precision, int32_t tile, int32_t cost_kind, int32_t *out_i,
                int32_t *out_j, double *out_r, int64_t *out_count, int64_t *out_nneg);
+
+/*
+ * Heuristic pricing (Section 3.4): otip_price restricted to the subset
+ * J = {(i, j) : integer cost key < key_limit} fixed before the iteration (the
+ * key is the cost itself, the squared norm for the 2-norm; otip_params
+ * heur_radius describes how the solver chooses key_limit).  Same arguments,
+ * ordering and exactness as otip_price in FP64; the selected columns, the
+ * count out_nneg and the values are those of the variables of J only.  The
+ * subset is built on the device for each call (per-source target lists,
+ * 4 bytes per member of J plus 8 bytes per source, held by the context).
+ *   key_limit: >= 1.  out_subset_size: HOST, optional, |J|.
+ */
+int otip_price_subset(otip_ctx *ctx, int32_t m, int32_t n, const int32_t *xs, const int32_t *xt,
+                      const double *y, const double *z, const uint32_t *support_bitmap,
+                      int64_t kmax, int32_t cost_kind, int64_t key_limit, int32_t *out_i,
+                      int32_t *out_j, double *out_r, int64_t *out_count, int64_t *out_nneg,
+                      int64_t *out_subset_size);
 
 /* min over ALL (i, j) of (C_ij - y_i) - z_j (C_ij of otip_cost cost_kind) and
  * the first variable index attaining it (Section 3.3: s_hat = c - A^T y_hat).

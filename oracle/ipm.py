@@ -74,8 +74,13 @@ class OracleParams:
     # near = max(rel r1, rel r2) <= remove_gate; small = p < remove_rel*min(a_i, b_j).
     remove_gate: float = 1e-3
     remove_rel: float = 1e-6
-    # Section 4.2: incomplete Cholesky with a drop tolerance lowered whenever
-    # a solve needs too many CG iterations, diagonal lifted for safety.
+    # Section 4.2: an incomplete factorisation with a drop tolerance lowered
+    # whenever a solve needs too many CG iterations, diagonal lifted for safety.
+    # The paper names incomplete Cholesky; this oracle uses SuperLU's threshold
+    # incomplete LU in symmetric mode (natural order, diagonal pivots) as the
+    # stand-in: on the symmetric, weakly diagonally dominant Schur complement it
+    # drops entries by the same threshold rule, but its factors are not exactly
+    # L and L^T, hence the flexible (Polak-Ribiere) CG in ``pcg``.
     droptol0: float = 1e-2
     droptol_min: float = 1e-6
     droptol_cg_limit: int = 100
@@ -100,7 +105,7 @@ class OracleParams:
     cg_floor: float = 1e-9
     # "auto" = CG then switch (Section 4.3); "pcg" or "direct" force one solver.
     linear_solver: str = "auto"
-    # "ic" (incomplete factorisation, Section 4.2) or "jacobi".
+    # "ic" (the incomplete factorisation above, Section 4.2) or "jacobi".
     preconditioner: str = "ic"
     # stop-test complementarity term: "relative" = psi*mu/max(1,|c^T p|);
     # "absolute" = mu exactly as printed in Section 3.2.
@@ -118,6 +123,22 @@ class OracleParams:
     # default workload), 1 the 1-norm, 2 the 2-norm, 3 the inf-norm of the
     # integer offset (see ``costs``)
     cost_kind: int = 0
+    # Section 3.4, heuristic pricing: price only J = {c < C_max} for heur_run
+    # consecutive iterations, then the full vector once.  C_max scales with the
+    # image side (Section 5.1) through the largest distance D between points:
+    # J = pairs closer than heur_radius * D in the cost's own norm (see
+    # ``heuristic_key_limit``).  0 = off (every iteration prices all m n).
+    heur_radius: float = 0.0
+    heur_run: int = 3
+    # Section 4.3 remark: after a switch made by the support-drop rule, return
+    # to CG once psi has grown by this fraction over the switch window; 0 =
+    # never.  force_switch_back_at >= 0 returns at that iteration (test hook).
+    switch_back_grow: float = 0.0
+    force_switch_back_at: int = -1
+    # Section 4.2 remark: keep the symbolic part of the factorisation (the
+    # fill-reducing ordering) across support updates while the pattern of the
+    # Schur complement stays inside the one it was computed for.
+    reuse_ordering: bool = True
 
 
 @dataclass
@@ -138,6 +159,8 @@ class OracleResult:
     direct_iterations: int
     max_fill_pct: float
     history: list = field(default_factory=list)
+    switches_back: int = 0
+    orderings_reused: int = 0
     seconds: float = 0.0
 
 
@@ -223,7 +246,7 @@ class SchurSolver:
     projected onto the range (mean-zero on every component) before solving.
     """
 
-    def __init__(self, S, comp, ncomp, mode, params, droptol, factor=None):
+    def __init__(self, S, comp, ncomp, mode, params, droptol, factor=None, cache=None):
         self.S = S
         self.comp = comp
         self.ncomp = ncomp
@@ -238,7 +261,7 @@ class SchurSolver:
         n = S.shape[0]
         if mode == "direct":
             if self.lu is None:
-                self.lu = direct_factor(S, params.pivot_tol)
+                self.lu = direct_factor(S, params.pivot_tol, cache)
             self.fill = 100.0 * self.lu.nnz_L / float(n * n)
         else:
             if params.preconditioner == "ic":
@@ -290,10 +313,25 @@ def min_degree_order(S):
     return np.argsort(lu.perm_c)
 
 
-def direct_factor(S, pivtol):
+def direct_factor(S, pivtol, cache=None):
     """Exact L D L^T of the Schur complement after a minimum-degree ordering,
-    with the infinite-pivot rule for vanishing pivots (Section 4.2)."""
-    return _cscan.LDL(S, min_degree_order(S), pivtol)
+    with the infinite-pivot rule for vanishing pivots (Section 4.2).  With a
+    cache (a dict), the ordering of an earlier factorisation is reused while the
+    pattern of S lies inside the pattern it was computed for (the remark of
+    Section 4.2 on updating the symbolic factorisation instead of redoing it):
+    any symmetric ordering gives the same factorisation up to rounding, and one
+    computed for a superset pattern gives no more fill than on that superset."""
+    pat = S.tocsr().copy()
+    pat.data = np.ones_like(pat.data)
+    if cache is not None and cache.get("pattern") is not None and \
+            cache["pattern"].shape == pat.shape and \
+            (pat - pat.multiply(cache["pattern"])).count_nonzero() == 0:
+        cache["reused"] = cache.get("reused", 0) + 1
+        return _cscan.LDL(S, cache["perm"], pivtol)
+    perm = min_degree_order(S)
+    if cache is not None:
+        cache["pattern"], cache["perm"] = pat, perm
+    return _cscan.LDL(S, perm, pivtol)
 
 
 def pcg(S, b, tol, maxit, prec, atol=math.inf):
@@ -335,6 +373,21 @@ def pcg(S, b, tol, maxit, prec, atol=math.inf):
 # ---------------------------------------------------------------------------
 # The method
 # ---------------------------------------------------------------------------
+
+def heuristic_key_limit(xs, xt, radius, kind=0):
+    """Integer bound L of the heuristic subset J = {cost key < L} (Section 3.4).
+    The cost key is the cost itself, or the squared norm for the 2-norm.  With
+    D the largest distance between points in the cost's norm, J holds the pairs
+    closer than radius * D: for the squared and 2-norm costs the key is the
+    squared 2-norm, so L = ceil(radius^2 * Dsq) (Dsq the largest squared
+    distance); for the 1- and inf-norm L = ceil(radius * D).  Double arithmetic
+    left to right, then the ceiling: for an integer key k and real t, k < t if
+    and only if k < ceil(t)."""
+    span = float(cost_span(xs, xt, kind))
+    if kind in (0, 2):
+        return int(math.ceil(radius * radius * span))
+    return int(math.ceil(radius * span))
+
 
 def initial_support(xs, xt, kappa, kind=0):
     """Section 3.2 (end): the variables of small cost, about kappa*(m+n-1) of
@@ -380,7 +433,8 @@ def _build_system(st, theta, mode, params, factor=None):
     comp = lab[m:] if side == "M" else lab[:m]
     # relabel compactly
     _, comp = np.unique(comp, return_inverse=True)
-    solver = SchurSolver(S, comp, int(comp.max()) + 1, mode, params, st.droptol, factor)
+    cache = getattr(st, "symbolic", None) if params.reuse_ordering else None
+    solver = SchurSolver(S, comp, int(comp.max()) + 1, mode, params, st.droptol, factor, cache)
     return M, N, V, side, solver
 
 
@@ -515,6 +569,11 @@ def solve(a, b, xs, xt, params: OracleParams | None = None, log=None) -> OracleR
     f_norm = math.sqrt(float(st.a @ st.a + st.b @ st.b))
     kcap = m if P.enter_cap <= 0 else P.enter_cap
 
+    st.heur_limit = heuristic_key_limit(st.xs, st.xt, P.heur_radius, st.kind) \
+        if P.heur_radius > 0.0 else 0
+    st.symbolic = {}
+    st.forced_switch_done = st.forced_back_done = st.switched_by_drop = False
+    st.switches_back = 0
     idx0, _T = initial_support(st.xs, st.xt, P.kappa, st.kind)
     _set_support(st, idx0, np.ones(idx0.shape[0]), np.ones(idx0.shape[0]))
     _starting_point(st, P)
@@ -576,22 +635,46 @@ def _iterate(st, P, tol_int, it, mode, psi_hist, hist, cg_total, direct_its, max
                          np.concatenate([st.s, np.full(int(big.sum()), sm)]))
             it += 1
             continue
-        # 6. switch test (Section 4.3)
+        # 6a. switch back to CG (remark of Section 4.3)
         factor = None
-        if mode == "pcg" and P.linear_solver == "auto":
+        just_back = False
+        if mode == "direct" and P.linear_solver == "auto":
             w = P.switch_window
-            force = (P.force_switch_at >= 0 and it >= P.force_switch_at) or cg_failed
+            back = None
+            if P.force_switch_back_at >= 0 and it >= P.force_switch_back_at \
+                    and not st.forced_back_done:
+                st.forced_back_done = True
+                back = "forced"
+            elif P.switch_back_grow > 0.0 and st.switched_by_drop and len(psi_hist) > w and \
+                    (psi_hist[-1] - psi_hist[-1 - w]) / psi_hist[-1 - w] >= P.switch_back_grow:
+                back = "support growing"
+            if back:
+                mode = "pcg"
+                st.switched_by_drop = False
+                st.switches_back += 1
+                cg_failed = False
+                just_back = True
+                rec["switch_back"] = back
+        # 6b. switch test (Section 4.3)
+        if mode == "pcg" and not just_back and P.linear_solver == "auto":
+            w = P.switch_window
+            forced = P.force_switch_at >= 0 and it >= P.force_switch_at and \
+                not st.forced_switch_done
+            force = forced or cg_failed
             drop_ok = len(psi_hist) > w and \
                 (psi_hist[-1 - w] - psi_hist[-1]) / psi_hist[-1 - w] >= P.switch_drop
             if force or drop_ok:
                 st.theta = st.p / st.s
                 M_, N_, V_ = normal_blocks(st.theta, st.rows, st.cols, m, n)
                 S_ = schur_complement(M_, N_, V_, "M" if n <= m else "N")
-                lu = direct_factor(S_, P.pivot_tol)
+                lu = direct_factor(S_, P.pivot_tol,
+                                   st.symbolic if P.reuse_ordering else None)
                 nnz_lower = (S_.nnz + S_.shape[0]) / 2.0
                 if force or lu.nnz_L <= P.switch_fill * nnz_lower:
                     mode = "direct"
                     factor = lu
+                    st.forced_switch_done = st.forced_switch_done or forced
+                    st.switched_by_drop = not force
         # 3. Newton direction
         st.theta = st.p / st.s
         sys = _build_system(st, st.theta, mode, P, factor)
@@ -644,9 +727,12 @@ def _iterate(st, P, tol_int, it, mode, psi_hist, hist, cg_total, direct_its, max
         st.y = st.y + ad * dy
         st.z = st.z + ad * dz
         mu_new = float(st.p @ st.s) / st.psi
-        # 5. pricing and support update
+        # 5. pricing and support update; heuristic pricing (Section 3.4):
+        # iterations it with it mod (heur_run + 1) < heur_run scan only J
+        heur = P.heur_radius > 0.0 and it % (P.heur_run + 1) < P.heur_run
         sel, rsel, nneg = _cscan.price(st.xs, st.xt, st.y / st.zeta, st.z / st.zeta,
-                                       st.idx, kcap, st.kind)
+                                       st.idx, kcap, st.kind,
+                                       st.heur_limit if heur else 0)
         keep = np.ones(st.psi, dtype=bool)
         if max(rel1, rel2) <= P.remove_gate:
             thr = P.remove_rel * np.minimum(st.a[st.rows], st.b[st.cols])
@@ -666,7 +752,7 @@ def _iterate(st, P, tol_int, it, mode, psi_hist, hist, cg_total, direct_its, max
                     removed += 1
         sm = math.sqrt(mu_new)
         k = sel.shape[0]
-        rec.update(added=int(k), removed=int((~keep).sum()), n_negative=nneg)
+        rec.update(added=int(k), removed=int((~keep).sum()), n_negative=nneg, heuristic=heur)
         _set_support(st, np.concatenate([st.idx[keep], sel]),
                      np.concatenate([st.p[keep], np.full(k, sm)]),
                      np.concatenate([st.s[keep], np.full(k, sm)]))
@@ -735,6 +821,8 @@ def _finalize(st, P, status, it, cg_total, direct_its, max_fill, hist, t0):
                         marginal_residual=float(marg), r_min=r_min, iterations=it,
                         cg_iterations=cg_total, direct_iterations=direct_its,
                         max_fill_pct=max_fill, history=hist,
+                        switches_back=st.switches_back,
+                        orderings_reused=st.symbolic.get("reused", 0),
                         seconds=time.perf_counter() - t0)
 
 

@@ -96,11 +96,15 @@ static int cmp_key(const void *a, const void *b)
  * sup     : the support, variable indices sorted ascending (psi entries).
  * out_idx, out_r : at least kmax entries.
  * n_neg   : number of strictly negative reduced costs outside the support.
+ * key_limit : > 0 restricts the scan to the heuristic subset of Section 3.4,
+ *           J = {(i, j) : cost key < key_limit} (the cost itself, the squared
+ *           norm for the 2-norm); <= 0 scans every variable.
  * returns the number of entries written (<= kmax), or -1 on allocation error.
  */
 int64_t orc_price(int64_t m, int64_t n, const int32_t *xs, const int32_t *xt,
                   const double *y, const double *z, const int64_t *sup, int64_t psi,
-                  int64_t kmax, int64_t *out_idx, double *out_r, int64_t *n_neg, int kind)
+                  int64_t kmax, int64_t *out_idx, double *out_r, int64_t *n_neg, int kind,
+                  int64_t key_limit)
 {
     key_t_ *h = NULL;
     int64_t hn = 0, neg = 0, sp = 0;
@@ -113,6 +117,7 @@ int64_t orc_price(int64_t m, int64_t n, const int32_t *xs, const int32_t *xt,
             int64_t idx = i + j * m;
             while (sp < psi && sup[sp] < idx) ++sp;
             if (sp < psi && sup[sp] == idx) continue;
+            if (key_limit > 0 && cost_key(xs, xt, i, j, kind) >= key_limit) continue;
             double c = cost_d(xs, xt, i, j, kind);
             double r = (c - y[i]) - z[j];
             if (!(r < 0.0)) continue;

@@ -22,7 +22,7 @@ from ._abi import (OTIP_OK, OTIP_EINVAL, OTIP_ENOMEM, OTIP_EHIP, OTIP_ENUMERIC, 
                    OTIP_COST_LINF, otip_params, otip_problem, otip_info)
 
 __all__ = ["otip_version", "otip_params_default", "Context", "OtipError", "SolveResult",
-           "otip_solve", "otip_solve_batch", "otip_price", "otip_rmin", "otip_kron_apply",
+           "otip_solve", "otip_solve_batch", "otip_price", "otip_price_subset", "otip_rmin", "otip_kron_apply",
            "otip_kron_apply_t", "otip_kron_apply_noalloc", "otip_schur", "otip_pcg", "PCGResult", "otip_state_save",
            "otip_state_load", "params", "otip_ws_param_count", "otip_ws_forward",
            "otip_ws_grad", "otip_ws_adam", "otip_ws_predict", "load_ws_weights"]
@@ -218,6 +218,30 @@ def otip_price(ctx: Context, xs, xt, y, z, bitmap, kmax: int, precision: int = O
                                   ctypes.byref(nneg)))
     c = int(cnt.value)
     return oi[:c], oj[:c], orr[:c], int(nneg.value)
+
+
+def otip_price_subset(ctx: Context, xs, xt, y, z, bitmap, kmax: int, key_limit: int,
+                      cost_kind: int = OTIP_COST_SQEUCLID):
+    """Heuristic pricing over J = {cost key < key_limit} (Section 3.4); returns
+    (i, j, r) device tensors, the count of negative reduced costs in J outside
+    the support, and |J|."""
+    torch = _torch()
+    XS, XT = _dev(xs, torch.int32, ctx.device), _dev(xt, torch.int32, ctx.device)
+    Y, Z = _dev(y, torch.float64, ctx.device), _dev(z, torch.float64, ctx.device)
+    BM = _dev(bitmap, torch.int32, ctx.device) if bitmap is not None else None
+    m, n = int(XS.shape[0]), int(XT.shape[0])
+    k = max(int(kmax), 1)
+    oi = torch.empty(k, dtype=torch.int32, device=Y.device)
+    oj = torch.empty(k, dtype=torch.int32, device=Y.device)
+    orr = torch.empty(k, dtype=torch.float64, device=Y.device)
+    cnt, nneg, size = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    ctx.check(ctx._lib.otip_price_subset(ctx.handle, m, n, _ptr(XS), _ptr(XT), _ptr(Y), _ptr(Z),
+                                         _ptr(BM) if BM is not None else None, int(kmax),
+                                         int(cost_kind), int(key_limit), _ptr(oi), _ptr(oj),
+                                         _ptr(orr), ctypes.byref(cnt), ctypes.byref(nneg),
+                                         ctypes.byref(size)))
+    c = int(cnt.value)
+    return oi[:c], oj[:c], orr[:c], int(nneg.value), int(size.value)
 
 
 def otip_rmin(ctx: Context, xs, xt, y, z, cost_kind: int = OTIP_COST_SQEUCLID):

@@ -35,6 +35,8 @@ class otip_params(ctypes.Structure):
         ("batch_workers", _c_i32),
         ("price_tile", _c_i32),
         ("ws_kappa", ctypes.c_double),
+        ("heur_radius", _c_f64), ("heur_run", _c_i32), ("switch_back_grow", _c_f64),
+        ("force_switch_back_at", _c_i32), ("schur_reuse", _c_i32),
     ]
 
 
@@ -56,6 +58,7 @@ class otip_info(ctypes.Structure):
         ("price_ms", _c_f64), ("price_elems", _c_f64), ("diag_launches", _c_i64),
         ("diag_ms", _c_f64), ("diag_flops", _c_f64), ("update_launches", _c_i64),
         ("update_ms", _c_f64), ("update_flops", _c_f64),
+        ("heuristic_scans", _c_i64), ("switches_back", _c_i64), ("patterns_kept", _c_i64),
     ]
 
     def as_dict(self):
@@ -80,6 +83,9 @@ SIGNATURES = {
     "otip_price": (ctypes.c_int, [_p, _c_i32, _c_i32, _p, _p, _p, _p, _p, _c_i64, _c_i32, _c_i32,
                                   _c_i32, _p, _p, _p, ctypes.POINTER(_c_i64),
                                   ctypes.POINTER(_c_i64)]),
+    "otip_price_subset": (ctypes.c_int, [_p, _c_i32, _c_i32, _p, _p, _p, _p, _p, _c_i64, _c_i32,
+                                         _c_i64, _p, _p, _p, ctypes.POINTER(_c_i64),
+                                         ctypes.POINTER(_c_i64), ctypes.POINTER(_c_i64)]),
     "otip_rmin": (ctypes.c_int, [_p, _c_i32, _c_i32, _p, _p, _p, _p, _c_i32,
                                  ctypes.POINTER(_c_f64), ctypes.POINTER(_c_i64)]),
     "otip_kron_apply": (ctypes.c_int, [_p, _c_i32, _c_i32, _p, _p, _p]),

@@ -62,13 +62,14 @@ int guarded(otip_ctx *ctx, F &&f) {
     }
 }
 
-// Checkpoint byte layout (host byte order): "OTIPCKP1", u32 version, i32 m,
-// n, u64 fingerprint, i32 it, mode, cg_its_last, solves_last, cg_failed,
-// warm_used, direct_its, i64 psi, psi_max, cg_total, f64 tol_int, max_fill,
+// Checkpoint byte layout (host byte order): "OTIPCKP1", u32 version (2), i32
+// m, n, u64 fingerprint, i32 it, mode, cg_its_last, solves_last, cg_failed,
+// warm_used, direct_its, forced_switch_done, forced_back_done,
+// switched_by_drop, switches_back, i64 psi, psi_max, cg_total, f64 tol_int, max_fill,
 // i64 hist_len, then i64 psi_hist[hist_len], u64 idx[psi], f64 p[psi],
 // s[psi], y[m], z[n].
 constexpr char kCkMagic[8] = {'O', 'T', 'I', 'P', 'C', 'K', 'P', '1'};
-constexpr uint32_t kCkVersion = 1;
+constexpr uint32_t kCkVersion = 2;
 
 template <class T>
 void put(std::vector<unsigned char> &o, const T *v, size_t count) {
@@ -88,7 +89,8 @@ std::vector<unsigned char> serialize(const otip::Checkpoint &c) {
     put1(o, c.n);
     put1(o, c.fingerprint);
     for (int32_t v : {c.it, c.mode, c.cg_its_last, c.solves_last, c.cg_failed, c.warm_used,
-                      c.direct_its})
+                      c.direct_its, c.forced_switch_done, c.forced_back_done, c.switched_by_drop,
+                      c.switches_back})
         put1(o, v);
     put1(o, c.psi);
     put1(o, c.psi_max);
@@ -135,7 +137,8 @@ std::unique_ptr<otip::Checkpoint> deserialize(const void *buf, size_t size) {
     c->n = r.get1<int32_t>();
     c->fingerprint = r.get1<uint64_t>();
     for (int32_t *v : {&c->it, &c->mode, &c->cg_its_last, &c->solves_last, &c->cg_failed,
-                       &c->warm_used, &c->direct_its})
+                       &c->warm_used, &c->direct_its, &c->forced_switch_done,
+                       &c->forced_back_done, &c->switched_by_drop, &c->switches_back})
         *v = r.get1<int32_t>();
     c->psi = r.get1<int64_t>();
     c->psi_max = r.get1<int64_t>();
@@ -212,6 +215,11 @@ void otip_params_default(otip_params *p) {
     p->batch_workers = 0;
     p->price_tile = 0;
     p->ws_kappa = 0.0;
+    p->heur_radius = 0.0;
+    p->heur_run = 3;
+    p->switch_back_grow = 0.0;
+    p->force_switch_back_at = -1;
+    p->schur_reuse = 1;
 }
 
 int otip_create(otip_ctx **ctx, int device, void *hip_stream) {
@@ -401,6 +409,40 @@ int otip_price(otip_ctx *ctx, int32_t m, int32_t n, const int32_t *xs, const int
         OTIP_HIP(hipStreamSynchronize(ctx->stream));
         if (out_count) *out_count = pr.count;
         if (out_nneg) *out_nneg = pr.nneg;
+    });
+}
+
+int otip_price_subset(otip_ctx *ctx, int32_t m, int32_t n, const int32_t *xs, const int32_t *xt,
+                      const double *y, const double *z, const uint32_t *support_bitmap,
+                      int64_t kmax, int32_t cost_kind, int64_t key_limit, int32_t *out_i,
+                      int32_t *out_j, double *out_r, int64_t *out_count, int64_t *out_nneg,
+                      int64_t *out_subset_size) {
+    return guarded(ctx, [&] {
+        OTIP_CHECK(m >= 1 && n >= 1 && xs && xt && y && z && kmax >= 0 && key_limit >= 1,
+                   OTIP_EINVAL, "otip_price_subset: bad arguments");
+        OTIP_CHECK(cost_kind >= OTIP_COST_SQEUCLID && cost_kind <= OTIP_COST_LINF, OTIP_EINVAL,
+                   "otip_price_subset: unknown cost kind");
+        OTIP_CHECK(kmax == 0 || (out_i && out_j && out_r), OTIP_EINVAL,
+                   "otip_price_subset: null outputs");
+        ctx->scan.tile = 0;
+        ctx->scan.kind = cost_kind;
+        const int64_t size = ctx->scan.set_subset(ctx->stream, m, n, xs, xt, key_limit);
+        otip::PriceResult pr{0, 0, 0};
+        if (size > 0) {
+            ctx->scan.use_subset = true;
+            try {
+                pr = ctx->scan.price(ctx->stream, m, n, xs, xt, y, z, support_bitmap, kmax, out_i,
+                                     out_j, out_r, nullptr);
+            } catch (...) {
+                ctx->scan.use_subset = false;
+                throw;
+            }
+            ctx->scan.use_subset = false;
+        }
+        OTIP_HIP(hipStreamSynchronize(ctx->stream));
+        if (out_count) *out_count = pr.count;
+        if (out_nneg) *out_nneg = pr.nneg;
+        if (out_subset_size) *out_subset_size = size;
     });
 }
 

@@ -32,6 +32,8 @@ struct Checkpoint {
     uint64_t fingerprint = 0;  // of m, n, the cost kind and the bytes of a, b, xs, xt
     int32_t it = 0, mode = 0, cg_its_last = 0, solves_last = 2, cg_failed = 0, warm_used = 0;
     int32_t direct_its = 0;
+    int32_t forced_switch_done = 0, forced_back_done = 0, switched_by_drop = 0,
+            switches_back = 0;
     int64_t psi = 0, psi_max = 0, cg_total = 0;
     double tol_int = 0.0, max_fill = 0.0;
     std::vector<int64_t> psi_hist;
@@ -66,7 +68,8 @@ class Solver {
     void max_steps(const Dir &d, double &ap, double &ad);
     void assemble();
     void residuals(double &rel1, double &rel2, double &mu, double &primal, double &r1n);
-    int64_t price(int64_t kmax, uint64_t *out_idx, double *out_r, int64_t *nneg);
+    int64_t price(int64_t kmax, uint64_t *out_idx, double *out_r, int64_t *nneg,
+                  bool heuristic = false);
     void update_support(const uint64_t *add_idx, int64_t nadd, double pin, const uint8_t *removed,
                         int64_t nrem);
     int64_t select_removals(uint8_t *removed);
@@ -127,6 +130,13 @@ class Solver {
 
     Mode mode = Mode::PCG;
     bool cg_failed = false;
+    bool heur_on = false;        // heuristic pricing subset built for this solve
+    int64_t heur_scans = 0;      // pricing calls on the subset
+    bool forced_switch_done = false, forced_back_done = false;
+    bool switched_by_drop = false;  // the last switch to Direct came from the psi-drop rule
+    int switches_back = 0;
+    bool pattern_kept = false;   // the last support update kept the Schur pattern
+    int64_t patterns_kept = 0;
     int cg_its_iter = 0, max_cg_solve = 0;
     int64_t cg_total = 0;
     int direct_its = 0, iterations = 0;

@@ -491,7 +491,8 @@ void Solver::residuals(double &rel1, double &rel2, double &mu, double &primal, d
 }
 
 // ------------------------------------------------------------------ pricing
-int64_t Solver::price(int64_t kmax, uint64_t *out_idx, double *out_r, int64_t *nneg) {
+int64_t Solver::price(int64_t kmax, uint64_t *out_idx, double *out_r, int64_t *nneg,
+                      bool heuristic) {
     double t0 = now();
     // pricing runs on the unscaled costs: duals divided by the power-of-two cost scale
     double *yu = yun.need(m), *zu = zun.need(n);
@@ -501,12 +502,14 @@ int64_t Solver::price(int64_t kmax, uint64_t *out_idx, double *out_r, int64_t *n
     foreach(st, n, [=] __device__(int64_t j) { zu[j] = zz[j] * iz; });
     PriceResult pr;
     t_price.begin_call();
+    scan.use_subset = heuristic && heur_on;
     if (P.precision == OTIP_MIXED)
         pr = scan.price_mixed(st, m, n, xs, xt, yu, zu, bitmap.get(), kmax, nullptr, nullptr,
                               out_r, out_idx);
     else
         pr = scan.price(st, m, n, xs, xt, yu, zu, bitmap.get(), kmax, nullptr, nullptr, out_r,
                         out_idx);
+    scan.use_subset = false;
     if (nneg) *nneg = pr.nneg;
     pricing_passes += pr.passes;
     OTIP_HIP(hipStreamSynchronize(st));
@@ -557,7 +560,16 @@ void Solver::update_support(const uint64_t *add_idx, int64_t nadd, double pin,
     OTIP_HIP(hipMemcpyAsync(idx.get(), kout, sizeof(uint64_t) * psi_new, hipMemcpyDeviceToDevice, st));
     OTIP_HIP(hipMemcpyAsync(p.get(), pout, sizeof(double) * psi_new, hipMemcpyDeviceToDevice, st));
     OTIP_HIP(hipMemcpyAsync(s.get(), sout, sizeof(double) * psi_new, hipMemcpyDeviceToDevice, st));
+    // a support that only lost entries keeps its Schur pattern (Section 4.2
+    // remark on updating the symbolic structure instead of rebuilding it)
+    const bool keep = P.schur_reuse && schur_valid && nadd == 0 && nrem > 0;
     rebuild_views();
+    if (keep) {
+        schur.keep_pattern(st, psi_, csr_pos.get(), sj.get());
+        schur_valid = true;
+    }
+    pattern_kept = keep;
+    patterns_kept += keep ? 1 : 0;
     psi_max = std::max(psi_max, psi_);
 }
 
@@ -785,6 +797,10 @@ void Solver::snapshot(int it, double tol_int, const std::vector<int64_t> &hist) 
     c.cg_failed = cg_failed ? 1 : 0;
     c.warm_used = warm_used ? 1 : 0;
     c.direct_its = direct_its;
+    c.forced_switch_done = forced_switch_done ? 1 : 0;
+    c.forced_back_done = forced_back_done ? 1 : 0;
+    c.switched_by_drop = switched_by_drop ? 1 : 0;
+    c.switches_back = switches_back;
     c.psi = psi_;
     c.psi_max = psi_max;
     c.cg_total = cg_total;
@@ -846,6 +862,10 @@ void Solver::resume_from(const Checkpoint &c) {
     solves_last = c.solves_last;
     warm_used = c.warm_used != 0;
     direct_its = c.direct_its;
+    forced_switch_done = c.forced_switch_done != 0;
+    forced_back_done = c.forced_back_done != 0;
+    switched_by_drop = c.switched_by_drop != 0;
+    switches_back = c.switches_back;
     cg_total = c.cg_total;
     max_fill = c.max_fill;
     OTIP_HIP(hipStreamSynchronize(st));
@@ -868,6 +888,12 @@ void Solver::reset_state() {
     max_fill = 0.0;
     cg_its_last = 0;
     solves_last = 2;
+    heur_on = false;
+    heur_scans = 0;
+    forced_switch_done = forced_back_done = switched_by_drop = false;
+    switches_back = 0;
+    pattern_kept = false;
+    patterns_kept = 0;
     t_pricing = t_newton = t_direct = t_update = t_setup = t_final = 0.0;
     t_spmv.reset();
     t_price.reset();
@@ -995,6 +1021,16 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
                       &q);
         fnorm = std::sqrt(q);
     }
+    // heuristic pricing subset (Section 3.4): pairs closer than heur_radius
+    // times the largest distance, as an integer bound on the cost key
+    if (P.heur_radius > 0.0 && P.heur_run >= 1) {
+        const double lim = (kind == OTIP_COST_L1 || kind == OTIP_COST_LINF)
+                               ? std::ceil(P.heur_radius * (double)cmax)
+                               : std::ceil(P.heur_radius * P.heur_radius * (double)cmax);
+        OTIP_CHECK(std::isfinite(lim) && lim < 9.0e18, OTIP_EINVAL, "heur_radius too large");
+        const int64_t L = std::max<int64_t>(1, (int64_t)lim);
+        heur_on = scan.set_subset(st, m, n, xs, xt, L) > 0;
+    }
     y.need(m);
     z.need(n);
     M.need(m);
@@ -1106,8 +1142,32 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
             log("otip: it %d certification re-entered %lld columns\n", it, (long long)nbig);
             continue;
         }
+        // ---- switch back to CG (remark of Section 4.3: the support grows again
+        // after a switch made by the support-drop rule), or a forced one
+        bool just_back = false;
+        if (mode == Mode::Direct && P.linear_solver == OTIP_LS_AUTO) {
+            const int wdw = P.switch_window;
+            const char *why = nullptr;
+            if (P.force_switch_back_at >= 0 && it >= P.force_switch_back_at && !forced_back_done) {
+                forced_back_done = true;
+                why = "forced";
+            } else if (P.switch_back_grow > 0.0 && switched_by_drop &&
+                       (int)psi_hist.size() > wdw) {
+                const double old = (double)psi_hist[psi_hist.size() - 1 - wdw];
+                if (((double)psi_ - old) / old >= P.switch_back_grow) why = "support growing";
+            }
+            if (why) {
+                mode = Mode::PCG;
+                switched_by_drop = false;
+                cg_failed = false;
+                ++switches_back;
+                just_back = true;
+                log("otip: it %d switch back to CG (%s)\n", it, why);
+            }
+        }
         // ---- switch test (Section 4.3)
-        if (mode == Mode::PCG && P.linear_solver == OTIP_LS_AUTO && n <= P.dense_max_n) {
+        if (mode == Mode::PCG && !just_back && P.linear_solver == OTIP_LS_AUTO &&
+            n <= P.dense_max_n) {
             const int wdw = P.switch_window;
             // fill "allows" a factorisation once it is cheaper than the CG it
             // replaces.  A fixed cost model (not wall time, so the switch point
@@ -1129,8 +1189,9 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
                                    solves_last * (8.0 * (double)n * n / 2e12 +
                                                   (split ? 6 : 2) * 6e-6);
             const bool cheaper = P.switch_cost && it >= 1 && t_dense < t_cg;
-            const bool force = (P.force_switch_at >= 0 && it >= P.force_switch_at) || cg_failed ||
-                               cheaper;
+            const bool forced =
+                P.force_switch_at >= 0 && it >= P.force_switch_at && !forced_switch_done;
+            const bool force = forced || cg_failed || cheaper;
             bool drop = false;
             if ((int)psi_hist.size() > wdw) {
                 const double old = (double)psi_hist[psi_hist.size() - 1 - wdw];
@@ -1138,6 +1199,8 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
             }
             if (force || drop) {
                 mode = Mode::Direct;
+                if (forced) forced_switch_done = true;
+                switched_by_drop = !force && drop;
                 log("otip: it %d switch to the direct solver (%s)\n", it,
                     cheaper ? "factorisation cheaper than CG"
                             : (force ? "forced/CG failure" : "support shrinking"));
@@ -1271,7 +1334,11 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
         t_newton += now() - tn;
         // ---- pricing and support update
         int64_t nneg = 0;
-        const int64_t k = price(kcap, sel_idx.get(), sel_r.get(), &nneg);
+        // heuristic pricing (Section 3.4): heur_run iterations on the subset J,
+        // then one full scan
+        const bool heur = heur_on && it % (P.heur_run + 1) < P.heur_run;
+        const int64_t k = price(kcap, sel_idx.get(), sel_r.get(), &nneg, heur);
+        if (heur) ++heur_scans;
         trace_val("ap", it, ap);
         trace_val("ad", it, ad);
         trace_val("ncorr", it, ncorr);
@@ -1325,6 +1392,9 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
     res.info.seconds_setup = t_setup;
     res.info.seconds_final = t_final;
     res.info.pricing_scans = scan.scans;
+    res.info.heuristic_scans = heur_scans;
+    res.info.switches_back = switches_back;
+    res.info.patterns_kept = patterns_kept;
     res.info.spmv_launches = t_spmv.launches;
     res.info.spmv_ms = t_spmv.ms;
     res.info.spmv_bytes = t_spmv.work;

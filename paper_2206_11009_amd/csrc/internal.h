@@ -67,6 +67,13 @@ class Scanner {
     int64_t warm_support(hipStream_t st, int m, int n, const int32_t *xs, const int32_t *xt,
                          const double *y0, const double *z0, double kappa,
                          DBuf<uint64_t> &out, DBuf<double> &yw, DBuf<double> &zw);
+    // heuristic subset J = {(i, j) : integer cost key < key_limit} of
+    // Section 3.4, kept as per-source target lists; returns |J|.  While
+    // use_subset is set, price() scans J only (in FP64, also for price_mixed).
+    int64_t set_subset(hipStream_t st, int m, int n, const int32_t *xs, const int32_t *xt,
+                       int64_t key_limit);
+    bool use_subset = false;
+    int64_t subset_size() const { return subset_nnz_; }
 
   private:
     void prepare(hipStream_t st, int m, int n, const int32_t *xt, const double *z);
@@ -79,6 +86,10 @@ class Scanner {
     DBuf<char> tmp_;
     DBuf<float> f32a_;
     DBuf<int> flag_;
+    DBuf<int64_t> sptr_, scnt_;
+    DBuf<int32_t> scol_;
+    int subset_m_ = -1;
+    int64_t subset_nnz_ = 0;
 };
 
 // ---------------------------------------------------------- fixed-order reductions
@@ -121,6 +132,10 @@ class SchurSolver {
     void symbolic(hipStream_t st, int m, int n, int64_t psi, const int32_t *col_ptr,
                   const int32_t *si, const int32_t *row_ptr, const int32_t *csr_pos,
                   const int32_t *sj);
+    // keep the pattern of the last symbolic() for a support that only lost
+    // entries (it is a superset of the new pattern; the extra entries get the
+    // value 0): repacks the per-source target lists of the new support
+    void keep_pattern(hipStream_t st, int64_t psi, const int32_t *csr_pos, const int32_t *sj);
     // values: S_jk = -sum_{i in col j and col k} theta_ij theta_ik / M_i (j != k),
     // S_jj = -sum_{k != j} S_jk; also the Jacobi inverse diagonal
     void numeric(hipStream_t st, int m, int n, const int32_t *col_ptr, const int32_t *si,

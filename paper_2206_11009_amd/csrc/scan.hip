@@ -246,6 +246,62 @@ __global__ __launch_bounds__(kScanBlock) void price_pass(PriceArgs a) {
     }
 }
 
+// Pricing pass over the heuristic subset J of Section 3.4, stored as
+// per-source target lists (jptr: m + 1 offsets, jcol: targets in increasing
+// j).  One wavefront per source at a time: the source's data is uniform
+// across the wave, each lane takes one target of the list and gathers its
+// table entry; the reduced cost is formed exactly as by price_pass, so the
+// values (and the selection) are those of the full scan restricted to J.
+// Lanes past the end of a list carry r = +inf so that every lane of the wave
+// takes part in the ballots.
+template <int MODE, int K>
+__global__ __launch_bounds__(kScanBlock) void price_list_pass(PriceArgs a,
+                                                              const int64_t *__restrict__ jptr,
+                                                              const int32_t *__restrict__ jcol) {
+    __shared__ unsigned int lh[MODE == 0 ? kHistBins : 1];
+    __shared__ uint64_t sbuf[MODE == 1 ? (kScanBlock / 64) * kStage * 2 : 1];
+    WaveStage<2> stg{sbuf + (MODE == 1 ? (threadIdx.x >> 6) * kStage * 2 : 0), 0, a.count,
+                     a.out_key, a.out_idx, a.cap};
+    if (MODE == 0) {
+        for (int t = threadIdx.x; t < kHistBins; t += kScanBlock) lh[t] = 0u;
+        __syncthreads();
+    }
+    const int lane = threadIdx.x & 63;
+    const int waves = gridDim.x * (kScanBlock / 64);
+    for (int i = blockIdx.x * (kScanBlock / 64) + (threadIdx.x >> 6); i < a.m; i += waves) {
+        const RowData rd = load_row(i, a.m, a.xs, a.y);
+        const int64_t e0 = jptr[i], e1 = jptr[i + 1];
+        for (int64_t base = e0; base < e1; base += 64) {
+            const int64_t e = base + lane;
+            int j = 0;
+            double r = INFINITY;
+            if (e < e1) {
+                j = jcol[e];
+                const JEntry t = a.jt[j];
+                r = (cost_of<K>(rd, t) - rd.y) - t.z;
+            }
+            price_one<MODE>(a, i, j, r, lh, stg);
+        }
+    }
+    if (MODE == 1) stg.flush();
+    if (MODE == 0) {
+        __syncthreads();
+        for (int t = threadIdx.x; t < kHistBins; t += kScanBlock)
+            if (lh[t]) atomicAdd(&a.hist[t], (unsigned long long)lh[t]);
+    }
+}
+
+// Heuristic subset J = {(i, j) : cost key < L} (Section 3.4) as per-source
+// target lists: one wavefront per source counts (pass 0) or writes, in
+// increasing j (pass 1), the targets whose integer cost key is below L.
+template <int PASS>
+__global__ __launch_bounds__(kScanBlock) void subset_lists(int m, int n, int kind,
+                                                           const int32_t *__restrict__ xs,
+                                                           const int32_t *__restrict__ xt,
+                                                           int64_t L, int64_t *cnt,
+                                                           const int64_t *__restrict__ off,
+                                                           int32_t *__restrict__ col);
+
 // Decode the selected (key, idx) into (i, j, r).
 __global__ void decode_selection(int64_t k, int m, const uint64_t *__restrict__ key,
                                  const uint64_t *__restrict__ idx, int32_t *oi, int32_t *oj,
@@ -290,6 +346,34 @@ void Scanner::prepare(hipStream_t st, int m, int n, const int32_t *xt, const dou
     OTIP_HIP(hipGetLastError());
 }
 
+int64_t Scanner::set_subset(hipStream_t st, int m, int n, const int32_t *xs, const int32_t *xt,
+                            int64_t key_limit) {
+    OTIP_CHECK(m >= 1 && n >= 1 && key_limit >= 1, OTIP_EINVAL, "subset: bad arguments");
+    scnt_.need((size_t)m);
+    sptr_.need((size_t)m + 1);
+    const unsigned blocks = grid_for(m, kScanBlock / 64);
+    hipLaunchKernelGGL(subset_lists<0>, dim3(blocks), dim3(kScanBlock), 0, st, m, n, kind, xs, xt,
+                       key_limit, scnt_.get(), (const int64_t *)nullptr, (int32_t *)nullptr);
+    OTIP_HIP(hipGetLastError());
+    exclusive_scan_i64(st, scnt_.get(), sptr_.get(), m, tmp_);
+    int64_t last_off = 0, last_cnt = 0;
+    OTIP_HIP(hipMemcpyAsync(&last_off, sptr_.get() + (m - 1), sizeof(int64_t),
+                            hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipMemcpyAsync(&last_cnt, scnt_.get() + (m - 1), sizeof(int64_t),
+                            hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipStreamSynchronize(st));
+    const int64_t total = last_off + last_cnt;
+    OTIP_HIP(hipMemcpyAsync(sptr_.get() + m, &total, sizeof(int64_t), hipMemcpyHostToDevice, st));
+    scol_.need((size_t)std::max<int64_t>(total, 1));
+    hipLaunchKernelGGL(subset_lists<1>, dim3(blocks), dim3(kScanBlock), 0, st, m, n, kind, xs, xt,
+                       key_limit, (int64_t *)nullptr, (const int64_t *)sptr_.get(), scol_.get());
+    OTIP_HIP(hipGetLastError());
+    OTIP_HIP(hipStreamSynchronize(st));  // the host value `total` above is on the stack
+    subset_m_ = m;
+    subset_nnz_ = total;
+    return total;
+}
+
 PriceResult Scanner::price(hipStream_t st, int m, int n, const int32_t *xs, const int32_t *xt,
                            const double *y, const double *z, const uint32_t *bitmap,
                            int64_t kmax, int32_t *oi, int32_t *oj, double *orr,
@@ -297,8 +381,30 @@ PriceResult Scanner::price(hipStream_t st, int m, int n, const int32_t *xs, cons
     PriceResult res{0, 0, 0};
     if (m <= 0 || n <= 0) return res;
     prepare(st, m, n, xt, z);
+    const bool sub = use_subset;
+    OTIP_CHECK(!sub || subset_m_ == m, OTIP_EINVAL, "pricing: no subset built for this problem");
     const int tj = pick_tj(m, n, tile);
     dim3 grid(grid_for(m, kScanBlock), grid_for(n, tj));
+    const dim3 lgrid(grid_for(m, kScanBlock / 64));
+    const double units = sub ? (double)subset_nnz_ : (double)m * (double)n;
+    // one pass of the given mode over all variables or over the subset
+    auto launch = [&](int mode, const PriceArgs &pa, hipEvent_t e0_, hipEvent_t e1_) {
+        if (sub) {
+            auto kfn = mode == 0 ? by_kind(kind, price_list_pass<0, 0>, price_list_pass<0, 1>,
+                                           price_list_pass<0, 2>, price_list_pass<0, 3>)
+                                 : by_kind(kind, price_list_pass<1, 0>, price_list_pass<1, 1>,
+                                           price_list_pass<1, 2>, price_list_pass<1, 3>);
+            hipExtLaunchKernelGGL(kfn, lgrid, dim3(kScanBlock), 0, st, e0_, e1_, 0, pa,
+                                  (const int64_t *)sptr_.get(), (const int32_t *)scol_.get());
+        } else {
+            auto kfn = mode == 0 ? by_kind(kind, price_pass<0, 0>, price_pass<0, 1>,
+                                           price_pass<0, 2>, price_pass<0, 3>)
+                                 : by_kind(kind, price_pass<1, 0>, price_pass<1, 1>,
+                                           price_pass<1, 2>, price_pass<1, 3>);
+            hipExtLaunchKernelGGL(kfn, grid, dim3(kScanBlock), 0, st, e0_, e1_, 0, pa);
+        }
+        OTIP_HIP(hipGetLastError());
+    };
     hist_.need(kHistBins);
     cnt_.need(1);
     PriceArgs a{};
@@ -319,12 +425,9 @@ PriceResult Scanner::price(hipStream_t st, int m, int n, const int32_t *xs, cons
         a.rcut = (shift + 12 >= 64) ? INFINITY
                                     : rcut_of_key(((prefix + 1) << (shift + 12)) - 1);
         hipEvent_t e0_, e1_;
-        if (timer) timer->arm((double)m * (double)n, &e0_, &e1_);
+        if (timer) timer->arm(units, &e0_, &e1_);
         else e0_ = e1_ = nullptr;
-        hipExtLaunchKernelGGL(by_kind(kind, price_pass<0, 0>, price_pass<0, 1>, price_pass<0, 2>,
-                                      price_pass<0, 3>),
-                              grid, dim3(kScanBlock), 0, st, e0_, e1_, 0, a);
-        OTIP_HIP(hipGetLastError());
+        launch(0, a, e0_, e1_);
         OTIP_HIP(hipMemcpyAsync(h.data(), hist_.get(), kHistBins * sizeof(unsigned long long),
                                 hipMemcpyDeviceToHost, st));
         OTIP_HIP(hipStreamSynchronize(st));
@@ -389,12 +492,9 @@ PriceResult Scanner::price(hipStream_t st, int m, int n, const int32_t *xs, cons
     a.out_idx = ci_.get();
     a.cap = cap;
     hipEvent_t e0_, e1_;
-    if (timer) timer->arm((double)m * (double)n, &e0_, &e1_);
+    if (timer) timer->arm(units, &e0_, &e1_);
     else e0_ = e1_ = nullptr;
-    hipExtLaunchKernelGGL(by_kind(kind, price_pass<1, 0>, price_pass<1, 1>, price_pass<1, 2>,
-                                  price_pass<1, 3>),
-                          grid, dim3(kScanBlock), 0, st, e0_, e1_, 0, a);
-    OTIP_HIP(hipGetLastError());
+    launch(1, a, e0_, e1_);
     unsigned long long emitted = 0;
     OTIP_HIP(hipMemcpyAsync(&emitted, cnt_.get(), sizeof(emitted), hipMemcpyDeviceToHost, st));
     OTIP_HIP(hipStreamSynchronize(st));
@@ -512,6 +612,33 @@ __device__ __forceinline__ int64_t int_cost(const int32_t *xs, const int32_t *xt
     if (kind == OTIP_COST_L1) return (d0 < 0 ? -d0 : d0) + (d1 < 0 ? -d1 : d1);
     if (kind == OTIP_COST_LINF) return max(d0 < 0 ? -d0 : d0, d1 < 0 ? -d1 : d1);
     return d0 * d0 + d1 * d1;
+}
+
+template <int PASS>
+__global__ __launch_bounds__(kScanBlock) void subset_lists(int m, int n, int kind,
+                                                           const int32_t *__restrict__ xs,
+                                                           const int32_t *__restrict__ xt,
+                                                           int64_t L, int64_t *cnt,
+                                                           const int64_t *__restrict__ off,
+                                                           int32_t *__restrict__ col) {
+    const int lane = threadIdx.x & 63;
+    const int waves = gridDim.x * (kScanBlock / 64);
+    for (int i = blockIdx.x * (kScanBlock / 64) + (threadIdx.x >> 6); i < m; i += waves) {
+        int64_t pos = PASS == 1 ? off[i] : 0;
+        int c = 0;
+        for (int j0 = 0; j0 < n; j0 += 64) {
+            const int j = j0 + lane;
+            const bool take = j < n && int_cost(xs, xt, i, j, kind) < L;
+            const uint64_t mask = __ballot(take);
+            if (PASS == 0) {
+                c += __popcll(mask);
+            } else {
+                if (take) col[pos + __popcll(mask & ((1ull << lane) - 1ull))] = j;
+                pos += __popcll(mask);
+            }
+        }
+        if (PASS == 0 && lane == 0) cnt[i] = c;
+    }
 }
 
 // histogram of (c - lo) >> shift for lo <= c <= hi; count of c < lo
@@ -966,6 +1093,9 @@ PriceResult Scanner::price_mixed(hipStream_t st, int m, int n, const int32_t *xs
                                  const int32_t *xt, const double *y, const double *z,
                                  const uint32_t *bitmap, int64_t kmax, int32_t *oi, int32_t *oj,
                                  double *orr, uint64_t *oidx) {
+    // the heuristic subset is scanned in FP64 (a small fraction of m n)
+    if (use_subset)
+        return price(st, m, n, xs, xt, y, z, bitmap, kmax, oi, oj, orr, oidx);
     PriceResult res{0, 0, 0};
     if (m <= 0 || n <= 0) return res;
     // the FP32 scan is written for the squared cost; the norm costs take the

@@ -195,6 +195,15 @@ void SchurSolver::symbolic(hipStream_t st, int m, int n, int64_t psi, const int3
     OTIP_HIP(hipGetLastError());
 }
 
+void SchurSolver::keep_pattern(hipStream_t st, int64_t psi, const int32_t *csr_pos,
+                               const int32_t *sj) {
+    OTIP_CHECK(psi >= 1 && psi <= psi_, OTIP_EINVAL, "Schur pattern reuse: support grew");
+    hipLaunchKernelGGL(pack_rows, dim3(std::min<unsigned>(4096, grid_for(psi, 256))), dim3(256), 0,
+                       st, psi, csr_pos, sj, nullptr, rk_.get(), nullptr);
+    OTIP_HIP(hipGetLastError());
+    psi_ = psi;
+}
+
 // ---------------------------------------------------------------- numeric
 // Off-diagonal entries by intersecting the (i-sorted) source lists of targets j
 // and k.  The product theta_ij * theta_ik is commutative, so S is exactly

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_version_and_defaults_without_gpu():
     import paper_2206_11009_amd as otip
-    assert otip.otip_version() == 3
+    assert otip.otip_version() == 4
     p = otip.otip_params_default()
     # the paper's stated parameters (Section 5.2, Section 3.3, Section 4.3)
     assert p.tol == 1e-6 and p.cg_tol_pred == 1e-6 and p.cg_tol_corr == 1e-3
