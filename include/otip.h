@@ -96,7 +96,9 @@ typedef struct otip_params {
     double cg_floor;
     int32_t linear_solver;   /* otip_linear_solver */
     int32_t precision;       /* otip_precision */
-    int32_t dense_max_n;     /* largest Schur order factorised by the dense LDL^T */
+    int32_t dense_max_n;     /* largest Schur order factorised by the dense LDL^T (65536);
+                                the factorisation also needs about 26 n^2 bytes of free
+                                device memory (112 GB at 65536), else CG continues */
     int32_t force_switch_at; /* >= 0: switch to the direct solver at this iteration */
     int32_t enter_cap;       /* max entering columns per iteration; <= 0 means m */
     int32_t scale;           /* power-of-two scaling of masses and costs (1 = on) */
@@ -380,6 +382,25 @@ int otip_schur(otip_ctx *ctx, int32_t m, int32_t n, int64_t psi, const int64_t *
 int otip_pcg(otip_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr, const int32_t *colidx,
              const double *vals, const double *b, double *x, double rtol, int32_t maxit,
              int32_t precision, int32_t *iterations, double *res_norm, double *spmv_stats);
+
+/*
+ * Direct solve of the Newton step after the switch (Section 4.2): the
+ * library's FP64 L D L^T of a caller's symmetric n x n CSR matrix with the
+ * infinite-pivot rule (a pivot d_k <= pivot_tol * A_kk or d_k <= 0 becomes
+ * +inf: that unknown is 0 in the solution, grounding one node of each
+ * connected component of a singular Schur complement), then x = (L D L^T)^+ b
+ * through the explicit inverse of L as inside otip_solve.
+ *   rowptr (n+1), colidx (nnz, in [0, n), both triangles), vals, b (n):
+ *   DEVICE, read only.  x (n): DEVICE, output.  flags: bit 0 solves by
+ *   substitution on L and L^T instead of the explicit inverse (the path taken
+ *   when the inverse is not finite).  out_ninf (infinite pivots) and
+ *   out_nnz_L (nonzeros of L counted as written, plus n): HOST, optional.
+ * Memory: about 3.25 * 8 n^2 bytes of device scratch for the call.
+ * Errors: OTIP_EINVAL, OTIP_ENOMEM, OTIP_EHIP.
+ */
+int otip_ldl_solve(otip_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr,
+                   const int32_t *colidx, const double *vals, double pivot_tol, int32_t flags,
+                   const double *b, double *x, int32_t *out_ninf, int64_t *out_nnz_L);
 
 /*
  * Checkpoint and resume (the paper has none; these serve long solves and the

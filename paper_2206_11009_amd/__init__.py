@@ -23,7 +23,7 @@ from ._abi import (OTIP_OK, OTIP_EINVAL, OTIP_ENOMEM, OTIP_EHIP, OTIP_ENUMERIC, 
 
 __all__ = ["otip_version", "otip_params_default", "Context", "OtipError", "SolveResult",
            "otip_solve", "otip_solve_batch", "otip_price", "otip_price_subset", "otip_rmin", "otip_kron_apply",
-           "otip_kron_apply_t", "otip_kron_apply_noalloc", "otip_schur", "otip_pcg", "PCGResult", "otip_state_save",
+           "otip_kron_apply_t", "otip_kron_apply_noalloc", "otip_schur", "otip_ldl_solve", "otip_pcg", "PCGResult", "otip_state_save",
            "otip_state_load", "params", "otip_ws_param_count", "otip_ws_forward",
            "otip_ws_grad", "otip_ws_adam", "otip_ws_predict", "load_ws_weights"]
 
@@ -294,6 +294,24 @@ def otip_schur(ctx: Context, m: int, n: int, idx, theta):
                                   ctypes.byref(nnz), _ptr(rp), _ptr(ci), _ptr(va), _ptr(M),
                                   _ptr(N)))
     return rp, ci[:nnz.value], va[:nnz.value], M, N
+
+
+def otip_ldl_solve(ctx: Context, rowptr, colidx, vals, b, pivot_tol: float = 1e-12,
+                   substitution: bool = False):
+    """Dense FP64 L D L^T with the infinite-pivot rule of a CSR matrix, then one
+    solve; returns (x as a device tensor, infinite pivots, nnz(L))."""
+    torch = _torch()
+    RP = _dev(rowptr, torch.int32, ctx.device)
+    CI = _dev(colidx, torch.int32, ctx.device)
+    VA = _dev(vals, torch.float64, ctx.device)
+    B = _dev(b, torch.float64, ctx.device)
+    n = int(RP.shape[0]) - 1
+    x = torch.empty(n, dtype=torch.float64, device=B.device)
+    ninf, nnzl = ctypes.c_int32(), ctypes.c_int64()
+    ctx.check(ctx._lib.otip_ldl_solve(ctx.handle, n, int(CI.shape[0]), _ptr(RP), _ptr(CI),
+                                      _ptr(VA), float(pivot_tol), 1 if substitution else 0,
+                                      _ptr(B), _ptr(x), ctypes.byref(ninf), ctypes.byref(nnzl)))
+    return x, int(ninf.value), int(nnzl.value)
 
 
 def otip_state_save(ctx: Context) -> bytes:

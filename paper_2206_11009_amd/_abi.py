@@ -95,6 +95,8 @@ SIGNATURES = {
                                   _p, _p, _p, _p, _p]),
     "otip_pcg": (ctypes.c_int, [_p, _c_i32, _c_i64, _p, _p, _p, _p, _p, _c_f64, _c_i32, _c_i32,
                                 ctypes.POINTER(_c_i32), ctypes.POINTER(_c_f64), _p]),
+    "otip_ldl_solve": (ctypes.c_int, [_p, _c_i32, _c_i64, _p, _p, _p, _c_f64, _c_i32, _p, _p,
+                                      ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i64)]),
     "otip_state_save": (ctypes.c_int, [_p, _p, _c_i64, ctypes.POINTER(_c_i64)]),
     "otip_state_load": (ctypes.c_int, [_p, _p, _c_i64]),
     "otip_ws_param_count": (_c_i64, []),

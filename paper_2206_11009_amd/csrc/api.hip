@@ -205,7 +205,7 @@ void otip_params_default(otip_params *p) {
     p->cg_floor = 1e-9;
     p->linear_solver = OTIP_LS_AUTO;
     p->precision = OTIP_FP64;
-    p->dense_max_n = 16384;
+    p->dense_max_n = 65536;
     p->force_switch_at = -1;
     p->enter_cap = 0;
     p->scale = 1;
@@ -531,6 +531,25 @@ int otip_pcg(otip_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr, const
     if (rc != OTIP_OK) return rc;
     if (cs.converged) return OTIP_OK;
     return cs.iterations >= maxit ? OTIP_EMAXITER : OTIP_ENUMERIC;
+}
+
+int otip_ldl_solve(otip_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr,
+                   const int32_t *colidx, const double *vals, double pivot_tol, int32_t flags,
+                   const double *b, double *x, int32_t *out_ninf, int64_t *out_nnz_L) {
+    return guarded(ctx, [&] {
+        OTIP_CHECK(n >= 1 && nnz >= 1 && nnz <= 0x7fffffff && rowptr && colidx && vals && b && x &&
+                       pivot_tol >= 0.0 && (flags & ~1) == 0,
+                   OTIP_EINVAL, "otip_ldl_solve: bad arguments");
+        otip::SchurSolver s;
+        s.load_csr(ctx->stream, n, nnz, rowptr, colidx, vals);
+        otip::DenseLDL ldl;
+        ldl.force_substitution = (flags & 1) != 0;
+        const int ninf = ldl.factor(ctx->stream, s.S, pivot_tol);
+        ldl.solve(ctx->stream, b, x);
+        OTIP_HIP(hipStreamSynchronize(ctx->stream));
+        if (out_ninf) *out_ninf = ninf;
+        if (out_nnz_L) *out_nnz_L = ldl.nnz_L();
+    });
 }
 
 int otip_state_save(otip_ctx *ctx, void *buf, int64_t cap, int64_t *size) {

@@ -699,7 +699,7 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
     if (tdiag) tdiag->collect();
     if (tupd) tupd->collect();
     nnzL_ = (int64_t)hc + n;
-    inverse_ok_ = hbad == 0;
+    inverse_ok_ = hbad == 0 && !force_substitution;
     if (!inverse_ok_)  // U = L^T for the backward substitution
         hipLaunchKernelGGL(transpose_lower, dim3(tl, tl), dim3(256), 0, st, n, A, XT_.get(),
                            (int *)nullptr, (const double *)nullptr, n);

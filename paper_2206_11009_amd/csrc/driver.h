@@ -74,6 +74,9 @@ class Solver {
                         int64_t nrem);
     int64_t select_removals(uint8_t *removed);
     void starting_point();
+    // the dense direct solver is allowed (dense_max_n) and its buffers fit in
+    // the device memory still free
+    bool direct_available();
     void finalize(Result &res);
     void reset_state();
     void snapshot(int it, double tol_int, const std::vector<int64_t> &hist);

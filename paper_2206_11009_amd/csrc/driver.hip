@@ -554,7 +554,12 @@ void Solver::update_support(const uint64_t *add_idx, int64_t nadd, double pin,
     }
     uint64_t *kout = tmp_u64b.need(tot);
     double *pout = tmp_f64c.need(tot), *sout = tmp_f64d.need(tot);
-    sort_pairs_u64_f64x2(st, kin, pin_, sin_, kout, pout, sout, tot, 64, tmp, tmp_i32a, tmp_i32b);
+    // variable indices are below m n; removed entries carry ~0, whose low
+    // `bits` bits (all ones) still order after every index
+    int bits = 2;
+    while (bits < 64 && (((uint64_t)1 << (bits - 1)) < (uint64_t)m * (uint64_t)n)) ++bits;
+    sort_pairs_u64_f64x2(st, kin, pin_, sin_, kout, pout, sout, tot, bits, tmp, tmp_i32a,
+                         tmp_i32b);
     psi_ = psi_new;
     if ((size_t)psi_new > idx.cap) alloc_support(psi_new * 2);
     OTIP_HIP(hipMemcpyAsync(idx.get(), kout, sizeof(uint64_t) * psi_new, hipMemcpyDeviceToDevice, st));
@@ -901,6 +906,7 @@ void Solver::reset_state() {
     t_upd.reset();
     ldl.restart_sampling();
     scan.scans = 0;
+    scan.reset_guess();
     warm_used = false;
 }
 
@@ -1085,7 +1091,8 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
     t_setup += now() - ts;
 
     if (mode == Mode::Direct)
-        OTIP_CHECK(n <= P.dense_max_n, OTIP_EUNSUPPORTED, "direct solver: n exceeds dense_max_n");
+        OTIP_CHECK(direct_available(), OTIP_EUNSUPPORTED,
+                   "direct solver: n exceeds dense_max_n or its buffers do not fit");
     std::vector<int64_t> psi_hist;
     if (resume) psi_hist = resume->psi_hist;
     const int64_t kcap = P.enter_cap > 0 ? P.enter_cap : m;
@@ -1167,7 +1174,7 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
         }
         // ---- switch test (Section 4.3)
         if (mode == Mode::PCG && !just_back && P.linear_solver == OTIP_LS_AUTO &&
-            n <= P.dense_max_n) {
+            direct_available()) {
             const int wdw = P.switch_window;
             // fill "allows" a factorisation once it is cheaper than the CG it
             // replaces.  A fixed cost model (not wall time, so the switch point
@@ -1410,6 +1417,16 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
     return status;
 }
 
+bool Solver::direct_available() {
+    if (n > P.dense_max_n) return false;
+    const size_t need = DenseLDL::bytes_for(n), held = ldl.held_bytes();
+    if (need <= held) return true;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return false;
+    // keep a margin for the Schur matrix and the support's arrays
+    return need - held + ((size_t)1 << 30) <= free_b;
+}
+
 // Mehrotra's starting-point heuristic on the restricted LP (Theta = I); the
 // paper leaves the starting point open.
 void Solver::starting_point() {
@@ -1420,7 +1437,8 @@ void Solver::starting_point() {
         ss[k] = 1.0;
     });
     assemble();
-    const bool direct = n <= P.dense_max_n;
+    // with Theta = I the system is well conditioned: CG serves large orders
+    const bool direct = n <= kDenseStartMaxN && direct_available();
     if (direct) ldl.factor(st, schur.S, P.pivot_tol);
     auto normal_solve = [&](const double *b1, const double *b2, double *dy, double *dz) {
         segsum(st, n, FRhs{col_ptr.get(), si.get(), theta.get(), b1, invM.get(), b2, rhs.get()});
@@ -1511,7 +1529,7 @@ void Solver::finalize(Result &res) {
                       v);
         if (v[0] / v[1] <= P.polish_tol) break;
         // Theta of the interior iterate, assembled and factorised once
-        const bool direct = n <= P.dense_max_n;
+        const bool direct = direct_available();
         if (!assembled) {
             assemble();
             if (direct) ldl.factor(st, schur.S, P.pivot_tol);

@@ -74,6 +74,11 @@ class Scanner {
                        int64_t key_limit);
     bool use_subset = false;
     int64_t subset_size() const { return subset_nnz_; }
+    // forget the cutoff guessed from the previous pricing call (a new problem)
+    void reset_guess() {
+        guess_key_ = 0;
+        guess_f_ = 0.5;
+    }
 
   private:
     void prepare(hipStream_t st, int m, int n, const int32_t *xt, const double *z);
@@ -90,6 +95,8 @@ class Scanner {
     DBuf<int32_t> scol_;
     int subset_m_ = -1;
     int64_t subset_nnz_ = 0;
+    uint64_t guess_key_ = 0;  // cutoff key for the first pass's compaction (0: none)
+    double guess_f_ = 0.5;    // the cutoff as a fraction of the last k-th selected value
 };
 
 // ---------------------------------------------------------- fixed-order reductions
@@ -172,6 +179,9 @@ class SchurSolver {
 // From this order on, the dense inverse X = L^-1 omits its top doubling level
 // and the solves apply the factor's off-diagonal block between the two halves.
 constexpr int kDenseSplitMinN = 2048;
+// Largest order whose starting point (Theta = I, a well-conditioned system)
+// is solved by the dense factorisation rather than by CG.
+constexpr int kDenseStartMaxN = 16384;
 
 // Dense LDL^T (FP64) of a Schur complement with the infinite-pivot rule.
 class DenseLDL {
@@ -180,6 +190,15 @@ class DenseLDL {
     int factor(hipStream_t st, const SchurCSR &S, double pivtol);
     void solve(hipStream_t st, const double *b, double *x);
     int64_t nnz_L() const { return nnzL_; }
+    // device bytes a factorisation of order n needs, and what this object holds
+    static size_t bytes_for(int n) {
+        const size_t nn = (size_t)n * (size_t)n;
+        return 8 * (3 * nn + nn / 4 + (size_t)2 * 64 * n + (size_t)64 * (n + 63) + 8 * (size_t)n);
+    }
+    size_t held_bytes() const {
+        return 8 * (A_.cap + X_.cap + XT_.cap + T_.cap + W_.cap + linv_.cap + d_.cap + orig_.cap +
+                    v_.cap + t_.cap);
+    }
     const double *pivots() const { return d_.get(); }
     int n = 0;
     // optional timers of the diagonal-factor and trailing-update launches;
@@ -187,6 +206,9 @@ class DenseLDL {
     // every dispatch of a dependent chain slow it down)
     LaunchTimer *diag_timer = nullptr, *update_timer = nullptr;
     int timer_stride = 8;
+    // solve by substitution on L even when the explicit inverse is finite
+    // (the path otherwise taken only when the inverse overflows)
+    bool force_substitution = false;
     void restart_sampling() { factorisations_ = 0; }
 
   private:

@@ -189,28 +189,29 @@ __device__ __forceinline__ void price_one(const PriceArgs &a, int i, int j, doub
         const uint64_t idx = (uint64_t)i + (uint64_t)j * (uint64_t)a.m;
         bool take = neg && !in_support(a.bitmap, idx);
         const uint64_t key = dkey(r);
-        if (MODE == 0) {
+        if (MODE != 1) {
             if (take && (pshift >= 64 || (key >> pshift) == a.prefix))
                 atomicAdd(&lh[(key >> a.shift) & 4095u], 1u);
-        } else {
-            stg.push(take && key <= a.key_max, key, idx);
         }
+        if (MODE != 0) stg.push(take && key <= a.key_max, key, idx);
     }
 }
 
 // Pricing pass.  MODE 0: histogram of one 12-bit digit of the ordered key of
 // every strictly negative reduced cost outside the support.  MODE 1: append
-// (key, idx) of those with key <= key_max.
+// (key, idx) of those with key <= key_max.  MODE 2: both in one pass (the
+// first pass of a call: the top digit's histogram, and the candidates below
+// a cutoff guessed from the previous call).
 template <int MODE, int K>
 __global__ __launch_bounds__(kScanBlock) void price_pass(PriceArgs a) {
-    __shared__ unsigned int lh[MODE == 0 ? kHistBins : 1];
-    __shared__ uint64_t sbuf[MODE == 1 ? (kScanBlock / 64) * kStage * 2 : 1];
-    WaveStage<2> stg{sbuf + (MODE == 1 ? (threadIdx.x >> 6) * kStage * 2 : 0), 0, a.count,
+    __shared__ unsigned int lh[MODE != 1 ? kHistBins : 1];
+    __shared__ uint64_t sbuf[MODE != 0 ? (kScanBlock / 64) * kStage * 2 : 1];
+    WaveStage<2> stg{sbuf + (MODE != 0 ? (threadIdx.x >> 6) * kStage * 2 : 0), 0, a.count,
                      a.out_key, a.out_idx, a.cap};
     const int i = blockIdx.x * kScanBlock + threadIdx.x;
     const int j0 = blockIdx.y * a.tj;
     const int j1 = min(a.n, j0 + a.tj);
-    if (MODE == 0) {
+    if (MODE != 1) {
         for (int t = threadIdx.x; t < kHistBins; t += kScanBlock) lh[t] = 0u;
         __syncthreads();
     }
@@ -238,8 +239,8 @@ __global__ __launch_bounds__(kScanBlock) void price_pass(PriceArgs a) {
         const double r = (cost_of<K>(rd, t) - rd.y) - t.z;
         price_one<MODE>(a, i, j, r, lh, stg);
     }
-    if (MODE == 1) stg.flush();
-    if (MODE == 0) {
+    if (MODE != 0) stg.flush();
+    if (MODE != 1) {
         __syncthreads();
         for (int t = threadIdx.x; t < kHistBins; t += kScanBlock)
             if (lh[t]) atomicAdd(&a.hist[t], (unsigned long long)lh[t]);
@@ -258,11 +259,11 @@ template <int MODE, int K>
 __global__ __launch_bounds__(kScanBlock) void price_list_pass(PriceArgs a,
                                                               const int64_t *__restrict__ jptr,
                                                               const int32_t *__restrict__ jcol) {
-    __shared__ unsigned int lh[MODE == 0 ? kHistBins : 1];
-    __shared__ uint64_t sbuf[MODE == 1 ? (kScanBlock / 64) * kStage * 2 : 1];
-    WaveStage<2> stg{sbuf + (MODE == 1 ? (threadIdx.x >> 6) * kStage * 2 : 0), 0, a.count,
+    __shared__ unsigned int lh[MODE != 1 ? kHistBins : 1];
+    __shared__ uint64_t sbuf[MODE != 0 ? (kScanBlock / 64) * kStage * 2 : 1];
+    WaveStage<2> stg{sbuf + (MODE != 0 ? (threadIdx.x >> 6) * kStage * 2 : 0), 0, a.count,
                      a.out_key, a.out_idx, a.cap};
-    if (MODE == 0) {
+    if (MODE != 1) {
         for (int t = threadIdx.x; t < kHistBins; t += kScanBlock) lh[t] = 0u;
         __syncthreads();
     }
@@ -283,8 +284,8 @@ __global__ __launch_bounds__(kScanBlock) void price_list_pass(PriceArgs a,
             price_one<MODE>(a, i, j, r, lh, stg);
         }
     }
-    if (MODE == 1) stg.flush();
-    if (MODE == 0) {
+    if (MODE != 0) stg.flush();
+    if (MODE != 1) {
         __syncthreads();
         for (int t = threadIdx.x; t < kHistBins; t += kScanBlock)
             if (lh[t]) atomicAdd(&a.hist[t], (unsigned long long)lh[t]);
@@ -323,6 +324,13 @@ static double rcut_of_key(uint64_t k) {
     double d;
     std::memcpy(&d, &u, sizeof d);
     return std::isnan(d) ? INFINITY : d;
+}
+
+// the ordered key of a double (host side; no NaNs)
+static uint64_t host_dkey(double r) {
+    uint64_t u;
+    std::memcpy(&u, &r, sizeof u);
+    return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
 }
 
 // the instance of a kernel templated on the cost kind
@@ -390,17 +398,21 @@ PriceResult Scanner::price(hipStream_t st, int m, int n, const int32_t *xs, cons
     // one pass of the given mode over all variables or over the subset
     auto launch = [&](int mode, const PriceArgs &pa, hipEvent_t e0_, hipEvent_t e1_) {
         if (sub) {
-            auto kfn = mode == 0 ? by_kind(kind, price_list_pass<0, 0>, price_list_pass<0, 1>,
-                                           price_list_pass<0, 2>, price_list_pass<0, 3>)
-                                 : by_kind(kind, price_list_pass<1, 0>, price_list_pass<1, 1>,
-                                           price_list_pass<1, 2>, price_list_pass<1, 3>);
+            auto kfn = mode == 0   ? by_kind(kind, price_list_pass<0, 0>, price_list_pass<0, 1>,
+                                             price_list_pass<0, 2>, price_list_pass<0, 3>)
+                       : mode == 1 ? by_kind(kind, price_list_pass<1, 0>, price_list_pass<1, 1>,
+                                             price_list_pass<1, 2>, price_list_pass<1, 3>)
+                                   : by_kind(kind, price_list_pass<2, 0>, price_list_pass<2, 1>,
+                                             price_list_pass<2, 2>, price_list_pass<2, 3>);
             hipExtLaunchKernelGGL(kfn, lgrid, dim3(kScanBlock), 0, st, e0_, e1_, 0, pa,
                                   (const int64_t *)sptr_.get(), (const int32_t *)scol_.get());
         } else {
-            auto kfn = mode == 0 ? by_kind(kind, price_pass<0, 0>, price_pass<0, 1>,
-                                           price_pass<0, 2>, price_pass<0, 3>)
-                                 : by_kind(kind, price_pass<1, 0>, price_pass<1, 1>,
-                                           price_pass<1, 2>, price_pass<1, 3>);
+            auto kfn = mode == 0   ? by_kind(kind, price_pass<0, 0>, price_pass<0, 1>,
+                                             price_pass<0, 2>, price_pass<0, 3>)
+                       : mode == 1 ? by_kind(kind, price_pass<1, 0>, price_pass<1, 1>,
+                                             price_pass<1, 2>, price_pass<1, 3>)
+                                   : by_kind(kind, price_pass<2, 0>, price_pass<2, 1>,
+                                             price_pass<2, 2>, price_pass<2, 3>);
             hipExtLaunchKernelGGL(kfn, grid, dim3(kScanBlock), 0, st, e0_, e1_, 0, pa);
         }
         OTIP_HIP(hipGetLastError());
@@ -436,83 +448,133 @@ PriceResult Scanner::price(hipStream_t st, int m, int n, const int32_t *xs, cons
         scans++;
     };
 
-    // radix select of the kmax smallest keys, 12 bits per level from the top
-    histogram(52, 0);
+    // First pass: the histogram of the top 12 key bits of every negative
+    // reduced cost outside the support (their count is the top digit's total)
+    // and, in the same pass, the candidates whose key is at most a cutoff
+    // guessed from the previous call's k-th selected value.  When those
+    // include the k smallest keys (at least kmax of them, or all negatives),
+    // the selection needs no further pass over m n.
+    const bool guessing = guess_key_ != 0 && kmax > 0;
+    const uint64_t gcap =
+        guessing ? (uint64_t)std::max<int64_t>(4 * kmax, (int64_t)1 << 20) : 0;
+    ck_.need(std::max<uint64_t>(gcap, 1));
+    ci_.need(std::max<uint64_t>(gcap, 1));
+    OTIP_HIP(hipMemsetAsync(hist_.get(), 0, kHistBins * sizeof(unsigned long long), st));
+    OTIP_HIP(hipMemsetAsync(cnt_.get(), 0, sizeof(unsigned long long), st));
+    a.shift = 52;
+    a.prefix = 0;
+    a.rcut = INFINITY;
+    a.key_max = guessing ? guess_key_ : 0;
+    a.count = cnt_.get();
+    a.out_key = ck_.get();
+    a.out_idx = ci_.get();
+    a.cap = gcap;
+    unsigned long long emitted = 0;
+    {
+        hipEvent_t e0_, e1_;
+        if (timer) timer->arm(units, &e0_, &e1_);
+        else e0_ = e1_ = nullptr;
+        launch(2, a, e0_, e1_);
+        OTIP_HIP(hipMemcpyAsync(h.data(), hist_.get(), kHistBins * sizeof(unsigned long long),
+                                hipMemcpyDeviceToHost, st));
+        OTIP_HIP(hipMemcpyAsync(&emitted, cnt_.get(), sizeof(emitted), hipMemcpyDeviceToHost, st));
+        OTIP_HIP(hipStreamSynchronize(st));
+        if (timer) timer->collect();
+        res.passes++;
+        scans++;
+    }
     uint64_t total = 0;
     for (auto v : h) total += v;
     res.nneg = (int64_t)total;
     if (kmax <= 0 || total == 0) return res;
 
-    uint64_t key_max;
-    uint64_t emit_bound;
-    if (total <= (uint64_t)kmax) {
-        key_max = ~0ull;
-        emit_bound = total;
+    uint64_t cap = 0;
+    if (guessing && emitted <= gcap &&
+        ((total <= (uint64_t)kmax && emitted == total) ||
+         (total > (uint64_t)kmax && emitted >= (uint64_t)kmax))) {
+        cap = emitted;  // the guess held
     } else {
-        uint64_t need = (uint64_t)kmax, less = 0, prefix = 0;
-        int shift = 52;
-        const uint64_t slack = (uint64_t)std::max<int64_t>(kmax, 1 << 16);
-        for (;;) {
-            uint64_t cum = 0;
-            int b = 0;
-            for (; b < kHistBins; ++b) {
-                if (cum + h[b] >= need) break;
-                cum += h[b];
-            }
-            OTIP_CHECK(b < kHistBins, 5, "pricing: histogram inconsistent");
-            less += cum;
-            need -= cum;
-            prefix = (prefix << 12) | (uint64_t)b;
-            const uint64_t bucket = h[b];
-            if (bucket <= slack || shift == 4) {
-                // every key whose top (64 - shift) bits are <= prefix
-                key_max = (shift == 0) ? prefix : (((prefix + 1) << shift) - 1);
-                if (shift == 4) key_max = ((prefix + 1) << 4) - 1;
-                emit_bound = less + bucket;
-                break;
-            }
-            shift = (shift >= 16) ? shift - 12 : 4;
-            if (shift == 4) {
-                // last level covers the remaining low bits in one digit
-                histogram(4, prefix);
-            } else {
+        // adapt the guess: too many candidates -> a cutoff further from 0
+        if (guessing && emitted > gcap) guess_f_ = std::min(0.95, 0.5 * (guess_f_ + 1.0));
+        if (guessing && emitted <= gcap) guess_f_ = std::max(0.05, 0.5 * guess_f_);
+        // radix select of the kmax smallest keys, 12 bits per level from the
+        // top, continuing from the first pass's histogram
+        uint64_t key_max;
+        uint64_t emit_bound;
+        if (total <= (uint64_t)kmax) {
+            key_max = ~0ull;
+            emit_bound = total;
+        } else {
+            uint64_t need = (uint64_t)kmax, less = 0, prefix = 0;
+            int shift = 52;
+            const uint64_t slack = (uint64_t)std::max<int64_t>(kmax, 1 << 16);
+            for (;;) {
+                uint64_t cum = 0;
+                int b = 0;
+                for (; b < kHistBins; ++b) {
+                    if (cum + h[b] >= need) break;
+                    cum += h[b];
+                }
+                OTIP_CHECK(b < kHistBins, 5, "pricing: histogram inconsistent");
+                less += cum;
+                need -= cum;
+                prefix = (prefix << 12) | (uint64_t)b;
+                const uint64_t bucket = h[b];
+                if (bucket <= slack || shift == 4) {
+                    // every key whose top (64 - shift) bits are <= prefix
+                    key_max = (shift == 0) ? prefix : (((prefix + 1) << shift) - 1);
+                    if (shift == 4) key_max = ((prefix + 1) << 4) - 1;
+                    emit_bound = less + bucket;
+                    break;
+                }
+                shift = (shift >= 16) ? shift - 12 : 4;
+                // the last level covers the remaining low bits in one digit
                 histogram(shift, prefix);
             }
         }
+        // compaction
+        cap = emit_bound;
+        ck_.need(cap);
+        ci_.need(cap);
+        OTIP_HIP(hipMemsetAsync(cnt_.get(), 0, sizeof(unsigned long long), st));
+        a.key_max = key_max;
+        a.rcut = key_max == ~0ull ? INFINITY : rcut_of_key(key_max);
+        a.count = cnt_.get();
+        a.out_key = ck_.get();
+        a.out_idx = ci_.get();
+        a.cap = cap;
+        hipEvent_t e0_, e1_;
+        if (timer) timer->arm(units, &e0_, &e1_);
+        else e0_ = e1_ = nullptr;
+        launch(1, a, e0_, e1_);
+        OTIP_HIP(hipMemcpyAsync(&emitted, cnt_.get(), sizeof(emitted), hipMemcpyDeviceToHost, st));
+        OTIP_HIP(hipStreamSynchronize(st));
+        if (timer) timer->collect();
+        res.passes++;
+        scans++;
+        OTIP_CHECK(emitted == cap, 5,
+                   "pricing: compaction count " + std::to_string(emitted) +
+                       " != histogram count " + std::to_string(cap));
     }
-    // compaction
-    const uint64_t cap = emit_bound;
-    ck_.need(cap);
-    ci_.need(cap);
-    OTIP_HIP(hipMemsetAsync(cnt_.get(), 0, sizeof(unsigned long long), st));
-    a.key_max = key_max;
-    a.rcut = key_max == ~0ull ? INFINITY : rcut_of_key(key_max);
-    a.count = cnt_.get();
-    a.out_key = ck_.get();
-    a.out_idx = ci_.get();
-    a.cap = cap;
-    hipEvent_t e0_, e1_;
-    if (timer) timer->arm(units, &e0_, &e1_);
-    else e0_ = e1_ = nullptr;
-    launch(1, a, e0_, e1_);
-    unsigned long long emitted = 0;
-    OTIP_HIP(hipMemcpyAsync(&emitted, cnt_.get(), sizeof(emitted), hipMemcpyDeviceToHost, st));
-    OTIP_HIP(hipStreamSynchronize(st));
-    if (timer) timer->collect();
-    res.passes++;
-    scans++;
-    OTIP_CHECK(emitted == cap, 5,
-               "pricing: compaction count " + std::to_string(emitted) + " != histogram count " +
-                   std::to_string(cap));
-    // order by (key, idx): sort by idx, then stably by key
+    // order by (key, idx): sort by idx, then stably by key (keys of negative
+    // values are below 2^63)
+    int ibits = 1;
+    while (ibits < 64 && (((uint64_t)1 << ibits) < (uint64_t)m * (uint64_t)n)) ++ibits;
     ck2_.need(cap);
     ci2_.need(cap);
-    sort_pairs_u64(st, ci_.get(), ck_.get(), ci2_.get(), ck2_.get(), (int64_t)cap, 0, 64, tmp_);
-    sort_pairs_u64(st, ck2_.get(), ci2_.get(), ck_.get(), ci_.get(), (int64_t)cap, 0, 64, tmp_);
+    sort_pairs_u64(st, ci_.get(), ck_.get(), ci2_.get(), ck2_.get(), (int64_t)cap, 0, ibits, tmp_);
+    sort_pairs_u64(st, ck2_.get(), ci2_.get(), ck_.get(), ci_.get(), (int64_t)cap, 0, 63, tmp_);
     const int64_t k = std::min<int64_t>(kmax, (int64_t)cap);
     hipLaunchKernelGGL(decode_selection, dim3(grid_for(k, 256)), dim3(256), 0, st, k, m,
                        ck_.get(), ci_.get(), oi, oj, orr, oidx);
     OTIP_HIP(hipGetLastError());
+    // next call's cutoff: a fraction guess_f_ of the k-th selected value
+    // (nearer to 0, so that the next iterate's k smallest are likely below it)
+    uint64_t kth = 0;
+    OTIP_HIP(hipMemcpyAsync(&kth, ck_.get() + (k - 1), sizeof(kth), hipMemcpyDeviceToHost, st));
+    OTIP_HIP(hipStreamSynchronize(st));
+    const double rk = rcut_of_key(kth);
+    guess_key_ = (std::isfinite(rk) && rk < 0.0) ? host_dkey(guess_f_ * rk) : 0;
     res.count = k;
     return res;
 }

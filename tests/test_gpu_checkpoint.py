@@ -12,7 +12,7 @@ from synthetic import config_instance
 
 pytestmark = pytest.mark.gpu
 
-HEADER = 104  # bytes before the support-size history in the record
+HEADER = 120  # bytes before the support-size history in the record (layout version 2)
 
 
 @pytest.fixture(scope="module")

@@ -83,6 +83,55 @@ def test_pricing_grid_64x64_full_size(ctx):
     np.testing.assert_array_equal(g_r, o_r)
 
 
+def price_both_prec(ctx, xs, xt, y, z, support, kmax, precision):
+    import paper_2206_11009_amd as otip
+    m, n = len(xs), len(xt)
+    bm = bitmap_of(support, m, n) if len(support) else None
+    oi, oj, orr, nneg = otip.otip_price(ctx, xs, xt, y, z, bm, kmax, precision=precision)
+    g_idx = oi.cpu().numpy().astype(np.int64) + oj.cpu().numpy().astype(np.int64) * m
+    return g_idx, orr.cpu().numpy(), nneg
+
+
+@pytest.mark.parametrize("cfg", ["c3", "c5"])
+def test_pricing_full_size_fp64_and_mixed(ctx, cfg):
+    """The 128 x 128 (268M variables) and 256 x 256 (4.29e9 variables, a
+    537 MB support bitmap) scans select the oracle's m columns bit for bit, in
+    FP64 and in the FP32 scan with its FP64 re-check, on duals at the scale of
+    the optimum's (many reduced costs negative and inside the FP32 band)."""
+    import paper_2206_11009_amd as otip
+    inst = config_instance(cfg, 0)
+    m = inst.m
+    rng = np.random.default_rng(31)
+    c0 = oracle.sq_costs(inst.xs, inst.xt, np.arange(m), np.arange(m)).astype(float)
+    y = rng.uniform(0, 60, m) + c0
+    z = rng.uniform(0, 60, m)
+    support = np.unique(rng.choice(m * m, 10 * m, replace=False))
+    o_idx, o_r, o_neg = _cscan.price(inst.xs, inst.xt, y, z, support, m)
+    assert o_neg > m
+    for prec in (otip.OTIP_FP64, otip.OTIP_MIXED):
+        g_idx, g_r, g_neg = price_both_prec(ctx, inst.xs, inst.xt, y, z, support, m, prec)
+        assert g_neg == o_neg, prec
+        np.testing.assert_array_equal(g_idx, o_idx)
+        np.testing.assert_array_equal(g_r, o_r)
+
+
+def test_pricing_variable_indices_above_2_32(ctx):
+    """m = 65536 sources, n = 70000 targets: variable indices i + j m reach
+    4.6e9, beyond 32 bits."""
+    rng = np.random.default_rng(47)
+    m, n = 65536, 70000
+    xs = rng.integers(0, 300, (m, 2)).astype(np.int32)
+    xt = rng.integers(0, 300, (n, 2)).astype(np.int32)
+    y = rng.uniform(0, 3000, m)
+    z = rng.uniform(0, 3000, n)
+    support = np.unique(rng.integers(0, m * n, 200000))
+    g_idx, g_r, g_neg, o_idx, o_r, o_neg = price_both(ctx, xs, xt, y, z, support, m)
+    assert o_neg > m and o_idx.max() > 2 ** 32
+    assert g_neg == o_neg
+    np.testing.assert_array_equal(g_idx, o_idx)
+    np.testing.assert_array_equal(g_r, o_r)
+
+
 def test_rmin(ctx):
     import paper_2206_11009_amd as otip
     rng = np.random.default_rng(5)
@@ -146,6 +195,46 @@ def test_schur_matches_oracle(ctx):
     for j in range(n):
         assert np.all(np.diff(ci[rp[j]:rp[j + 1]]) > 0)
     assert np.array_equal(G, G.T)   # exactly symmetric
+
+
+@pytest.mark.parametrize("cfg,extra", [("c2", 20000), ("c3", 40000)])
+def test_schur_matches_oracle_full_size(ctx, cfg, extra):
+    """S_M at n = 4096 (rows accumulated in LDS) and n = 16384 (the merge of
+    source lists used above 8192 targets), on the initial support plus random
+    far entries (rows of S spanning more than 8192 columns), against the
+    oracle's sparse N - V^T M^-1 V."""
+    import scipy.sparse as sp
+    import paper_2206_11009_amd as otip
+    inst = config_instance(cfg, 0)
+    m, n = inst.m, inst.n
+    idx, _ = oracle.initial_support(inst.xs, inst.xt, 5.0)
+    rng = np.random.default_rng(17)
+    idx = np.unique(np.concatenate([idx, rng.choice(m * n, extra, replace=False)]))
+    theta = np.exp(rng.uniform(-8.0, 8.0, idx.size))      # IPM-like spread of Theta
+    rp, ci, va, M, N = otip.otip_schur(ctx, m, n, idx, theta)
+    rp, ci, va = rp.cpu().numpy(), ci.cpu().numpy()[:rp[-1]], va.cpu().numpy()[:rp[-1]]
+    G = sp.csr_matrix((va, ci, rp), shape=(n, n))
+    rows, cols = idx % m, idx // m
+    Mo, No, V = oracle.normal_blocks(theta, rows, cols, m, n)
+    S = oracle.schur_complement(Mo, No, V, "M").tocsr()
+    np.testing.assert_allclose(M.cpu().numpy(), Mo, rtol=1e-13)
+    np.testing.assert_allclose(N.cpu().numpy(), No, rtol=1e-13)
+    D = (G - S).tocoo()
+    scale = abs(S).max()
+    assert abs(D.data).max() <= 1e-12 * scale
+    # the pattern holds every pair of targets sharing a source, sorted per row
+    P = (V.T @ V).tocsr()
+    P.data[:] = 1.0
+    Gp = G.copy()
+    Gp.data[:] = 1.0
+    assert (P - P.multiply(Gp)).count_nonzero() == 0
+    assert all(np.all(np.diff(ci[rp[j]:rp[j + 1]]) > 0) for j in range(n))
+    assert (G - G.T).count_nonzero() == 0
+    spans = np.array([ci[rp[j + 1] - 1] - ci[rp[j]] for j in range(n)])
+    if n > 8192:
+        assert spans.max() > 8192
+    # zero row sums (eq. diagdom)
+    assert abs(np.asarray(G.sum(axis=1)).ravel()).max() <= 1e-12 * scale
 
 
 @pytest.mark.parametrize("m,n,kmax,seed", [(300, 257, 300, 1), (1000, 700, 50, 2), (64, 64, 100000, 3),

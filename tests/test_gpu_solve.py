@@ -95,6 +95,24 @@ def test_gaussian_64x64_matches_stored_oracle(ctx, k):
     assert abs(res.objective - ref) <= 1e-6 * abs(ref)
 
 
+@pytest.mark.parametrize("k,precision", [(0, "mixed"), (1, "mixed"), (2, "mixed"), (0, "fp64")])
+def test_white_noise_128x128_matches_stored_oracle(ctx, k, precision):
+    """128x128 white-noise grids (268M variables), the mixed-precision form of
+    the workload (FP32 pricing with the FP64 re-check, FP32 CG inside FP64
+    refinement) and FP64: objective within 1e-6 of the FP64 oracle's stored
+    optimum (its relative error printed), certified gap and marginals."""
+    import paper_2206_11009_amd as otip
+    inst = config_instance("c3", k)
+    prec = otip.OTIP_MIXED if precision == "mixed" else otip.OTIP_FP64
+    res = otip.otip_solve(ctx, inst.a, inst.b, inst.xs, inst.xt, otip.params(precision=prec))
+    check_result(res, inst.a, inst.b, inst.xs, inst.xt)
+    ref = {r["seed"]: r for r in load_golden("c3")}[k]["objective"]
+    err = abs(res.objective - ref) / abs(ref)
+    print(f"c3 seed {k} {precision}: objective {res.objective!r}, oracle {ref!r}, "
+          f"relative error {err:.2e}, {res.iterations} iterations, {res.seconds_total:.2f} s")
+    assert err <= 1e-6
+
+
 @pytest.mark.parametrize("cfg,k", [("c1", 0), ("c1", 5), ("c2", 2)])
 def test_mixed_precision_solve(ctx, cfg, k):
     """FP32 pricing with FP64 re-check and FP32 CG inside FP64 refinement reach
