@@ -123,7 +123,12 @@ def side_of(inst):
     return side if side * side == inst.m == inst.n else None
 
 
-def run_single(ctx, dev, insts, prm, weights, steps, warmup, cost_kind=0):
+def progress(msg):
+    """One line on stderr per finished solve (a long run keeps reporting)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def run_single(ctx, dev, insts, prm, weights, steps, warmup, cost_kind=0, label=""):
     """Seconds per LP over `steps` solves (after `warmup`), with the learned
     prediction (inside the timed region) when weights are given."""
     import torch
@@ -132,9 +137,13 @@ def run_single(ctx, dev, insts, prm, weights, steps, warmup, cost_kind=0):
     def one(k):
         a, b, xs, xt = dev[k]
         if weights is None:
-            return otip.otip_solve(ctx, a, b, xs, xt, prm, cost_kind=cost_kind)
-        y0, z0 = otip.otip_ws_predict(ctx, weights, side_of(insts[k]), a, b)
-        return otip.otip_solve(ctx, a, b, xs, xt, prm, y0=y0, z0=z0, cost_kind=cost_kind)
+            r = otip.otip_solve(ctx, a, b, xs, xt, prm, cost_kind=cost_kind)
+        else:
+            y0, z0 = otip.otip_ws_predict(ctx, weights, side_of(insts[k]), a, b)
+            r = otip.otip_solve(ctx, a, b, xs, xt, prm, y0=y0, z0=z0, cost_kind=cost_kind)
+        progress(f"{label} solve {k + 1}/{warmup + steps}: {r.seconds_total:.3f} s, "
+                 f"{r.iterations} iterations, gap {r.rel_gap:.1e}")
+        return r
 
     for k in range(warmup):
         one(k)
@@ -159,13 +168,15 @@ def run_batch(ctx, dev, insts, prm, weights, steps, warmup):
             probs.append((a, b, xs, xt, y0, z0))
         return otip.otip_solve_batch(ctx, probs, prm)
 
-    for _ in range(warmup):
+    for q in range(warmup):
         one()
+        progress(f"batch {q + 1}/{warmup + steps}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
-    for _ in range(steps):
+    for q in range(steps):
         infos += [r.info for r in one()]
+        progress(f"batch {warmup + q + 1}/{warmup + steps}")
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / (steps * len(dev)), infos
 
@@ -283,8 +294,11 @@ def main():
     dev = upload(insts)
     prec = otip.OTIP_MIXED if args.precision == "mixed" else otip.OTIP_FP64
     tune = tuned(max(i.m for i in insts), max(i.n for i in insts), batched)
+    if args.config == "c5":
+        tune = dict(tune, max_iter=500)   # the iteration limit for this workload
+    kw = {} if batched else {"label": f"{args.precision}_plain"}
     sec, infos = run(ctx, dev, insts, otip.params(profile=1, precision=prec, **tune), None,
-                     args.steps, args.warmup)
+                     args.steps, args.warmup, **kw)
     if not summary(sec, infos)["certified"]:
         raise SystemExit(f"solve not certified: {infos}")
     dominant, other, gcosts = rooflines(infos)
@@ -296,13 +310,17 @@ def main():
         todo = [("mixed_plain", otip.OTIP_MIXED, None),
                 (f"{args.precision}_learned", prec, weights),
                 ("mixed_learned", otip.OTIP_MIXED, weights)]
-        if args.config == "c5":  # minutes per solve: the metric's comparison only
-            todo = todo[2:]
+        if args.config in ("c3", "c5"):
+            # the metric's comparison (and, at 128 x 128, the mixed-precision
+            # form alone): the whole run stays within a few minutes
+            todo = [t for t in todo if t[0] == "mixed_learned" or
+                    (args.config == "c3" and t[0] == "mixed_plain")]
         for name, p, w in todo:
             if name in forms:
                 continue
+            kw = {} if batched else {"label": name}
             s2, inf2 = run(ctx, dev, insts, otip.params(precision=p, **tune), w, args.steps,
-                           args.warmup)
+                           args.warmup, **kw)
             forms[name] = summary(s2, inf2)
             forms[name]["speedup_vs_plain"] = sec / s2
     # the same problems under the costs of Section 5.1 (1-, 2- and inf-norm of
@@ -310,8 +328,9 @@ def main():
     norm_costs = {}
     if not args.no_forms and not batched and args.config in ("c1", "c2"):
         for name, kind in (("l1", 1), ("l2", 2), ("linf", 3)):
-            s3, inf3 = run_single(ctx, dev, insts, otip.params(precision=prec, **tune), None,
-                                  args.steps, args.warmup, cost_kind=kind)
+            s3, inf3 = run_single(ctx, dev, insts,
+                                  otip.params(precision=prec, max_iter=500, **tune), None,
+                                  args.steps, args.warmup, cost_kind=kind, label=name)
             norm_costs[name] = summary(s3, inf3)
 
     out = {
@@ -342,6 +361,7 @@ def main():
         "norm_costs": norm_costs,
     }
     if not args.no_cpu_baseline and not batched:
+        progress("CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(args.config, fallback_its=out["iterations_mean"])
     print(json.dumps(out), flush=True)
 

@@ -129,6 +129,9 @@ typedef struct otip_params {
     int32_t schur_reuse;     /* 1: keep the Schur pattern across support updates that
                                 only remove entries (a superset of the new one; its
                                 extra entries get the value 0) */
+    int32_t ws_union;        /* warm start: 1 (default) starts from the union of the
+                                predicted support and the plain rule's (end of
+                                Section 3.2); 0 from the predicted support alone */
 } otip_params;
 
 /* Problem description.  All arrays are DEVICE pointers.

@@ -36,7 +36,7 @@ class otip_params(ctypes.Structure):
         ("price_tile", _c_i32),
         ("ws_kappa", ctypes.c_double),
         ("heur_radius", _c_f64), ("heur_run", _c_i32), ("switch_back_grow", _c_f64),
-        ("force_switch_back_at", _c_i32), ("schur_reuse", _c_i32),
+        ("force_switch_back_at", _c_i32), ("schur_reuse", _c_i32), ("ws_union", _c_i32),
     ]
 
 

@@ -220,6 +220,7 @@ void otip_params_default(otip_params *p) {
     p->switch_back_grow = 0.0;
     p->force_switch_back_at = -1;
     p->schur_reuse = 1;
+    p->ws_union = 1;
 }
 
 int otip_create(otip_ctx **ctx, int device, void *hip_stream) {

@@ -118,7 +118,8 @@ class Solver {
     DBuf<double> tmp_f64a, tmp_f64b, tmp_f64c, tmp_f64d;
     DBuf<int32_t> tmp_i32a, tmp_i32b;
     DBuf<uint32_t> tmp_u32a;
-    DBuf<uint64_t> init_, sel_idx_;
+    DBuf<uint64_t> init_, init2_, sel_idx_;
+    DBuf<unsigned long long> ucnt_;
     DBuf<double> sel_r_;
     DBuf<uint8_t> removed_;
     DBuf<int32_t> zc_;

@@ -1070,6 +1070,21 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
             psi0 = scan.warm_support(st, m, n, xs, xt, pr.y0, pr.z0,
                                      P.ws_kappa > 0 ? P.ws_kappa : P.kappa, init, yws_, zws_);
             warm_used = psi0 >= 0;
+            if (warm_used && P.ws_union) {
+                // the plain rule's support joined to the predicted one: a poor
+                // prediction then adds columns without taking the cheap ones away
+                const int64_t psi_p =
+                    scan.initial_support(st, m, n, xs, xt, P.kappa, cmax, init2_, &T);
+                const int64_t tot = psi0 + psi_p;
+                uint64_t *cat = tmp_u64a.need(tot), *srt = tmp_u64b.need(tot);
+                OTIP_HIP(hipMemcpyAsync(cat, init.get(), sizeof(uint64_t) * psi0,
+                                        hipMemcpyDeviceToDevice, st));
+                OTIP_HIP(hipMemcpyAsync(cat + psi0, init2_.get(), sizeof(uint64_t) * psi_p,
+                                        hipMemcpyDeviceToDevice, st));
+                sort_keys_u64(st, cat, srt, tot, tmp);
+                init.need(tot);
+                psi0 = unique_u64(st, srt, init.get(), tot, tmp, ucnt_);
+            }
         }
         if (psi0 < 0) psi0 = scan.initial_support(st, m, n, xs, xt, P.kappa, cmax, init, &T);
         alloc_support(std::max<int64_t>(psi0 * 2, psi0 + 4 * (int64_t)std::max(m, n)));

@@ -7,7 +7,7 @@ at sizes where running the oracle inside a test would take minutes.
     python tests/golden/make_golden.py c1 c2
     python tests/golden/make_golden.py c2:costs
 
-A name ``cfg:costs`` writes ``oracle_cfg_costs.json``: seed 0 of the workload
+A name ``cfg:costs`` writes ``oracle_cfg_costs.json``: every seed of the workload
 under each norm cost of Section 5.1 (1-, 2- and inf-norm, cost kinds 1-3).
 """
 import json
@@ -25,15 +25,17 @@ from synthetic import CONFIGS, config_instance  # noqa: E402
 def costs(cfg):
     out = os.path.join(HERE, f"oracle_{cfg}_costs.json")
     rows = []
-    inst = config_instance(cfg, 0)
-    for kind in (1, 2, 3):
-        t = time.perf_counter()
-        r = oracle.solve(inst.a, inst.b, inst.xs, inst.xt, oracle.OracleParams(cost_kind=kind))
-        rows.append(dict(seed=0, cost_kind=kind, m=inst.m, n=inst.n, status=r.status,
-                         objective=r.objective, dual_bound=r.dual_bound, rel_gap=r.rel_gap,
-                         marginal_residual=r.marginal_residual, nnz=int(len(r.flows)),
-                         iterations=r.iterations, seconds=time.perf_counter() - t))
-        print(cfg, rows[-1], flush=True)
+    for k in range(CONFIGS[cfg]["seeds"]):
+        inst = config_instance(cfg, k)
+        for kind in (1, 2, 3):
+            t = time.perf_counter()
+            r = oracle.solve(inst.a, inst.b, inst.xs, inst.xt,
+                             oracle.OracleParams(cost_kind=kind))
+            rows.append(dict(seed=k, cost_kind=kind, m=inst.m, n=inst.n, status=r.status,
+                             objective=r.objective, dual_bound=r.dual_bound, rel_gap=r.rel_gap,
+                             marginal_residual=r.marginal_residual, nnz=int(len(r.flows)),
+                             iterations=r.iterations, seconds=time.perf_counter() - t))
+            print(cfg, rows[-1], flush=True)
     with open(out, "w") as f:
         json.dump({"config": cfg, "generator": "synthetic.config_instance",
                    "solver": "oracle.solve (OracleParams(cost_kind=k))", "results": rows}, f,
