@@ -64,6 +64,10 @@ __global__ void dense_zero(size_t total, double *A) {
 constexpr int kDiagStepBlock = 16;
 static_assert(NB % kDiagStepBlock == 0, "the last hand-over must follow pivot NB - 1");
 
+// s_waitcnt operand (GFX9 encoding) that waits for every vector memory load of
+// the wave: vmcnt 0, expcnt and lgkmcnt at their maxima (no wait)
+constexpr int kWaitVmcnt0 = 0x0F70;
+
 __device__ __forceinline__ double rdlane(double v, int lane) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
     const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
@@ -137,9 +141,10 @@ __global__ __launch_bounds__(128) void ldl_diag(int n, int kb, int nb, double *A
 // L21 = W21 D1^-1.  One workgroup per TR-row tile forms W = A21 Linv^T on the
 // FP64 matrix cores (Linv is zero above its diagonal); its four waves split
 // the TR x 64 tile into blocks of 16 x 16, with their operands loaded straight
-// from global memory into the registers of the matrix-core layout (no LDS, no
-// barrier).  Small tiles (TR = 16) give the early block steps enough
-// workgroups and each wave a short chain of products.
+// from global memory into the registers of the matrix-core layout (no LDS;
+// one barrier before the in-place store of L21).  Small tiles (TR = 16) give
+// the early block steps enough workgroups and each wave a short chain of
+// products.
 template <int TR>
 __global__ __launch_bounds__(256) void ldl_panel(int n, int kb, int nb, double *A,
                                                  const double *d, double *W,
@@ -180,6 +185,12 @@ __global__ __launch_bounds__(256) void ldl_panel(int n, int kb, int nb, double *
         for (int u = 0; u < UR; ++u)
 #pragma unroll
             for (int v = 0; v < VC; ++v) acc[u][v] = mfma4(av[u][t], bv[v][t], acc[u][v]);
+    // L21 overwrites A21 in place, and the waves that share a row block each
+    // store a different column slice of it after reading the whole row: every
+    // wave's loads have returned (vmcnt 0; the barrier alone lets the compiler
+    // leave some in flight across it) before any wave of the workgroup stores.
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+    __syncthreads();
 #pragma unroll
     for (int u = 0; u < UR; ++u)
 #pragma unroll
@@ -211,18 +222,54 @@ constexpr int kPanelRows = 16;
 // index); each wave forms a 32x32 quarter of the tile as 2x2 blocks of 16x16
 // matrix-core products, with its operands loaded straight from global memory
 // into the registers of the matrix-core layout (no LDS, no barrier).  Panel p
-// holds the columns [kcol, kcol + nb) of L (in A) and its W with row r0 + j at
-// wrow0 + j (leading dimension wld).  Two panels per launch halve the passes
-// over the trailing matrix; first_col restricts the launch to the first tile
-// column (the next diagonal block and the rows below it).
+// holds the 64 columns [kcol, kcol + 64) of L (in A) and its W with row r0 + j
+// at wrow0 + j (leading dimension wld); a panel always has 64 columns, since
+// only a block with rows below it forms one.  Up to kDenseUpdPanels panels per
+// launch: the trailing matrix is read and written once per group of block
+// steps.  first_col restricts the launch to the first tile column (the next
+// diagonal block and the rows below it).
+//
+// Rows past the trailing matrix (in the last tile row or column when its order
+// is not a multiple of 64) are clamped to its last row: they read valid memory
+// and feed only outputs that are not stored, so no load is conditional.  Every
+// address is a wave-uniform base plus a 32-bit lane offset fixed for the whole
+// tile, so the loads of a k step need no per-lane address arithmetic.
 struct UpdPanel {
     const double *W;
-    int kcol, nb, wrow0, wld;
+    int kcol, wrow0, wld;
 };
 struct UpdArgs {
-    int n, r0, first_col;
-    UpdPanel p[2];
+    int n, r0, first_col, super_order;
+    UpdPanel p[kDenseUpdPanels];
 };
+// Tile order of a large trailing update.  Workgroups go to the eight XCDs in
+// turn (workgroup b to XCD b mod 8), and each XCD keeps about 128 of these
+// workgroups resident (32 CUs, four per CU).  Row-major tiles would give each
+// XCD tiles from every tile column at once, so every tile fetches its 64 rows
+// of W (and of L) from beyond the XCD's 4 MB L2.  Instead the lower triangle
+// is cut into super-tiles of kSuperRows x kSuperCols tiles, dealt to the XCDs
+// in turn, and XCD x takes the tiles of its super-tile together: 128 tiles
+// that share 16 row blocks of L and 8 of W (3 MB with four panels).  Super-row
+// I (tile rows 16I..16I+15) has the 2I + 2 super-tiles that reach the diagonal,
+// so super-tile s lies in the row I with I(I+1) <= s < (I+1)(I+2).
+constexpr int kSuperRows = 16, kSuperCols = 8, kSuperTiles = kSuperRows * kSuperCols;
+constexpr int kXcds = 8;
+// smallest trailing triangle (in 64-row tiles) that takes the super-tile order:
+// with fewer super-tiles than about nine per XCD the last round leaves XCDs
+// idle, which costs more than the extra operand traffic (measured equal time
+// from here on, at 2.6 times less L2-miss traffic).  OTIP_DENSE_SUPER_MIN in the
+// environment overrides it (a tuning aid).
+constexpr int kSuperMinTiles = 128;
+static int super_min_tiles() {
+    static const int v = [] {
+        const char *e = std::getenv("OTIP_DENSE_SUPER_MIN");
+        return e ? std::max(1, std::atoi(e)) : kSuperMinTiles;
+    }();
+    return v;
+}
+__device__ __forceinline__ double ld_at(const double *base, uint32_t byte_off) {
+    return *(const double *)((const char *)base + byte_off);
+}
 // TR: rows per workgroup tile.  The triangle of tiles uses 64 x 64 tiles;
 // a first-column launch may use TR = 16 (one workgroup per 16 rows of the
 // 64-wide block column, four waves of 16 x 16 across its columns), which
@@ -232,12 +279,23 @@ __global__ __launch_bounds__(256) void ldl_update(double *A, UpdArgs a) {
     constexpr int WC = TR >= 32 ? 2 : 4;
     constexpr int UR = TR / (4 / WC) / 16, VC = 64 / WC / 16;
     const int n = a.n, r0 = a.r0;
-    const int rows = n - r0;
+    const int rows = n - r0, last = rows - 1;
     const int blk = blockIdx.x;
     int i0, j0;
     if (a.first_col) {
         i0 = blk * TR;
         j0 = 0;
+    } else if (a.super_order) {
+        const int slot = blk / kXcds;
+        const int sidx = (slot / kSuperTiles) * kXcds + blk % kXcds, w = slot % kSuperTiles;
+        int I = (int)((sqrt(4.0 * sidx + 1.0) - 1.0) * 0.5);
+        while ((I + 1) * (I + 2) <= sidx) ++I;
+        while (I * (I + 1) > sidx) --I;
+        const int J = sidx - I * (I + 1);
+        const int ti = kSuperRows * I + w / kSuperCols, tj = kSuperCols * J + w % kSuperCols;
+        if (tj > ti || ti * NB >= rows) return;  // outside the triangle (no barrier follows)
+        i0 = ti * NB;
+        j0 = tj * NB;
     } else {
         int ti = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);
         while ((ti + 1) * (ti + 2) / 2 <= blk) ++ti;
@@ -249,8 +307,9 @@ __global__ __launch_bounds__(256) void ldl_update(double *A, UpdArgs a) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wr = (wave / WC) * (16 * UR), wc = (wave % WC) * (16 * VC);
     const int li = lane & 15, lk = lane >> 4;
-    // the tile's current values, requested with the operands so that their
-    // latency is hidden behind the products
+    // the tile: base at (r0, r0 + j0), lane offsets of its entries (clamped)
+    double *C = A + (size_t)(r0 + j0) * n + r0;
+    uint32_t coff[UR][VC][4];
     double cur[UR][VC][4];
 #pragma unroll
     for (int u = 0; u < UR; ++u)
@@ -258,12 +317,18 @@ __global__ __launch_bounds__(256) void ldl_update(double *A, UpdArgs a) {
         for (int v = 0; v < VC; ++v)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int ii = i0 + wr + 16 * u + mfma_row(lane, q);
-                const int jj = j0 + wc + 16 * v + li;
-                cur[u][v][q] = (ii < rows && jj < rows && ii >= jj)
-                                   ? A[(size_t)(r0 + ii) + (size_t)(r0 + jj) * n]
-                                   : 0.0;
+                const int ii = min(i0 + wr + 16 * u + mfma_row(lane, q), last);
+                const int jj = min(j0 + wc + 16 * v + li, last) - j0;
+                coff[u][v][q] = 8u * ((uint32_t)ii + (uint32_t)jj * (uint32_t)n);
+                // requested with the operands, so that the latency is hidden
+                cur[u][v][q] = ld_at(C, coff[u][v][q]);
             }
+    // operand rows of this lane (clamped), relative to r0
+    int ar[UR], br[VC];
+#pragma unroll
+    for (int u = 0; u < UR; ++u) ar[u] = min(i0 + wr + 16 * u + li, last);
+#pragma unroll
+    for (int v = 0; v < VC; ++v) br[v] = min(j0 + wc + 16 * v + li, last);
     d4 acc[UR][VC];
 #pragma unroll
     for (int u = 0; u < UR; ++u)
@@ -272,26 +337,24 @@ __global__ __launch_bounds__(256) void ldl_update(double *A, UpdArgs a) {
 #pragma unroll
     for (int pi = 0; pi < NP; ++pi) {
         const UpdPanel P = a.p[pi];
-        // operands: L(r0 + i0 + wr + 16u + li, kcol + k) and W(j0 + wc + 16v + li, k),
-        // k = 4t + lk
+        // operands: L(r0 + ar[u], kcol + k) and W(wrow0 + br[v], k), k = 4t + lk
+        const double *Lb = A + (size_t)P.kcol * n + r0;
+        const double *Wb = P.W + P.wrow0;
+        uint32_t ao[UR], bo[VC];
+#pragma unroll
+        for (int u = 0; u < UR; ++u) ao[u] = 8u * ((uint32_t)ar[u] + (uint32_t)lk * (uint32_t)n);
+#pragma unroll
+        for (int v = 0; v < VC; ++v)
+            bo[v] = 8u * ((uint32_t)br[v] + (uint32_t)lk * (uint32_t)P.wld);
         double av[UR][16], bv[VC][16];
 #pragma unroll
         for (int t = 0; t < 16; ++t) {
-            const int k = 4 * t + lk;
+            const double *Lt = Lb + (size_t)(4 * t) * n;
+            const double *Wt = Wb + (size_t)(4 * t) * P.wld;
 #pragma unroll
-            for (int u = 0; u < UR; ++u) {
-                const int ii = i0 + wr + 16 * u + li;
-                av[u][t] = (ii < rows && k < P.nb)
-                               ? A[(size_t)(r0 + ii) + (size_t)(P.kcol + k) * n]
-                               : 0.0;
-            }
+            for (int u = 0; u < UR; ++u) av[u][t] = ld_at(Lt, ao[u]);
 #pragma unroll
-            for (int v = 0; v < VC; ++v) {
-                const int jj = j0 + wc + 16 * v + li;
-                bv[v][t] = (jj < rows && k < P.nb)
-                               ? P.W[(size_t)(P.wrow0 + jj) + (size_t)k * P.wld]
-                               : 0.0;
-            }
+            for (int v = 0; v < VC; ++v) bv[v][t] = ld_at(Wt, bo[v]);
         }
 #pragma unroll
         for (int t = 0; t < 16; ++t)
@@ -309,7 +372,7 @@ __global__ __launch_bounds__(256) void ldl_update(double *A, UpdArgs a) {
                 const int ii = i0 + wr + 16 * u + mfma_row(lane, q);
                 const int jj = j0 + wc + 16 * v + li;
                 if (ii < rows && jj < rows && ii >= jj)
-                    A[(size_t)(r0 + ii) + (size_t)(r0 + jj) * n] = cur[u][v][q] - acc[u][v][q];
+                    *(double *)((char *)C + coff[u][v][q]) = cur[u][v][q] - acc[u][v][q];
             }
 }
 
@@ -578,6 +641,26 @@ __global__ __launch_bounds__(256) void transpose_lower(int n, const double *__re
     }
 }
 
+static_assert(kDenseUpdPanels == 4, "launch_update instantiates one to four panels");
+template <int TR>
+static void launch_update(int np, unsigned blocks, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
+                          double *A, const UpdArgs &u) {
+    switch (np) {
+    case 1:
+        hipExtLaunchKernelGGL((ldl_update<1, TR>), dim3(blocks), dim3(256), 0, st, e0, e1, 0, A, u);
+        break;
+    case 2:
+        hipExtLaunchKernelGGL((ldl_update<2, TR>), dim3(blocks), dim3(256), 0, st, e0, e1, 0, A, u);
+        break;
+    case 3:
+        hipExtLaunchKernelGGL((ldl_update<3, TR>), dim3(blocks), dim3(256), 0, st, e0, e1, 0, A, u);
+        break;
+    default:
+        hipExtLaunchKernelGGL((ldl_update<4, TR>), dim3(blocks), dim3(256), 0, st, e0, e1, 0, A, u);
+        break;
+    }
+}
+
 int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
     n = S.n;
     const size_t total = (size_t)n * n;
@@ -585,7 +668,7 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
     double *A = A_.need(total);
     d_.need(n);
     orig_.need(n);
-    W_.need((size_t)2 * n * NB);
+    double *W = W_.need((size_t)kDenseUpdPanels * n * NB);
     double *linv = linv_.need((size_t)nblk * NB * NB);
     ninf_.need(1);
     hipLaunchKernelGGL(dense_zero, dim3(2048), dim3(256), 0, st, total, A);
@@ -596,7 +679,6 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
     OTIP_HIP(hipMemsetAsync(nzL, 0, sizeof(unsigned long long), st));
     const bool timed = factorisations_++ % std::max(1, timer_stride) == 0;
     LaunchTimer *tdiag = timed ? diag_timer : nullptr, *tupd = timed ? update_timer : nullptr;
-    double *Wa = W_.get(), *Wb = W_.get() + (size_t)n * NB;
     auto diag = [&](int kb, int nb) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (tdiag) tdiag->arm(2.0 * nb * nb * nb / 3.0, &e0, &e1);
@@ -612,46 +694,58 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
     auto update = [&](int np, const UpdArgs &u, unsigned blocks, double flops) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (tupd) tupd->arm(flops, &e0, &e1);
-        if (np == 2)
-            hipExtLaunchKernelGGL((ldl_update<2, 64>), dim3(blocks), dim3(256), 0, st, e0, e1, 0,
-                                  A, u);
-        else if (u.first_col)
-            hipExtLaunchKernelGGL((ldl_update<1, kFirstColRows>), dim3(blocks), dim3(256), 0, st,
-                                  e0, e1, 0, A, u);
+        if (u.first_col)
+            launch_update<kFirstColRows>(np, blocks, st, e0, e1, A, u);
         else
-            hipExtLaunchKernelGGL((ldl_update<1, 64>), dim3(blocks), dim3(256), 0, st, e0, e1, 0,
-                                  A, u);
+            launch_update<NB>(np, blocks, st, e0, e1, A, u);
     };
-    // Block steps, two at a time where a pair leaves rows below it: after
-    // the first block's panel only the second block's column is updated, the
-    // second block is factorised, and the rest of the trailing matrix takes
-    // both panels in one pass.
+    // Block steps in groups of up to kDenseUpdPanels: each block of a group
+    // first takes the group's earlier panels on its own block column (a
+    // first-column launch), is factorised and forms its panel; the rest of the
+    // trailing matrix then takes all of the group's panels in one pass.  A
+    // group closes early when the next block is the last one.  Every block
+    // that forms a panel has 64 columns (only the last block can be narrower,
+    // and it has no rows below it).
     for (int kb = 0; kb < n;) {
-        const int nb = std::min(NB, n - kb);
-        diag(kb, nb);
-        const int rows = n - kb - nb;
-        if (rows == 0) break;
-        panel(kb, nb, Wa);
-        const UpdPanel pa{Wa, kb, nb, 0, rows};
-        const int kb2 = kb + nb, nb2 = std::min(NB, n - kb2), rows2 = n - kb2 - nb2;
-        if (rows2 > 0) {
-            UpdArgs u1{n, kb2, 1, {pa, pa}};
-            update(1, u1, grid_for(rows, kFirstColRows),
-                   2.0 * nb * ((double)nb2 * (rows - nb2) + nb2 * (nb2 + 1) / 2.0));
-            diag(kb2, nb2);
-            panel(kb2, nb2, Wb);
-            const UpdPanel pa2{Wa, kb, nb, nb2, rows};
-            const UpdPanel pb{Wb, kb2, nb2, 0, rows2};
-            UpdArgs u2{n, kb2 + nb2, 0, {pa2, pb}};
-            const unsigned t2 = grid_for(rows2, NB);
-            update(2, u2, t2 * (t2 + 1) / 2, (double)rows2 * rows2 * (nb + nb2));
-            kb = kb2 + nb2;
-        } else {
-            UpdArgs u1{n, kb2, 0, {pa, pa}};
-            const unsigned t1 = grid_for(rows, NB);
-            update(1, u1, t1 * (t1 + 1) / 2, (double)rows * rows * nb);
-            kb = kb2;
+        UpdArgs u{n, 0, 0, 0, {}};
+        int g = 0, kq = kb;
+        for (;;) {
+            const int nbq = std::min(NB, n - kq);
+            if (g > 0) {
+                u.r0 = kq;
+                u.first_col = 1;
+                for (int p = 0; p < g; ++p) u.p[p].wrow0 = kq - u.p[p].kcol - NB;
+                const double rq = n - kq;
+                update(g, u, grid_for(n - kq, kFirstColRows),
+                       2.0 * g * NB * (nbq * (rq - nbq) + nbq * (nbq + 1) / 2.0));
+            }
+            diag(kq, nbq);
+            const int below = n - kq - nbq;
+            if (below == 0) {  // the last block (g == 0 here: see the loop's exit test)
+                kq = n;
+                break;
+            }
+            double *Wq = W + (size_t)g * n * NB;
+            panel(kq, nbq, Wq);
+            u.p[g] = UpdPanel{Wq, kq, 0, below};
+            ++g;
+            kq += nbq;
+            if (g == kDenseUpdPanels || n - kq <= NB) break;
         }
+        if (kq >= n) break;
+        u.r0 = kq;
+        u.first_col = 0;
+        for (int p = 0; p < g; ++p) u.p[p].wrow0 = kq - u.p[p].kcol - NB;
+        const unsigned t = grid_for(n - kq, NB);
+        u.super_order = t >= (unsigned)super_min_tiles();
+        unsigned blocks = t * (t + 1) / 2;
+        if (u.super_order) {
+            const unsigned srows = (t + kSuperRows - 1) / kSuperRows;
+            const unsigned supers = srows * (srows + 1);
+            blocks = (supers + kXcds - 1) / kXcds * kXcds * kSuperTiles;
+        }
+        update(g, u, blocks, (double)(n - kq) * (n - kq) * g * NB);
+        kb = kq;
     }
     // X = L^-1 (unit lower; the strict lower part of A holds L)
     double *X = X_.need(total);

@@ -182,6 +182,9 @@ constexpr int kDenseSplitMinN = 2048;
 // Largest order whose starting point (Theta = I, a well-conditioned system)
 // is solved by the dense factorisation rather than by CG.
 constexpr int kDenseStartMaxN = 16384;
+// Panels (64-column blocks of L) the dense factorisation's trailing update
+// applies per pass over the trailing matrix.
+constexpr int kDenseUpdPanels = 4;
 
 // Dense LDL^T (FP64) of a Schur complement with the infinite-pivot rule.
 class DenseLDL {
@@ -193,7 +196,8 @@ class DenseLDL {
     // device bytes a factorisation of order n needs, and what this object holds
     static size_t bytes_for(int n) {
         const size_t nn = (size_t)n * (size_t)n;
-        return 8 * (3 * nn + nn / 4 + (size_t)2 * 64 * n + (size_t)64 * (n + 63) + 8 * (size_t)n);
+        return 8 * (3 * nn + nn / 4 + (size_t)kDenseUpdPanels * 64 * n + (size_t)64 * (n + 63) +
+                    8 * (size_t)n);
     }
     size_t held_bytes() const {
         return 8 * (A_.cap + X_.cap + XT_.cap + T_.cap + W_.cap + linv_.cap + d_.cap + orig_.cap +

@@ -63,16 +63,71 @@ def test_direct_solve_n2025_and_split_n4096(ctx, substitution):
     formed) and n = 4096 (64 x 64, where the solves apply L21 between the two
     halves' inverses)."""
     for side in (45, 64):
-        m = n = side * side
-        rng = np.random.default_rng(side)
-        xs = np.stack([np.arange(m) // side, np.arange(m) % side], 1).astype(np.int32)
-        idx, _ = oracle.initial_support(xs, xs, 5.0)
-        idx = np.unique(np.concatenate([idx, rng.choice(m * n, 5 * m, replace=False)]))
-        theta = np.exp(rng.uniform(-3.0, 3.0, idx.size))
-        M, N, V = oracle.normal_blocks(theta, idx % m, idx // m, m, n)
-        S = oracle.schur_complement(M, N, V, "M").tocsr()
-        S.sort_indices()
+        S, rng = grid_schur(side, side)
         run_case(ctx, S, rng, substitution)
+
+
+def grid_schur(side, seed):
+    """Schur complement (M-side) of a side x side grid pair: the initial support
+    plus 5 m random entries, theta log-uniform over [e^-3, e^3]."""
+    m = n = side * side
+    rng = np.random.default_rng(seed)
+    xs = np.stack([np.arange(m) // side, np.arange(m) % side], 1).astype(np.int32)
+    idx, _ = oracle.initial_support(xs, xs, 5.0)
+    idx = np.unique(np.concatenate([idx, rng.choice(m * n, 5 * m, replace=False)]))
+    theta = np.exp(rng.uniform(-3.0, 3.0, idx.size))
+    M, N, V = oracle.normal_blocks(theta, idx % m, idx // m, m, n)
+    S = oracle.schur_complement(M, N, V, "M").tocsr()
+    S.sort_indices()
+    return S, rng
+
+
+def solve_both_ways(ctx, S, rng):
+    """The solve with the explicit inverse and by substitution: each leaves a
+    residual at rounding level, and the two agree up to the null vector e."""
+    import paper_2206_11009_amd as otip
+    b = rng.standard_normal(S.shape[0])
+    b -= b.mean()                      # in the range of S (connected support)
+    xs = []
+    for substitution in (False, True):
+        x, ninf, _ = otip.otip_ldl_solve(ctx, S.indptr, S.indices, S.data, b,
+                                         substitution=substitution)
+        x = x.cpu().numpy()
+        assert ninf == 1
+        assert np.linalg.norm(S @ x - b) <= 1e-9 * np.linalg.norm(b)
+        xs.append(x)
+    assert np.ptp(xs[0] - xs[1]) <= 1e-7 * max(1.0, np.abs(xs[1]).max())
+
+
+def test_direct_solve_ragged_update_n4900(ctx):
+    """n = 4900 (70 x 70): row-major trailing updates with a ragged last tile
+    row (4644 = 72 * 64 + 36 rows after the first group of panels).  The
+    oracle's sparse factorisation of this order takes most of a minute on the
+    CPU, so the checks are the residual and the agreement of the two solve
+    paths (the oracle is compared at n = 4096)."""
+    S, rng = grid_schur(70, 70)
+    solve_both_ways(ctx, S, rng)
+
+
+def test_direct_solve_super_tiled_update_n9409(ctx):
+    """n = 9409 (97 x 97): trailing triangles of 144 down to 128 tiles take the
+    super-tile order, the first with a ragged last tile row (9153 = 143 * 64 + 1
+    rows)."""
+    S, rng = grid_schur(97, 97)
+    solve_both_ways(ctx, S, rng)
+
+
+def test_direct_solve_is_deterministic(ctx):
+    """The same factorisation and solve twice give the same bits (each panel
+    workgroup reads its rows of A21 before any of its waves overwrites them
+    with L21)."""
+    import paper_2206_11009_amd as otip
+    S, rng = grid_schur(97, 97)
+    b = rng.standard_normal(S.shape[0])
+    b -= b.mean()
+    x1, _, _ = otip.otip_ldl_solve(ctx, S.indptr, S.indices, S.data, b)
+    x2, _, _ = otip.otip_ldl_solve(ctx, S.indptr, S.indices, S.data, b)
+    np.testing.assert_array_equal(x1.cpu().numpy(), x2.cpu().numpy())
 
 
 def test_direct_solve_two_components_two_infinite_pivots(ctx):

@@ -128,10 +128,10 @@ def test_mixed_precision_solve(ctx, cfg, k):
 
 def test_profile_counts_dense_factor_launches(ctx):
     """With profiling on, every dense factorisation of the 256 x 256 Schur
-    complement times its 4 diagonal-block launches and 3 trailing updates (the
-    second block's column after the first panel, the last two blocks with both
-    panels of the first pair, the last block after the third panel), and their
-    algorithmic flops are the stated per-launch formulas."""
+    complement times its 4 diagonal-block launches and 3 trailing updates (one
+    group of three panels: the second block's column after the first panel,
+    the third block's column after the first two, the last block after all
+    three), and their algorithmic flops are the stated per-launch formulas."""
     import paper_2206_11009_amd as otip
     inst = config_instance("c1", 1)
     res = otip.otip_solve(ctx, inst.a, inst.b, inst.xs, inst.xt, otip.params(profile=1))
@@ -139,9 +139,12 @@ def test_profile_counts_dense_factor_launches(ctx):
     nd, nu = res.diag_launches, res.update_launches
     assert nd > 0 and nd % 4 == 0 and nu == 3 * nd // 4
     factorisations = nd // 4
+
+    def first_col(panels, rows):   # a 64-wide block column of `rows` rows
+        return 2.0 * panels * 64 * (64 * (rows - 64) + 64 * 65 / 2.0)
+
     assert res.diag_flops == pytest.approx(nd * 2.0 * 64 ** 3 / 3.0, rel=1e-12)
-    first_col = 2.0 * 64 * (64 * (192 - 64) + 64 * 65 / 2.0)
-    per_factorisation = first_col + 128 ** 2 * 128 + 64 ** 2 * 64
+    per_factorisation = first_col(1, 192) + first_col(2, 128) + 64 ** 2 * 3 * 64
     assert res.update_flops == pytest.approx(factorisations * per_factorisation, rel=1e-12)
     assert res.diag_ms > 0.0 and res.update_ms > 0.0
     plain = otip.otip_solve(ctx, inst.a, inst.b, inst.xs, inst.xt)
