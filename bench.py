@@ -36,20 +36,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-# HBM traffic per launch measured by rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
-# (separate runs) on `bench.py --steps 1 --warmup 0 --no-cpu-baseline
-# --no-forms`, scaled by what the counters read for a 1 GiB device copy, mean
-# over the launches that did work; valid only for the kernel source it was
-# measured on (the SHA-256 of the text of the listed functions).
+# HBM traffic per launch of a kernel on a workload, measured by rocprofv3
+# --pmc FETCH_SIZE and WRITE_SIZE (separate runs) on `bench.py --config <cfg>
+# --steps 1 --warmup 0 --no-cpu-baseline --no-forms`, scaled by what the
+# counters read for a 1 GiB device copy, mean over the launches that did work;
+# valid only for the kernel source it was measured on (the SHA-256 of the text
+# of the listed functions).
 KERNEL_TRAFFIC = {
-    "spmv_dir": {"source": "paper_2206_11009_amd/csrc/schur.hip",
-                 "functions": ["load_chunk", "spmv_dir"],
-                 "sha256": "b7d3d64dbbdb6f1b70dc204ca01743bbd6207ed3a1ff743a2bc37396851125fb",
-                 "bytes_per_launch": 2519256.0},
-    "ldl_diag": {"source": "paper_2206_11009_amd/csrc/dense.hip",
-                 "functions": ["ldl_diag"],
-                 "sha256": "763182764fc82dfa612048fdcdd197df49aa3945a703918e1749b5f425ff1ade",
-                 "bytes_per_launch": 351733.0},
+    ("spmv_dir", "c2"): {"source": "paper_2206_11009_amd/csrc/schur.hip",
+                         "functions": ["load_chunk", "spmv_dir"],
+                         "sha256": "b7d3d64dbbdb6f1b70dc204ca01743bbd6207ed3a1ff743a2bc37396851125fb",
+                         "bytes_per_launch": 2519256.0},
+    ("spmv_dir", "c3"): {"source": "paper_2206_11009_amd/csrc/schur.hip",
+                         "functions": ["load_chunk", "spmv_dir"],
+                         "sha256": "b7d3d64dbbdb6f1b70dc204ca01743bbd6207ed3a1ff743a2bc37396851125fb",
+                         "bytes_per_launch": 9606508.9},
+    ("ldl_update", "c3"): {"source": "paper_2206_11009_amd/csrc/dense.hip",
+                           "functions": ["ldl_update"],
+                           "sha256": "eb4f5649549eddf3c31f346b038b09527de249dd8e9a5093e39ba6dbcbbbaa36",
+                           "bytes_per_launch": 296944356.5},
+    ("ldl_diag", "c2"): {"source": "paper_2206_11009_amd/csrc/dense.hip",
+                         "functions": ["ldl_diag"],
+                         "sha256": "763182764fc82dfa612048fdcdd197df49aa3945a703918e1749b5f425ff1ade",
+                         "bytes_per_launch": 351733.0},
 }
 FP64_VECTOR_PEAK_TF = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 FP64_MATRIX_PEAK_TF = 78.6     # dense FP64 matrix-core peak
@@ -208,10 +217,11 @@ def kernel_source_sha256(path, names):
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
-    """Counter-measured bytes per launch of a kernel, or None when none were
-    taken or once its source differs from the one the counters were taken on."""
-    t = KERNEL_TRAFFIC.get(kernel)
+def measured_traffic(kernel, cfg):
+    """Counter-measured bytes per launch of a kernel on a workload, or None
+    when none were taken or once its source differs from the one the counters
+    were taken on."""
+    t = KERNEL_TRAFFIC.get((kernel, cfg))
     if t is None or t["sha256"] is None:
         return None
     if kernel_source_sha256(t["source"], t["functions"]) != t["sha256"]:
@@ -219,7 +229,7 @@ def measured_traffic(kernel):
     return t["bytes_per_launch"]
 
 
-def rooflines(infos):
+def rooflines(infos, cfg):
     spmv_ms = sum(i["spmv_ms"] for i in infos)
     spmv_n = sum(i["spmv_launches"] for i in infos)
     spmv_b = sum(i["spmv_bytes"] for i in infos)
@@ -229,7 +239,7 @@ def rooflines(infos):
     spmv = {"bound": "hbm", "kernel": "spmv_dir (Schur SpMV fused with the CG direction update)",
             "achieved": spmv_b / max(spmv_ms, 1e-12) / 1e6, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "avg_launch_us": 1e3 * spmv_ms / max(spmv_n, 1), "launches": spmv_n,
-            "total_ms": spmv_ms, "traffic": measured_traffic("spmv_dir"),
+            "total_ms": spmv_ms, "traffic": measured_traffic("spmv_dir", cfg),
             "algorithmic_bytes_per_launch": spmv_b / max(spmv_n, 1)}
     price = {"bound": "alu", "kernel": "price_pass (pricing scan)",
              "achieved": PRICE_FLOPS_PER_COST * pr_e / max(pr_ms, 1e-12) / 1e9,
@@ -246,12 +256,12 @@ def rooflines(infos):
             "unit lower factor, two wavefronts)",
             "achieved": dg_f / max(dg_ms, 1e-12) / 1e9, "peak": FP64_VECTOR_PEAK_TF,
             "unit": "TFLOP/s", "avg_launch_us": 1e3 * dg_ms / max(dg_n, 1), "launches": dg_n,
-            "total_ms": dg_ms, "traffic": measured_traffic("ldl_diag"),
+            "total_ms": dg_ms, "traffic": measured_traffic("ldl_diag", cfg),
             "algorithmic_flops_per_launch": dg_f / max(dg_n, 1)}
     update = {"bound": "mfma", "kernel": "ldl_update (trailing update of the dense LDL^T)",
               "achieved": up_f / max(up_ms, 1e-12) / 1e9, "peak": FP64_MATRIX_PEAK_TF,
               "unit": "TFLOP/s", "avg_launch_us": 1e3 * up_ms / max(up_n, 1), "launches": up_n,
-              "total_ms": up_ms, "traffic": None,
+              "total_ms": up_ms, "traffic": measured_traffic("ldl_update", cfg),
               "algorithmic_flops_per_launch": up_f / max(up_n, 1)}
     named = {"spmv_dir": spmv, "price_pass": price, "ldl_diag": diag, "ldl_update": update}
     for r in named.values():
@@ -301,7 +311,7 @@ def main():
                      args.steps, args.warmup, **kw)
     if not summary(sec, infos)["certified"]:
         raise SystemExit(f"solve not certified: {infos}")
-    dominant, other, gcosts = rooflines(infos)
+    dominant, other, gcosts = rooflines(infos, args.config)
 
     forms = {f"{args.precision}_plain": summary(sec, infos)}
     weights = None

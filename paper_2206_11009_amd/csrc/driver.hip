@@ -1195,18 +1195,19 @@ int Solver::run(const otip_problem &pr, const otip_params &prm, Result &res) {
             // replaces.  A fixed cost model (not wall time, so the switch point
             // is reproducible): CG iteration = SpMV bytes at 3 TB/s + three
             // launches of 6 us; dense = factor and inverse (2 n^3/3 flops at
-            // 12 TF/s) + their dependent launches (3 per 64-column block, 2 per
-            // doubling level, 20 us each) + per solve two products over n^2/2
-            // entries each at 2 TB/s and two launches of 6 us.  From
-            // kDenseSplitMinN the inverse's top level is not formed: n^3/12 flops for the
-            // inverse, one level fewer, six launches per solve.
+            // 30 TF/s, the rate measured for both at n = 16384) + their
+            // dependent launches (3 per 64-column block, 2 per doubling level,
+            // 20 us each) + per solve two products over n^2/2 entries each at
+            // 2 TB/s and two launches of 6 us.  From kDenseSplitMinN the
+            // inverse's top level is not formed: n^3/12 flops for the inverse,
+            // one level fewer, six launches per solve.
             const double nb = (double)((n + 63) / 64);
             const bool split = n >= kDenseSplitMinN;
             const double levels =
                 std::ceil(std::log2(std::max(1.0, nb))) - (split ? 1.0 : 0.0);
             const double t_cg = cg_its_last * ((12.0 * (double)schur.S.nnz + 20.0 * n) / 3e12 +
                                                3 * 6e-6);
-            const double t_dense = (split ? 5.0 / 12.0 : 2.0 / 3.0) * (double)n * n * n / 12e12 +
+            const double t_dense = (split ? 5.0 / 12.0 : 2.0 / 3.0) * (double)n * n * n / 30e12 +
                                    (3.0 * nb + 2.0 * levels) * 20e-6 +
                                    solves_last * (8.0 * (double)n * n / 2e12 +
                                                   (split ? 6 : 2) * 6e-6);
