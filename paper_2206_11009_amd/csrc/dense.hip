@@ -395,20 +395,35 @@ __global__ void inv_init(int n, const double *__restrict__ linv, double *__restr
     }
 }
 
-__global__ __launch_bounds__(256) void inv_mul(int n, int b, int mode, const double *__restrict__ L,
+// Reduction chunk of inv_mul: 32 columns of the left operand and 32 rows of
+// the right one per LDS stage (33 KB of LDS per workgroup instead of 66 KB
+// with 64-wide chunks, so four workgroups fit a compute unit's 160 KB).  The
+// mode is a template parameter, each thread's chunk elements keep one row and
+// step in columns, and rows outside the matrix are clamped with their values
+// replaced by 0 (no branches); held to 128 VGPRs, four waves per SIMD.
+constexpr int kInvKC = 32;
+template <int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void inv_mul(
+    int n, int b, const double *__restrict__ L,
                                                double *__restrict__ X, double *__restrict__ T) {
     const int p = blockIdx.z;
     const int c1 = 2 * p * b, r2 = c1 + b;
     const int rows2 = min(b, n - r2);
-    const int ti = blockIdx.x, tj = blockIdx.y;
+    // a tile's work grows with b/64 - tj (MODE 0) or with ti (MODE 1); the
+    // slower-varying grid index walks it from the heaviest tiles down, so the
+    // launch ends on light tiles
+    const int ti = MODE == 0 ? blockIdx.x : (int)gridDim.y - 1 - (int)blockIdx.y;
+    const int tj = MODE == 0 ? blockIdx.y : blockIdx.x;
     if (ti * NB >= rows2) return;
-    __shared__ double As[NB][NB + 1];
-    __shared__ double Bs[NB][NB + 1];
+    __shared__ double As[NB][kInvKC + 1];
+    __shared__ double Bs[kInvKC][NB + 1];
     double *Tp = T + (size_t)p * b * b;  // b x b column-major, rows < rows2 used
-    // mode 0: A(r, k) = L(r2 + r, c1 + k), B(k, c) = X(c1 + k, c1 + c), zero for k < c
-    // mode 1: A(r, k) = X(r2 + r, r2 + k), zero for k > r; B(k, c) = T(k, c)
-    const int kt0 = mode == 0 ? tj : 0;
-    const int kt1 = mode == 0 ? b / NB : ti + 1;
+    // MODE 0: A(r, k) = L(r2 + r, c1 + k), B(k, c) = X(c1 + k, c1 + c), zero for k < c
+    // MODE 1: A(r, k) = X(r2 + r, r2 + k), zero for k > r; B(k, c) = T(k, c)
+    // (chunk indices: kInvKC columns of A and rows of B each)
+    constexpr int per64 = NB / kInvKC;
+    const int kt0 = MODE == 0 ? tj * per64 : 0;
+    const int kt1 = MODE == 0 ? (b / NB) * per64 : (ti + 1) * per64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
@@ -417,40 +432,57 @@ __global__ __launch_bounds__(256) void inv_mul(int n, int b, int mode, const dou
     for (int u = 0; u < 2; ++u)
 #pragma unroll
         for (int v = 0; v < 2; ++v) acc[u][v] = d4{0.0, 0.0, 0.0, 0.0};
-    // each thread moves elements t = threadIdx.x + 256 e of the two tiles; the
-    // next k-tile is fetched into registers while the current one is multiplied
-    double pa[NB * NB / 256], pb[NB * NB / 256];
+    // Thread tid moves A chunk elements (q, k) = (tid % 64, tid / 64 + 4e) and
+    // B chunk elements (k2, c) = (tid % 32, tid / 32 + 8e), e < kE: the row in
+    // memory is fixed per thread, the column steps by 4 (A) or 8 (B).
+    constexpr int kE = NB * kInvKC / 256;
+    const int q = threadIdx.x % NB, k0 = threadIdx.x / NB;
+    const int k2 = threadIdx.x % kInvKC, cb0 = threadIdx.x / kInvKC;
+    const int ar = ti * NB + q;
+    const bool a_in = ar < rows2;
+    const int arc = min(ar, rows2 - 1);
+    // column-major operands: A base at (row base, column base), B likewise
+    const double *Abase = MODE == 0 ? L + (size_t)(c1)*n + r2 : X + (size_t)r2 * n + r2;
+    const int lda = n;
+    const double *Bbase = MODE == 0 ? X + (size_t)(c1 + tj * NB) * n + c1 : Tp + (size_t)(tj * NB) * b;
+    const int ldb = MODE == 0 ? n : b;
+    double pa[kE], pb[kE];
     auto fetch = [&](int kt) {
+        const int kc = kt * kInvKC;  // first reduction index of the chunk
+        const double *Ak = Abase + (size_t)kc * lda;
+        // B row of this thread, clamped (MODE 1 reads T rows below rows2 as 0)
+        const int bk = kc + k2;
+        const bool b_in = MODE == 0 || bk < rows2;
+        const int bkc = MODE == 0 ? bk : min(bk, rows2 - 1);
 #pragma unroll
-        for (int e = 0; e < NB * NB / 256; ++e) {
-            const int t = threadIdx.x + 256 * e;
-            const int q = t % NB, k = t / NB;  // element (q, k) of the A and B tiles
-            const int ar = ti * NB + q, ak = kt * NB + k;
-            const int bk = kt * NB + q, bc = tj * NB + k;
-            double av = 0.0, bv = 0.0;
-            if (mode == 0) {
-                if (ar < rows2) av = L[(size_t)(r2 + ar) + (size_t)(c1 + ak) * n];
-                bv = X[(size_t)(c1 + bk) + (size_t)(c1 + bc) * n];
+        for (int e = 0; e < kE; ++e) {
+            const int k = k0 + 4 * e;
+            double av, bv;
+            if (MODE == 0) {
+                av = Ak[(size_t)arc + (size_t)k * lda];
+                av = a_in ? av : 0.0;
             } else {
-                if (ar < rows2 && ak < rows2) av = X[(size_t)(r2 + ar) + (size_t)(r2 + ak) * n];
-                if (bk < rows2) bv = Tp[(size_t)bk + (size_t)bc * b];
+                const int ak = kc + k;
+                const int akc = min(ak, rows2 - 1);
+                av = Abase[(size_t)arc + (size_t)akc * lda];
+                av = (a_in && ak < rows2) ? av : 0.0;
             }
+            bv = Bbase[(size_t)bkc + (size_t)(cb0 + 8 * e) * ldb];
             pa[e] = av;
-            pb[e] = bv;
+            pb[e] = b_in ? bv : 0.0;
         }
     };
     if (kt0 < kt1) fetch(kt0);
     for (int kt = kt0; kt < kt1; ++kt) {
 #pragma unroll
-        for (int e = 0; e < NB * NB / 256; ++e) {
-            const int t = threadIdx.x + 256 * e;
-            As[t % NB][t / NB] = pa[e];
-            Bs[t % NB][t / NB] = pb[e];
+        for (int e = 0; e < kE; ++e) {
+            As[q][k0 + 4 * e] = pa[e];
+            Bs[k2][cb0 + 8 * e] = pb[e];
         }
         __syncthreads();
         if (kt + 1 < kt1) fetch(kt + 1);
-#pragma unroll 4
-        for (int k = 0; k < NB; k += 4) {
+#pragma unroll
+        for (int k = 0; k < kInvKC; k += 4) {
             const double a0 = As[wr + li][k + lk], a1 = As[wr + 16 + li][k + lk];
             const double b0 = Bs[k + lk][wc + li], b1 = Bs[k + lk][wc + 16 + li];
             acc[0][0] = mfma4(a0, b0, acc[0][0]);
@@ -465,14 +497,14 @@ __global__ __launch_bounds__(256) void inv_mul(int n, int b, int mode, const dou
 #pragma unroll
         for (int v = 0; v < 2; ++v)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int r = ti * NB + wr + 16 * u + mfma_row(lane, q);
+            for (int qq = 0; qq < 4; ++qq) {
+                const int r = ti * NB + wr + 16 * u + mfma_row(lane, qq);
                 const int c = tj * NB + wc + 16 * v + li;
                 if (r >= rows2) continue;
-                if (mode == 0)
-                    Tp[(size_t)r + (size_t)c * b] = acc[u][v][q];
+                if (MODE == 0)
+                    Tp[(size_t)r + (size_t)c * b] = acc[u][v][qq];
                 else
-                    X[(size_t)(r2 + r) + (size_t)(c1 + c) * n] = -acc[u][v][q];
+                    X[(size_t)(r2 + r) + (size_t)(c1 + c) * n] = -acc[u][v][qq];
             }
 }
 
@@ -769,8 +801,8 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
         for (int b = NB; b < bend; b *= 2) {
             const int pairs = (n - b + 2 * b - 1) / (2 * b);
             dim3 grid(b / NB, b / NB, pairs);
-            hipLaunchKernelGGL(inv_mul, grid, dim3(256), 0, st, n, b, 0, A, X, T);
-            hipLaunchKernelGGL(inv_mul, grid, dim3(256), 0, st, n, b, 1, A, X, T);
+            hipLaunchKernelGGL(inv_mul<0>, grid, dim3(256), 0, st, n, b, A, X, T);
+            hipLaunchKernelGGL(inv_mul<1>, grid, dim3(256), 0, st, n, b, A, X, T);
         }
     }
     OTIP_HIP(hipGetLastError());
