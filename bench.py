@@ -282,6 +282,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the mixed-precision and learned-warm-start forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--verbose", action="store_true",
+                    help="the library's per-iteration log on stderr (long solves)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures a single GPU; this build has no multi-GPU path "
@@ -306,6 +308,8 @@ def main():
     tune = tuned(max(i.m for i in insts), max(i.n for i in insts), batched)
     if args.config == "c5":
         tune = dict(tune, max_iter=500)   # the iteration limit for this workload
+    if args.verbose:
+        tune = dict(tune, verbose=1)
     kw = {} if batched else {"label": f"{args.precision}_plain"}
     sec, infos = run(ctx, dev, insts, otip.params(profile=1, precision=prec, **tune), None,
                      args.steps, args.warmup, **kw)
@@ -360,7 +364,8 @@ def main():
                    "instances": (f"512 per step" if batched else
                                  f"step k solves seed k mod {CONFIGS[args.config]['seeds']}"),
                    "certified_rel_gap": 1e-6, "precision": args.precision,
-                   "form": "plain initial support", "tuned": tune},
+                   "form": "plain initial support",
+                   "tuned": {k: v for k, v in tune.items() if k != "verbose"}},
         "roofline": dominant,
         "roofline_other": other,
         "pricing_gcosts_per_s": gcosts,

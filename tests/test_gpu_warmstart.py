@@ -60,9 +60,15 @@ def test_learned_start_gains_over_plain(ctx, weights):
 
 
 def test_predicted_duals_are_near_optimal(ctx, weights):
-    """The c-transform of the prediction is a valid dual bound, on average
-    within 30% of the optimum (the plain rule's cost-only start corresponds to
-    zero duals, whose c-transform bounds these grid pairs by 0)."""
+    """The c-transform of the prediction is a valid dual bound, and on each of
+    these 12 problems of the batched family (the distribution the network was
+    trained on) within 40% of the optimum, within 25% on average.  Measured:
+    0.760 to 0.947 of the optimum, mean 0.846, with the network trained on
+    20,000 problems (0.707 to 0.920 with the earlier one trained on 15,051;
+    the prediction and the solve are deterministic, so the margins only absorb
+    retraining).  The plain rule's
+    cost-only start corresponds to zero duals, whose c-transform bounds these
+    grid pairs by 0."""
     import paper_2206_11009_amd as otip
     insts = batch_instances(12)
     ratios = []
@@ -73,4 +79,5 @@ def test_predicted_duals_are_near_optimal(ctx, weights):
         assert bound <= opt * (1 + 1e-9)
         ratios.append(bound / opt)
     print("bound / optimum:", np.round(ratios, 3))
-    assert np.mean(ratios) >= 0.7
+    assert min(ratios) >= 0.6
+    assert np.mean(ratios) >= 0.75
