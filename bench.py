@@ -43,14 +43,6 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 # valid only for the kernel source it was measured on (the SHA-256 of the text
 # of the listed functions).
 KERNEL_TRAFFIC = {
-    ("spmv_dir", "c2"): {"source": "paper_2206_11009_amd/csrc/schur.hip",
-                         "functions": ["load_chunk", "spmv_dir"],
-                         "sha256": "b7d3d64dbbdb6f1b70dc204ca01743bbd6207ed3a1ff743a2bc37396851125fb",
-                         "bytes_per_launch": 2519256.0},
-    ("spmv_dir", "c3"): {"source": "paper_2206_11009_amd/csrc/schur.hip",
-                         "functions": ["load_chunk", "spmv_dir"],
-                         "sha256": "b7d3d64dbbdb6f1b70dc204ca01743bbd6207ed3a1ff743a2bc37396851125fb",
-                         "bytes_per_launch": 9606508.9},
     ("ldl_update", "c3"): {"source": "paper_2206_11009_amd/csrc/dense.hip",
                            "functions": ["ldl_update"],
                            "sha256": "eb4f5649549eddf3c31f346b038b09527de249dd8e9a5093e39ba6dbcbbbaa36",
@@ -236,10 +228,11 @@ def rooflines(infos, cfg):
     pr_ms = sum(i["price_ms"] for i in infos)
     pr_n = sum(i["price_launches"] for i in infos)
     pr_e = sum(i["price_elems"] for i in infos)
-    spmv = {"bound": "hbm", "kernel": "spmv_dir (Schur SpMV fused with the CG direction update)",
+    spmv = {"bound": "hbm", "kernel": "cg_step (one Jacobi-PCG iteration: Schur SpMV with the "
+            "vector updates and a single reduction)",
             "achieved": spmv_b / max(spmv_ms, 1e-12) / 1e6, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "avg_launch_us": 1e3 * spmv_ms / max(spmv_n, 1), "launches": spmv_n,
-            "total_ms": spmv_ms, "traffic": measured_traffic("spmv_dir", cfg),
+            "total_ms": spmv_ms, "traffic": measured_traffic("cg_step", cfg),
             "algorithmic_bytes_per_launch": spmv_b / max(spmv_n, 1)}
     price = {"bound": "alu", "kernel": "price_pass (pricing scan)",
              "achieved": PRICE_FLOPS_PER_COST * pr_e / max(pr_ms, 1e-12) / 1e9,
@@ -263,7 +256,7 @@ def rooflines(infos, cfg):
               "unit": "TFLOP/s", "avg_launch_us": 1e3 * up_ms / max(up_n, 1), "launches": up_n,
               "total_ms": up_ms, "traffic": measured_traffic("ldl_update", cfg),
               "algorithmic_flops_per_launch": up_f / max(up_n, 1)}
-    named = {"spmv_dir": spmv, "price_pass": price, "ldl_diag": diag, "ldl_update": update}
+    named = {"cg_step": spmv, "price_pass": price, "ldl_diag": diag, "ldl_update": update}
     for r in named.values():
         r["frac"] = r["achieved"] / r["peak"]
     top = max(named, key=lambda k: named[k]["total_ms"])

@@ -164,15 +164,15 @@ class SchurSolver {
   private:
     template <typename T>
     CGStats pcg_impl(hipStream_t st, const T *val, const T *dinv, const T *b, T *x, double rtol,
-                     double atol, int maxit, DBuf<T> &r, DBuf<T> &p, DBuf<T> &q);
+                     double atol, int maxit, DBuf<T> &p, DBuf<T> &g);
     DBuf<int32_t> cnt_, rk_;
     DBuf<double> rth_;
     int64_t psi_ = 0;  // support size of the last symbolic()
     int32_t span_ = 0;  // largest kmax - kmin + 1 over the rows of S
     DBuf<char> tmp_;
     DBuf<int64_t> off64_, cnt64_;
-    DBuf<double> r_, p_, q_, part_, scal_, rd_, sx_, rpart_;
-    DBuf<float> val32_, dinv32_, rf_, df_, rf2_, pf_, qf_;
+    DBuf<double> p_, g_, part_, scal_, rd_, sx_, rpart_;
+    DBuf<float> val32_, dinv32_, rf_, df_, pf_, gf_;
     DBuf<int> flag_;
 };
 

@@ -393,12 +393,24 @@ __global__ __launch_bounds__(256) void spmv_rows(int n, const int32_t *__restric
     }
 }
 
-// Device-side CG scalars.  rho is double-buffered by iteration parity: the
-// direction kernel of iteration parity par reads the previous rho from
-// rho[par ^ 1] in every workgroup and workgroup 0 writes the new one to
-// rho[par], so no extra launch commits it.
+// Jacobi-preconditioned CG in the single-reduction form of Chronopoulos and
+// Gear (mathematically the same iterates as CG), one launch per iteration.
+// With u = D^-1 r and w = S u:
+//   gamma_i = r_i.u_i, delta_i = w_i.u_i, beta_i = gamma_i / gamma_{i-1},
+//   alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1})  (beta_0 = 0),
+//   p_i = u_i + beta_i p_{i-1}, s_i = w_i + beta_i s_{i-1}  (s_i = S p_i),
+//   x_{i+1} = x_i + alpha_i p_i, r_{i+1} = r_i - alpha_i s_i.
+// All three dot products of an iteration come from one reduction, so the
+// launch that forms w_{i+1} = S u_{i+1} also applies the updates: every
+// workgroup sums the previous launch's partials in the same order (the same
+// alpha_i and beta_i everywhere), and u_{i+1} of a neighbour row is formed
+// where the SpMV gathers that row's (r_i, w_i, s_{i-1}, d).
+
+// Device-side CG scalars.  gamma and alpha are double-buffered by launch
+// parity: a launch reads its predecessor's at [par ^ 1] in every workgroup,
+// and workgroup 0 writes its own at [par].
 struct CGScal {
-    double rho[2], rr, target, its;
+    double gam[2], alpha[2], rr, target, its;
 };
 
 // fixed-order sum of nb per-block partials, computed by wave 0 and broadcast
@@ -415,45 +427,61 @@ __device__ __forceinline__ double sum_partials(const double *p, int nb, double *
     return v;
 }
 
-// The preconditioned residual z and the search direction p of one iteration
-// parity, interleaved so that the SpMV gathers both with one load per nonzero.
-template <typename T>
-struct __attribute__((aligned(2 * sizeof(T)))) ZP {
-    T z, p;
-};
-
-template <typename T>
-__global__ __launch_bounds__(kCGThreads) void cg_init(int n, const T *__restrict__ b,
-                                                      const T *__restrict__ dinv, T *x, T *r,
-                                                      ZP<T> *w, double *part) {
-    __shared__ double lds[16];
-    double rz = 0.0, rr = 0.0;
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
-        const T bj = b[j];
-        const T zj = dinv[j] * bj;
-        x[j] = (T)0;
-        r[j] = bj;
-        w[j] = ZP<T>{zj, (T)0};  // the first direction is z itself (beta = 0)
-        rz = fma((double)bj, (double)zj, rz);
-        rr = fma((double)bj, (double)bj, rr);
+// the three partial sums of a launch (gamma, delta, r.r: kSpmvMaxBlocks slots
+// apart), one per wavefront in parallel, each in the fixed order of
+// sum_partials; broadcast to the workgroup
+__device__ __forceinline__ void sum_partials3(const double *p, int nb, double *lds,
+                                              double (&out)[3]) {
+    const int wv = threadIdx.x >> 6;
+    if (wv < 3) {
+        const double *q = p + wv * kSpmvMaxBlocks;
+        double s = 0.0;
+        for (int k = threadIdx.x & 63; k < nb; k += 64) s += q[k];
+        s = wave_sum(s);
+        if ((threadIdx.x & 63) == 0) lds[wv] = s;
     }
-    double t1 = block_sum(rz, lds);
-    double t2 = block_sum(rr, lds);
-    if (threadIdx.x == 0) {
-        part[blockIdx.x] = t1;
-        part[kCGBlocks + blockIdx.x] = t2;
-    }
+    __syncthreads();
+    out[0] = lds[0];
+    out[1] = lds[1];
+    out[2] = lds[2];
+    __syncthreads();
 }
 
+// One row's state as the next launch gathers it: r_i, w_i, s_{i-1} and the
+// Jacobi inverse d, double-buffered by launch parity.
+template <typename T>
+struct __attribute__((aligned(4 * sizeof(T)))) RWS {
+    T r, w, s, d;
+};
+
+// s_i = w_i + beta s_{i-1} and r_{i+1} = r_i - alpha s_i of one row, in the one
+// order used both by the row's owner and where its u_{i+1} = d r_{i+1} is
+// gathered
+template <typename T>
+__device__ __forceinline__ T next_r(const RWS<T> &q, T alpha, T beta, T &s) {
+    s = fma(beta, q.s, q.w);
+    return fma(-alpha, s, q.r);
+}
+
+// partial-sum slots of one launch: gamma, delta, r.r, kSpmvMaxBlocks each
+constexpr int kCGPart = 3 * kSpmvMaxBlocks;
+
+// the state the first launch gathers: r = b, w = s = 0, d = D^-1
+template <typename T>
+__global__ __launch_bounds__(kCGThreads) void cg_init(int n, const T *__restrict__ b,
+                                                      const T *__restrict__ dinv,
+                                                      RWS<T> *__restrict__ g) {
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x)
+        g[j] = RWS<T>{b[j], (T)0, (T)0, dinv[j]};
+}
+
+// after the first launch: the target from |b| and the done flag
 __global__ __launch_bounds__(64) void cg_init_finish(int nb, const double *part, double rtol,
                                                      double atol, CGScal *sc, int *done) {
     __shared__ double lds[2];
-    const double rz = sum_partials(part, nb, lds);
-    const double rr = sum_partials(part + kCGBlocks, nb, lds);
+    const double rr = sum_partials(part + 2 * kSpmvMaxBlocks, nb, lds);
     if (threadIdx.x == 0) {
         const double target = fmin(rtol * sqrt(rr), atol);
-        sc->rho[0] = 0.0;
-        sc->rho[1] = 1.0;  // previous rho of the first iteration (its beta is 0)
         sc->rr = rr;
         sc->target = target;
         sc->its = 0.0;
@@ -462,13 +490,15 @@ __global__ __launch_bounds__(64) void cg_init_finish(int nb, const double *part,
 }
 
 // Entries e, e + G, ..., e + (kSpmvU - 1) G of a row ending at e1 (those past
-// the end get column -1): columns and values, then the gathered (z, p) pairs.
-constexpr int kSpmvU = 8;
+// the end get column -1): columns and values, then the gathered row states.
+// Four at a time: a gathered state is four values, and eight kept the kernel
+// at over 200 VGPRs (two waves per SIMD).
+constexpr int kSpmvU = 4;
 template <int G, bool NT, typename T>
 __device__ __forceinline__ void load_chunk(int e, int e1, const int32_t *__restrict__ col,
                                            const T *__restrict__ val,
-                                           const ZP<T> *__restrict__ wold, int (&c)[kSpmvU],
-                                           T (&v)[kSpmvU], ZP<T> (&w)[kSpmvU]) {
+                                           const RWS<T> *__restrict__ gold, int (&c)[kSpmvU],
+                                           T (&v)[kSpmvU], RWS<T> (&w)[kSpmvU]) {
 #pragma unroll
     for (int k = 0; k < kSpmvU; ++k) {
         const int ek = e + k * G;
@@ -481,32 +511,31 @@ __device__ __forceinline__ void load_chunk(int e, int e1, const int32_t *__restr
         }
     }
 #pragma unroll
-    for (int k = 0; k < kSpmvU; ++k) w[k] = c[k] >= 0 ? wold[c[k]] : ZP<T>{(T)0, (T)0};
+    for (int k = 0; k < kSpmvU; ++k)
+        w[k] = c[k] >= 0 ? gold[c[k]] : RWS<T>{(T)0, (T)0, (T)0, (T)0};
 }
 
-// One CG iteration's first half.  From the previous update's partials:
-// rho = r.z and r.r (convergence test); beta = rho / rho_prev (0 on the first
-// iteration); the new direction p_new = z + beta p_old is formed where the
-// SpMV gathers it (from the pairs wold = (z, p_old)), q = S p_new, p_new goes
-// to wnew[r].p and the rows' p_new . q to partial.  rho is double-buffered by
-// parity: every workgroup reads rho[par ^ 1] (the previous one) and workgroup
-// 0 writes rho[par].
-//
+// One launch of the iteration.  mode 0: the start (alpha = beta = 0: x = 0,
+// r_0 = b, w_0 = S u_0 and its partials); mode 1: the first iteration
+// (beta = 0); mode 2: the others.  From the predecessor's partials pin:
+// gamma_i, delta_i and r_i.r_i (the convergence test), then alpha_i and beta_i.
 // G lanes per row; each lane takes its entries e, e + G, ... kSpmvU at a
 // time, all their loads in flight together (the summation order is that of
-// one entry at a time).  Nothing loaded depends on beta, so the first chunk
-// is requested before the partials are summed, and each row's first chunk and
-// the next row's pointers before the previous row's lane reduction.  NT: the
-// matrix streams past the caches (nontemporal loads), for matrices too large
-// to stay cache-resident between iterations, so that the gathered pairs stay.
+// one entry at a time).  The first chunk is requested before the partials
+// are summed, and each row's first chunk and the next row's pointers before
+// the previous row's lane reduction.  NT: the matrix streams past the caches
+// (nontemporal loads), for matrices too large to stay cache-resident between
+// iterations, so that the gathered states stay.
 template <int G, bool NT, typename T>
-__global__ __launch_bounds__(256) void spmv_dir(int n, const int32_t *__restrict__ rowptr,
-                                                const int32_t *__restrict__ col,
-                                                const T *__restrict__ val,
-                                                const ZP<T> *__restrict__ wold,
-                                                ZP<T> *__restrict__ wnew, T *__restrict__ q,
-                                                int nb2, const double *part2, double *partial,
-                                                CGScal *sc, int *done, int first, int par) {
+__global__ __launch_bounds__(256) void cg_step(int n, const int32_t *__restrict__ rowptr,
+                                               const int32_t *__restrict__ col,
+                                               const T *__restrict__ val,
+                                               const RWS<T> *__restrict__ gold,
+                                               RWS<T> *__restrict__ gnew, T *__restrict__ x,
+                                               T *__restrict__ p, int nbp,
+                                               const double *__restrict__ pin,
+                                               double *__restrict__ pout, CGScal *sc, int *done,
+                                               int mode, int par) {
     __shared__ double lds[16];
     const int groups = 256 / G;
     const int g = threadIdx.x / G, l = threadIdx.x % G;
@@ -523,37 +552,80 @@ __global__ __launch_bounds__(256) void spmv_dir(int n, const int32_t *__restrict
     }
     int c[kSpmvU];
     T v[kSpmvU];
-    ZP<T> w[kSpmvU];
-    load_chunk<G, NT>(e, e1, col, val, wold, c, v, w);
-    if (*done) return;
-    const double rz = sum_partials(part2, nb2, lds);
-    const double rr = sum_partials(part2 + kCGBlocks, nb2, lds);
-    if (sqrt(rr) <= sc->target || rr == 0.0) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            sc->rr = rr;
-            *done = 1;
+    RWS<T> w[kSpmvU];
+    load_chunk<G, NT>(e, e1, col, val, gold, c, v, w);
+    T alpha = (T)0, beta = (T)0;
+    // the row's own state, x and p, requested with its first chunk
+    RWS<T> own{};
+    T xo = (T)0, po = (T)0;
+    if (l == 0 && r < n) {
+        own = gold[r];
+        if (mode != 0) {
+            xo = x[r];
+            po = p[r];
         }
-        return;
     }
-    const T beta = first ? (T)0 : (T)(rz / sc->rho[par ^ 1]);
-    double dot = 0.0;
+    if (mode != 0) {
+        if (*done) return;
+        double sums[3];
+        sum_partials3(pin, nbp, lds, sums);
+        const double gam = sums[0], del = sums[1], rr = sums[2];
+        const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+        if (sqrt(rr) <= sc->target || rr == 0.0) {
+            if (lead) {
+                sc->rr = rr;
+                *done = 1;
+            }
+            return;
+        }
+        const double b64 = mode == 1 ? 0.0 : gam / sc->gam[par ^ 1];
+        const double den = mode == 1 ? del : del - b64 * gam / sc->alpha[par ^ 1];
+        if (!(den > 0.0)) {  // breakdown (S is positive semidefinite)
+            if (lead) {
+                sc->rr = rr;
+                *done = 2;
+            }
+            return;
+        }
+        const double a64 = gam / den;
+        alpha = (T)a64;
+        beta = (T)b64;
+        if (lead) {
+            sc->gam[par] = gam;
+            sc->alpha[par] = a64;
+            sc->rr = rr;
+            sc->its += 1.0;
+        }
+    }
+    double dg = 0.0, dd = 0.0, dr = 0.0;
     while (r < n) {
         T acc = (T)0;
         for (;;) {
 #pragma unroll
-            for (int k = 0; k < kSpmvU; ++k)
-                if (c[k] >= 0) acc = fma(v[k], fma(beta, w[k].p, w[k].z), acc);
+            for (int k = 0; k < kSpmvU; ++k) {
+                T sk;
+                const T uk = w[k].d * next_r(w[k], alpha, beta, sk);
+                if (c[k] >= 0) acc = fma(v[k], uk, acc);
+            }
             e += kSpmvU * G;
             if (e >= e1) break;
-            load_chunk<G, NT>(e, e1, col, val, wold, c, v, w);
+            load_chunk<G, NT>(e, e1, col, val, gold, c, v, w);
         }
         const int rc = r;
-        const ZP<T> wr = wold[rc];
+        const RWS<T> cur = own;
+        const T xc = xo, pc = po;
         r += stride;
         e = en;
         e1 = en1;
         if (r < n) {
-            load_chunk<G, NT>(e, e1, col, val, wold, c, v, w);
+            load_chunk<G, NT>(e, e1, col, val, gold, c, v, w);
+            if (l == 0) {
+                own = gold[r];
+                if (mode != 0) {
+                    xo = x[r];
+                    po = p[r];
+                }
+            }
             if (r + stride < n) {
                 en = rowptr[r + stride] + l;
                 en1 = rowptr[r + stride + 1];
@@ -561,79 +633,45 @@ __global__ __launch_bounds__(256) void spmv_dir(int n, const int32_t *__restrict
         }
         for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
         if (l == 0) {
-            const T pr = fma(beta, wr.p, wr.z);
-            wnew[rc].p = pr;
-            q[rc] = acc;
-            dot = fma((double)pr, (double)acc, dot);
+            // p_i = u_i + beta p_{i-1} (the start leaves p = u_0; x = 0)
+            const T pj = fma(beta, pc, cur.d * cur.r);
+            T sj;
+            const T rn = next_r(cur, alpha, beta, sj);
+            const T un = cur.d * rn;
+            x[rc] = mode == 0 ? (T)0 : fma(alpha, pj, xc);
+            p[rc] = pj;
+            gnew[rc] = RWS<T>{rn, acc, sj, cur.d};
+            dg = fma((double)rn, (double)un, dg);
+            dd = fma((double)acc, (double)un, dd);
+            dr = fma((double)rn, (double)rn, dr);
         }
     }
-    const double t = block_sum(dot, lds);
-    if (threadIdx.x == 0) partial[blockIdx.x] = t;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        sc->rho[par] = rz;
-        sc->rr = rr;
+    // the three block sums (wave sums, then the waves in order) behind one barrier
+    dg = wave_sum(dg);
+    dd = wave_sum(dd);
+    dr = wave_sum(dr);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+        lds[wv] = dg;
+        lds[4 + wv] = dd;
+        lds[8 + wv] = dr;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double t = 0.0;
+        for (int k = 0; k < nw; ++k) t += lds[4 * threadIdx.x + k];
+        pout[threadIdx.x * kSpmvMaxBlocks + blockIdx.x] = t;
     }
 }
 
-// alpha = rho / (p.q); x += alpha p; r -= alpha q; z = D^-1 r into w[j].z;
-// partials r.z, r.r
-template <typename T>
-__global__ __launch_bounds__(kCGThreads) void cg_update(int n, int nb1, const double *part1,
-                                                        ZP<T> *w, const T *__restrict__ q,
-                                                        const T *__restrict__ dinv, T *x, T *r,
-                                                        double *part2, CGScal *sc, int *done,
-                                                        int par) {
-    __shared__ double lds[16];
-    // the first element's operands are requested before the partials are summed
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    T pj = (T)0, qj = (T)0, rj = (T)0, xj = (T)0, dj = (T)0;
-    if (j < n) {
-        pj = w[j].p;
-        qj = q[j];
-        rj = r[j];
-        xj = x[j];
-        dj = dinv[j];
-    }
-    if (*done) return;
-    const double pq = sum_partials(part1, nb1, lds);
-    if (!(pq > 0.0)) {  // breakdown (S is positive semidefinite)
-        if (blockIdx.x == 0 && threadIdx.x == 0) *done = 2;
-        return;
-    }
-    const T alpha = (T)(sc->rho[par] / pq);
-    double rz = 0.0, rr = 0.0;
-    for (bool head = true; j < n; j += gridDim.x * blockDim.x, head = false) {
-        if (!head) {
-            pj = w[j].p;
-            qj = q[j];
-            rj = r[j];
-            xj = x[j];
-            dj = dinv[j];
-        }
-        x[j] = fma(alpha, pj, xj);
-        rj = fma(-alpha, qj, rj);
-        r[j] = rj;
-        const T zj = dj * rj;
-        w[j].z = zj;
-        rz = fma((double)rj, (double)zj, rz);
-        rr = fma((double)rj, (double)rj, rr);
-    }
-    double t1 = block_sum(rz, lds);
-    double t2 = block_sum(rr, lds);
-    if (threadIdx.x == 0) {
-        part2[blockIdx.x] = t1;
-        part2[kCGBlocks + blockIdx.x] = t2;
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) sc->its += 1.0;
-}
-
-// convergence test on the last update's partials (end of a chunk of
+// convergence test on the last launch's partials (end of a chunk of
 // iterations, so that a converged last iteration is reported as such)
-__global__ __launch_bounds__(64) void cg_check(int nb2, const double *part2, CGScal *sc,
+__global__ __launch_bounds__(64) void cg_check(int nb, const double *part, CGScal *sc,
                                                int *done) {
     __shared__ double lds[2];
     if (*done) return;
-    const double rr = sum_partials(part2 + kCGBlocks, nb2, lds);
+    const double rr = sum_partials(part + 2 * kSpmvMaxBlocks, nb, lds);
     if (threadIdx.x == 0) {
         sc->rr = rr;
         if (sqrt(rr) <= sc->target || rr == 0.0) *done = 1;
@@ -663,39 +701,34 @@ static void launch_spmv(hipStream_t st, const SchurCSR &S, const T *val, const T
 
 // e0, e1: events recorded at the dispatch's own start and end (may be null)
 template <typename T>
-static void launch_spmv_dir(hipStream_t st, const SchurCSR &S, const T *val, const ZP<T> *wold,
-                            ZP<T> *wnew, T *q, int nb2, const double *part2, double *partial,
-                            CGScal *sc, int *done, int first, int par, unsigned &nb_out,
-                            hipEvent_t e0, hipEvent_t e1) {
+static void launch_cg_step(hipStream_t st, const SchurCSR &S, const T *val, const RWS<T> *gold,
+                           RWS<T> *gnew, T *x, T *p, int nbp, const double *pin, double *pout,
+                           CGScal *sc, int *done, int mode, int par, unsigned nb, hipEvent_t e0,
+                           hipEvent_t e1) {
     const int n = S.n;
     const int G = lanes_per_row(S);
-    // about as many workgroups as stay resident at once (three per compute
-    // unit at this kernel's register use): each lane group then walks several
-    // rows with the next row's loads in flight
-    const unsigned nb = std::min<unsigned>(kSpmvDirBlocks, grid_for(n, 256 / G));
-    nb_out = nb;
     const int32_t *rp = S.rowptr.get(), *cl = S.col.get();
     // matrices beyond this size do not stay cache-resident between iterations
     const bool nt = ((double)sizeof(T) + 4.0) * (double)S.nnz > 96.0 * (1 << 20);
-#define OTIP_SPMV_DIR(GG, NT)                                                                  \
-    hipExtLaunchKernelGGL(spmv_dir<GG, NT, T>, dim3(nb), dim3(256), 0, st, e0, e1, 0, n, rp,   \
-                          cl, val, wold, wnew, q, nb2, part2, partial, sc, done, first, par)
+#define OTIP_CG_STEP(GG, NT)                                                                   \
+    hipExtLaunchKernelGGL(cg_step<GG, NT, T>, dim3(nb), dim3(256), 0, st, e0, e1, 0, n, rp, cl, \
+                          val, gold, gnew, x, p, nbp, pin, pout, sc, done, mode, par)
     if (nt) {
         switch (G) {
-            case 64: OTIP_SPMV_DIR(64, true); break;
-            case 32: OTIP_SPMV_DIR(32, true); break;
-            case 16: OTIP_SPMV_DIR(16, true); break;
-            default: OTIP_SPMV_DIR(8, true); break;
+            case 64: OTIP_CG_STEP(64, true); break;
+            case 32: OTIP_CG_STEP(32, true); break;
+            case 16: OTIP_CG_STEP(16, true); break;
+            default: OTIP_CG_STEP(8, true); break;
         }
     } else {
         switch (G) {
-            case 64: OTIP_SPMV_DIR(64, false); break;
-            case 32: OTIP_SPMV_DIR(32, false); break;
-            case 16: OTIP_SPMV_DIR(16, false); break;
-            default: OTIP_SPMV_DIR(8, false); break;
+            case 64: OTIP_CG_STEP(64, false); break;
+            case 32: OTIP_CG_STEP(32, false); break;
+            case 16: OTIP_CG_STEP(16, false); break;
+            default: OTIP_CG_STEP(8, false); break;
         }
     }
-#undef OTIP_SPMV_DIR
+#undef OTIP_CG_STEP
 }
 
 // Jacobi inverse diagonal of a caller's CSR matrix, by the rule of schur_diag
@@ -759,59 +792,61 @@ void SchurSolver::spmv(hipStream_t st, const double *x, double *y) {
     OTIP_HIP(hipGetLastError());
 }
 
-// Jacobi-preconditioned CG in storage type T on S x = b.
+// Jacobi-preconditioned CG in storage type T on S x = b (one launch per
+// iteration, the form above).
 template <typename T>
 CGStats SchurSolver::pcg_impl(hipStream_t st, const T *val, const T *dinv, const T *b, T *x,
-                              double rtol, double atol, int maxit, DBuf<T> &r_, DBuf<T> &p_,
-                              DBuf<T> &q_) {
+                              double rtol, double atol, int maxit, DBuf<T> &p_, DBuf<T> &g_) {
     const int n = S.n;
     CGStats out;
-    r_.need(n);
-    p_.need(4 * (size_t)n);  // two (z, p) pair arrays, alternating by iteration parity
-    q_.need(n);
-    part_.need(kSpmvMaxBlocks + 2 * kCGBlocks);
+    T *p = p_.need(n);
+    g_.need(8 * (size_t)n);  // two row-state arrays, alternating by launch parity
+    part_.need(2 * (size_t)kCGPart);
     scal_.need(sizeof(CGScal) / sizeof(double));
     flag_.need(1);
-    double *part1 = part_.get();
-    double *part2 = part_.get() + kSpmvMaxBlocks;
+    double *part[2] = {part_.get(), part_.get() + kCGPart};
     CGScal *sc = (CGScal *)scal_.get();
     int *done = flag_.get();
-    ZP<T> *W[2] = {(ZP<T> *)p_.get(), (ZP<T> *)(p_.get() + 2 * (size_t)n)};
+    RWS<T> *G[2] = {(RWS<T> *)g_.get(), (RWS<T> *)(g_.get() + 4 * (size_t)n)};
+    // about as many workgroups as stay resident at once: each lane group then
+    // walks several rows with the next row's loads in flight
+    const unsigned nb =
+        std::min<unsigned>(kSpmvDirBlocks, grid_for(n, 256 / lanes_per_row(S)));
     const unsigned nbv = std::min<unsigned>(kCGBlocks, grid_for(n, kCGThreads));
-    hipLaunchKernelGGL((cg_init<T>), dim3(nbv), dim3(kCGThreads), 0, st, n, b, dinv, x, r_.get(),
-                       W[1], part2);
-    hipLaunchKernelGGL(cg_init_finish, dim3(1), dim3(64), 0, st, (int)nbv, part2, rtol, atol, sc,
+    hipLaunchKernelGGL((cg_init<T>), dim3(nbv), dim3(kCGThreads), 0, st, n, b, dinv, G[1]);
+    launch_cg_step<T>(st, S, val, G[1], G[0], x, p, (int)nb, part[1], part[0], sc, done, 0, 0,
+                      nb, nullptr, nullptr);
+    hipLaunchKernelGGL(cg_init_finish, dim3(1), dim3(64), 0, st, (int)nb, part[0], rtol, atol, sc,
                        done);
     OTIP_HIP(hipGetLastError());
     int chunk = std::min(4, std::max(1, maxit));
-    int launched = 0;
+    int launched = 1;  // launch 0 was the start
     CGScal hs{};
     int hdone = 0;
     double its_prev = 0.0, rr_prev = -1.0;  // at the previous check
-    // algorithmic bytes of one fused launch: values and columns, row pointers,
-    // the two gathered vectors read once, the new direction and q written
+    // algorithmic bytes of one launch: values and columns, row pointers, each
+    // row's state read once (gathered and by its owner) and written, x and p
+    // read and written
     const double bytes = ((double)sizeof(T) + 4.0) * (double)S.nnz +
-                         (4.0 + 4.0 * (double)sizeof(T)) * n;
+                         (4.0 + 12.0 * (double)sizeof(T)) * n;
     while (true) {
         for (int c = 0; c < chunk; ++c) {
             const int par = launched & 1;
-            unsigned nbs;
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (timer) timer->arm(bytes, &e0, &e1);
-            launch_spmv_dir<T>(st, S, val, W[par ^ 1], W[par], q_.get(), (int)nbv, part2, part1,
-                               sc, done, launched == 0 ? 1 : 0, par, nbs, e0, e1);
-            hipLaunchKernelGGL((cg_update<T>), dim3(nbv), dim3(kCGThreads), 0, st, n, (int)nbs,
-                               part1, W[par], q_.get(), dinv, x, r_.get(), part2, sc, done, par);
+            launch_cg_step<T>(st, S, val, G[par ^ 1], G[par], x, p, (int)nb, part[par ^ 1],
+                              part[par], sc, done, launched == 1 ? 1 : 2, par, nb, e0, e1);
             ++launched;
         }
-        hipLaunchKernelGGL(cg_check, dim3(1), dim3(64), 0, st, (int)nbv, part2, sc, done);
+        hipLaunchKernelGGL(cg_check, dim3(1), dim3(64), 0, st, (int)nb, part[(launched - 1) & 1],
+                           sc, done);
         OTIP_HIP(hipGetLastError());
         OTIP_HIP(hipMemcpyAsync(&hs, sc, sizeof(CGScal), hipMemcpyDeviceToHost, st));
         OTIP_HIP(hipMemcpyAsync(&hdone, done, sizeof(int), hipMemcpyDeviceToHost, st));
         OTIP_HIP(hipStreamSynchronize(st));
         // launches past the last executed iteration found the work done
         if (timer) timer->collect((size_t)std::max(0.0, hs.its - its_prev));
-        if (hdone || launched >= maxit) break;
+        if (hdone || launched - 1 >= maxit) break;
         // next chunk: the iterations still needed at the rate the residual
         // fell over the last chunk (plus a tenth), else twice the last chunk;
         // launches past convergence return at once but still cost a dispatch
@@ -825,7 +860,7 @@ CGStats SchurSolver::pcg_impl(hipStream_t st, const T *val, const T *dinv, const
         }
         rr_prev = hs.rr;
         its_prev = hs.its;
-        chunk = std::min(next, maxit - launched);
+        chunk = std::min(next, maxit - (launched - 1));
         if (chunk <= 0) break;
     }
     out.iterations = (int)hs.its;
@@ -836,7 +871,7 @@ CGStats SchurSolver::pcg_impl(hipStream_t st, const T *val, const T *dinv, const
 
 CGStats SchurSolver::pcg(hipStream_t st, const double *b, double *x, double rtol, double atol,
                          int maxit) {
-    return pcg_impl<double>(st, S.val.get(), S.dinv.get(), b, x, rtol, atol, maxit, r_, p_, q_);
+    return pcg_impl<double>(st, S.val.get(), S.dinv.get(), b, x, rtol, atol, maxit, p_, g_);
 }
 
 __global__ void to_f32(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
@@ -900,7 +935,7 @@ CGStats SchurSolver::pcg_mixed(hipStream_t st, const double *b, double *x, doubl
         if (out.iterations >= maxit) break;
         const double inner = std::max(1e-4, 0.5 * target / rn);
         CGStats cs = pcg_impl<float>(st, val32_.get(), dinv32_.get(), r32, d32, inner, 1e300,
-                                     maxit - out.iterations, rf2_, pf_, qf_);
+                                     maxit - out.iterations, pf_, gf_);
         out.iterations += std::max(cs.iterations, 1);
         hipLaunchKernelGGL(add_f32, dim3(nbv), dim3(256), 0, st, n, d32, x);
     }
