@@ -96,7 +96,8 @@ class Scanner {
     int subset_m_ = -1;
     int64_t subset_nnz_ = 0;
     uint64_t guess_key_ = 0;  // cutoff key for the first pass's compaction (0: none)
-    double guess_f_ = 0.5;    // the cutoff as a fraction of the last k-th selected value
+    double guess_f_ = 0.5;    // with fewer than 4 kmax candidates kept: the next cutoff as a
+                              // fraction of the last candidate's value
 };
 
 // ---------------------------------------------------------- fixed-order reductions

@@ -168,8 +168,10 @@ struct PriceArgs {
     int shift;
     uint64_t prefix;
     unsigned long long *hist;
-    // compaction mode: every key <= key_max
+    // compaction mode: every key <= key_max; rkey is the double whose key is
+    // key_max (a group whose smallest r is above it has no candidate)
     uint64_t key_max;
+    double rkey;
     // no key of interest belongs to an r above rcut (the double whose key is
     // the largest one of interest, or +inf): groups with no r <= rcut skip
     double rcut;
@@ -181,7 +183,8 @@ struct PriceArgs {
 // the per-variable part of a pricing pass (all lanes of the wave call it)
 template <int MODE>
 __device__ __forceinline__ void price_one(const PriceArgs &a, int i, int j, double r,
-                                          unsigned int *lh, WaveStage<2> &stg) {
+                                          unsigned int *lh, WaveStage<2> &stg,
+                                          bool group_cand = true) {
     {
         const int pshift = a.shift + 12;
         const bool neg = r < 0.0 && r <= a.rcut;
@@ -193,7 +196,8 @@ __device__ __forceinline__ void price_one(const PriceArgs &a, int i, int j, doub
             if (take && (pshift >= 64 || (key >> pshift) == a.prefix))
                 atomicAdd(&lh[(key >> a.shift) & 4095u], 1u);
         }
-        if (MODE != 0) stg.push(take && key <= a.key_max, key, idx);
+        // group_cand is wave-uniform: no lane's group of four has an r <= rkey
+        if (MODE != 0 && group_cand) stg.push(take && key <= a.key_max, key, idx);
     }
 }
 
@@ -229,10 +233,13 @@ __global__ __launch_bounds__(kScanBlock) void price_pass(PriceArgs a) {
         const double r3 = (cost_of<K>(rd, t3) - rd.y) - t3.z;
         const double lo = fmin(fmin(r0, r1), fmin(r2, r3));
         if (__ballot(lo < 0.0 && lo <= a.rcut) == 0ull) continue;
-        price_one<MODE>(a, i, j, r0, lh, stg);
-        price_one<MODE>(a, i, j + 1, r1, lh, stg);
-        price_one<MODE>(a, i, j + 2, r2, lh, stg);
-        price_one<MODE>(a, i, j + 3, r3, lh, stg);
+        // the first pass histograms every negative; its candidate compaction
+        // only matters where some r is at most the guessed cutoff
+        const bool cand = MODE != 2 || __ballot(lo <= a.rkey) != 0ull;
+        price_one<MODE>(a, i, j, r0, lh, stg, cand);
+        price_one<MODE>(a, i, j + 1, r1, lh, stg, cand);
+        price_one<MODE>(a, i, j + 2, r2, lh, stg, cand);
+        price_one<MODE>(a, i, j + 3, r3, lh, stg, cand);
     }
     for (; j < j1; ++j) {
         const JEntry t = ldj(jt, j);
@@ -465,6 +472,7 @@ PriceResult Scanner::price(hipStream_t st, int m, int n, const int32_t *xs, cons
     a.prefix = 0;
     a.rcut = INFINITY;
     a.key_max = guessing ? guess_key_ : 0;
+    a.rkey = guessing ? rcut_of_key(guess_key_) : -INFINITY;
     a.count = cnt_.get();
     a.out_key = ck_.get();
     a.out_idx = ci_.get();
@@ -539,6 +547,7 @@ PriceResult Scanner::price(hipStream_t st, int m, int n, const int32_t *xs, cons
         OTIP_HIP(hipMemsetAsync(cnt_.get(), 0, sizeof(unsigned long long), st));
         a.key_max = key_max;
         a.rcut = key_max == ~0ull ? INFINITY : rcut_of_key(key_max);
+        a.rkey = a.rcut;
         a.count = cnt_.get();
         a.out_key = ck_.get();
         a.out_idx = ci_.get();
@@ -568,13 +577,17 @@ PriceResult Scanner::price(hipStream_t st, int m, int n, const int32_t *xs, cons
     hipLaunchKernelGGL(decode_selection, dim3(grid_for(k, 256)), dim3(256), 0, st, k, m,
                        ck_.get(), ci_.get(), oi, oj, orr, oidx);
     OTIP_HIP(hipGetLastError());
-    // next call's cutoff: a fraction guess_f_ of the k-th selected value
-    // (nearer to 0, so that the next iterate's k smallest are likely below it)
-    uint64_t kth = 0;
-    OTIP_HIP(hipMemcpyAsync(&kth, ck_.get() + (k - 1), sizeof(kth), hipMemcpyDeviceToHost, st));
+    // next call's cutoff: the key that admits about 4 kmax of this call's
+    // candidates (the first pass keeps up to 16 kmax, so the next iterate's
+    // distribution may move either way); with fewer candidates than that, a
+    // fraction guess_f_ of the last one's value (nearer to 0: more of them)
+    const int64_t want = std::min<int64_t>(4 * (int64_t)kmax, (int64_t)cap);
+    uint64_t gk = 0;
+    OTIP_HIP(hipMemcpyAsync(&gk, ck_.get() + (want - 1), sizeof(gk), hipMemcpyDeviceToHost, st));
     OTIP_HIP(hipStreamSynchronize(st));
-    const double rk = rcut_of_key(kth);
-    guess_key_ = (std::isfinite(rk) && rk < 0.0) ? host_dkey(guess_f_ * rk) : 0;
+    double rg = rcut_of_key(gk);
+    if (want < 4 * (int64_t)kmax) rg *= guess_f_;
+    guess_key_ = (std::isfinite(rg) && rg < 0.0) ? host_dkey(rg) : 0;
     res.count = k;
     return res;
 }
