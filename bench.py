@@ -43,6 +43,10 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 # valid only for the kernel source it was measured on (the SHA-256 of the text
 # of the listed functions).
 KERNEL_TRAFFIC = {
+    ("cg_step", "c3"): {"source": "paper_2206_11009_amd/csrc/schur.hip",
+                        "functions": ["load_chunk", "cg_step"],
+                        "sha256": "d40ada58b6ba7e92d40721e9d0e7ea37fbd37063db0c70e3b728a3eb4f43f261",
+                        "bytes_per_launch": 10974378.1},
     ("ldl_update", "c3"): {"source": "paper_2206_11009_amd/csrc/dense.hip",
                            "functions": ["ldl_update"],
                            "sha256": "eb4f5649549eddf3c31f346b038b09527de249dd8e9a5093e39ba6dbcbbbaa36",

@@ -183,12 +183,12 @@ typedef struct otip_info {
     int64_t pricing_scans;     /* full m*n passes of the pricing and certificate scans */
     /* with params.profile: event-timed launches of the hot kernels, sampled so
        that the events do not slow the solve */
-    int64_t spmv_launches;     /* Schur SpMV launches inside CG (fused with the direction
-                                  update p = z + beta p), those of the first of every 8 CG
-                                  solves */
+    int64_t spmv_launches;     /* CG iteration launches (Schur SpMV with the vector updates
+                                  and the dot products, one per iteration), those of the
+                                  first of every 8 CG solves */
     double spmv_ms;            /* their summed durations */
-    double spmv_bytes;         /* their algorithmic bytes: 12 nnz + 36 n per launch (FP64;
-                                  8 nnz + 20 n for the FP32 inner solves) */
+    double spmv_bytes;         /* their algorithmic bytes: 12 nnz + 100 n per launch (FP64;
+                                  8 nnz + 52 n for the FP32 inner solves) */
     int64_t price_launches;    /* pricing-pass launches of the first of every 8 pricing
                                   calls */
     double price_ms;
@@ -364,8 +364,8 @@ int otip_schur(otip_ctx *ctx, int32_t m, int32_t n, int64_t psi, const int64_t *
  * solves S x = b for a symmetric positive (semi)definite n x n CSR matrix with
  * the Jacobi preconditioner, stopping when ||b - S x||_2 <= rtol ||b||_2 (as
  * the iteration's recurrence tracks it) or after maxit iterations.  Each
- * iteration is one fused launch (SpMV with the direction update) and one
- * vector update, as inside otip_solve.
+ * iteration is one launch (the single-reduction form of CG: SpMV, vector
+ * updates and the three dot products together), as inside otip_solve.
  *   rowptr (n+1 int32), colidx (nnz int32, in [0, n)), vals (nnz), b (n):
  *   DEVICE, read only (copied; rowptr is validated on the host, colidx on the
  *   device).  x (n): DEVICE, output (the iteration starts from 0).  A row
@@ -375,9 +375,9 @@ int otip_schur(otip_ctx *ctx, int32_t m, int32_t n, int64_t psi, const int64_t *
  *   precision: OTIP_FP64, or OTIP_MIXED (FP32 CG inside FP64 iterative
  *   refinement on the FP64 residual).
  *   iterations, res_norm: HOST, optional.  spmv_stats: HOST, optional, 3
- *   values: fused SpMV launches that did work, their mean duration in seconds
+ *   values: iteration launches that did work, their mean duration in seconds
  *   (events recorded at the dispatches' own start and end), and their
- *   algorithmic bytes per launch ((w + 4) nnz + (4 + 4 w) n, w = 8 in FP64
+ *   algorithmic bytes per launch ((w + 4) nnz + (4 + 12 w) n, w = 8 in FP64
  *   and 4 in the FP32 inner solves).
  * Returns OTIP_OK when converged, OTIP_EMAXITER when maxit was reached,
  * OTIP_ENUMERIC on a breakdown (p'Sp <= 0).

@@ -1,4 +1,5 @@
-"""Bandwidth of the Newton step's fused Schur SpMV at large n.
+"""Bandwidth of the Newton step's CG iteration (one launch: Schur SpMV with the
+vector updates) at large n.
 
     python -m paper_2206_11009_amd.pcg_bench [--side 256] [--kappa 10]
         [--pattern random|local] [--maxit 200] [--precision 0|1]
@@ -12,9 +13,9 @@ kappa): "random" draws each row's targets uniformly (nnz(S_M) close to the sum
 of squared row degrees, the largest pattern for that support size), "local"
 takes the targets nearest to the source pixel (a banded pattern like the
 cost-driven supports of the method).  theta is log-uniform over 10^[-3, 3].
-Prints one JSON line: sizes, the fused SpMV launches that did work, their mean
+Prints one JSON line: sizes, the iteration launches that did work, their mean
 duration from events recorded at the dispatches themselves, and the
-algorithmic GB/s ((w + 4) nnz + (4 + 4 w) n bytes per launch) against the 8
+algorithmic GB/s ((w + 4) nnz + (4 + 12 w) n bytes per launch) against the 8
 TB/s HBM peak.
 """
 from __future__ import annotations
