@@ -232,8 +232,8 @@ def rooflines(infos, cfg):
     pr_ms = sum(i["price_ms"] for i in infos)
     pr_n = sum(i["price_launches"] for i in infos)
     pr_e = sum(i["price_elems"] for i in infos)
-    spmv = {"bound": "hbm", "kernel": "cg_step (one Jacobi-PCG iteration: Schur SpMV with the "
-            "vector updates and a single reduction)",
+    spmv = {"bound": "hbm", "kernel": "CG iteration (cg_step: Schur SpMV with the vector updates "
+            "and a single reduction; spmv_dir + cg_update for a Schur matrix beyond 96 MB)",
             "achieved": spmv_b / max(spmv_ms, 1e-12) / 1e6, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "avg_launch_us": 1e3 * spmv_ms / max(spmv_n, 1), "launches": spmv_n,
             "total_ms": spmv_ms, "traffic": measured_traffic("cg_step", cfg),

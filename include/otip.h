@@ -188,7 +188,9 @@ typedef struct otip_info {
                                   first of every 8 CG solves */
     double spmv_ms;            /* their summed durations */
     double spmv_bytes;         /* their algorithmic bytes: 12 nnz + 100 n per launch (FP64;
-                                  8 nnz + 52 n for the FP32 inner solves) */
+                                  8 nnz + 52 n for the FP32 inner solves); a Schur matrix
+                                  beyond 96 MB takes two launches per iteration, of which
+                                  the SpMV is timed: 12 nnz + 36 n (8 nnz + 20 n) */
     int64_t price_launches;    /* pricing-pass launches of the first of every 8 pricing
                                   calls */
     double price_ms;
@@ -363,9 +365,10 @@ int otip_schur(otip_ctx *ctx, int32_t m, int32_t n, int64_t psi, const int64_t *
  * the Schur complement; tolerances of Section 5.2), on a caller's matrix:
  * solves S x = b for a symmetric positive (semi)definite n x n CSR matrix with
  * the Jacobi preconditioner, stopping when ||b - S x||_2 <= rtol ||b||_2 (as
- * the iteration's recurrence tracks it) or after maxit iterations.  Each
- * iteration is one launch (the single-reduction form of CG: SpMV, vector
- * updates and the three dot products together), as inside otip_solve.
+ * the iteration's recurrence tracks it) or after maxit iterations, as inside
+ * otip_solve: one launch per iteration (the single-reduction form of CG:
+ * SpMV, vector updates and the three dot products together), or two for a
+ * matrix that streams from HBM (below).
  *   rowptr (n+1 int32), colidx (nnz int32, in [0, n)), vals (nnz), b (n):
  *   DEVICE, read only (copied; rowptr is validated on the host, colidx on the
  *   device).  x (n): DEVICE, output (the iteration starts from 0).  A row
@@ -378,7 +381,10 @@ int otip_schur(otip_ctx *ctx, int32_t m, int32_t n, int64_t psi, const int64_t *
  *   values: iteration launches that did work, their mean duration in seconds
  *   (events recorded at the dispatches' own start and end), and their
  *   algorithmic bytes per launch ((w + 4) nnz + (4 + 12 w) n, w = 8 in FP64
- *   and 4 in the FP32 inner solves).
+ *   and 4 in the FP32 inner solves).  A matrix whose values and columns
+ *   exceed 96 MB streams from HBM at every iteration: it takes two launches
+ *   per iteration (an SpMV with the direction update, timed here at
+ *   (w + 4) nnz + (4 + 4 w) n bytes, and a vector update).
  * Returns OTIP_OK when converged, OTIP_EMAXITER when maxit was reached,
  * OTIP_ENUMERIC on a breakdown (p'Sp <= 0).
  */

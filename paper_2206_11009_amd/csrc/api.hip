@@ -526,7 +526,7 @@ int otip_pcg(otip_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rowptr, const
             const double w = precision == OTIP_MIXED ? 4.0 : 8.0;
             spmv_stats[0] = (double)t.launches;
             spmv_stats[1] = t.launches ? t.ms * 1e-3 / (double)t.launches : 0.0;
-            spmv_stats[2] = (w + 4.0) * (double)nnz + (4.0 + 12.0 * w) * n;
+            spmv_stats[2] = otip::cg_launch_bytes(w, nnz, n);
         }
     });
     if (rc != OTIP_OK) return rc;

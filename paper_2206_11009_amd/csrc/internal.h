@@ -133,6 +133,18 @@ struct CGStats {
     double res_norm = 0.0;
 };
 
+struct CGScal;  // device-side CG scalars (schur.hip)
+
+// CG on a Schur matrix of nnz values of w bytes: beyond 96 MB of values and
+// columns the matrix streams from HBM at every iteration and the two-launch
+// form runs (an SpMV launch with the direction, an update launch); below, one
+// launch per iteration.  Algorithmic bytes of the timed launch of each form:
+// values and columns, row pointers, and the vectors read and written once.
+inline bool cg_streams(double w, int64_t nnz) { return (w + 4.0) * (double)nnz > 96.0 * (1 << 20); }
+inline double cg_launch_bytes(double w, int64_t nnz, int n) {
+    return (w + 4.0) * (double)nnz + (cg_streams(w, nnz) ? 4.0 + 4.0 * w : 4.0 + 12.0 * w) * n;
+}
+
 class SchurSolver {
   public:
     LaunchTimer *timer = nullptr;  // SpMV launches inside CG (optional)
@@ -166,6 +178,10 @@ class SchurSolver {
     template <typename T>
     CGStats pcg_impl(hipStream_t st, const T *val, const T *dinv, const T *b, T *x, double rtol,
                      double atol, int maxit, DBuf<T> &p, DBuf<T> &g);
+    template <typename T>
+    CGStats pcg_stream(hipStream_t st, const T *val, const T *dinv, const T *b, T *x,
+                       double rtol, double atol, int maxit, T *r, T *g, double *part,
+                       CGScal *sc, int *done);
     DBuf<int32_t> cnt_, rk_;
     DBuf<double> rth_;
     int64_t psi_ = 0;  // support size of the last symbolic()

@@ -406,11 +406,12 @@ __global__ __launch_bounds__(256) void spmv_rows(int n, const int32_t *__restric
 // alpha_i and beta_i everywhere), and u_{i+1} of a neighbour row is formed
 // where the SpMV gathers that row's (r_i, w_i, s_{i-1}, d).
 
-// Device-side CG scalars.  gamma and alpha are double-buffered by launch
-// parity: a launch reads its predecessor's at [par ^ 1] in every workgroup,
-// and workgroup 0 writes its own at [par].
+// Device-side CG scalars.  gamma and alpha (single-reduction form) and rho
+// (two-launch form) are double-buffered by launch parity: a launch reads its
+// predecessor's at [par ^ 1] in every workgroup, and workgroup 0 writes its
+// own at [par].
 struct CGScal {
-    double gam[2], alpha[2], rr, target, its;
+    double gam[2], alpha[2], rho[2], rr, target, its;
 };
 
 // fixed-order sum of nb per-block partials, computed by wave 0 and broadcast
@@ -524,8 +525,8 @@ __device__ __forceinline__ void load_chunk(int e, int e1, const int32_t *__restr
 // one entry at a time).  The first chunk is requested before the partials
 // are summed, and each row's first chunk and the next row's pointers before
 // the previous row's lane reduction.  NT: the matrix streams past the caches
-// (nontemporal loads), for matrices too large to stay cache-resident between
-// iterations, so that the gathered states stay.
+// (nontemporal loads); the launcher takes this form for cache-resident
+// matrices only (NT false), larger ones take the two-launch form below.
 template <int G, bool NT, typename T>
 __global__ __launch_bounds__(256) void cg_step(int n, const int32_t *__restrict__ rowptr,
                                                const int32_t *__restrict__ col,
@@ -678,6 +679,238 @@ __global__ __launch_bounds__(64) void cg_check(int nb, const double *part, CGSca
     }
 }
 
+// ---- The two-launch form, for matrices that stream from HBM.  There the
+// iteration is bound by the matrix stream and the gathers, and the single-
+// reduction form's four-value row states halve the loads in flight per lane
+// (628 against 438 us per iteration at n = 65536).  Standard CG: an SpMV
+// launch that also forms the direction, and an update launch.
+
+// The preconditioned residual z and the search direction p of one iteration
+// parity, interleaved so that the SpMV gathers both with one load per nonzero.
+template <typename T>
+struct __attribute__((aligned(2 * sizeof(T)))) ZP {
+    T z, p;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kCGThreads) void cg2_init(int n, const T *__restrict__ b,
+                                                      const T *__restrict__ dinv, T *x, T *r,
+                                                      ZP<T> *w, double *part) {
+    __shared__ double lds[16];
+    double rz = 0.0, rr = 0.0;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+        const T bj = b[j];
+        const T zj = dinv[j] * bj;
+        x[j] = (T)0;
+        r[j] = bj;
+        w[j] = ZP<T>{zj, (T)0};  // the first direction is z itself (beta = 0)
+        rz = fma((double)bj, (double)zj, rz);
+        rr = fma((double)bj, (double)bj, rr);
+    }
+    double t1 = block_sum(rz, lds);
+    double t2 = block_sum(rr, lds);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = t1;
+        part[kCGBlocks + blockIdx.x] = t2;
+    }
+}
+
+__global__ __launch_bounds__(64) void cg2_init_finish(int nb, const double *part, double rtol,
+                                                     double atol, CGScal *sc, int *done) {
+    __shared__ double lds[2];
+    const double rz = sum_partials(part, nb, lds);
+    const double rr = sum_partials(part + kCGBlocks, nb, lds);
+    if (threadIdx.x == 0) {
+        const double target = fmin(rtol * sqrt(rr), atol);
+        sc->rho[0] = 0.0;
+        sc->rho[1] = 1.0;  // previous rho of the first iteration (its beta is 0)
+        sc->rr = rr;
+        sc->target = target;
+        sc->its = 0.0;
+        *done = (sqrt(rr) <= target || rr == 0.0) ? 1 : 0;
+    }
+}
+
+// Entries e, e + G, ..., e + (kSpmvU2 - 1) G of a row ending at e1 (those past
+// the end get column -1): columns and values, then the gathered (z, p) pairs
+// (eight at a time: the pairs are half the size of the row states above).
+constexpr int kSpmvU2 = 8;
+template <int G, bool NT, typename T>
+__device__ __forceinline__ void load_chunk2(int e, int e1, const int32_t *__restrict__ col,
+                                           const T *__restrict__ val,
+                                           const ZP<T> *__restrict__ wold, int (&c)[kSpmvU2],
+                                           T (&v)[kSpmvU2], ZP<T> (&w)[kSpmvU2]) {
+#pragma unroll
+    for (int k = 0; k < kSpmvU2; ++k) {
+        const int ek = e + k * G;
+        if (ek < e1) {
+            c[k] = NT ? __builtin_nontemporal_load(col + ek) : col[ek];
+            v[k] = NT ? __builtin_nontemporal_load(val + ek) : val[ek];
+        } else {
+            c[k] = -1;
+            v[k] = (T)0;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kSpmvU2; ++k) w[k] = c[k] >= 0 ? wold[c[k]] : ZP<T>{(T)0, (T)0};
+}
+
+// One CG iteration's first half.  From the previous update's partials:
+// rho = r.z and r.r (convergence test); beta = rho / rho_prev (0 on the first
+// iteration); the new direction p_new = z + beta p_old is formed where the
+// SpMV gathers it (from the pairs wold = (z, p_old)), q = S p_new, p_new goes
+// to wnew[r].p and the rows' p_new . q to partial.  rho is double-buffered by
+// parity: every workgroup reads rho[par ^ 1] (the previous one) and workgroup
+// 0 writes rho[par].
+//
+// G lanes per row; each lane takes its entries e, e + G, ... kSpmvU2 at a
+// time, all their loads in flight together (the summation order is that of
+// one entry at a time).  Nothing loaded depends on beta, so the first chunk
+// is requested before the partials are summed, and each row's first chunk and
+// the next row's pointers before the previous row's lane reduction.  NT: the
+// matrix streams past the caches (nontemporal loads), for matrices too large
+// to stay cache-resident between iterations, so that the gathered pairs stay.
+template <int G, bool NT, typename T>
+__global__ __launch_bounds__(256) void spmv_dir(int n, const int32_t *__restrict__ rowptr,
+                                                const int32_t *__restrict__ col,
+                                                const T *__restrict__ val,
+                                                const ZP<T> *__restrict__ wold,
+                                                ZP<T> *__restrict__ wnew, T *__restrict__ q,
+                                                int nb2, const double *part2, double *partial,
+                                                CGScal *sc, int *done, int first, int par) {
+    __shared__ double lds[16];
+    const int groups = 256 / G;
+    const int g = threadIdx.x / G, l = threadIdx.x % G;
+    const int stride = gridDim.x * groups;
+    int r = blockIdx.x * groups + g;
+    int e = 0, e1 = 0, en = 0, en1 = 0;
+    if (r < n) {
+        e = rowptr[r] + l;
+        e1 = rowptr[r + 1];
+    }
+    if (r + stride < n) {
+        en = rowptr[r + stride] + l;
+        en1 = rowptr[r + stride + 1];
+    }
+    int c[kSpmvU2];
+    T v[kSpmvU2];
+    ZP<T> w[kSpmvU2];
+    load_chunk2<G, NT>(e, e1, col, val, wold, c, v, w);
+    if (*done) return;
+    const double rz = sum_partials(part2, nb2, lds);
+    const double rr = sum_partials(part2 + kCGBlocks, nb2, lds);
+    if (sqrt(rr) <= sc->target || rr == 0.0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc->rr = rr;
+            *done = 1;
+        }
+        return;
+    }
+    const T beta = first ? (T)0 : (T)(rz / sc->rho[par ^ 1]);
+    double dot = 0.0;
+    while (r < n) {
+        T acc = (T)0;
+        for (;;) {
+#pragma unroll
+            for (int k = 0; k < kSpmvU2; ++k)
+                if (c[k] >= 0) acc = fma(v[k], fma(beta, w[k].p, w[k].z), acc);
+            e += kSpmvU2 * G;
+            if (e >= e1) break;
+            load_chunk2<G, NT>(e, e1, col, val, wold, c, v, w);
+        }
+        const int rc = r;
+        const ZP<T> wr = wold[rc];
+        r += stride;
+        e = en;
+        e1 = en1;
+        if (r < n) {
+            load_chunk2<G, NT>(e, e1, col, val, wold, c, v, w);
+            if (r + stride < n) {
+                en = rowptr[r + stride] + l;
+                en1 = rowptr[r + stride + 1];
+            }
+        }
+        for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+        if (l == 0) {
+            const T pr = fma(beta, wr.p, wr.z);
+            wnew[rc].p = pr;
+            q[rc] = acc;
+            dot = fma((double)pr, (double)acc, dot);
+        }
+    }
+    const double t = block_sum(dot, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->rho[par] = rz;
+        sc->rr = rr;
+    }
+}
+
+// alpha = rho / (p.q); x += alpha p; r -= alpha q; z = D^-1 r into w[j].z;
+// partials r.z, r.r
+template <typename T>
+__global__ __launch_bounds__(kCGThreads) void cg_update(int n, int nb1, const double *part1,
+                                                        ZP<T> *w, const T *__restrict__ q,
+                                                        const T *__restrict__ dinv, T *x, T *r,
+                                                        double *part2, CGScal *sc, int *done,
+                                                        int par) {
+    __shared__ double lds[16];
+    // the first element's operands are requested before the partials are summed
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    T pj = (T)0, qj = (T)0, rj = (T)0, xj = (T)0, dj = (T)0;
+    if (j < n) {
+        pj = w[j].p;
+        qj = q[j];
+        rj = r[j];
+        xj = x[j];
+        dj = dinv[j];
+    }
+    if (*done) return;
+    const double pq = sum_partials(part1, nb1, lds);
+    if (!(pq > 0.0)) {  // breakdown (S is positive semidefinite)
+        if (blockIdx.x == 0 && threadIdx.x == 0) *done = 2;
+        return;
+    }
+    const T alpha = (T)(sc->rho[par] / pq);
+    double rz = 0.0, rr = 0.0;
+    for (bool head = true; j < n; j += gridDim.x * blockDim.x, head = false) {
+        if (!head) {
+            pj = w[j].p;
+            qj = q[j];
+            rj = r[j];
+            xj = x[j];
+            dj = dinv[j];
+        }
+        x[j] = fma(alpha, pj, xj);
+        rj = fma(-alpha, qj, rj);
+        r[j] = rj;
+        const T zj = dj * rj;
+        w[j].z = zj;
+        rz = fma((double)rj, (double)zj, rz);
+        rr = fma((double)rj, (double)rj, rr);
+    }
+    double t1 = block_sum(rz, lds);
+    double t2 = block_sum(rr, lds);
+    if (threadIdx.x == 0) {
+        part2[blockIdx.x] = t1;
+        part2[kCGBlocks + blockIdx.x] = t2;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->its += 1.0;
+}
+
+// convergence test on the last update's partials (end of a chunk of
+// iterations, so that a converged last iteration is reported as such)
+__global__ __launch_bounds__(64) void cg2_check(int nb2, const double *part2, CGScal *sc,
+                                               int *done) {
+    __shared__ double lds[2];
+    if (*done) return;
+    const double rr = sum_partials(part2 + kCGBlocks, nb2, lds);
+    if (threadIdx.x == 0) {
+        sc->rr = rr;
+        if (sqrt(rr) <= sc->target || rr == 0.0) *done = 1;
+    }
+}
+
 // lanes per row: at least four nonzeros per lane on average, 8 to 64 lanes
 static int lanes_per_row(const SchurCSR &S) {
     const double avg = (double)S.nnz / std::max(1, S.n);
@@ -705,30 +938,57 @@ static void launch_cg_step(hipStream_t st, const SchurCSR &S, const T *val, cons
                            RWS<T> *gnew, T *x, T *p, int nbp, const double *pin, double *pout,
                            CGScal *sc, int *done, int mode, int par, unsigned nb, hipEvent_t e0,
                            hipEvent_t e1) {
+    // only cache-resident matrices take this form (no nontemporal loads)
     const int n = S.n;
     const int G = lanes_per_row(S);
     const int32_t *rp = S.rowptr.get(), *cl = S.col.get();
+#define OTIP_CG_STEP(GG)                                                                        \
+    hipExtLaunchKernelGGL(cg_step<GG, false, T>, dim3(nb), dim3(256), 0, st, e0, e1, 0, n, rp,  \
+                          cl, val, gold, gnew, x, p, nbp, pin, pout, sc, done, mode, par)
+    switch (G) {
+        case 64: OTIP_CG_STEP(64); break;
+        case 32: OTIP_CG_STEP(32); break;
+        case 16: OTIP_CG_STEP(16); break;
+        default: OTIP_CG_STEP(8); break;
+    }
+#undef OTIP_CG_STEP
+}
+
+// e0, e1: events recorded at the dispatch's own start and end (may be null)
+template <typename T>
+static void launch_spmv_dir(hipStream_t st, const SchurCSR &S, const T *val, const ZP<T> *wold,
+                            ZP<T> *wnew, T *q, int nb2, const double *part2, double *partial,
+                            CGScal *sc, int *done, int first, int par, unsigned &nb_out,
+                            hipEvent_t e0, hipEvent_t e1) {
+    const int n = S.n;
+    const int G = lanes_per_row(S);
+    // about as many workgroups as stay resident at once (three per compute
+    // unit at this kernel's register use): each lane group then walks several
+    // rows with the next row's loads in flight
+    const unsigned nb = std::min<unsigned>(kSpmvDirBlocks, grid_for(n, 256 / G));
+    nb_out = nb;
+    const int32_t *rp = S.rowptr.get(), *cl = S.col.get();
     // matrices beyond this size do not stay cache-resident between iterations
     const bool nt = ((double)sizeof(T) + 4.0) * (double)S.nnz > 96.0 * (1 << 20);
-#define OTIP_CG_STEP(GG, NT)                                                                   \
-    hipExtLaunchKernelGGL(cg_step<GG, NT, T>, dim3(nb), dim3(256), 0, st, e0, e1, 0, n, rp, cl, \
-                          val, gold, gnew, x, p, nbp, pin, pout, sc, done, mode, par)
+#define OTIP_SPMV_DIR(GG, NT)                                                                  \
+    hipExtLaunchKernelGGL(spmv_dir<GG, NT, T>, dim3(nb), dim3(256), 0, st, e0, e1, 0, n, rp,   \
+                          cl, val, wold, wnew, q, nb2, part2, partial, sc, done, first, par)
     if (nt) {
         switch (G) {
-            case 64: OTIP_CG_STEP(64, true); break;
-            case 32: OTIP_CG_STEP(32, true); break;
-            case 16: OTIP_CG_STEP(16, true); break;
-            default: OTIP_CG_STEP(8, true); break;
+            case 64: OTIP_SPMV_DIR(64, true); break;
+            case 32: OTIP_SPMV_DIR(32, true); break;
+            case 16: OTIP_SPMV_DIR(16, true); break;
+            default: OTIP_SPMV_DIR(8, true); break;
         }
     } else {
         switch (G) {
-            case 64: OTIP_CG_STEP(64, false); break;
-            case 32: OTIP_CG_STEP(32, false); break;
-            case 16: OTIP_CG_STEP(16, false); break;
-            default: OTIP_CG_STEP(8, false); break;
+            case 64: OTIP_SPMV_DIR(64, false); break;
+            case 32: OTIP_SPMV_DIR(32, false); break;
+            case 16: OTIP_SPMV_DIR(16, false); break;
+            default: OTIP_SPMV_DIR(8, false); break;
         }
     }
-#undef OTIP_CG_STEP
+#undef OTIP_SPMV_DIR
 }
 
 // Jacobi inverse diagonal of a caller's CSR matrix, by the rule of schur_diag
@@ -792,8 +1052,75 @@ void SchurSolver::spmv(hipStream_t st, const double *x, double *y) {
     OTIP_HIP(hipGetLastError());
 }
 
-// Jacobi-preconditioned CG in storage type T on S x = b (one launch per
-// iteration, the form above).
+// The two-launch form's iteration loop (matrices that stream from HBM); r is
+// n values of scratch, g 8 n (two (z, p) pair arrays and q), part the partial
+// sums, sc and done the device scalars.
+template <typename T>
+CGStats SchurSolver::pcg_stream(hipStream_t st, const T *val, const T *dinv, const T *b, T *x,
+                                double rtol, double atol, int maxit, T *r, T *g, double *part,
+                                CGScal *sc, int *done) {
+    const int n = S.n;
+    CGStats out;
+    double *part1 = part;
+    double *part2 = part + kSpmvMaxBlocks;
+    ZP<T> *W[2] = {(ZP<T> *)g, (ZP<T> *)(g + 2 * (size_t)n)};
+    T *q = g + 4 * (size_t)n;
+    const unsigned nbv = std::min<unsigned>(kCGBlocks, grid_for(n, kCGThreads));
+    hipLaunchKernelGGL((cg2_init<T>), dim3(nbv), dim3(kCGThreads), 0, st, n, b, dinv, x, r, W[1],
+                       part2);
+    hipLaunchKernelGGL(cg2_init_finish, dim3(1), dim3(64), 0, st, (int)nbv, part2, rtol, atol, sc,
+                       done);
+    OTIP_HIP(hipGetLastError());
+    int chunk = std::min(4, std::max(1, maxit));
+    int launched = 0;
+    CGScal hs{};
+    int hdone = 0;
+    double its_prev = 0.0, rr_prev = -1.0;  // at the previous check
+    // algorithmic bytes of one SpMV launch: values and columns, row pointers,
+    // the two gathered vectors read once, the new direction and q written
+    const double bytes = cg_launch_bytes((double)sizeof(T), S.nnz, n);
+    while (true) {
+        for (int c = 0; c < chunk; ++c) {
+            const int par = launched & 1;
+            unsigned nbs;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (timer) timer->arm(bytes, &e0, &e1);
+            launch_spmv_dir<T>(st, S, val, W[par ^ 1], W[par], q, (int)nbv, part2, part1, sc, done,
+                               launched == 0 ? 1 : 0, par, nbs, e0, e1);
+            hipLaunchKernelGGL((cg_update<T>), dim3(nbv), dim3(kCGThreads), 0, st, n, (int)nbs,
+                               part1, W[par], q, dinv, x, r, part2, sc, done, par);
+            ++launched;
+        }
+        hipLaunchKernelGGL(cg2_check, dim3(1), dim3(64), 0, st, (int)nbv, part2, sc, done);
+        OTIP_HIP(hipGetLastError());
+        OTIP_HIP(hipMemcpyAsync(&hs, sc, sizeof(CGScal), hipMemcpyDeviceToHost, st));
+        OTIP_HIP(hipMemcpyAsync(&hdone, done, sizeof(int), hipMemcpyDeviceToHost, st));
+        OTIP_HIP(hipStreamSynchronize(st));
+        // launches past the last executed iteration found the work done
+        if (timer) timer->collect((size_t)std::max(0.0, hs.its - its_prev));
+        if (hdone || launched >= maxit) break;
+        int next = std::min(chunk * 2, 64);
+        const double ran = hs.its - its_prev;
+        if (rr_prev > 0.0 && hs.rr > 0.0 && hs.rr < rr_prev && ran > 0.0) {
+            const double rate = std::log(hs.rr / rr_prev) / ran;
+            const double need = std::log(hs.target * hs.target / hs.rr) / rate;
+            if (std::isfinite(need))
+                next = (int)std::min(64.0, std::max(4.0, std::ceil(1.1 * need) + 1.0));
+        }
+        rr_prev = hs.rr;
+        its_prev = hs.its;
+        chunk = std::min(next, maxit - launched);
+        if (chunk <= 0) break;
+    }
+    out.iterations = (int)hs.its;
+    out.res_norm = std::sqrt(std::max(0.0, hs.rr));
+    out.converged = (hdone == 1);
+    return out;
+}
+
+// Jacobi-preconditioned CG in storage type T on S x = b: one launch per
+// iteration (the single-reduction form) while the matrix stays cache-resident,
+// the two-launch form beyond.
 template <typename T>
 CGStats SchurSolver::pcg_impl(hipStream_t st, const T *val, const T *dinv, const T *b, T *x,
                               double rtol, double atol, int maxit, DBuf<T> &p_, DBuf<T> &g_) {
@@ -807,6 +1134,9 @@ CGStats SchurSolver::pcg_impl(hipStream_t st, const T *val, const T *dinv, const
     double *part[2] = {part_.get(), part_.get() + kCGPart};
     CGScal *sc = (CGScal *)scal_.get();
     int *done = flag_.get();
+    if (cg_streams((double)sizeof(T), S.nnz))
+        return pcg_stream<T>(st, val, dinv, b, x, rtol, atol, maxit, p, g_.get(), part[0], sc,
+                             done);
     RWS<T> *G[2] = {(RWS<T> *)g_.get(), (RWS<T> *)(g_.get() + 4 * (size_t)n)};
     // about as many workgroups as stay resident at once: each lane group then
     // walks several rows with the next row's loads in flight
@@ -827,8 +1157,7 @@ CGStats SchurSolver::pcg_impl(hipStream_t st, const T *val, const T *dinv, const
     // algorithmic bytes of one launch: values and columns, row pointers, each
     // row's state read once (gathered and by its owner) and written, x and p
     // read and written
-    const double bytes = ((double)sizeof(T) + 4.0) * (double)S.nnz +
-                         (4.0 + 12.0 * (double)sizeof(T)) * n;
+    const double bytes = cg_launch_bytes((double)sizeof(T), S.nnz, n);
     while (true) {
         for (int c = 0; c < chunk; ++c) {
             const int par = launched & 1;
