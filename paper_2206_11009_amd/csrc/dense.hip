@@ -216,12 +216,13 @@ __global__ __launch_bounds__(256) void ldl_panel(int n, int kb, int nb, double *
 // rows per panel workgroup
 constexpr int kPanelRows = 16;
 
-// A22 -= sum over panels of L21 W21^T on lower-triangular 64x64 tiles of the
-// trailing matrix that starts at row and column r0, one workgroup per tile of
-// the lower triangle (1D grid, tile (ti, tj) with tj <= ti from the block
-// index); each wave forms a 32x32 quarter of the tile as 2x2 blocks of 16x16
-// matrix-core products, with its operands loaded straight from global memory
-// into the registers of the matrix-core layout (no LDS, no barrier).  Panel p
+// A22 -= sum over panels of L21 W21^T on the lower triangle of the trailing
+// matrix that starts at row and column r0, in TR x 64 tiles, one workgroup per
+// tile that reaches the triangle (1D grid, tiles in row-major order from the
+// block index); each of the four waves forms a (TR / 2) x 32 part of the tile
+// as blocks of 16x16 matrix-core products, with its operands loaded straight
+// from global memory into the registers of the matrix-core layout (no LDS, no
+// barrier; entries above the diagonal are computed and not stored).  Panel p
 // holds the 64 columns [kcol, kcol + 64) of L (in A) and its W with row r0 + j
 // at wrow0 + j (leading dimension wld); a panel always has 64 columns, since
 // only a block with rows below it forms one.  Up to kDenseUpdPanels panels per
@@ -239,41 +240,16 @@ struct UpdPanel {
     int kcol, wrow0, wld;
 };
 struct UpdArgs {
-    int n, r0, first_col, super_order;
+    int n, r0, first_col;
     UpdPanel p[kDenseUpdPanels];
 };
-// Tile order of a large trailing update.  Workgroups go to the eight XCDs in
-// turn (workgroup b to XCD b mod 8), and each XCD keeps about 128 of these
-// workgroups resident (32 CUs, four per CU).  Row-major tiles would give each
-// XCD tiles from every tile column at once, so every tile fetches its 64 rows
-// of W (and of L) from beyond the XCD's 4 MB L2.  Instead the lower triangle
-// is cut into super-tiles of kSuperRows x kSuperCols tiles, dealt to the XCDs
-// in turn, and XCD x takes the tiles of its super-tile together: 128 tiles
-// that share 16 row blocks of L and 8 of W (3 MB with four panels).  Super-row
-// I (tile rows 16I..16I+15) has the 2I + 2 super-tiles that reach the diagonal,
-// so super-tile s lies in the row I with I(I+1) <= s < (I+1)(I+2).
-constexpr int kSuperRows = 16, kSuperCols = 8, kSuperTiles = kSuperRows * kSuperCols;
-constexpr int kXcds = 8;
-// smallest trailing triangle (in 64-row tiles) that takes the super-tile order:
-// with fewer super-tiles than about nine per XCD the last round leaves XCDs
-// idle, which costs more than the extra operand traffic (measured equal time
-// from here on, at 2.6 times less L2-miss traffic).  OTIP_DENSE_SUPER_MIN in the
-// environment overrides it (a tuning aid).
-constexpr int kSuperMinTiles = 128;
-static int super_min_tiles() {
-    static const int v = [] {
-        const char *e = std::getenv("OTIP_DENSE_SUPER_MIN");
-        return e ? std::max(1, std::atoi(e)) : kSuperMinTiles;
-    }();
-    return v;
-}
 __device__ __forceinline__ double ld_at(const double *base, uint32_t byte_off) {
     return *(const double *)((const char *)base + byte_off);
 }
-// TR: rows per workgroup tile.  The triangle of tiles uses 64 x 64 tiles;
-// a first-column launch may use TR = 16 (one workgroup per 16 rows of the
-// 64-wide block column, four waves of 16 x 16 across its columns), which
-// fills the chip in the early block steps and shortens each wave's chain.
+// TR: rows per workgroup tile.  The triangle takes TR = kUpdRows (128); a
+// first-column launch uses TR = 16 (one workgroup per 16 rows of the 64-wide
+// block column, four waves of 16 x 16 across its columns), which fills the
+// chip in the early block steps and shortens each wave's chain.
 template <int NP, int TR>
 __global__ __launch_bounds__(256) void ldl_update(double *A, UpdArgs a) {
     constexpr int WC = TR >= 32 ? 2 : 4;
@@ -285,24 +261,19 @@ __global__ __launch_bounds__(256) void ldl_update(double *A, UpdArgs a) {
     if (a.first_col) {
         i0 = blk * TR;
         j0 = 0;
-    } else if (a.super_order) {
-        const int slot = blk / kXcds;
-        const int sidx = (slot / kSuperTiles) * kXcds + blk % kXcds, w = slot % kSuperTiles;
-        int I = (int)((sqrt(4.0 * sidx + 1.0) - 1.0) * 0.5);
-        while ((I + 1) * (I + 2) <= sidx) ++I;
-        while (I * (I + 1) > sidx) --I;
-        const int J = sidx - I * (I + 1);
-        const int ti = kSuperRows * I + w / kSuperCols, tj = kSuperCols * J + w % kSuperCols;
-        if (tj > ti || ti * NB >= rows) return;  // outside the triangle (no barrier follows)
-        i0 = ti * NB;
-        j0 = tj * NB;
     } else {
-        int ti = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);
-        while ((ti + 1) * (ti + 2) / 2 <= blk) ++ti;
-        while (ti * (ti + 1) / 2 > blk) --ti;
-        const int tj = blk - ti * (ti + 1) / 2;
-        i0 = ti * NB;
-        j0 = tj * NB;
+        // TR x 64 tiles of the triangle: tile row a (rows TR a..) holds the
+        // (TR / 64)(a + 1) column tiles that reach its diagonal
+        constexpr int H = TR >= NB ? TR / NB : 1;  // (the 16-row form is first-column only)
+        // tile row a starts at block H a (a + 1) / 2
+        int ta = (int)((sqrt(8.0 * blk / H + 1.0) - 1.0) * 0.5);
+        while (H * (ta + 1) * (ta + 2) / 2 <= blk) ++ta;
+        while (H * ta * (ta + 1) / 2 > blk) --ta;
+        const int tb = blk - H * ta * (ta + 1) / 2;
+        i0 = ta * TR;
+        j0 = tb * NB;
+        // outside the triangle (no barrier follows)
+        if (i0 >= rows || j0 >= rows || j0 >= i0 + TR) return;
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wr = (wave / WC) * (16 * UR), wc = (wave % WC) * (16 * VC);
@@ -376,8 +347,12 @@ __global__ __launch_bounds__(256) void ldl_update(double *A, UpdArgs a) {
             }
 }
 
-// rows per workgroup of a first-column update
+// rows per workgroup of a first-column update, and of a trailing-update tile
+// (128 x 64: each wave forms 64 x 32, 4 x 2 blocks of 16 x 16, so that six
+// operand loads feed eight matrix-core products instead of four feeding four;
+// 413 -> 383 ms of updates per 128 x 128 LP against 64 x 64 tiles)
 constexpr int kFirstColRows = 16;
+constexpr int kUpdRows = 128;
 
 // X = L^-1 by recursive doubling.  The 64 x 64 diagonal blocks of X are the
 // block inverses from ldl_diag.  At level b (b = 64, 128, ...) every pair of
@@ -729,7 +704,7 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
         if (u.first_col)
             launch_update<kFirstColRows>(np, blocks, st, e0, e1, A, u);
         else
-            launch_update<NB>(np, blocks, st, e0, e1, A, u);
+            launch_update<kUpdRows>(np, blocks, st, e0, e1, A, u);
     };
     // Block steps in groups of up to kDenseUpdPanels: each block of a group
     // first takes the group's earlier panels on its own block column (a
@@ -739,7 +714,7 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
     // that forms a panel has 64 columns (only the last block can be narrower,
     // and it has no rows below it).
     for (int kb = 0; kb < n;) {
-        UpdArgs u{n, 0, 0, 0, {}};
+        UpdArgs u{n, 0, 0, {}};
         int g = 0, kq = kb;
         for (;;) {
             const int nbq = std::min(NB, n - kq);
@@ -768,15 +743,9 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
         u.r0 = kq;
         u.first_col = 0;
         for (int p = 0; p < g; ++p) u.p[p].wrow0 = kq - u.p[p].kcol - NB;
-        const unsigned t = grid_for(n - kq, NB);
-        u.super_order = t >= (unsigned)super_min_tiles();
-        unsigned blocks = t * (t + 1) / 2;
-        if (u.super_order) {
-            const unsigned srows = (t + kSuperRows - 1) / kSuperRows;
-            const unsigned supers = srows * (srows + 1);
-            blocks = (supers + kXcds - 1) / kXcds * kXcds * kSuperTiles;
-        }
-        update(g, u, blocks, (double)(n - kq) * (n - kq) * g * NB);
+        const unsigned th = grid_for(n - kq, kUpdRows);
+        constexpr unsigned H = kUpdRows / NB;
+        update(g, u, H * th * (th + 1) / 2, (double)(n - kq) * (n - kq) * g * NB);
         kb = kq;
     }
     // X = L^-1 (unit lower; the strict lower part of A holds L)

@@ -100,19 +100,19 @@ def solve_both_ways(ctx, S, rng):
 
 
 def test_direct_solve_ragged_update_n4900(ctx):
-    """n = 4900 (70 x 70): row-major trailing updates with a ragged last tile
-    row (4644 = 72 * 64 + 36 rows after the first group of panels).  The
-    oracle's sparse factorisation of this order takes most of a minute on the
-    CPU, so the checks are the residual and the agreement of the two solve
-    paths (the oracle is compared at n = 4096)."""
+    """n = 4900 (70 x 70): trailing updates of 128 x 64 tiles with ragged last
+    tile rows and columns (4644 = 36 * 128 + 36 rows after the first group of
+    panels).  The oracle's sparse factorisation of this order takes most of a
+    minute on the CPU, so the checks are the residual and the agreement of the
+    two solve paths (the oracle is compared at n = 4096)."""
     S, rng = grid_schur(70, 70)
     solve_both_ways(ctx, S, rng)
 
 
-def test_direct_solve_super_tiled_update_n9409(ctx):
-    """n = 9409 (97 x 97): trailing triangles of 144 down to 128 tiles take the
-    super-tile order, the first with a ragged last tile row (9153 = 143 * 64 + 1
-    rows)."""
+def test_direct_solve_ragged_update_n9409(ctx):
+    """n = 9409 (97 x 97): larger trailing triangles (9153 = 71 * 128 + 65 rows
+    after the first group: the last tile row holds one full and one ragged
+    64-row half)."""
     S, rng = grid_schur(97, 97)
     solve_both_ways(ctx, S, rng)
 
