@@ -46,11 +46,11 @@ KERNEL_TRAFFIC = {
     ("cg_step", "c3"): {"source": "paper_2206_11009_amd/csrc/schur.hip",
                         "functions": ["load_chunk", "cg_step"],
                         "sha256": "d40ada58b6ba7e92d40721e9d0e7ea37fbd37063db0c70e3b728a3eb4f43f261",
-                        "bytes_per_launch": 10974378.1},
+                        "bytes_per_launch": 10988670.8},
     ("ldl_update", "c3"): {"source": "paper_2206_11009_amd/csrc/dense.hip",
                            "functions": ["ldl_update"],
-                           "sha256": "eb4f5649549eddf3c31f346b038b09527de249dd8e9a5093e39ba6dbcbbbaa36",
-                           "bytes_per_launch": 296944356.5},
+                           "sha256": "9b3b924ba051673635bb01b18dabd8041e50a044bf437ec3571be12477d1f813",
+                           "bytes_per_launch": 369547727.9},
     ("ldl_diag", "c2"): {"source": "paper_2206_11009_amd/csrc/dense.hip",
                          "functions": ["ldl_diag"],
                          "sha256": "763182764fc82dfa612048fdcdd197df49aa3945a703918e1749b5f425ff1ade",
