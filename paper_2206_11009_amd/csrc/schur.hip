@@ -361,9 +361,8 @@ __global__ __launch_bounds__(256) void spmv_rows(int n, const int32_t *__restric
                                                  const int32_t *__restrict__ col,
                                                  const T *__restrict__ val,
                                                  const T *__restrict__ x, T *__restrict__ y,
-                                                 double *partial, const int *done) {
+                                                 double *partial) {
     __shared__ double lds[16];
-    if (done && *done) return;
     const int groups = 256 / G;
     const int g = threadIdx.x / G, l = threadIdx.x % G;
     double dot = 0.0;
@@ -428,11 +427,24 @@ __device__ __forceinline__ double sum_partials(const double *p, int nb, double *
     return v;
 }
 
+// The device flag *f as one value for the whole workgroup.  Workgroup 0 of
+// the same launch may set it while other workgroups read it; read once and
+// broadcast, every wave of a workgroup takes the same branch, so none leaves
+// while the others wait at a barrier or read its partial sum.
+__device__ __forceinline__ int block_flag(const int *f, double *lds) {
+    if (threadIdx.x == 0) lds[15] = (double)*f;
+    __syncthreads();
+    const int v = (int)lds[15];
+    __syncthreads();
+    return v;
+}
+
 // the three partial sums of a launch (gamma, delta, r.r: kSpmvMaxBlocks slots
 // apart), one per wavefront in parallel, each in the fixed order of
 // sum_partials; broadcast to the workgroup
-__device__ __forceinline__ void sum_partials3(const double *p, int nb, double *lds,
-                                              double (&out)[3]) {
+// (and the device flag *f, read once by the fourth wave and returned to all)
+__device__ __forceinline__ int sum_partials3(const double *p, int nb, double *lds,
+                                             double (&out)[3], const int *f) {
     const int wv = threadIdx.x >> 6;
     if (wv < 3) {
         const double *q = p + wv * kSpmvMaxBlocks;
@@ -440,12 +452,16 @@ __device__ __forceinline__ void sum_partials3(const double *p, int nb, double *l
         for (int k = threadIdx.x & 63; k < nb; k += 64) s += q[k];
         s = wave_sum(s);
         if ((threadIdx.x & 63) == 0) lds[wv] = s;
+    } else if (threadIdx.x == 192) {
+        lds[3] = (double)*f;
     }
     __syncthreads();
     out[0] = lds[0];
     out[1] = lds[1];
     out[2] = lds[2];
+    const int flag = (int)lds[3];
     __syncthreads();
+    return flag;
 }
 
 // One row's state as the next launch gathers it: r_i, w_i, s_{i-1} and the
@@ -567,9 +583,8 @@ __global__ __launch_bounds__(256) void cg_step(int n, const int32_t *__restrict_
         }
     }
     if (mode != 0) {
-        if (*done) return;
         double sums[3];
-        sum_partials3(pin, nbp, lds, sums);
+        if (sum_partials3(pin, nbp, lds, sums, done)) return;
         const double gam = sums[0], del = sums[1], rr = sums[2];
         const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
         if (sqrt(rr) <= sc->target || rr == 0.0) {
@@ -796,7 +811,7 @@ __global__ __launch_bounds__(256) void spmv_dir(int n, const int32_t *__restrict
     T v[kSpmvU2];
     ZP<T> w[kSpmvU2];
     load_chunk2<G, NT>(e, e1, col, val, wold, c, v, w);
-    if (*done) return;
+    if (block_flag(done, lds)) return;
     const double rz = sum_partials(part2, nb2, lds);
     const double rr = sum_partials(part2 + kCGBlocks, nb2, lds);
     if (sqrt(rr) <= sc->target || rr == 0.0) {
@@ -865,7 +880,7 @@ __global__ __launch_bounds__(kCGThreads) void cg_update(int n, int nb1, const do
         xj = x[j];
         dj = dinv[j];
     }
-    if (*done) return;
+    if (block_flag(done, lds)) return;
     const double pq = sum_partials(part1, nb1, lds);
     if (!(pq > 0.0)) {  // breakdown (S is positive semidefinite)
         if (blockIdx.x == 0 && threadIdx.x == 0) *done = 2;
@@ -919,17 +934,17 @@ static int lanes_per_row(const SchurCSR &S) {
 
 template <typename T>
 static void launch_spmv(hipStream_t st, const SchurCSR &S, const T *val, const T *x, T *y,
-                        double *partial, const int *done, unsigned &nb_out) {
+                        double *partial, unsigned &nb_out) {
     const int n = S.n;
     const int G = lanes_per_row(S) >= 64 ? 64 : 16;
     const unsigned nb = std::min<unsigned>(kSpmvMaxBlocks, grid_for(n, 256 / G));
     nb_out = nb;
     if (G == 64)
         hipLaunchKernelGGL((spmv_rows<64, T>), dim3(nb), dim3(256), 0, st, n, S.rowptr.get(),
-                           S.col.get(), val, x, y, partial, done);
+                           S.col.get(), val, x, y, partial);
     else
         hipLaunchKernelGGL((spmv_rows<16, T>), dim3(nb), dim3(256), 0, st, n, S.rowptr.get(),
-                           S.col.get(), val, x, y, partial, done);
+                           S.col.get(), val, x, y, partial);
 }
 
 // e0, e1: events recorded at the dispatch's own start and end (may be null)
@@ -1048,7 +1063,7 @@ void SchurSolver::load_csr(hipStream_t st, int n, int64_t nnz, const int32_t *ro
 
 void SchurSolver::spmv(hipStream_t st, const double *x, double *y) {
     unsigned nb;
-    launch_spmv<double>(st, S, S.val.get(), x, y, nullptr, nullptr, nb);
+    launch_spmv<double>(st, S, S.val.get(), x, y, nullptr, nb);
     OTIP_HIP(hipGetLastError());
 }
 
