@@ -45,12 +45,12 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 KERNEL_TRAFFIC = {
     ("cg_step", "c3"): {"source": "paper_2206_11009_amd/csrc/schur.hip",
                         "functions": ["load_chunk", "cg_step"],
-                        "sha256": "d40ada58b6ba7e92d40721e9d0e7ea37fbd37063db0c70e3b728a3eb4f43f261",
-                        "bytes_per_launch": 10988670.8},
+                        "sha256": "aa72e5b796946081a1d66dd41743c0e67e6194fce9b3ef43a634c6e26ff597de",
+                        "bytes_per_launch": 10995319.7},
     ("ldl_update", "c3"): {"source": "paper_2206_11009_amd/csrc/dense.hip",
                            "functions": ["ldl_update"],
                            "sha256": "9b3b924ba051673635bb01b18dabd8041e50a044bf437ec3571be12477d1f813",
-                           "bytes_per_launch": 369547727.9},
+                           "bytes_per_launch": 369494186.8},
     ("ldl_diag", "c2"): {"source": "paper_2206_11009_amd/csrc/dense.hip",
                          "functions": ["ldl_diag"],
                          "sha256": "763182764fc82dfa612048fdcdd197df49aa3945a703918e1749b5f425ff1ade",
