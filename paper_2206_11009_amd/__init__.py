@@ -332,8 +332,9 @@ def otip_state_load(ctx: Context, data: bytes) -> None:
 
 class PCGResult:
     """Outcome of otip_pcg: status (OTIP_OK, OTIP_EMAXITER or OTIP_ENUMERIC),
-    iterations, final residual norm, and the fused SpMV launches that did work
-    with their mean duration (s) and algorithmic bytes per launch."""
+    iterations, final residual norm, and the timed iteration launches that did
+    work (one per iteration; the SpMV launch for a matrix beyond 96 MB) with
+    their mean duration (s) and algorithmic bytes per launch."""
 
     def __init__(self, status, iterations, res_norm, stats):
         self.status = status

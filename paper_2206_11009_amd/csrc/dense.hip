@@ -7,8 +7,9 @@
 //   1. the 64 x 64 diagonal block is factorised by one wavefront while a
 //      second inverts its unit lower factor, column by column behind it;
 //   2. the rows below form W21 = A21 L11^-T (= L21 D1) and L21 = W21 D1^-1;
-//   3. the trailing lower triangle is updated, A22 -= L21 W21^T, in 64 x 64
-//      tiles (16-row tiles where only the next block column is updated).
+//   3. the trailing lower triangle is updated, A22 -= L21 W21^T, in 128 x 64
+//      tiles once per group of four block steps (16-row tiles where only the
+//      next block column is updated, inside a group).
 // Steps 2 and 3 run on the FP64 matrix cores with operands loaded straight
 // into registers.
 // A pivot d_k <= pivtol * S_kk (original diagonal) or d_k <= 0 becomes +inf:

@@ -2,8 +2,9 @@
 that the oracle builds (Section 4): the residual bound it promises, the same
 image S x as the oracle's own PCG, iteration counts close to the oracle's (the
 same Jacobi preconditioner, so the same iterates in exact arithmetic), both
-storage precisions, the SpMV's two lane-group shapes, ragged sizes, degenerate
-matrices and rejected inputs."""
+storage precisions, the SpMV's two lane-group shapes, both forms of the
+iteration (one launch, or two for a matrix beyond 96 MB), ragged sizes,
+degenerate matrices and rejected inputs."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -75,6 +76,26 @@ def test_pcg_meets_its_bound_and_matches_the_oracle(ctx, m, n, per_row, seed, pr
         assert res.spmv_launches == res.iterations
         assert res.spmv_bytes == 12.0 * S.nnz + 100.0 * S.shape[0]   # a cache-resident S
         assert res.spmv_seconds > 0.0
+
+
+def test_pcg_two_launch_form_beyond_96_mb(ctx):
+    """A Schur matrix of about 11.5M nonzeros (138 MB of values and columns):
+    the CG takes its two-launch form (timed SpMV bytes 12 nnz + 36 n), meets
+    its bound, and matches the oracle's image and iteration count."""
+    S, b = schur_case(20000, 20000, 24, 11, spread=4.0)
+    assert 12.0 * S.nnz > 96.0 * (1 << 20)
+    rtol = 1e-8
+    x, res = run(ctx, S, b, rtol)
+    assert res.status == 0, res.status
+    nb = np.linalg.norm(b)
+    assert np.linalg.norm(b - S @ x) <= 1.5 * rtol * nb + 1e-13 * nb
+    d = 1.0 / S.diagonal()
+    xo, its_o, ok = oracle.ipm.pcg(S, b, rtol, 1000, lambda r: d * r)
+    assert ok
+    assert np.linalg.norm(S @ (x - xo)) <= 3 * rtol * nb
+    assert abs(res.iterations - its_o) <= 2 + 0.1 * its_o, (res.iterations, its_o)
+    assert res.spmv_launches == res.iterations
+    assert res.spmv_bytes == 12.0 * S.nnz + 36.0 * S.shape[0]
 
 
 def test_pcg_on_the_solver_shaped_schur_of_a_grid_problem(ctx):
