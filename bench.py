@@ -86,6 +86,7 @@ def cpu_baseline(cfg, budget_s=20.0, fallback_its=None):
 
     inst = config_instance(cfg, 0)
     t0 = time.perf_counter()
+    c0 = time.process_time()   # CPU time of all the process's threads
     marks = []
 
     def log(rec):
@@ -98,6 +99,10 @@ def cpu_baseline(cfg, budget_s=20.0, fallback_its=None):
         done = True
     except Stop:
         done = False
+    wall = time.perf_counter() - t0
+    # the cores the oracle kept busy (its C scan and scipy's sparse kernels are
+    # single-threaded; numpy's BLAS calls may use more)
+    cores = max(1, int(round((time.process_time() - c0) / max(wall, 1e-9))))
     elapsed = (marks[-1] if marks else time.perf_counter()) - t0
     its = len(marks)
     golden = os.path.join(ROOT, "tests", "golden", f"oracle_{cfg}.json")
@@ -115,7 +120,7 @@ def cpu_baseline(cfg, budget_s=20.0, fallback_its=None):
         how = (f"first {its} outer iterations of the seed-0 oracle solve ({elapsed:.1f} s), "
                f"mean time per iteration x {full_its} iterations of the oracle's full solve")
     return {"value": value, "unit": "s per LP (estimated)" if not done else "s per LP",
-            "cores": 1, "kind": "oracle", "sample": how}
+            "cores": cores, "kind": "oracle", "sample": how}
 
 
 def upload(insts):
