@@ -141,6 +141,11 @@ struct LaunchTimer {
         used += 2;
         pending_work.push_back(w);
     }
+    // replace the units of work of the k-th launch armed since the last
+    // collect (work known only once the launch has run)
+    void set_pending(size_t k, double w) {
+        if (k < pending_work.size()) pending_work[k] = w;
+    }
     void reset() {
         active = true;
         calls = 0;

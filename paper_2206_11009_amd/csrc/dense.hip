@@ -69,6 +69,11 @@ static_assert(NB % kDiagStepBlock == 0, "the last hand-over must follow pivot NB
 // the wave: vmcnt 0, expcnt and lgkmcnt at their maxima (no wait)
 constexpr int kWaitVmcnt0 = 0x0F70;
 
+__device__ __forceinline__ int wave_max_i(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
 __device__ __forceinline__ double rdlane(double v, int lane) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
     const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
@@ -150,12 +155,13 @@ template <int TR>
 __global__ __launch_bounds__(256) void ldl_panel(int n, int kb, int nb, double *A,
                                                  const double *d, double *W,
                                                  const double *Linv,
-                                                 unsigned long long *nnz) {
+                                                 unsigned long long *nnz, int *hrow) {
     // the four waves split the TR x 64 tile into WC column groups of 64 / WC
     // columns and 4 / WC row groups: UR 16-row and VC 16-column blocks each
     constexpr int WC = TR >= 32 ? 2 : 4;
     constexpr int UR = TR / (4 / WC) / 16, VC = 64 / WC / 16;
-    int nz = 0;  // nonzeros of L21 written here (the fill statistic)
+    int nz = 0;     // nonzeros of L21 written here (the fill statistic)
+    int last = -1;  // the last row with a nonzero entry of L21 or W21 written here
     const int r0 = kb + nb + blockIdx.x * TR;
     const int rows = n - kb - nb;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -208,10 +214,13 @@ __global__ __launch_bounds__(256) void ldl_panel(int n, int kb, int nb, double *
                     W[(size_t)(i - kb - nb) + (size_t)k * rows] = wk;
                     A[(size_t)i + (size_t)(kb + k) * n] = lv;
                     nz += lv != 0.0;
+                    if (wk != 0.0 || lv != 0.0) last = max(last, i);
                 }
             }
     nz = wave_sum_i(nz);
     if ((threadIdx.x & 63) == 0 && nz) atomicAdd(nnz, (unsigned long long)nz);
+    last = wave_max_i(last);
+    if ((threadIdx.x & 63) == 0 && last >= 0) atomicMax(hrow + kb / NB, last);
 }
 
 // rows per panel workgroup
@@ -242,6 +251,11 @@ struct UpdPanel {
 };
 struct UpdArgs {
     int n, r0, first_col;
+    // hrow[q]: the last row with a nonzero entry in block q's L21 or W21 (-1:
+    // none).  Rows and columns of the trailing matrix beyond the group's last
+    // such row take exactly zero from its panels, so their tiles are skipped:
+    // the factors of these Schur complements are banded (a few percent of n^2).
+    const int *hrow;
     UpdPanel p[kDenseUpdPanels];
 };
 __device__ __forceinline__ double ld_at(const double *base, uint32_t byte_off) {
@@ -258,10 +272,16 @@ __global__ __launch_bounds__(256) void ldl_update(double *A, UpdArgs a) {
     const int n = a.n, r0 = a.r0;
     const int rows = n - r0, last = rows - 1;
     const int blk = blockIdx.x;
+    // rows (relative to r0) that the group's panels reach
+    int reach = -1;
+#pragma unroll
+    for (int pi = 0; pi < NP; ++pi) reach = max(reach, a.hrow[a.p[pi].kcol / NB]);
+    const int live = min(rows, reach - r0 + 1);
     int i0, j0;
     if (a.first_col) {
         i0 = blk * TR;
         j0 = 0;
+        if (i0 >= live) return;  // (no barrier follows)
     } else {
         // TR x 64 tiles of the triangle: tile row a (rows TR a..) holds the
         // (TR / 64)(a + 1) column tiles that reach its diagonal
@@ -273,8 +293,8 @@ __global__ __launch_bounds__(256) void ldl_update(double *A, UpdArgs a) {
         const int tb = blk - H * ta * (ta + 1) / 2;
         i0 = ta * TR;
         j0 = tb * NB;
-        // outside the triangle (no barrier follows)
-        if (i0 >= rows || j0 >= rows || j0 >= i0 + TR) return;
+        // outside the triangle or beyond the panels' reach (no barrier follows)
+        if (i0 >= live || j0 >= live || j0 >= i0 + TR) return;
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wr = (wave / WC) * (16 * UR), wc = (wave % WC) * (16 * VC);
@@ -685,6 +705,8 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
     OTIP_HIP(hipMemsetAsync(ninf_.get(), 0, sizeof(int), st));
     unsigned long long *nzL = cnt_.need(1);  // nonzeros of L, counted where they are written
     OTIP_HIP(hipMemsetAsync(nzL, 0, sizeof(unsigned long long), st));
+    int *hrow = hrow_.need(nblk);  // last nonzero row of each block's panel
+    OTIP_HIP(hipMemsetAsync(hrow, 0xff, sizeof(int) * nblk, st));
     const bool timed = factorisations_++ % std::max(1, timer_stride) == 0;
     LaunchTimer *tdiag = timed ? diag_timer : nullptr, *tupd = timed ? update_timer : nullptr;
     auto diag = [&](int kb, int nb) {
@@ -697,11 +719,22 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
     auto panel = [&](int kb, int nb, double *W) {
         hipLaunchKernelGGL(ldl_panel<kPanelRows>, dim3(grid_for(n - kb - nb, kPanelRows)), dim3(256), 0, st, n, kb,
                            nb, A, d_.get(), W, (const double *)(linv + (size_t)(kb / NB) * NB * NB),
-                           nzL);
+                           nzL, hrow);
     };
+    // the timed update launches, whose algorithmic flops (over the rows the
+    // panels reach) are known once the factorisation has run
+    struct UpdRec {
+        int first_col, r0, np, kcol[kDenseUpdPanels];
+    };
+    std::vector<UpdRec> recs;
     auto update = [&](int np, const UpdArgs &u, unsigned blocks, double flops) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (tupd) tupd->arm(flops, &e0, &e1);
+        if (tupd) {
+            tupd->arm(flops, &e0, &e1);
+            UpdRec r{u.first_col, u.r0, np, {}};
+            for (int p = 0; p < np; ++p) r.kcol[p] = u.p[p].kcol;
+            recs.push_back(r);
+        }
         if (u.first_col)
             launch_update<kFirstColRows>(np, blocks, st, e0, e1, A, u);
         else
@@ -715,7 +748,7 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
     // that forms a panel has 64 columns (only the last block can be narrower,
     // and it has no rows below it).
     for (int kb = 0; kb < n;) {
-        UpdArgs u{n, 0, 0, {}};
+        UpdArgs u{n, 0, 0, hrow, {}};
         int g = 0, kq = kb;
         for (;;) {
             const int nbq = std::min(NB, n - kq);
@@ -791,9 +824,29 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
     OTIP_HIP(hipMemcpyAsync(&hn, ninf_.get(), sizeof(int), hipMemcpyDeviceToHost, st));
     OTIP_HIP(hipMemcpyAsync(&hc, nzL, sizeof(hc), hipMemcpyDeviceToHost, st));
     OTIP_HIP(hipMemcpyAsync(&hbad, bad_.get(), sizeof(int), hipMemcpyDeviceToHost, st));
+    std::vector<int> hh(tupd ? nblk : 0);
+    if (tupd)
+        OTIP_HIP(hipMemcpyAsync(hh.data(), hrow, sizeof(int) * nblk, hipMemcpyDeviceToHost, st));
     OTIP_HIP(hipStreamSynchronize(st));
     if (tdiag) tdiag->collect();
-    if (tupd) tupd->collect();
+    if (tupd) {
+        // algorithmic flops of each timed update: over the rows its panels reach
+        for (size_t k = 0; k < recs.size(); ++k) {
+            const UpdRec &r = recs[k];
+            int reach = -1;
+            for (int p = 0; p < r.np; ++p) reach = std::max(reach, hh[r.kcol[p] / NB]);
+            const double live = std::max(0, std::min(n - r.r0, reach - r.r0 + 1));
+            double entries;  // lower-triangle entries of the launch's region
+            if (r.first_col) {
+                const double w = std::min(NB, n - r.r0);
+                entries = live >= w ? w * (w + 1) / 2.0 + (live - w) * w : live * (live + 1) / 2.0;
+            } else {
+                entries = live * live / 2.0;
+            }
+            tupd->set_pending(k, 2.0 * NB * r.np * entries);
+        }
+        tupd->collect();
+    }
     nnzL_ = (int64_t)hc + n;
     inverse_ok_ = hbad == 0 && !force_substitution;
     if (!inverse_ok_)  // U = L^T for the backward substitution

@@ -234,7 +234,7 @@ class DenseLDL {
 
   private:
     DBuf<double> A_, X_, XT_, T_, d_, orig_, W_, v_, linv_, t_;
-    DBuf<int> ninf_, bad_;
+    DBuf<int> ninf_, bad_, hrow_;
     DBuf<unsigned long long> cnt_;
     int64_t nnzL_ = 0;
     int64_t factorisations_ = 0;
