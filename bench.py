@@ -255,7 +255,7 @@ def rooflines(infos, cfg):
     up_n = sum(i["update_launches"] for i in infos)
     up_f = sum(i["update_flops"] for i in infos)
     diag = {"bound": "alu", "kernel": "ldl_diag (64x64 diagonal-block LDL^T and inverse of its "
-            "unit lower factor, two wavefronts)",
+            "unit lower factor, four wavefronts)",
             "achieved": dg_f / max(dg_ms, 1e-12) / 1e9, "peak": FP64_VECTOR_PEAK_TF,
             "unit": "TFLOP/s", "avg_launch_us": 1e3 * dg_ms / max(dg_n, 1), "launches": dg_n,
             "total_ms": dg_ms, "traffic": measured_traffic("ldl_diag", cfg),

@@ -49,21 +49,24 @@ __global__ void dense_zero(size_t total, double *A) {
         A[t] = 0.0;
 }
 
-// Factor the diagonal block [kb, kb+nb) and invert its unit lower factor, two
-// wavefronts.  In the factor wave, lane i keeps row i of the block in
-// registers; every value one lane needs from another (the pivot, column k of
-// L) is read with v_readlane at a compile-time lane index into a scalar
-// register, so the recurrence runs without LDS round trips.  Right-looking: at
-// pivot k each lane applies the rank-one update to its row (entries right of
-// its diagonal receive values that are never read).  Lane c of the inverse
-// wave solves L11 x = e_c for column c of L11^-1 (right-looking, dependent
-// chains 64 long), which goes to Linv (64 x 64 column-major, identity-padded)
-// through LDS for a coalesced store.  Column s of that recurrence needs only
-// column s of L, final once pivot s is done: the factor wave hands the columns
-// over through LDS after every kDiagStepBlock pivots, so the inverse runs
-// behind the factor instead of after it.
-constexpr int kDiagStepBlock = 16;
-static_assert(NB % kDiagStepBlock == 0, "the last hand-over must follow pivot NB - 1");
+// Factor the diagonal block [kb, kb+nb) and invert its unit lower factor, four
+// wavefronts.  Wave q keeps, for lane i, columns [16q, 16q+16) of row i of the
+// block and rows [16q, 16q+16) of column i of L11^-1, in registers.  Pivot k
+// (right-looking) takes one workgroup barrier: the wave that holds column k
+// reads the pivot from lane k (v_readlane), forms every row's l = u_k / d_k
+// and writes it to row k of Lt (Lt[k][r] = L(r, k): column k of L,
+// contiguous); after the barrier each wave reads its 16 entries of that column
+// as LDS broadcasts (all lanes read one address) and applies the rank-one
+// update to its columns of every row, and step k of the inverse (L11 x = e_c,
+// x_r -= L(r, k) x_k) to its rows of every column.  x_k is published in Xs by
+// the wave that holds row k once step k - 1 is applied.  Entries that a step
+// does not change (columns and rows at or left of k, where column k of L is
+// zero) take an exact no-op, and waves whose 16 columns and rows are all
+// finished skip the step.  The pivot chain is the kernel's bound: one wave
+// does all of a pivot's dependent work (pivot test, division, publication),
+// while the rank-one work is spread over four SIMDs.
+constexpr int kDiagWaves = 4;
+constexpr int kDiagCols = NB / kDiagWaves;  // columns (and inverse rows) per wave
 
 // s_waitcnt operand (GFX9 encoding) that waits for every vector memory load of
 // the wave: vmcnt 0, expcnt and lgkmcnt at their maxima (no wait)
@@ -80,66 +83,69 @@ __device__ __forceinline__ double rdlane(double v, int lane) {
     return __hiloint2double(hi, lo);
 }
 
-__global__ __launch_bounds__(128) void ldl_diag(int n, int kb, int nb, double *A,
-                                                const double *orig, double *d, double pivtol,
-                                                int *ninf, double *Linv) {
-    __shared__ double Lc[NB][NB + 1];  // columns of L, factor wave -> inverse wave
-    __shared__ double Ls[NB][NB + 1];  // L11^-1, transposed for the store
+__global__ __launch_bounds__(64 * kDiagWaves) void ldl_diag(int n, int kb, int nb, double *A,
+                                                            const double *orig, double *d,
+                                                            double pivtol, int *ninf,
+                                                            double *Linv) {
+    __shared__ __align__(16) double Lt[NB][NB];  // Lt[k][r] = L(r, k)
+    __shared__ double Xs[NB][NB];                // Xs[s][c] = L11^-1 (s, c), final
+    __shared__ double Ls[NB][NB + 1];            // L11^-1, transposed for the store
+    __shared__ double pm[NB];                    // d_k, or 0 where pivot k is dropped
     const int i = threadIdx.x & 63;
-    const bool fw = threadIdx.x < 64;  // the factor wave (wave-uniform)
-    // factor wave: row i of the block; inverse wave: column i of L11^-1
-    double u[NB];
-    const double oi = (fw && i < nb) ? orig[kb + i] : 1.0;
+    const int q0 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * kDiagCols;
+    double u[kDiagCols], x[kDiagCols];  // row i: columns q0 + m; L11^-1 column i: rows q0 + m
 #pragma unroll
-    for (int c = 0; c < NB; ++c)
-        u[c] = fw ? ((i < nb && c < nb && c <= i) ? A[(size_t)(kb + i) + (size_t)(kb + c) * n]
-                                                  : 0.0)
-                  : ((c == i) ? 1.0 : 0.0);
+    for (int m = 0; m < kDiagCols; ++m) {
+        const int c = q0 + m;
+        u[m] = (i < nb && c < nb && c <= i) ? A[(size_t)(kb + i) + (size_t)(kb + c) * n] : 0.0;
+        x[m] = (c == i) ? 1.0 : 0.0;
+    }
+    const double oi = (i < nb) ? orig[kb + i] : 1.0;
     int ninf_local = 0;
-    double dmine = 0.0;
+    if (q0 == 0) Xs[0][i] = x[0];
+    for (int kq = 0; kq < kDiagWaves; ++kq) {
+        const int owner = kq * kDiagCols;
 #pragma unroll
-    for (int k = 0; k < NB; ++k) {
-        if (fw) {
-            const bool act = k < nb;
-            double piv = rdlane(u[k], k);
-            const bool bad = !(piv > pivtol * rdlane(oi, k)) || !(piv > 0.0);
-            piv = bad ? INFINITY : piv;
-            const bool fin = act && !bad;
-            ninf_local += (act && bad) ? 1 : 0;
-            dmine = (i == k) ? piv : dmine;
-            const double l = (fin && i > k && i < nb) ? u[k] / piv : 0.0;
-            const double ld = fin ? l * piv : 0.0;
-#pragma unroll
-            for (int j = k + 1; j < NB; ++j) u[j] = fma(-ld, rdlane(l, j), u[j]);
-            u[k] = (act && i > k) ? l : u[k];
-            Lc[i][k] = u[k];
-        }
-        if (k % kDiagStepBlock == kDiagStepBlock - 1) {
-            __syncthreads();
-            if (!fw) {
-#pragma unroll
-                for (int s2 = k + 1 - kDiagStepBlock; s2 <= k; ++s2) {
-                    const double l = Lc[i][s2];
-#pragma unroll
-                    for (int r = s2 + 1; r < NB; ++r) u[r] = fma(-rdlane(l, r), u[s2], u[r]);
+        for (int m = 0; m < kDiagCols; ++m) {
+            const int k = owner + m;
+            if (q0 == owner) {
+                const bool act = k < nb;
+                double piv = rdlane(u[m], k);
+                const bool bad = !(piv > pivtol * rdlane(oi, k)) || !(piv > 0.0);
+                piv = bad ? INFINITY : piv;
+                const bool fin = act && !bad;
+                ninf_local += (act && bad) ? 1 : 0;
+                Lt[k][i] = (fin && i > k && i < nb) ? u[m] / piv : 0.0;
+                if (i == 0) {
+                    pm[k] = fin ? piv : 0.0;
+                    if (act) d[kb + k] = piv;
                 }
+            }
+            __syncthreads();
+            if (q0 >= owner) {
+                const double ld = Lt[k][i] * pm[k];  // l_i d_k, 0 for a dropped pivot
+                const double xk = Xs[k][i];
+#pragma unroll
+                for (int m2 = 0; m2 < kDiagCols; ++m2) {
+                    const double lj = Lt[k][q0 + m2];
+                    u[m2] = fma(-ld, lj, u[m2]);
+                    x[m2] = fma(-lj, xk, x[m2]);
+                }
+                const int m1 = (m + 1) % kDiagCols;
+                const int next = (m + 1 == kDiagCols) ? owner + kDiagCols : owner;
+                if (k + 1 < NB && q0 == next) Xs[k + 1][i] = x[m1];
             }
         }
     }
-    if (fw) {
-        if (i < nb) d[kb + i] = dmine;
-        if (i == 0 && ninf_local) atomicAdd(ninf, ninf_local);
 #pragma unroll
-        for (int c = 0; c < NB; ++c)
-            if (i < nb && c < i && c < nb) A[(size_t)(kb + i) + (size_t)(kb + c) * n] = u[c];
-    } else {
-#pragma unroll
-        for (int r = 0; r < NB; ++r) Ls[r][i] = u[r];
-    }
+    for (int m = 0; m < kDiagCols; ++m) Ls[q0 + m][i] = x[m];
+    if (i == 0 && ninf_local) atomicAdd(ninf, ninf_local);
     __syncthreads();
-    if (!fw) {
 #pragma unroll
-        for (int c = 0; c < NB; ++c) Linv[(size_t)i + (size_t)c * NB] = Ls[i][c];
+    for (int m = 0; m < kDiagCols; ++m) {
+        const int c = q0 + m;
+        if (i < nb && c < i) A[(size_t)(kb + i) + (size_t)(kb + c) * n] = Lt[c][i];
+        Linv[(size_t)i + (size_t)c * NB] = Ls[i][c];
     }
 }
 
@@ -712,7 +718,7 @@ int DenseLDL::factor(hipStream_t st, const SchurCSR &S, double pivtol) {
     auto diag = [&](int kb, int nb) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (tdiag) tdiag->arm(2.0 * nb * nb * nb / 3.0, &e0, &e1);
-        hipExtLaunchKernelGGL(ldl_diag, dim3(1), dim3(128), 0, st, e0, e1, 0, n, kb, nb, A,
+        hipExtLaunchKernelGGL(ldl_diag, dim3(1), dim3(64 * kDiagWaves), 0, st, e0, e1, 0, n, kb, nb, A,
                               (const double *)orig_.get(), d_.get(), pivtol, ninf_.get(),
                               linv + (size_t)(kb / NB) * NB * NB);
     };
