@@ -49,12 +49,12 @@ KERNEL_TRAFFIC = {
                         "bytes_per_launch": 10995319.7},
     ("ldl_update", "c3"): {"source": "paper_2206_11009_amd/csrc/dense.hip",
                            "functions": ["ldl_update"],
-                           "sha256": "9b3b924ba051673635bb01b18dabd8041e50a044bf437ec3571be12477d1f813",
-                           "bytes_per_launch": 369494186.8},
-    ("ldl_diag", "c2"): {"source": "paper_2206_11009_amd/csrc/dense.hip",
+                           "sha256": "1bcb344e821bde84dfe7c46499b80875ff4f1e928d8e6c6f328d7bc88c1d6eac",
+                           "bytes_per_launch": 4408930.8},
+    ("ldl_diag", "c3"): {"source": "paper_2206_11009_amd/csrc/dense.hip",
                          "functions": ["ldl_diag"],
-                         "sha256": "763182764fc82dfa612048fdcdd197df49aa3945a703918e1749b5f425ff1ade",
-                         "bytes_per_launch": 351733.0},
+                         "sha256": "96f87f3041ccc01070127ff805ed6ea8d5ef17cb834cb68c4b02db230b83934c",
+                         "bytes_per_launch": 102391.1},
 }
 FP64_VECTOR_PEAK_TF = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 FP64_MATRIX_PEAK_TF = 78.6     # dense FP64 matrix-core peak
