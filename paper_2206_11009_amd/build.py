@@ -16,10 +16,8 @@ ARCH = os.environ.get("OTIP_ARCH", "gfx950")
 HIPFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wno-unused-result", "-I", os.path.join(HERE, "..", "include")]
-# per-source additions: the diagonal-block factor's fully unrolled pivot loop
-# (two wavefronts, 64 steps) is above the default size limit for a pragma
-# unroll; left rolled in the early passes, its register arrays go to scratch
-FILE_FLAGS = {"dense.hip": ["-mllvm", "-pragma-unroll-threshold=65536"]}
+# per-source additions (none at present)
+FILE_FLAGS = {}
 
 
 def sources():
